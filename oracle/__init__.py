@@ -1,0 +1,260 @@
+"""CPU oracle of the batched gridworld step -- TEST INFRASTRUCTURE ONLY.
+
+Python handle on ``gridworld_oracle.c`` (plain C, built with gcc).  Only the
+tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py``
+may import this package; the GPU library never does, and the two share no
+code.  See the C file for what each function follows in the NAVIX paper
+(arXiv 2407.19396) and how it is pinned.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gridworld_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# encoding of the oracle (MiniGrid's canonical indices)
+EMPTY, WALL, DOOR, KEY, GOAL = 1, 2, 4, 5, 8
+OPEN, CLOSED, LOCKED = 0, 1, 2
+FLAG_TERMINATED, FLAG_TRUNCATED, FLAG_FIRST = 1, 2, 4
+ACTION_NONE = 0xFF
+FAMILY_EMPTY, FAMILY_TWOROOM, FAMILY_FOURROOMS = 0, 1, 2
+OBS_BYTES = 147
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no FMA contraction, no fast math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+               "-fopenmp", "-shared", "-fPIC", "-Wall", "-Wextra",
+               "-o", _LIB + ".tmp", _SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+class _Batch(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32),
+                ("family", ctypes.c_void_p), ("side", ctypes.c_void_p),
+                ("max_steps", ctypes.c_void_p), ("seed", ctypes.c_void_p),
+                ("rng_id", ctypes.c_void_p), ("grid_off", ctypes.c_void_p),
+                ("reward_mode", ctypes.c_int32)]
+
+
+class _State(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_void_p), ("x", ctypes.c_void_p),
+                ("y", ctypes.c_void_p), ("dir", ctypes.c_void_p),
+                ("t", ctypes.c_void_p), ("carry", ctypes.c_void_p),
+                ("episode", ctypes.c_void_p), ("done_prev", ctypes.c_void_p)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        L.ox_philox4x32_10.argtypes = [P, P, P]
+        L.ox_uniform.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+        L.ox_uniform.restype = ctypes.c_uint32
+        L.ox_policy_action.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                       ctypes.c_uint32]
+        L.ox_policy_action.restype = ctypes.c_uint32
+        L.ox_side_ok.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.ox_side_ok.restype = ctypes.c_int
+        L.ox_layout.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32,
+                                ctypes.c_uint32, P, P, P, P]
+        L.ox_layout.restype = ctypes.c_int
+        L.ox_observe.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_int32, P]
+        L.ox_goal_reward.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int]
+        L.ox_goal_reward.restype = ctypes.c_float
+        L.ox_reset.argtypes = [ctypes.POINTER(_Batch), ctypes.POINTER(_State), P, P, P, P,
+                               ctypes.c_int]
+        L.ox_reset.restype = ctypes.c_int
+        L.ox_rollout.argtypes = [ctypes.POINTER(_Batch), ctypes.POINTER(_State), ctypes.c_int32,
+                                 P, ctypes.c_int32, P, P, P, P, ctypes.c_int]
+        L.ox_rollout.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+# ---------------------------------------------------------------- scalars
+def philox4x32_10(ctr, key):
+    c = np.asarray(ctr, dtype=np.uint32).copy()
+    k = np.asarray(key, dtype=np.uint32).copy()
+    out = np.zeros(4, dtype=np.uint32)
+    lib().ox_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def uniform(word: int, n: int) -> int:
+    return int(lib().ox_uniform(word, n))
+
+
+def policy_action(seed: int, rng_id: int, episode: int, t: int) -> int:
+    return int(lib().ox_policy_action(seed, rng_id, episode, t))
+
+
+def side_ok(family: int, side: int) -> bool:
+    return bool(lib().ox_side_ok(family, side))
+
+
+def layout(family: int, side: int, seed: int, rng_id: int, episode: int):
+    """Start state of one env: (grid [S][S][3] uint8, x, y, dir)."""
+    g = np.zeros((side, side, 3), dtype=np.uint8)
+    x, y, d = (ctypes.c_int(), ctypes.c_int(), ctypes.c_int())
+    rc = lib().ox_layout(family, side, seed, rng_id, episode, _ptr(g),
+                         ctypes.addressof(x), ctypes.addressof(y), ctypes.addressof(d))
+    if rc != 0:
+        raise ValueError(f"layout failed ({rc}) for family={family} side={side}")
+    return g, x.value, y.value, d.value
+
+
+def observe(grid: np.ndarray, x: int, y: int, d: int, carry: int = EMPTY) -> np.ndarray:
+    """First-person view [7][7][3] (row j, column i, channel) of one env."""
+    g = np.ascontiguousarray(grid, dtype=np.uint8)
+    obs = np.zeros((7, 7, 3), dtype=np.uint8)
+    lib().ox_observe(_ptr(g), g.shape[0], x, y, d, carry, _ptr(obs))
+    return obs
+
+
+def goal_reward(t: int, T: int, reward_mode: int = 0) -> float:
+    return float(np.float32(lib().ox_goal_reward(t, T, reward_mode)))
+
+
+def pack_carry(type_: int, colour: int = 0, state: int = 0) -> int:
+    return type_ | (colour << 8) | (state << 16)
+
+
+# ---------------------------------------------------------------- batches
+@dataclass
+class Batch:
+    family: np.ndarray      # u8[N]
+    side: np.ndarray        # u8[N]
+    max_steps: np.ndarray   # i32[N]
+    seed: np.ndarray        # u64[N]
+    rng_id: np.ndarray      # u32[N]
+    reward_mode: int = 0
+
+    @property
+    def n(self) -> int:
+        return int(self.family.shape[0])
+
+    def grid_offsets(self) -> np.ndarray:
+        cells = 3 * self.side.astype(np.uint64) ** 2
+        off = np.zeros(self.n, dtype=np.uint64)
+        if self.n > 1:
+            off[1:] = np.cumsum(cells)[:-1]
+        return off
+
+    def grid_bytes(self) -> int:
+        return int((3 * self.side.astype(np.uint64) ** 2).sum())
+
+
+@dataclass
+class State:
+    grid: np.ndarray
+    x: np.ndarray
+    y: np.ndarray
+    dir: np.ndarray
+    t: np.ndarray
+    carry: np.ndarray
+    episode: np.ndarray
+    done_prev: np.ndarray
+
+    @staticmethod
+    def empty(batch: Batch) -> "State":
+        n = batch.n
+        z = lambda dt: np.zeros(n, dtype=dt)  # noqa: E731
+        return State(np.zeros(batch.grid_bytes(), dtype=np.uint8), z(np.int32), z(np.int32),
+                     z(np.int32), z(np.int32), z(np.int32), z(np.uint32), z(np.uint8))
+
+    def copy(self) -> "State":
+        return State(*(getattr(self, f).copy() for f in
+                       ("grid", "x", "y", "dir", "t", "carry", "episode", "done_prev")))
+
+
+def _cbatch(b: Batch, keep: list):
+    arrs = [np.ascontiguousarray(b.family, dtype=np.uint8),
+            np.ascontiguousarray(b.side, dtype=np.uint8),
+            np.ascontiguousarray(b.max_steps, dtype=np.int32),
+            np.ascontiguousarray(b.seed, dtype=np.uint64),
+            np.ascontiguousarray(b.rng_id, dtype=np.uint32),
+            b.grid_offsets()]
+    keep.extend(arrs)
+    return _Batch(b.n, *[a.ctypes.data for a in arrs], b.reward_mode)
+
+
+def _cstate(s: State):
+    for f in ("grid", "x", "y", "dir", "t", "carry", "episode", "done_prev"):
+        a = getattr(s, f)
+        assert a.flags.c_contiguous, f
+    return _State(*[getattr(s, f).ctypes.data for f in
+                    ("grid", "x", "y", "dir", "t", "carry", "episode", "done_prev")])
+
+
+@dataclass
+class Outputs:
+    obs: np.ndarray | None   # u8[rows][N][7][7][3]
+    reward: np.ndarray       # f32[rows][N]
+    flags: np.ndarray        # u8[rows][N]
+    action: np.ndarray       # u8[rows][N]
+
+    @staticmethod
+    def empty(rows: int, n: int, with_obs: bool = True) -> "Outputs":
+        return Outputs(np.zeros((rows, n, 7, 7, 3), dtype=np.uint8) if with_obs else None,
+                       np.zeros((rows, n), dtype=np.float32),
+                       np.zeros((rows, n), dtype=np.uint8),
+                       np.zeros((rows, n), dtype=np.uint8))
+
+
+def reset(batch: Batch, state: State, out: Outputs | None = None, nthreads: int = 0) -> Outputs:
+    out = out or Outputs.empty(1, batch.n)
+    keep: list = []
+    cb = _cbatch(batch, keep)
+    cs = _cstate(state)
+    rc = lib().ox_reset(ctypes.byref(cb), ctypes.byref(cs), _ptr(out.obs), _ptr(out.reward),
+                        _ptr(out.flags), _ptr(out.action), nthreads)
+    if rc != 0:
+        raise ValueError(f"oracle reset failed ({rc})")
+    return out
+
+
+def rollout(batch: Batch, state: State, n_steps: int, actions: np.ndarray | None = None,
+            rows: int | None = None, with_obs: bool = True, nthreads: int = 0) -> Outputs:
+    """Run n_steps steps; step k lands in output row k % rows."""
+    rows = n_steps if rows is None else rows
+    out = Outputs.empty(rows, batch.n, with_obs)
+    if actions is not None:
+        actions = np.ascontiguousarray(actions, dtype=np.uint8)
+        assert actions.shape == (n_steps, batch.n), actions.shape
+    keep: list = []
+    cb = _cbatch(batch, keep)
+    cs = _cstate(state)
+    rc = lib().ox_rollout(ctypes.byref(cb), ctypes.byref(cs), n_steps, _ptr(actions), rows,
+                          _ptr(out.obs), _ptr(out.reward), _ptr(out.flags), _ptr(out.action),
+                          nthreads)
+    if rc != 0:
+        raise ValueError(f"oracle rollout failed ({rc})")
+    return out
+
+
+def step(batch: Batch, state: State, actions: np.ndarray, with_obs: bool = True) -> Outputs:
+    """One step for every env with the given actions (u8[N])."""
+    a = np.asarray(actions, dtype=np.uint8).reshape(1, batch.n)
+    return rollout(batch, state, 1, a, with_obs=with_obs)

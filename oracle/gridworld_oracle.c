@@ -1,0 +1,516 @@
+/*
+ * gridworld_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously-correct CPU model of the batched gridworld
+ * environment step of NAVIX (Pignatelli et al., "NAVIX: Scaling MiniGrid
+ * Environments with JAX", arXiv 2407.19396).  It exists to check the HIP
+ * path; nothing in the product may link, import or execute it.  Only the
+ * tests, the smoke entry and the CPU-baseline leg of the benchmark use it.
+ *
+ * It shares no code, header, table or constant with the GPU library.
+ *
+ * What it follows:
+ *   - the timestep protocol and autoreset (Sec. 3.2.2, "Stateful and fully
+ *     jittable": timestep tuple, reset pads action -1 / reward 0, step
+ *     autoresets when done);
+ *   - the systems in their order: intervention, transition, observation,
+ *     reward, termination (Table "systems"; App. A);
+ *   - the entities and components (Tables "components", "entities"):
+ *     walls, doors (openable, possibly locked), keys (pickable), goal;
+ *   - the reward of Sec. 3.2.1 / Eq. (1) in the time-discounted form
+ *     r = 1 - 0.9 * (t / T) evaluated in IEEE fp32, with t the number of
+ *     steps since reset after the current one, or the Markovian unit reward
+ *     the paper defaults to (reward_mode 1);
+ *   - the first-person symbolic observation (Table "observations",
+ *     symbolic_first_person, R = 7) with MiniGrid's occlusion rule, since
+ *     Sec. 3.2.1 states the environments match MiniGrid exactly;
+ *   - the Empty, DoorKey (two rooms) and FourRooms families (Table "envs").
+ *
+ * Every point the paper leaves open is fixed by a documented reading; the
+ * readings are listed next to each function.  Parity status of each
+ * function is stated in its comment ("pinned by" / "parity unpinned").
+ *
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC.
+ * No FMA contraction: the reward must be three separately rounded fp32
+ * operations.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---- encoding (MiniGrid's canonical object/colour/state indices) ---- */
+enum { O_UNSEEN = 0, O_EMPTY = 1, O_WALL = 2, O_FLOOR = 3, O_DOOR = 4,
+       O_KEY = 5, O_BALL = 6, O_BOX = 7, O_GOAL = 8, O_LAVA = 9,
+       O_AGENT = 10 };
+enum { C_RED = 0, C_GREEN = 1, C_BLUE = 2, C_PURPLE = 3, C_YELLOW = 4,
+       C_GREY = 5 };
+enum { D_OPEN = 0, D_CLOSED = 1, D_LOCKED = 2 };
+/* actions (MiniGrid order): left, right, forward, pickup, drop, toggle, done */
+enum { A_LEFT = 0, A_RIGHT = 1, A_FORWARD = 2, A_PICKUP = 3, A_DROP = 4,
+       A_TOGGLE = 5, A_DONE = 6 };
+enum { FAM_EMPTY = 0, FAM_TWOROOM = 1, FAM_FOURROOMS = 2 };
+
+#define OX_FLAG_TERMINATED 1u
+#define OX_FLAG_TRUNCATED 2u
+#define OX_FLAG_FIRST 4u
+#define OX_ACTION_NONE 0xFFu
+#define OX_VIEW 7
+
+/* direction d: 0 = +x (east), 1 = +y (south), 2 = -x (west), 3 = -y (north) */
+static const int DIR_X[4] = {1, 0, -1, 0};
+static const int DIR_Y[4] = {0, 1, 0, -1};
+
+/* ------------------------------------------------------------------ */
+/* Philox4x32-10, written from Salmon, Moraes, Dror, Shaw, "Parallel   */
+/* random numbers: as easy as 1, 2, 3" (SC'11), Sec. 3.3 / Table 2:    */
+/* each round multiplies counter words 0 and 2 by the two round         */
+/* multipliers, swaps in the high halves xored with the other words and */
+/* the round key, and the key is advanced by the two Weyl constants     */
+/* between rounds.  Pinned by the known-answer vectors of that paper's  */
+/* reference distribution (tests/golden/philox_kat.json).               */
+/* ------------------------------------------------------------------ */
+void ox_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2],
+                      uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n1 = lo1;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    uint32_t n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Uniform integer in [0, n): floor(word * n / 2^32). */
+uint32_t ox_uniform(uint32_t word, uint32_t n) {
+  return (uint32_t)(((uint64_t)word * (uint64_t)n) >> 32);
+}
+
+/* Random words of one layout draw: key = seed, counter =
+ * (rng_id, episode, word_index / 4, 0); word w is lane w % 4. */
+static uint32_t layout_word(uint64_t seed, uint32_t rng_id, uint32_t episode,
+                            uint32_t w) {
+  uint32_t ctr[4] = {rng_id, episode, w / 4u, 0u};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t out[4];
+  ox_philox4x32_10(ctr, key, out);
+  return out[w % 4u];
+}
+
+/* Random-policy action for the step taken at pre-step counter t of
+ * episode `episode`: counter = (rng_id, episode, t / 4, 1), lane t % 4,
+ * uniform over the 7 actions. */
+uint32_t ox_policy_action(uint64_t seed, uint32_t rng_id, uint32_t episode,
+                          uint32_t t) {
+  uint32_t ctr[4] = {rng_id, episode, t / 4u, 1u};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t out[4];
+  ox_philox4x32_10(ctr, key, out);
+  return ox_uniform(out[t % 4u], 7u);
+}
+
+/* ------------------------------------------------------------------ */
+/* grid helpers: grid is [y][x][3] bytes (type, colour, state)         */
+/* ------------------------------------------------------------------ */
+static uint8_t *cell(uint8_t *g, int S, int x, int y) {
+  return g + 3 * (y * S + x);
+}
+static void put(uint8_t *g, int S, int x, int y, int type, int colour,
+                int state) {
+  uint8_t *c = cell(g, S, x, y);
+  c[0] = (uint8_t)type; c[1] = (uint8_t)colour; c[2] = (uint8_t)state;
+}
+
+/* The k-th cell (0-based, row-major: y then x) inside the rectangle
+ * [x0,x1] x [y0,y1] whose type is empty.  Returns 0 on success. */
+static int kth_empty(const uint8_t *g, int S, int x0, int x1, int y0, int y1,
+                     uint32_t k, int *ox, int *oy) {
+  uint32_t seen = 0;
+  for (int y = y0; y <= y1; ++y)
+    for (int x = x0; x <= x1; ++x) {
+      if (g[3 * (y * S + x)] != O_EMPTY) continue;
+      if (seen == k) { *ox = x; *oy = y; return 0; }
+      ++seen;
+    }
+  return -1;
+}
+static uint32_t count_empty(const uint8_t *g, int S, int x0, int x1, int y0,
+                            int y1) {
+  uint32_t n = 0;
+  for (int y = y0; y <= y1; ++y)
+    for (int x = x0; x <= x1; ++x)
+      if (g[3 * (y * S + x)] == O_EMPTY) ++n;
+  return n;
+}
+
+/* Side limits of each family. */
+int ox_side_ok(int family, int side) {
+  if (side > 32) return 0;
+  switch (family) {
+    case FAM_EMPTY: return side >= 4;
+    case FAM_TWOROOM: return side >= 5;
+    case FAM_FOURROOMS: return side >= 7 && (side % 2) == 1;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Start-state distribution P0 (Sec. 3.2.2, reset(key); Table "envs"  */
+/* for the families; App. D, custom-env _reset: build the grid, place */
+/* the entities).  Draws are taken from the layout stream in the      */
+/* order written.  "Uniform placement" = the k-th empty cell of the   */
+/* region in row-major order, k uniform over the count.               */
+/*                                                                     */
+/* Empty(S): wall border, goal (green) at (S-2, S-2); agent uniform    */
+/*   over the empty interior; direction uniform.                       */
+/* TwoRoom(S) (DoorKey): wall column c = 2 + u(S-4); door row          */
+/*   d = 1 + u(S-3); door colour u(6), locked; goal at (S-2, S-2); key */
+/*   of the door's colour uniform over the empty cells of the left     */
+/*   room x in [1, c-1]; agent uniform over the remaining empty cells  */
+/*   of the left room; direction uniform.                              */
+/* FourRooms(S odd): walls along row m and column m, m = S / 2; one    */
+/*   opening per wall segment, drawn in the order (m, 1+u(m-1)),       */
+/*   (m, m+1+u(m-1)), (1+u(m-1), m), (m+1+u(m-1), m); goal uniform     */
+/*   over all empty cells, agent uniform over the remaining empty      */
+/*   cells; direction uniform.                                          */
+/* Pinned by: structural invariants, uniformity tests and the hand     */
+/* layouts in tests; agreement with MiniGrid's own generators: parity  */
+/* unpinned (MiniGrid is not available).                               */
+/* ------------------------------------------------------------------ */
+int ox_layout(int family, int S, uint64_t seed, uint32_t rng_id,
+              uint32_t episode, uint8_t *grid, int *ax, int *ay, int *adir) {
+  if (!ox_side_ok(family, S)) return -1;
+  uint32_t w = 0;
+#define DRAW(n) ox_uniform(layout_word(seed, rng_id, episode, w++), (uint32_t)(n))
+  for (int y = 0; y < S; ++y)
+    for (int x = 0; x < S; ++x) {
+      int border = (x == 0 || y == 0 || x == S - 1 || y == S - 1);
+      if (border) put(grid, S, x, y, O_WALL, C_GREY, 0);
+      else put(grid, S, x, y, O_EMPTY, 0, 0);
+    }
+  if (family == FAM_EMPTY) {
+    put(grid, S, S - 2, S - 2, O_GOAL, C_GREEN, 0);
+    uint32_t n = count_empty(grid, S, 1, S - 2, 1, S - 2);
+    if (kth_empty(grid, S, 1, S - 2, 1, S - 2, DRAW(n), ax, ay)) return -2;
+    *adir = (int)DRAW(4);
+  } else if (family == FAM_TWOROOM) {
+    int c = 2 + (int)DRAW(S - 4);
+    int d = 1 + (int)DRAW(S - 3);
+    int colour = (int)DRAW(6);
+    for (int y = 0; y < S; ++y) put(grid, S, c, y, O_WALL, C_GREY, 0);
+    put(grid, S, c, d, O_DOOR, colour, D_LOCKED);
+    put(grid, S, S - 2, S - 2, O_GOAL, C_GREEN, 0);
+    int kx, ky;
+    uint32_t n = count_empty(grid, S, 1, c - 1, 1, S - 2);
+    if (kth_empty(grid, S, 1, c - 1, 1, S - 2, DRAW(n), &kx, &ky)) return -2;
+    put(grid, S, kx, ky, O_KEY, colour, 0);
+    n = count_empty(grid, S, 1, c - 1, 1, S - 2);
+    if (kth_empty(grid, S, 1, c - 1, 1, S - 2, DRAW(n), ax, ay)) return -2;
+    *adir = (int)DRAW(4);
+  } else {
+    int m = S / 2;
+    for (int i = 0; i < S; ++i) {
+      put(grid, S, m, i, O_WALL, C_GREY, 0);
+      put(grid, S, i, m, O_WALL, C_GREY, 0);
+    }
+    int g1 = 1 + (int)DRAW(m - 1);
+    int g2 = m + 1 + (int)DRAW(m - 1);
+    int g3 = 1 + (int)DRAW(m - 1);
+    int g4 = m + 1 + (int)DRAW(m - 1);
+    put(grid, S, m, g1, O_EMPTY, 0, 0);
+    put(grid, S, m, g2, O_EMPTY, 0, 0);
+    put(grid, S, g3, m, O_EMPTY, 0, 0);
+    put(grid, S, g4, m, O_EMPTY, 0, 0);
+    int gx, gy;
+    uint32_t n = count_empty(grid, S, 1, S - 2, 1, S - 2);
+    if (kth_empty(grid, S, 1, S - 2, 1, S - 2, DRAW(n), &gx, &gy)) return -2;
+    put(grid, S, gx, gy, O_GOAL, C_GREEN, 0);
+    n = count_empty(grid, S, 1, S - 2, 1, S - 2);
+    if (kth_empty(grid, S, 1, S - 2, 1, S - 2, DRAW(n), ax, ay)) return -2;
+    *adir = (int)DRAW(4);
+  }
+#undef DRAW
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Observation system O: S -> O, symbolic_first_person with R = 7     */
+/* (Table "observations"), following MiniGrid's partial view because  */
+/* the environments match MiniGrid (Sec. 3.2.1):                      */
+/*  1. the 7x7 view, agent at view column 3, row 6, facing row 0:     */
+/*     world(i, j) = agent + (i-3) * right + (6-j) * forward, with    */
+/*     right = (-forward_y, forward_x); cells outside the grid are    */
+/*     walls;                                                          */
+/*  2. occlusion: walls and non-open doors block sight.  Row by row   */
+/*     from the agent's row (6) to the farthest (0): a left-to-right  */
+/*     pass, then a right-to-left pass, over visible see-through cells*/
+/*     which make their row neighbour and the two cells ahead visible;*/
+/*  3. encoding: invisible cells (0,0,0); visible cells their         */
+/*     (type, colour, state); the agent's own cell shows what it      */
+/*     carries, or an empty cell (1,0,0) for an empty hand.           */
+/* Output layout obs[j][i][c]: row j (0 = farthest), column i         */
+/* (0 = the agent's left), channel c.                                  */
+/* Pinned by the hand-worked views in tests/golden/ and by rotation    */
+/* invariance; agreement with MiniGrid itself: parity unpinned.        */
+/* ------------------------------------------------------------------ */
+void ox_observe(const uint8_t *grid, int S, int ax, int ay, int dir,
+                int32_t carry, uint8_t *obs /* [7][7][3] */) {
+  uint8_t view[OX_VIEW][OX_VIEW][3]; /* [i][j][c] */
+  int see[OX_VIEW][OX_VIEW];
+  int vis[OX_VIEW][OX_VIEW];
+  int fx = DIR_X[dir], fy = DIR_Y[dir];
+  int rx = -fy, ry = fx;
+  for (int i = 0; i < OX_VIEW; ++i)
+    for (int j = 0; j < OX_VIEW; ++j) {
+      int wx = ax + (i - 3) * rx + (6 - j) * fx;
+      int wy = ay + (i - 3) * ry + (6 - j) * fy;
+      if (wx < 0 || wy < 0 || wx >= S || wy >= S) {
+        view[i][j][0] = O_WALL; view[i][j][1] = C_GREY; view[i][j][2] = 0;
+      } else {
+        const uint8_t *c = grid + 3 * (wy * S + wx);
+        view[i][j][0] = c[0]; view[i][j][1] = c[1]; view[i][j][2] = c[2];
+      }
+      int type = view[i][j][0];
+      int opaque = (type == O_WALL) || (type == O_DOOR && view[i][j][2] != D_OPEN);
+      see[i][j] = !opaque;
+      vis[i][j] = 0;
+    }
+  vis[3][6] = 1;
+  for (int j = OX_VIEW - 1; j >= 0; --j) {
+    for (int i = 0; i < OX_VIEW - 1; ++i) {
+      if (!vis[i][j] || !see[i][j]) continue;
+      vis[i + 1][j] = 1;
+      if (j > 0) { vis[i + 1][j - 1] = 1; vis[i][j - 1] = 1; }
+    }
+    for (int i = OX_VIEW - 1; i >= 1; --i) {
+      if (!vis[i][j] || !see[i][j]) continue;
+      vis[i - 1][j] = 1;
+      if (j > 0) { vis[i - 1][j - 1] = 1; vis[i][j - 1] = 1; }
+    }
+  }
+  for (int j = 0; j < OX_VIEW; ++j)
+    for (int i = 0; i < OX_VIEW; ++i) {
+      uint8_t *o = obs + 3 * (j * OX_VIEW + i);
+      if (i == 3 && j == 6) {
+        o[0] = (uint8_t)(carry & 0xFF);
+        o[1] = (uint8_t)((carry >> 8) & 0xFF);
+        o[2] = (uint8_t)((carry >> 16) & 0xFF);
+      } else if (vis[i][j]) {
+        o[0] = view[i][j][0]; o[1] = view[i][j][1]; o[2] = view[i][j][2];
+      } else {
+        o[0] = 0; o[1] = 0; o[2] = 0;
+      }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Reward R (Sec. 3.2.1, Eq. (1); Table "rewards", on_goal_reached),  */
+/* in fp32, three separately rounded operations:                       */
+/*   q = t / T, p = 0.9 * q, r = 1 - p  (t counted after this step).   */
+/* reward_mode 1 is the Markovian unit reward the paper uses instead.  */
+/* Pinned by the exact rational 1 - 9t/(10T) within fp32 error bounds. */
+/* ------------------------------------------------------------------ */
+float ox_goal_reward(int32_t t, int32_t T, int reward_mode) {
+  if (reward_mode == 1) return 1.0f;
+  volatile float q = (float)t / (float)T;
+  volatile float p = 0.9f * q;
+  volatile float r = 1.0f - p;
+  return r;
+}
+
+/* one env of a batch */
+typedef struct {
+  uint8_t *grid;
+  int32_t *x, *y, *dir, *t, *carry;
+  uint32_t *episode;
+  uint8_t *done_prev;
+} ox_env_ref;
+
+static int is_pickable(int type) {
+  return type == O_KEY || type == O_BALL || type == O_BOX;
+}
+
+/* ------------------------------------------------------------------ */
+/* One environment step: the interaction protocol of Sec. 3.2.2 with  */
+/* autoreset.  If the previous step ended the episode, this call      */
+/* ignores its action and returns the first timestep of the next      */
+/* episode (reset pads: action -1 recorded as 0xFF, reward 0).        */
+/* Otherwise: intervention I(s, a) (turn, forward with collision,     */
+/* pickup, drop, toggle with colour-matched keys; App. A), transition */
+/* (identity for these families), observation O(s'), reward R, and    */
+/* termination (goal reached) plus truncation at t = T.               */
+/* ------------------------------------------------------------------ */
+static void step_one(int family, int S, int32_t T, uint64_t seed,
+                     uint32_t rng_id, int reward_mode, ox_env_ref e,
+                     uint32_t action, uint8_t *obs, float *reward,
+                     uint8_t *flags, uint8_t *rec_action) {
+  if (*e.done_prev) {
+    *e.episode += 1u;
+    ox_layout(family, S, seed, rng_id, *e.episode, e.grid, e.x, e.y, e.dir);
+    *e.t = 0;
+    *e.carry = O_EMPTY;
+    *e.done_prev = 0;
+    if (obs) ox_observe(e.grid, S, *e.x, *e.y, *e.dir, *e.carry, obs);
+    *reward = 0.0f;
+    *flags = OX_FLAG_FIRST;
+    *rec_action = OX_ACTION_NONE;
+    return;
+  }
+  int dir = *e.dir;
+  int fx = *e.x + DIR_X[dir], fy = *e.y + DIR_Y[dir];
+  uint8_t *front = cell(e.grid, S, fx, fy);
+  int terminated = 0;
+  switch (action) {
+    case A_LEFT: *e.dir = (dir + 3) % 4; break;
+    case A_RIGHT: *e.dir = (dir + 1) % 4; break;
+    case A_FORWARD: {
+      int type = front[0];
+      int walkable = type == O_EMPTY || type == O_GOAL ||
+                     (type == O_DOOR && front[2] == D_OPEN);
+      if (walkable) { *e.x = fx; *e.y = fy; }
+      if (type == O_GOAL) terminated = 1;
+      break;
+    }
+    case A_PICKUP:
+      if (*e.carry == O_EMPTY && is_pickable(front[0])) {
+        *e.carry = front[0] | (front[1] << 8) | (front[2] << 16);
+        front[0] = O_EMPTY; front[1] = 0; front[2] = 0;
+      }
+      break;
+    case A_DROP:
+      if (*e.carry != O_EMPTY && front[0] == O_EMPTY) {
+        front[0] = (uint8_t)(*e.carry & 0xFF);
+        front[1] = (uint8_t)((*e.carry >> 8) & 0xFF);
+        front[2] = (uint8_t)((*e.carry >> 16) & 0xFF);
+        *e.carry = O_EMPTY;
+      }
+      break;
+    case A_TOGGLE:
+      if (front[0] == O_DOOR) {
+        if (front[2] == D_LOCKED) {
+          int carry_type = *e.carry & 0xFF, carry_colour = (*e.carry >> 8) & 0xFF;
+          if (carry_type == O_KEY && carry_colour == front[1]) front[2] = D_OPEN;
+        } else {
+          front[2] = front[2] == D_OPEN ? D_CLOSED : D_OPEN;
+        }
+      }
+      break;
+    default: /* done, and any out-of-range action: no-op */
+      break;
+  }
+  *e.t += 1;
+  int truncated = *e.t >= T;
+  *reward = terminated ? ox_goal_reward(*e.t, T, reward_mode) : 0.0f;
+  *flags = (uint8_t)((terminated ? OX_FLAG_TERMINATED : 0) |
+                     (truncated ? OX_FLAG_TRUNCATED : 0));
+  *rec_action = (uint8_t)action;
+  *e.done_prev = (uint8_t)(terminated || truncated);
+  if (obs) ox_observe(e.grid, S, *e.x, *e.y, *e.dir, *e.carry, obs);
+}
+
+/* ------------------------------------------------------------------ */
+/* Batch entry points (SoA, host memory).  Per env i:                  */
+/*   family[i], side[i], max_steps[i], seed[i], rng_id[i],            */
+/*   grid + grid_off[i] ([side][side][3]),                             */
+/*   x, y, dir, t, carry, episode, done_prev.                          */
+/* Outputs are [N] rows; obs rows are 147 bytes; obs may be NULL.      */
+/* nthreads > 0 runs envs in parallel with OpenMP (timing mode).       */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  int32_t n;
+  const uint8_t *family, *side;
+  const int32_t *max_steps;
+  const uint64_t *seed;
+  const uint32_t *rng_id;
+  const uint64_t *grid_off;
+  int32_t reward_mode;
+} ox_batch;
+
+typedef struct {
+  uint8_t *grid;
+  int32_t *x, *y, *dir, *t, *carry;
+  uint32_t *episode;
+  uint8_t *done_prev;
+} ox_state;
+
+static ox_env_ref env_ref(const ox_batch *b, const ox_state *s, int i) {
+  ox_env_ref e;
+  e.grid = s->grid + b->grid_off[i];
+  e.x = s->x + i; e.y = s->y + i; e.dir = s->dir + i; e.t = s->t + i;
+  e.carry = s->carry + i; e.episode = s->episode + i;
+  e.done_prev = s->done_prev + i;
+  return e;
+}
+
+static void set_threads(int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+}
+
+/* Reset every env to episode 0 (reset(key) of Sec. 3.2.2). */
+int ox_reset(const ox_batch *b, const ox_state *s, uint8_t *obs, float *reward,
+             uint8_t *flags, uint8_t *action, int nthreads) {
+  for (int i = 0; i < b->n; ++i)
+    if (!ox_side_ok(b->family[i], b->side[i])) return -1;
+  set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64) if (nthreads > 0)
+  for (int i = 0; i < b->n; ++i) {
+    ox_env_ref e = env_ref(b, s, i);
+    *e.episode = 0;
+    ox_layout(b->family[i], b->side[i], b->seed[i], b->rng_id[i], 0, e.grid,
+              e.x, e.y, e.dir);
+    *e.t = 0;
+    *e.carry = O_EMPTY;
+    *e.done_prev = 0;
+    if (obs)
+      ox_observe(e.grid, b->side[i], *e.x, *e.y, *e.dir, *e.carry,
+                 obs + (size_t)147 * i);
+    if (reward) reward[i] = 0.0f;
+    if (flags) flags[i] = OX_FLAG_FIRST;
+    if (action) action[i] = OX_ACTION_NONE;
+  }
+  return 0;
+}
+
+/* n_steps steps.  actions: [n_steps][N] bytes, or NULL for the random
+ * policy.  Step k writes output row k % rows. */
+int ox_rollout(const ox_batch *b, const ox_state *s, int32_t n_steps,
+               const uint8_t *actions, int32_t rows, uint8_t *obs,
+               float *reward, uint8_t *flags, uint8_t *action, int nthreads) {
+  if (rows <= 0) return -1;
+  set_threads(nthreads);
+  const size_t N = (size_t)b->n;
+#pragma omp parallel for schedule(dynamic, 64) if (nthreads > 0)
+  for (int i = 0; i < b->n; ++i) {
+    ox_env_ref e = env_ref(b, s, i);
+    for (int k = 0; k < n_steps; ++k) {
+      size_t row = (size_t)(k % rows);
+      uint32_t a;
+      if (actions) a = actions[(size_t)k * N + i];
+      else a = *e.done_prev ? 0u
+                            : ox_policy_action(b->seed[i], b->rng_id[i],
+                                               *e.episode, (uint32_t)*e.t);
+      step_one(b->family[i], b->side[i], b->max_steps[i], b->seed[i],
+               b->rng_id[i], b->reward_mode, e, a,
+               obs ? obs + 147 * (row * N + i) : NULL, reward + row * N + i,
+               flags + row * N + i, action + row * N + i);
+    }
+  }
+  return 0;
+}

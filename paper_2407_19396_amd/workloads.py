@@ -1,0 +1,141 @@
+"""Seeded synthetic workloads shared by the GPU path's tests, the oracle's
+tests and the benchmark.
+
+This module only *describes inputs*: which family and grid side each env
+has, its truncation limit, its RNG seed and id, and external action
+streams.  It holds none of the environment dynamics, so both sides of a
+parity check can use it without sharing any of the method's arithmetic.
+
+The workloads stand in for the paper's MiniGrid tasks (NAVIX, Table
+"envs": Empty-5x5 / 8x8 / 16x16, DoorKey-5x5 ... 16x16, FourRooms), which
+are generated procedurally, so no dataset is involved.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+FAMILY_EMPTY, FAMILY_TWOROOM, FAMILY_FOURROOMS = 0, 1, 2
+FAMILY_NAMES = {FAMILY_EMPTY: "Empty", FAMILY_TWOROOM: "TwoRoom", FAMILY_FOURROOMS: "FourRooms"}
+N_ACTIONS = 7
+
+
+def default_max_steps(family: int, side: int) -> int:
+    """MiniGrid's default step limits for each family: 4*S^2 (Empty),
+    10*S^2 (DoorKey), 100 (FourRooms)."""
+    if family == FAMILY_EMPTY:
+        return 4 * side * side
+    if family == FAMILY_TWOROOM:
+        return 10 * side * side
+    return 100
+
+
+@dataclass
+class EnvTable:
+    """Per-env configuration (host arrays)."""
+    family: np.ndarray     # u8[N]
+    side: np.ndarray       # u8[N]
+    max_steps: np.ndarray  # i32[N]
+    seed: np.ndarray       # u64[N]
+    rng_id: np.ndarray     # u32[N]
+    name: str = ""
+
+    @property
+    def n(self) -> int:
+        return int(self.family.shape[0])
+
+    def subset(self, idx) -> "EnvTable":
+        idx = np.asarray(idx)
+        return EnvTable(self.family[idx].copy(), self.side[idx].copy(), self.max_steps[idx].copy(),
+                        self.seed[idx].copy(), self.rng_id[idx].copy(), self.name + "[subset]")
+
+
+def _table(family, side, seed: int, name: str, max_steps=None) -> EnvTable:
+    family = np.asarray(family, dtype=np.uint8)
+    side = np.asarray(side, dtype=np.uint8)
+    n = family.shape[0]
+    if max_steps is None:
+        max_steps = np.array([default_max_steps(int(f), int(s)) for f, s in zip(family, side)],
+                             dtype=np.int32)
+    else:
+        max_steps = np.broadcast_to(np.asarray(max_steps, dtype=np.int32), (n,)).copy()
+    return EnvTable(family, side, max_steps, np.full(n, seed, dtype=np.uint64),
+                    np.arange(n, dtype=np.uint32), name)
+
+
+def uniform_table(n: int, family: int, side: int, seed: int = 0, max_steps=None) -> EnvTable:
+    """n envs of one family and side."""
+    return _table(np.full(n, family), np.full(n, side), seed,
+                  f"{FAMILY_NAMES[family]}-{side}x{side} x{n}", max_steps)
+
+
+def mixed_table(n: int, seed: int = 0, mix_seed: int = 12345) -> EnvTable:
+    """The uneven-size mix: 40 % single rooms and 40 % two-room key/door
+    layouts with side uniform over {5, 6, 8, 16}, 20 % 19x19 four-room
+    layouts; family and side drawn i.i.d. per env from a seeded generator."""
+    rng = np.random.default_rng(mix_seed)
+    u = rng.random(n)
+    family = np.where(u < 0.4, FAMILY_EMPTY, np.where(u < 0.8, FAMILY_TWOROOM, FAMILY_FOURROOMS))
+    side = np.array([5, 6, 8, 16], dtype=np.int64)[rng.integers(0, 4, n)]
+    side = np.where(family == FAMILY_FOURROOMS, 19, side)
+    return _table(family, side, seed, f"mixed x{n}")
+
+
+# The five workloads (sizes as stated for the batched step).
+def workload_empty5(seed: int = 0) -> EnvTable:
+    """16 single rooms 5x5, max_steps 100 (plain step, 100 steps)."""
+    return uniform_table(16, FAMILY_EMPTY, 5, seed)
+
+
+def workload_empty8(seed: int = 0) -> EnvTable:
+    """4096 single rooms 8x8, max_steps 256 (plain step, 1000 steps)."""
+    return uniform_table(4096, FAMILY_EMPTY, 8, seed)
+
+
+def workload_tworoom8(seed: int = 0) -> EnvTable:
+    """65536 two-room key/door 8x8, max_steps 640 (fused, 2048 steps)."""
+    return uniform_table(65536, FAMILY_TWOROOM, 8, seed)
+
+
+def workload_mixed(seed: int = 0, n: int = 262144) -> EnvTable:
+    """262144 envs of uneven sizes (fused persistent launch, 4096 steps)."""
+    return mixed_table(n, seed)
+
+
+WORKLOAD_STEPS = {"empty5": 100, "empty8": 1000, "tworoom8": 2048, "mixed": 4096}
+
+
+def random_actions(n_steps: int, n_envs: int, seed: int) -> np.ndarray:
+    """External action stream u8[n_steps][n_envs], uniform over {0..6}."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, N_ACTIONS, size=(n_steps, n_envs), dtype=np.uint8)
+
+
+@dataclass
+class Request:
+    """One rollout request of the serving workload."""
+    rid: int
+    arrival_s: float
+    n_envs: int
+    n_steps: int
+    seed: int
+    table: EnvTable
+
+
+def serving_requests(n_requests: int, rate_per_s: float, master_seed: int = 0,
+                     max_envs: int = 8192) -> list[Request]:
+    """Poisson arrivals; each request has log-uniform 1..max_envs envs drawn
+    from the uneven-size mix, n_steps uniform in [64, 1024] and its own seed."""
+    rng = np.random.default_rng(master_seed)
+    t = 0.0
+    reqs = []
+    for rid in range(n_requests):
+        t += rng.exponential(1.0 / rate_per_s)
+        n_envs = int(min(max_envs, max(1, np.floor(2.0 ** (rng.random() * np.log2(max_envs))))))
+        n_steps = int(rng.integers(64, 1025))
+        seed = int(rng.integers(0, 2 ** 63))
+        table = mixed_table(n_envs, seed=seed, mix_seed=int(rng.integers(0, 2 ** 31)))
+        table.name = f"request {rid}"
+        reqs.append(Request(rid, t, n_envs, n_steps, seed, table))
+    return reqs
