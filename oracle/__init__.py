@@ -67,8 +67,7 @@ def lib():
         L.ox_philox4x32_10.argtypes = [P, P, P]
         L.ox_uniform.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
         L.ox_uniform.restype = ctypes.c_uint32
-        L.ox_policy_action.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
-                                       ctypes.c_uint32]
+        L.ox_policy_action.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64]
         L.ox_policy_action.restype = ctypes.c_uint32
         L.ox_side_ok.argtypes = [ctypes.c_int, ctypes.c_int]
         L.ox_side_ok.restype = ctypes.c_int
@@ -83,7 +82,7 @@ def lib():
                                ctypes.c_int]
         L.ox_reset.restype = ctypes.c_int
         L.ox_rollout.argtypes = [ctypes.POINTER(_Batch), ctypes.POINTER(_State), ctypes.c_int32,
-                                 P, ctypes.c_int32, P, P, P, P, ctypes.c_int]
+                                 P, ctypes.c_uint64, ctypes.c_int32, P, P, P, P, ctypes.c_int]
         L.ox_rollout.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -106,8 +105,8 @@ def uniform(word: int, n: int) -> int:
     return int(lib().ox_uniform(word, n))
 
 
-def policy_action(seed: int, rng_id: int, episode: int, t: int) -> int:
-    return int(lib().ox_policy_action(seed, rng_id, episode, t))
+def policy_action(seed: int, rng_id: int, call: int) -> int:
+    return int(lib().ox_policy_action(seed, rng_id, call))
 
 
 def side_ok(family: int, side: int) -> bool:
@@ -236,8 +235,10 @@ def reset(batch: Batch, state: State, out: Outputs | None = None, nthreads: int 
 
 
 def rollout(batch: Batch, state: State, n_steps: int, actions: np.ndarray | None = None,
-            rows: int | None = None, with_obs: bool = True, nthreads: int = 0) -> Outputs:
-    """Run n_steps steps; step k lands in output row k % rows."""
+            rows: int | None = None, with_obs: bool = True, nthreads: int = 0,
+            call0: int = 0) -> Outputs:
+    """Run n_steps steps; step k lands in output row k % rows.  Without
+    actions the random policy draws with call index call0 + k."""
     rows = n_steps if rows is None else rows
     out = Outputs.empty(rows, batch.n, with_obs)
     if actions is not None:
@@ -246,7 +247,7 @@ def rollout(batch: Batch, state: State, n_steps: int, actions: np.ndarray | None
     keep: list = []
     cb = _cbatch(batch, keep)
     cs = _cstate(state)
-    rc = lib().ox_rollout(ctypes.byref(cb), ctypes.byref(cs), n_steps, _ptr(actions), rows,
+    rc = lib().ox_rollout(ctypes.byref(cb), ctypes.byref(cs), n_steps, _ptr(actions), call0, rows,
                           _ptr(out.obs), _ptr(out.reward), _ptr(out.flags), _ptr(out.action),
                           nthreads)
     if rc != 0:

@@ -110,16 +110,18 @@ static uint32_t layout_word(uint64_t seed, uint32_t rng_id, uint32_t episode,
   return out[w % 4u];
 }
 
-/* Random-policy action for the step taken at pre-step counter t of
- * episode `episode`: counter = (rng_id, episode, t / 4, 1), lane t % 4,
- * uniform over the 7 actions. */
-uint32_t ox_policy_action(uint64_t seed, uint32_t rng_id, uint32_t episode,
-                          uint32_t t) {
-  uint32_t ctr[4] = {rng_id, episode, t / 4u, 1u};
+/* Random-policy action of the call with index `call` (calls are counted
+ * per context from its reset, every env advancing together): counter =
+ * (rng_id, (call / 4) low 32 bits, (call / 4) high 32 bits, 1), lane
+ * call % 4, uniform over the 7 actions.  The action drawn on a call that
+ * autoresets is not used. */
+uint32_t ox_policy_action(uint64_t seed, uint32_t rng_id, uint64_t call) {
+  uint64_t block = call / 4u;
+  uint32_t ctr[4] = {rng_id, (uint32_t)block, (uint32_t)(block >> 32), 1u};
   uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
   uint32_t out[4];
   ox_philox4x32_10(ctr, key, out);
-  return ox_uniform(out[t % 4u], 7u);
+  return ox_uniform(out[call % 4u], 7u);
 }
 
 /* ------------------------------------------------------------------ */
@@ -489,9 +491,10 @@ int ox_reset(const ox_batch *b, const ox_state *s, uint8_t *obs, float *reward,
 }
 
 /* n_steps steps.  actions: [n_steps][N] bytes, or NULL for the random
- * policy.  Step k writes output row k % rows. */
+ * policy, whose call index is call0 + k on step k.  Step k writes output
+ * row k % rows. */
 int ox_rollout(const ox_batch *b, const ox_state *s, int32_t n_steps,
-               const uint8_t *actions, int32_t rows, uint8_t *obs,
+               const uint8_t *actions, uint64_t call0, int32_t rows, uint8_t *obs,
                float *reward, uint8_t *flags, uint8_t *action, int nthreads) {
   if (rows <= 0) return -1;
   set_threads(nthreads);
@@ -503,9 +506,7 @@ int ox_rollout(const ox_batch *b, const ox_state *s, int32_t n_steps,
       size_t row = (size_t)(k % rows);
       uint32_t a;
       if (actions) a = actions[(size_t)k * N + i];
-      else a = *e.done_prev ? 0u
-                            : ox_policy_action(b->seed[i], b->rng_id[i],
-                                               *e.episode, (uint32_t)*e.t);
+      else a = ox_policy_action(b->seed[i], b->rng_id[i], call0 + (uint64_t)k);
       step_one(b->family[i], b->side[i], b->max_steps[i], b->seed[i],
                b->rng_id[i], b->reward_mode, e, a,
                obs ? obs + 147 * (row * N + i) : NULL, reward + row * N + i,

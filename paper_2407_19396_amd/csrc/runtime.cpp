@@ -1,0 +1,272 @@
+// runtime.cpp -- host side of libgridenv.so: argument validation, the
+// per-env tables and tiling of a context, and kernel launches.  Every
+// public function is extern "C", returns a GX_* status and never throws.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/gridenv.h"
+#include "launch.h"
+
+struct gx_ctx {
+  int device = 0;
+  int32_t n = 0;
+  int32_t reward_mode = 0;
+  uint64_t grid_bytes = 0;
+  uint64_t calls = 0;
+  bool has_reset = false;
+  // device tables
+  uint32_t* d_meta = nullptr;
+  int32_t* d_max_steps = nullptr;
+  uint2* d_seed = nullptr;
+  uint32_t* d_rng_id = nullptr;
+  uint64_t* d_grid_off = nullptr;
+  // fused tiling and launch shape
+  int32_t n_tiles = 0;
+  int32_t max_tile_cells = 0;
+  int32_t blocks = 0;
+  int32_t k_default = 64;
+};
+
+namespace {
+
+constexpr int kTileEnvs = 64;
+
+bool side_ok(int family, int side) {
+  if (side > 32) return false;
+  switch (family) {
+    case GX_FAMILY_EMPTY: return side >= 4;
+    case GX_FAMILY_TWOROOM: return side >= 5;
+    case GX_FAMILY_FOURROOMS: return side >= 7 && (side & 1) == 1;
+    default: return false;
+  }
+}
+
+// Reports (and clears) a pending asynchronous error of earlier GPU work.
+int device_status() {
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? GX_OK : GX_EDEVICE;
+}
+
+template <class T>
+int upload(T** dst, const std::vector<T>& src) {
+  if (hipMalloc(reinterpret_cast<void**>(dst), src.size() * sizeof(T)) != hipSuccess) return GX_ENOMEM;
+  if (hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    return GX_EDEVICE;
+  return GX_OK;
+}
+
+void free_tables(gx_ctx* c) {
+  (void)hipFree(c->d_meta);
+  (void)hipFree(c->d_max_steps);
+  (void)hipFree(c->d_seed);
+  (void)hipFree(c->d_rng_id);
+  (void)hipFree(c->d_grid_off);
+  c->d_meta = nullptr;
+  c->d_max_steps = nullptr;
+  c->d_seed = nullptr;
+  c->d_rng_id = nullptr;
+  c->d_grid_off = nullptr;
+}
+
+bool state_ok(const gx_state* st) {
+  return st && st->grid && st->x && st->y && st->dir && st->t && st->carry && st->episode &&
+         st->done_prev;
+}
+
+bool traj_ok(const gx_traj* tr) {
+  return tr && tr->reward && tr->flags && tr->action && tr->rows >= 1;
+}
+
+gx::EnvTables tables_of(const gx_ctx* c) {
+  return gx::EnvTables{c->n, c->d_meta, c->d_max_steps, c->d_seed, c->d_rng_id, c->d_grid_off,
+                       c->reward_mode};
+}
+
+gx::StateBufs state_of(const gx_state* st) {
+  return gx::StateBufs{st->grid, st->x, st->y, st->dir, st->t, st->carry, st->episode, st->done_prev};
+}
+
+gx::TrajBufs traj_of(const gx_traj* tr) {
+  return gx::TrajBufs{tr->obs, tr->reward, tr->flags, tr->action, tr->rows};
+}
+
+int check_device(const gx_ctx* c) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return GX_EDEVICE;
+  return dev == c->device ? GX_OK : GX_EINVAL;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* env_strerror(int status) {
+  switch (status) {
+    case GX_OK: return "ok";
+    case GX_EINVAL: return "invalid argument";
+    case GX_ENOMEM: return "out of memory";
+    case GX_EDEVICE: return "HIP device error";
+    case GX_ESTATE: return "call order violated (reset the envs first)";
+    default: return "unknown status";
+  }
+}
+
+int env_create(const gx_config* cfg, gx_ctx** out) {
+  if (!out) return GX_EINVAL;
+  *out = nullptr;
+  if (!cfg || cfg->n_envs < 1 || !cfg->family || !cfg->side || !cfg->max_steps) return GX_EINVAL;
+  if (cfg->reward_mode != 0 && cfg->reward_mode != 1) return GX_EINVAL;
+  const int32_t n = cfg->n_envs;
+  // the grid of a tile must fit the LDS of one workgroup; side <= 32 and
+  // 64 envs per tile bound it at 64 KiB of cells
+  std::vector<uint32_t> meta(n);
+  std::vector<int32_t> max_steps(n);
+  std::vector<uint2> seed(n);
+  std::vector<uint32_t> rng_id(n);
+  std::vector<uint64_t> grid_off(n);
+  uint64_t off = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const int fam = cfg->family[i], S = cfg->side[i];
+    if (!side_ok(fam, S) || cfg->max_steps[i] < 1) return GX_EINVAL;
+    meta[i] = (uint32_t)fam | ((uint32_t)S << 8);
+    max_steps[i] = cfg->max_steps[i];
+    const uint64_t sd = cfg->seed ? cfg->seed[i] : cfg->seed_all;
+    seed[i] = make_uint2((uint32_t)sd, (uint32_t)(sd >> 32));
+    rng_id[i] = cfg->rng_id ? cfg->rng_id[i] : (uint32_t)i;
+    grid_off[i] = off;
+    off += 3ull * (uint64_t)S * (uint64_t)S;
+  }
+  gx_ctx* c = new (std::nothrow) gx_ctx();
+  if (!c) return GX_ENOMEM;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return GX_EDEVICE;
+  }
+  c->n = n;
+  c->reward_mode = cfg->reward_mode;
+  c->grid_bytes = off;
+  c->n_tiles = (n + kTileEnvs - 1) / kTileEnvs;
+  for (int32_t t = 0; t < c->n_tiles; ++t) {
+    int32_t cells = 0;
+    for (int32_t i = t * kTileEnvs; i < std::min(n, (t + 1) * kTileEnvs); ++i)
+      cells += (int32_t)cfg->side[i] * (int32_t)cfg->side[i];
+    c->max_tile_cells = std::max(c->max_tile_cells, cells);
+  }
+  int rc = upload(&c->d_meta, meta);
+  if (rc == GX_OK) rc = upload(&c->d_max_steps, max_steps);
+  if (rc == GX_OK) rc = upload(&c->d_seed, seed);
+  if (rc == GX_OK) rc = upload(&c->d_rng_id, rng_id);
+  if (rc == GX_OK) rc = upload(&c->d_grid_off, grid_off);
+  if (rc != GX_OK) {
+    free_tables(c);
+    delete c;
+    return rc;
+  }
+  // persistent grid: as many single-wave workgroups as the LDS of every
+  // compute unit holds, but no more than there are tiles
+  hipDeviceProp_t prop;
+  int cus = 256;
+  size_t lds_per_cu = 160 * 1024;
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
+    cus = prop.multiProcessorCount;
+    if (prop.maxSharedMemoryPerMultiProcessor > 0) lds_per_cu = prop.maxSharedMemoryPerMultiProcessor;
+  }
+  const size_t lds = gx::fused_lds_bytes(c->max_tile_cells);
+  const int per_cu = std::max<int>(1, std::min<int>(16, (int)(lds_per_cu / lds)));
+  c->blocks = std::min<int32_t>(c->n_tiles, cus * per_cu);
+  *out = c;
+  return GX_OK;
+}
+
+int env_sizes(const gx_ctx* c, size_t* grid_bytes, int32_t* n_envs) {
+  if (!c) return GX_EINVAL;
+  if (grid_bytes) *grid_bytes = (size_t)c->grid_bytes;
+  if (n_envs) *n_envs = c->n;
+  return GX_OK;
+}
+
+int env_info(const gx_ctx* c, gx_info* info) {
+  if (!c || !info) return GX_EINVAL;
+  info->n_envs = c->n;
+  info->n_tiles = c->n_tiles;
+  info->max_tile_cells = c->max_tile_cells;
+  info->lds_bytes = (int32_t)gx::fused_lds_bytes(c->max_tile_cells);
+  info->blocks = c->blocks;
+  info->k_default = c->k_default;
+  info->grid_bytes = c->grid_bytes;
+  info->calls = c->calls;
+  return GX_OK;
+}
+
+int env_reset(gx_ctx* c, const gx_state* st, const gx_traj* first, void* stream) {
+  if (!c || !state_ok(st)) return GX_EINVAL;
+  if (first && !traj_ok(first)) return GX_EINVAL;
+  int rc = check_device(c);
+  if (rc != GX_OK) return rc;
+  if ((rc = device_status()) != GX_OK) return rc;
+  gx::TrajBufs tb{nullptr, nullptr, nullptr, nullptr, 1};
+  if (first) tb = traj_of(first);
+  if (gx::launch_plain(tables_of(c), state_of(st), nullptr, 0, 1, tb, 0,
+                       reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
+    return GX_EDEVICE;
+  c->calls = 0;
+  c->has_reset = true;
+  return GX_OK;
+}
+
+int env_step(gx_ctx* c, const gx_state* st, const uint8_t* actions, const gx_traj* out,
+             void* stream) {
+  if (!c || !state_ok(st) || !traj_ok(out)) return GX_EINVAL;
+  if (!c->has_reset) return GX_ESTATE;
+  int rc = check_device(c);
+  if (rc != GX_OK) return rc;
+  if ((rc = device_status()) != GX_OK) return rc;
+  if (gx::launch_plain(tables_of(c), state_of(st), actions, c->calls, 0, traj_of(out), 0,
+                       reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
+    return GX_EDEVICE;
+  c->calls += 1;
+  return GX_OK;
+}
+
+int env_rollout(gx_ctx* c, const gx_state* st, int32_t n_steps, const uint8_t* actions,
+                const gx_traj* traj, int32_t K, void* stream) {
+  if (!c || !state_ok(st) || !traj_ok(traj) || n_steps < 0 || K < 0) return GX_EINVAL;
+  if (!c->has_reset) return GX_ESTATE;
+  int rc = check_device(c);
+  if (rc != GX_OK) return rc;
+  if ((rc = device_status()) != GX_OK) return rc;
+  const int32_t k = K > 0 ? K : c->k_default;
+  const gx::TileTables tiles{c->n_tiles, c->max_tile_cells};
+  for (int32_t s0 = 0; s0 < n_steps; s0 += k) {
+    const int32_t ks = std::min(k, n_steps - s0);
+    const uint8_t* act = actions ? actions + (size_t)s0 * (size_t)c->n : nullptr;
+    if (gx::launch_fused(tables_of(c), tiles, state_of(st), act, c->calls, ks, traj_of(traj),
+                         s0 % traj->rows, c->blocks, reinterpret_cast<hipStream_t>(stream)) !=
+        hipSuccess)
+      return GX_EDEVICE;
+    c->calls += (uint64_t)ks;
+  }
+  return GX_OK;
+}
+
+int env_set_launch(gx_ctx* c, int32_t K, int32_t blocks) {
+  if (!c || K < 1 || blocks < 0) return GX_EINVAL;
+  c->k_default = K;
+  if (blocks > 0) c->blocks = blocks;
+  return GX_OK;
+}
+
+int env_destroy(gx_ctx* c) {
+  if (!c) return GX_EINVAL;
+  free_tables(c);
+  delete c;
+  return GX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,55 @@
+"""Helpers for GPU-vs-oracle parity: run the same seeded inputs through the
+HIP library (via its C-ABI binding) and through the CPU oracle, and compare
+every output element by element (bit-exact, rewards compared as bits)."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle as ox
+from paper_2407_19396_amd import workloads as wl
+
+FIELDS = ("grid", "x", "y", "dir", "t", "carry", "episode", "done_prev")
+
+
+def ox_batch(table: wl.EnvTable, reward_mode: int = 0) -> ox.Batch:
+    return ox.Batch(table.family, table.side, table.max_steps, table.seed, table.rng_id, reward_mode)
+
+
+def to_np(t):
+    return None if t is None else t.detach().cpu().numpy()
+
+
+def assert_rows_equal(gpu, ref: ox.Outputs, rows=None, what=""):
+    """gpu: gridenv.Traj; ref: oracle Outputs; compare the given rows."""
+    rows = slice(None) if rows is None else rows
+    g_rew = to_np(gpu.reward)[rows]
+    np.testing.assert_array_equal(to_np(gpu.flags)[rows], ref.flags[rows], err_msg=f"flags {what}")
+    np.testing.assert_array_equal(to_np(gpu.action)[rows], ref.action[rows], err_msg=f"action {what}")
+    np.testing.assert_array_equal(g_rew.view(np.uint32), ref.reward[rows].view(np.uint32),
+                                  err_msg=f"reward bits {what}")
+    if gpu.obs is not None and ref.obs is not None:
+        g_obs = to_np(gpu.obs)[rows]
+        r_obs = ref.obs[rows]
+        if not np.array_equal(g_obs, r_obs):
+            bad = np.argwhere((g_obs != r_obs).any(axis=(-1, -2, -3)))
+            k, e = bad[0][:2]
+            raise AssertionError(f"obs mismatch {what} at row {k} env {e} ({len(bad)} records):\n"
+                                 f"gpu types\n{g_obs[k, e, :, :, 0]}\noracle types\n{r_obs[k, e, :, :, 0]}")
+
+
+def assert_state_equal(env, ref: ox.State, what=""):
+    g = env.state_numpy()
+    for f in FIELDS:
+        r = getattr(ref, f)
+        a = g[f].view(r.dtype) if g[f].dtype.itemsize == r.dtype.itemsize else g[f].astype(r.dtype)
+        if not np.array_equal(a.reshape(-1)[:r.size], r.reshape(-1)):
+            idx = np.argwhere(a.reshape(-1)[:r.size] != r.reshape(-1))[:5].ravel()
+            raise AssertionError(f"state.{f} mismatch {what} at {idx}: gpu {a.reshape(-1)[idx]} "
+                                 f"oracle {r.reshape(-1)[idx]}")
+
+
+def oracle_reset(table: wl.EnvTable, reward_mode: int = 0):
+    b = ox_batch(table, reward_mode)
+    s = ox.State.empty(b)
+    first = ox.reset(b, s, nthreads=8)
+    return b, s, first

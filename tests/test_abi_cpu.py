@@ -1,0 +1,80 @@
+"""Host-side checks of the C-ABI: the library loads, exports every entry
+point the public header declares, and rejects bad arguments before any
+device work (these paths never touch a GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2407_19396_amd import gridenv as ge
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gridenv.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(env_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_names():
+    assert declared_functions() == sorted(ge.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(ge.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_strerror():
+    assert ge.env_strerror(0) == "ok"
+    assert "invalid" in ge.env_strerror(ge.GX_EINVAL)
+    assert ge.env_strerror(-99) == "unknown status"
+
+
+def _cfg(family, side, max_steps, n=None, reward_mode=0):
+    family = np.asarray(family, np.uint8)
+    side = np.asarray(side, np.uint8)
+    max_steps = np.asarray(max_steps, np.int32)
+    keep = (family, side, max_steps)
+    n = len(family) if n is None else n
+    return ge.GxConfig(n, reward_mode, family.ctypes.data, side.ctypes.data, max_steps.ctypes.data,
+                       None, 0, None), keep
+
+
+@pytest.mark.parametrize("family,side,T,n,mode", [
+    ([0], [3], [10], None, 0),          # Empty needs side >= 4
+    ([1], [4], [10], None, 0),          # TwoRoom needs side >= 5
+    ([2], [8], [10], None, 0),          # FourRooms needs an odd side
+    ([2], [5], [10], None, 0),          # FourRooms needs side >= 7
+    ([0], [33], [10], None, 0),         # side <= 32
+    ([3], [8], [10], None, 0),          # unknown family
+    ([0], [8], [0], None, 0),           # max_steps >= 1
+    ([0], [8], [10], 0, 0),             # n_envs >= 1
+    ([0], [8], [10], None, 2),          # reward mode 0 or 1
+])
+def test_create_rejects_bad_configs(family, side, T, n, mode):
+    lib = ge.load()
+    cfg, keep = _cfg(family, side, T, n, mode)
+    ctx = ctypes.c_void_p(1)
+    assert lib.env_create(ctypes.byref(cfg), ctypes.byref(ctx)) == ge.GX_EINVAL
+    assert ctx.value is None
+
+
+def test_null_arguments_are_rejected():
+    lib = ge.load()
+    assert lib.env_create(None, None) == ge.GX_EINVAL
+    ctx = ctypes.c_void_p()
+    assert lib.env_create(None, ctypes.byref(ctx)) == ge.GX_EINVAL
+    st, tr = ge.GxState(), ge.GxTraj()
+    assert lib.env_sizes(None, None, None) == ge.GX_EINVAL
+    assert lib.env_info(None, None) == ge.GX_EINVAL
+    assert lib.env_reset(None, ctypes.byref(st), None, None) == ge.GX_EINVAL
+    assert lib.env_step(None, ctypes.byref(st), None, ctypes.byref(tr), None) == ge.GX_EINVAL
+    assert lib.env_rollout(None, ctypes.byref(st), 1, None, ctypes.byref(tr), 0, None) == ge.GX_EINVAL
+    assert lib.env_set_launch(None, 4, 0) == ge.GX_EINVAL
+    assert lib.env_destroy(None) == ge.GX_EINVAL

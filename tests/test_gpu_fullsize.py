@@ -1,0 +1,118 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times: the small workloads compared whole, the large ones on a
+strided sample of envs whose every record and final state the oracle
+recomputes env by env (envs are independent, so a subset is exact)."""
+import numpy as np
+import pytest
+
+import oracle as ox
+import parity as P
+from paper_2407_19396_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _ge():
+    from paper_2407_19396_amd import gridenv as ge
+    return ge
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_empty5_plain_whole(seed):
+    """16 single rooms 5x5, 100 plain steps of external random actions."""
+    import torch
+    ge = _ge()
+    table = wl.workload_empty5(seed)
+    acts = wl.random_actions(100, table.n, seed)
+    env = ge.GridEnv(table)
+    first = ge.Traj.alloc(1, table.n)
+    env.reset(first)
+    b, s, ref0 = P.oracle_reset(table)
+    P.assert_rows_equal(first, ref0)
+    ref = ox.rollout(b, s, 100, acts)
+    traj = ge.Traj.alloc(100, table.n)
+    d = torch.from_numpy(acts).cuda()
+    for k in range(100):
+        env.step(ge.Traj(traj.obs[k:k + 1], traj.reward[k:k + 1], traj.flags[k:k + 1], traj.action[k:k + 1]), d[k])
+    torch.cuda.synchronize()
+    P.assert_rows_equal(traj, ref, what=f"empty5 seed {seed}")
+    P.assert_state_equal(env, s)
+
+
+def test_empty8_plain_whole():
+    """4096 single rooms 8x8, 1000 plain steps, one launch per step."""
+    import torch
+    ge = _ge()
+    table = wl.workload_empty8(0)
+    acts = wl.random_actions(1000, table.n, 0)
+    env = ge.GridEnv(table)
+    env.reset()
+    b, s, _ = P.oracle_reset(table)
+    ref = ox.rollout(b, s, 1000, acts, nthreads=16)
+    traj = ge.Traj.alloc(1000, table.n)
+    d = torch.from_numpy(acts).cuda()
+    for k in range(1000):
+        env.step(ge.Traj(traj.obs[k:k + 1], traj.reward[k:k + 1], traj.flags[k:k + 1], traj.action[k:k + 1]), d[k])
+    torch.cuda.synchronize()
+    P.assert_rows_equal(traj, ref, what="empty8")
+    P.assert_state_equal(env, s)
+
+
+def sampled_run(table, n_steps, K, sample, blocks=0):
+    """Fused rollout of the whole table in chunks of K steps (the bench's
+    launch shape); returns sampled records and the final state."""
+    import torch
+    ge = _ge()
+    env = ge.GridEnv(table)
+    if blocks:
+        env.set_launch(K, blocks)
+    env.reset()
+    traj = ge.Traj.alloc(K, table.n)
+    idx = torch.from_numpy(sample).cuda()
+    obs, rew, flg, act = [], [], [], []
+    for c in range(n_steps // K):
+        env.rollout(K, traj, K=K)
+        obs.append(traj.obs[:, idx].cpu())
+        rew.append(traj.reward[:, idx].cpu())
+        flg.append(traj.flags[:, idx].cpu())
+        act.append(traj.action[:, idx].cpu())
+    torch.cuda.synchronize()
+    cat = lambda xs: torch.cat(xs).numpy()  # noqa: E731
+    st = env.state_numpy()
+    env.close()
+    return cat(obs), cat(rew), cat(flg), cat(act), st
+
+
+def check_sample(table, n_steps, K, stride):
+    sample = np.arange(0, table.n, stride)
+    obs, rew, flg, act, st = sampled_run(table, n_steps, K, sample)
+    sub = table.subset(sample)
+    b, s, _ = P.oracle_reset(sub)
+    ref = ox.rollout(b, s, n_steps, None, nthreads=16)
+    np.testing.assert_array_equal(flg, ref.flags)
+    np.testing.assert_array_equal(act, ref.action)
+    np.testing.assert_array_equal(rew.view(np.uint32), ref.reward.view(np.uint32))
+    np.testing.assert_array_equal(obs, ref.obs)
+    for f in ("x", "y", "dir", "t", "carry", "done_prev"):
+        np.testing.assert_array_equal(st[f][sample], getattr(s, f))
+    np.testing.assert_array_equal(st["episode"][sample], s.episode)
+    offs = np.concatenate([[0], np.cumsum(3 * table.side.astype(np.int64) ** 2)])
+    for j, i in enumerate(sample):
+        so = P.ox_batch(sub).grid_offsets()[j]
+        n3 = 3 * int(table.side[i]) ** 2
+        np.testing.assert_array_equal(st["grid"][offs[i]:offs[i] + n3], s.grid[so:so + n3])
+    # every env (not only the sample): agents stay inside, counters in range
+    assert ((st["t"] >= 0) & (st["t"] <= table.max_steps)).all()
+    assert ((st["x"] >= 1) & (st["x"] <= table.side.astype(np.int32) - 2)).all()
+    assert ((st["y"] >= 1) & (st["y"] <= table.side.astype(np.int32) - 2)).all()
+    assert (st["episode"] > 0).any()
+
+
+def test_tworoom8_fused_sampled():
+    """65536 two-room 8x8 layouts, 2048 steps, fused, random policy."""
+    check_sample(wl.workload_tworoom8(0), 2048, 64, stride=257)
+
+
+def test_mixed_fused_sampled():
+    """262144 mixed-size envs, 4096 steps, fused persistent launches."""
+    check_sample(wl.workload_mixed(0), 4096, 64, stride=683)

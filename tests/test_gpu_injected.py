@@ -1,0 +1,75 @@
+"""Parity on injected states that random rollouts rarely reach: closed and
+open doors, keys of every colour (matching or not) in hand or on the
+floor, several doors and keys, agents next to goals, and so on.  The state
+buffers belong to the caller, so both sides start from the same picture."""
+import numpy as np
+import pytest
+
+import oracle as ox
+import parity as P
+from paper_2407_19396_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def random_state(rng, S):
+    g = np.zeros((S, S, 3), np.uint8)
+    g[:, :] = (1, 0, 0)
+    for y in range(1, S - 1):
+        for x in range(1, S - 1):
+            u = rng.random()
+            c = int(rng.integers(0, 6))
+            if u < 0.15:
+                g[y, x] = (2, 5, 0)
+            elif u < 0.25:
+                g[y, x] = (4, c, int(rng.integers(0, 3)))
+            elif u < 0.35:
+                g[y, x] = (5, c, 0)
+            elif u < 0.38:
+                g[y, x] = (8, 1, 0)
+    g[0, :] = g[-1, :] = g[:, 0] = g[:, -1] = (2, 5, 0)
+    free = [(x, y) for y in range(1, S - 1) for x in range(1, S - 1) if g[y, x, 0] == 1]
+    x, y = free[int(rng.integers(0, len(free)))]
+    carry = 1 if rng.random() < 0.5 else (5 | (int(rng.integers(0, 6)) << 8))
+    return g, x, y, int(rng.integers(0, 4)), carry
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("kernel", ["plain", "fused"])
+def test_injected_state_parity(seed, kernel):
+    import torch
+    from paper_2407_19396_amd import gridenv as ge
+    rng = np.random.default_rng(seed)
+    n = 2000
+    fam = rng.choice([0, 1], n).astype(np.uint8)
+    side = rng.choice([5, 6, 8, 11, 16], n).astype(np.uint8)
+    T = rng.integers(5, 60, n).astype(np.int32)
+    table = wl.EnvTable(fam, side, T, np.full(n, 1234 + seed, np.uint64), np.arange(n, dtype=np.uint32))
+    grids, xs, ys, ds, cs = [], [], [], [], []
+    for i in range(n):
+        g, x, y, d, c = random_state(rng, int(side[i]))
+        grids.append(g.reshape(-1)); xs.append(x); ys.append(y); ds.append(d); cs.append(c)
+    st = dict(grid=np.concatenate(grids), x=np.array(xs, np.int32), y=np.array(ys, np.int32),
+              dir=np.array(ds, np.int32), t=rng.integers(0, 5, n).astype(np.int32),
+              carry=np.array(cs, np.int32), episode=rng.integers(0, 9, n).astype(np.uint32),
+              done_prev=np.zeros(n, np.uint8))
+    steps = 80
+    acts = wl.random_actions(steps, n, seed=seed + 100)
+    b = P.ox_batch(table)
+    s = ox.State(**{k: v.copy() for k, v in st.items()})
+    ref = ox.rollout(b, s, steps, acts, nthreads=16)
+    env = ge.GridEnv(table)
+    env.reset()
+    env.load_state(st)
+    traj = ge.Traj.alloc(steps, n)
+    dacts = torch.from_numpy(acts).cuda()
+    if kernel == "fused":
+        env.rollout(steps, traj, dacts, K=13)
+    else:
+        for k in range(steps):
+            env.step(ge.Traj(traj.obs[k:k + 1], traj.reward[k:k + 1], traj.flags[k:k + 1],
+                             traj.action[k:k + 1]), dacts[k])
+    torch.cuda.synchronize()
+    P.assert_rows_equal(traj, ref, what=f"injected seed {seed} {kernel}")
+    P.assert_state_equal(env, s, f"injected seed {seed} {kernel}")
+    env.close()

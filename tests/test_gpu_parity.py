@@ -1,0 +1,209 @@
+"""GPU parity: the HIP kernels, called through the C-ABI, against the CPU
+oracle on the same seeded inputs, element by element and bit-exact (the
+whole method is integer except the fp32 reward, whose bits must match)."""
+import numpy as np
+import pytest
+
+import oracle as ox
+import parity as P
+from paper_2407_19396_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ge():
+    import torch
+    from paper_2407_19396_amd import gridenv
+    assert torch.cuda.is_available()
+    gridenv.load()
+    return gridenv
+
+
+def make(ge, table, reward_mode=0):
+    env = ge.GridEnv(table, reward_mode)
+    first = ge.Traj.alloc(1, table.n)
+    env.reset(first)
+    return env, first
+
+
+def tables():
+    return {
+        "empty5": wl.workload_empty5(seed=3),
+        "empty8": wl.workload_empty8(seed=4),
+        "tworoom8": wl.uniform_table(2048, wl.FAMILY_TWOROOM, 8, seed=5),
+        "fourrooms19": wl.uniform_table(512, wl.FAMILY_FOURROOMS, 19, seed=6),
+        "mixed": wl.mixed_table(3000, seed=7, mix_seed=8),
+        "all_sides": all_sides_table(),
+    }
+
+
+def all_sides_table():
+    fam, side = [], []
+    for s in range(4, 33):
+        fam.append(0); side.append(s)
+    for s in range(5, 33):
+        fam.append(1); side.append(s)
+    for s in range(7, 32, 2):
+        fam.append(2); side.append(s)
+    fam, side = np.array(fam * 3), np.array(side * 3)
+    ms = np.array([wl.default_max_steps(int(f), int(s)) for f, s in zip(fam, side)]) // 8 + 1
+    return wl.EnvTable(fam.astype(np.uint8), side.astype(np.uint8), ms.astype(np.int32),
+                       np.full(len(fam), 77, np.uint64), np.arange(len(fam), dtype=np.uint32), "all sides")
+
+
+@pytest.mark.parametrize("name", list(tables()))
+def test_reset_parity(ge, name):
+    table = tables()[name]
+    env, first = make(ge, table)
+    b, s, ref = P.oracle_reset(table)
+    P.assert_rows_equal(first, ref, what=f"reset {name}")
+    P.assert_state_equal(env, s, f"reset {name}")
+
+
+@pytest.mark.parametrize("name,steps", [("empty5", 100), ("empty8", 300), ("tworoom8", 300),
+                                        ("fourrooms19", 250), ("mixed", 300), ("all_sides", 200)])
+@pytest.mark.parametrize("policy", [False, True])
+def test_plain_step_parity(ge, name, steps, policy):
+    import torch
+    table = tables()[name]
+    env, _ = make(ge, table)
+    b, s, _ = P.oracle_reset(table)
+    acts = wl.random_actions(steps, table.n, seed=11) if not policy else None
+    ref = ox.rollout(b, s, steps, acts, nthreads=8)
+    traj = ge.Traj.alloc(steps, table.n)
+    dacts = torch.from_numpy(acts).cuda() if acts is not None else None
+    for k in range(steps):
+        row = ge.Traj(traj.obs[k:k + 1], traj.reward[k:k + 1], traj.flags[k:k + 1], traj.action[k:k + 1])
+        env.step(row, dacts[k] if dacts is not None else None)
+    torch.cuda.synchronize()
+    P.assert_rows_equal(traj, ref, what=f"plain {name}")
+    P.assert_state_equal(env, s, f"plain {name}")
+
+
+@pytest.mark.parametrize("name,steps", [("empty5", 100), ("empty8", 300), ("tworoom8", 300),
+                                        ("fourrooms19", 250), ("mixed", 300), ("all_sides", 200)])
+@pytest.mark.parametrize("K", [1, 7, 64])
+@pytest.mark.parametrize("policy", [False, True])
+def test_fused_rollout_parity(ge, name, steps, K, policy):
+    import torch
+    table = tables()[name]
+    env, _ = make(ge, table)
+    b, s, _ = P.oracle_reset(table)
+    acts = wl.random_actions(steps, table.n, seed=12) if not policy else None
+    ref = ox.rollout(b, s, steps, acts, nthreads=8)
+    traj = ge.Traj.alloc(steps, table.n)
+    env.rollout(steps, traj, torch.from_numpy(acts).cuda() if acts is not None else None, K=K)
+    torch.cuda.synchronize()
+    P.assert_rows_equal(traj, ref, what=f"fused {name} K={K}")
+    P.assert_state_equal(env, s, f"fused {name} K={K}")
+
+
+def test_mixed_calls_share_one_counter(ge):
+    """Reset, plain steps and fused chunks interleave and still follow the
+    oracle's single call counter for the random policy."""
+    import torch
+    table = wl.mixed_table(700, seed=31, mix_seed=32)
+    env, _ = make(ge, table)
+    b, s, _ = P.oracle_reset(table)
+    plan = [("step", 1), ("roll", 10), ("step", 1), ("step", 1), ("roll", 37), ("roll", 1), ("step", 1)]
+    call = 0
+    for kind, n in plan:
+        ref = ox.rollout(b, s, n, None, nthreads=8, call0=call)
+        traj = ge.Traj.alloc(n, table.n)
+        if kind == "step":
+            env.step(traj)
+        else:
+            env.rollout(n, traj, K=5)
+        torch.cuda.synchronize()
+        P.assert_rows_equal(traj, ref, what=f"{kind} at call {call}")
+        call += n
+    P.assert_state_equal(env, s, "interleaved")
+    assert env.info()["calls"] == call
+
+
+def test_ring_rows_and_zero_steps(ge):
+    import torch
+    table = wl.uniform_table(130, wl.FAMILY_TWOROOM, 6, seed=2)
+    env, _ = make(ge, table)
+    b, s, _ = P.oracle_reset(table)
+    traj = ge.Traj.alloc(8, table.n)
+    env.rollout(0, traj, K=4)
+    torch.cuda.synchronize()
+    assert int(traj.flags.sum()) == 0
+    ref = ox.rollout(b, s, 21, None, rows=8, nthreads=8)
+    env.rollout(21, traj, K=4)
+    torch.cuda.synchronize()
+    P.assert_rows_equal(traj, ref, what="ring of 8 rows")
+    P.assert_state_equal(env, s, "ring")
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 127, 129])
+def test_ragged_batches(ge, n):
+    import torch
+    table = wl.mixed_table(n, seed=n, mix_seed=n + 1)
+    env, first = make(ge, table)
+    b, s, ref0 = P.oracle_reset(table)
+    P.assert_rows_equal(first, ref0, what=f"reset n={n}")
+    ref = ox.rollout(b, s, 40, None, nthreads=8)
+    traj = ge.Traj.alloc(40, n)
+    env.rollout(40, traj, K=16)
+    torch.cuda.synchronize()
+    P.assert_rows_equal(traj, ref, what=f"n={n}")
+    P.assert_state_equal(env, s, f"n={n}")
+
+
+def test_unit_reward_mode(ge):
+    import torch
+    table = wl.uniform_table(256, wl.FAMILY_EMPTY, 5, seed=9)
+    env, _ = make(ge, table, reward_mode=1)
+    b, s, _ = P.oracle_reset(table, reward_mode=1)
+    ref = ox.rollout(b, s, 200, None, nthreads=8)
+    traj = ge.Traj.alloc(200, table.n)
+    env.rollout(200, traj, K=32)
+    torch.cuda.synchronize()
+    P.assert_rows_equal(traj, ref, what="unit reward")
+    assert set(np.unique(ref.reward)) <= {0.0, 1.0} and (ref.reward == 1.0).any()
+
+
+def test_observations_skipped_when_null(ge):
+    import torch
+    table = wl.mixed_table(500, seed=4, mix_seed=5)
+    env, _ = make(ge, table)
+    b, s, _ = P.oracle_reset(table)
+    ref = ox.rollout(b, s, 50, None, nthreads=8)
+    traj = ge.Traj.alloc(50, table.n, with_obs=False)
+    env.rollout(30, traj, K=8)
+    row = ge.Traj(None, traj.reward[30:31], traj.flags[30:31], traj.action[30:31])
+    env.step(row)
+    env.rollout(19, ge.Traj(None, traj.reward[31:], traj.flags[31:], traj.action[31:]), K=8)
+    torch.cuda.synchronize()
+    P.assert_rows_equal(traj, ref, what="no obs")
+    P.assert_state_equal(env, s, "no obs")
+
+
+def test_step_before_reset_is_an_error(ge):
+    table = wl.uniform_table(8, wl.FAMILY_EMPTY, 5)
+    env = ge.GridEnv(table)
+    traj = ge.Traj.alloc(1, 8)
+    with pytest.raises(ge.GridEnvError) as ei:
+        env.step(traj)
+    assert ei.value.status == ge.GX_ESTATE
+    with pytest.raises(ge.GridEnvError):
+        env.rollout(3, traj)
+
+
+def test_rollouts_are_deterministic(ge):
+    import torch
+    table = wl.mixed_table(4096, seed=1, mix_seed=2)
+    outs = []
+    for _ in range(2):
+        env, _ = make(ge, table)
+        traj = ge.Traj.alloc(64, table.n)
+        env.rollout(200, traj, K=50)
+        torch.cuda.synchronize()
+        outs.append((P.to_np(traj.obs).copy(), P.to_np(traj.flags).copy(), env.state_numpy()))
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+    for f in P.FIELDS:
+        np.testing.assert_array_equal(outs[0][2][f], outs[1][2][f])

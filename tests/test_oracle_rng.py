@@ -40,17 +40,31 @@ def test_uniform_is_floor_of_scaled_word(ox, n):
 
 
 def test_policy_actions_uniform_and_keyed(ox):
-    counts = np.zeros(7)
-    seen = {}
-    for ep in range(40):
-        for t in range(100):
-            a = ox.policy_action(7, 3, ep, t)
-            counts[a] += 1
-            seen[(ep, t)] = a
+    calls = range(4000)
+    acts = [ox.policy_action(7, 3, c) for c in calls]
+    counts = np.bincount(acts, minlength=7)
     # chi-square with 6 degrees of freedom, 0.1 % critical value 22.46
     exp = counts.sum() / 7
     assert ((counts - exp) ** 2 / exp).sum() < 22.46
-    # deterministic in (seed, id, episode, t); other ids give other streams
-    assert all(ox.policy_action(7, 3, ep, t) == a for (ep, t), a in list(seen.items())[:50])
-    other = [ox.policy_action(7, 4, 0, t) for t in range(100)]
-    assert other != [seen[(0, t)] for t in range(100)]
+    # the action is lane (call % 4) of the block (call / 4) of the stream
+    for c in (0, 1, 5, 4003, 2**32 + 6):
+        blk = ox.philox4x32_10([3, (c // 4) & 0xFFFFFFFF, (c // 4) >> 32, 1], [7, 0])
+        assert ox.policy_action(7, 3, c) == (int(blk[c % 4]) * 7) >> 32
+    # other ids and seeds give other streams
+    assert [ox.policy_action(7, 4, c) for c in range(100)] != acts[:100]
+    assert [ox.policy_action(8, 3, c) for c in range(100)] != acts[:100]
+
+
+def test_policy_rollout_uses_call_index(ox):
+    from paper_2407_19396_amd import workloads as wl
+    t = wl.uniform_table(3, 0, 8, seed=21)
+    b = ox.Batch(t.family, t.side, t.max_steps, t.seed, t.rng_id)
+    s = ox.State.empty(b)
+    ox.reset(b, s)
+    out = ox.rollout(b, s, 9, call0=5)
+    for k in range(9):
+        for i in range(3):
+            if out.flags[k, i] & 4:
+                assert out.action[k, i] == 0xFF
+            else:
+                assert out.action[k, i] == ox.policy_action(21, i, 5 + k)
