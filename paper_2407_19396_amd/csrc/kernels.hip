@@ -31,6 +31,7 @@ constexpr int kWave = 64;
 constexpr int kView = 7;
 constexpr int kObsBytes = kView * kView * 3;        // 147
 constexpr int kStageBytes = kWave * kObsBytes;      // 9408, a multiple of 16
+constexpr int kHalfStageBytes = kStageBytes / 2;    // 4704, a multiple of 16
 constexpr int kObsWords = 37;                       // ceil(147 / 4)
 
 // Cell triples are packed as type | colour << 8 | state << 16 (MiniGrid's
@@ -291,75 +292,75 @@ __device__ __forceinline__ uint32_t visible_row(uint32_t seeds, uint32_t see, ui
   return seeds | next;
 }
 
-// Fills w[37] with the 147-byte record obs[j][i][c].  Cells(x, y) returns
-// the triple of world cell (x, y) with kSeeBit set when it is see-through.
-template <class Cells>
-__device__ __forceinline__ void observe(const Cells& cells, int ax, int ay, int dir, uint32_t carry,
-                                        uint32_t (&w)[kObsWords]) {
-  const int fx = dir_dx(dir), fy = dir_dy(dir);
-  const int rx = -fy, ry = fx;
-  uint32_t tri[kView * kView + 1];
-  uint32_t seeds = 1u << 3;
+// Computes the lane's observation obs[j][i][c] (147 bytes) as the 38 words
+// u[0..37] it occupies once placed at byte 147 * slot of a record stage
+// (slot = the lane's position in the staged group; slot 0 starts a group).
+// rows.load(j, c) fills c[i] with the triple of view cell (i, j), kSeeBit set
+// when it is see-through.  Lanes with valid == false produce zeros (their
+// loader must still be safe to call).
+//
+// Records are realigned to their byte offset with byte permutes.  A word
+// shared by two neighbouring records belongs to the higher one: u[0] of a
+// record starting mid-word already holds the lower record's tail, received
+// by a cross-lane shuffle; store_words writes exactly the words a record
+// owns.
+template <class Rows>
+__device__ __forceinline__ void observe_words(const Rows& rows, uint32_t carry, bool valid, int slot,
+                                              uint32_t (&u)[kObsWords + 1]) {
+  const uint32_t m = (uint32_t)(kObsBytes * slot) & 3u;
+  const uint32_t realign = 0x07060504u - m * 0x01010101u;
+
+  // all 49 reads first: they are independent and stay in flight together
+  uint32_t cells[kView][kView];
+#pragma unroll
+  for (int j = kView - 1; j >= 0; --j) rows.load(j, cells[j]);
+
+  uint32_t seeds = valid ? (1u << 3) : 0u;
+  uint32_t later_first = 0;   // masked first cell of the row processed before (row j + 1)
+  uint32_t w_hi = 0;          // record word d + 1 (word 37 is past the end: zero)
 #pragma unroll
   for (int j = kView - 1; j >= 0; --j) {
-    const int bx = ax - 3 * rx + (6 - j) * fx, by = ay - 3 * ry + (6 - j) * fy;
+    uint32_t (&c)[kView] = cells[j];
+    // see-through bits, bit i = column i: each funnel shift moves one flag in
     uint32_t see = 0;
 #pragma unroll
-    for (int i = 0; i < kView; ++i) {
-      const uint32_t c = cells(bx + i * rx, by + i * ry);
-      tri[j * kView + i] = c;
-      see |= (c >> 31) << i;
-    }
+    for (int i = kView - 1; i >= 0; --i) see = __builtin_amdgcn_alignbit(see, c[i], 31);
     uint32_t next;
     const uint32_t vis = visible_row(seeds, see, next);
-#pragma unroll
-    for (int i = 0; i < kView; ++i) {
-      const int32_t keep = ((int32_t)(vis << (31 - i))) >> 31;
-      tri[j * kView + i] &= (uint32_t)keep;
-    }
     seeds = next;
-  }
-  tri[6 * kView + 3] = carry;   // the agent's own cell shows what it carries
-  tri[kView * kView] = 0;
-  // stream byte b belongs to cell b / 3; every dword spans two cells
 #pragma unroll
-  for (int d = 0; d < kObsWords; ++d) {
-    const int k = (4 * d) / 3, off = (4 * d) % 3;
-    const uint32_t sel = off == 0 ? 0x04020100u : (off == 1 ? 0x05040201u : 0x06050402u);
-    w[d] = __builtin_amdgcn_perm(tri[k + 1], tri[k], sel);
+    for (int i = 0; i < kView; ++i) c[i] &= (uint32_t)(((int32_t)(vis << (31 - i))) >> 31);
+    if (j == kView - 1) c[3] = valid ? carry : 0u;   // the agent's cell shows what it carries
+    // record words whose lower cell lies in this row; word d spans cells
+    // 4d/3 and 4d/3 + 1 (byte b belongs to cell b / 3)
+#pragma unroll
+    for (int d = kObsWords - 1; d >= 0; --d) {
+      const int k = (4 * d) / 3;
+      if (k / kView != j) continue;
+      const int i = k - kView * j, off = (4 * d) % 3;
+      const uint32_t sel = off == 0 ? 0x04020100u : (off == 1 ? 0x05040201u : 0x06050402u);
+      const uint32_t wd = __builtin_amdgcn_perm(i + 1 < kView ? c[i + 1] : later_first, c[i], sel);
+      u[d + 1] = __builtin_amdgcn_perm(w_hi, wd, realign);
+      w_hi = wd;
+    }
+    later_first = c[0];
   }
+  u[0] = __builtin_amdgcn_perm(w_hi, 0u, realign);
+  // the word a record shares with the next one: u[36] when the record starts
+  // on a word boundary, u[37] when it starts two or three bytes in
+  const uint32_t tail = m == 0 ? u[kObsWords - 1] : u[kObsWords];
+  const uint32_t lower_tail = (uint32_t)__shfl_up((int)tail, 1, kWave);
+  if (m != 0) u[0] |= lower_tail;
 }
 
-// Writes the lane's 147-byte record to stage[147 * lane ...] exactly: the
-// record is realigned to the lane's byte offset with byte permutes; each
-// dword shared by two neighbouring lanes is written by the higher lane,
-// which takes the lower lane's tail through a cross-lane shuffle.
-__device__ __forceinline__ void stage_record(uint8_t* stage, int lane, const uint32_t (&w)[kObsWords]) {
-  const uint32_t s = (uint32_t)(kObsBytes * lane);
+// Writes the words a record owns (see observe_words) at stage + 147 * slot.
+__device__ __forceinline__ void store_words(uint8_t* stage, int slot, const uint32_t (&u)[kObsWords + 1]) {
+  const uint32_t s = (uint32_t)(kObsBytes * slot);
   const uint32_t m = s & 3u;
   uint32_t* base = reinterpret_cast<uint32_t*>(stage) + (s >> 2);
-  const uint32_t sel = 0x07060504u - m * 0x01010101u;
-  uint32_t u[kObsWords + 1];
-  uint32_t prev = 0;
 #pragma unroll
-  for (int q = 0; q <= kObsWords; ++q) {
-    const uint32_t cur = q < kObsWords ? w[q] : 0u;
-    u[q] = __builtin_amdgcn_perm(cur, prev, sel);
-    prev = cur;
-  }
-  const int last = (int)((m + kObsBytes - 1) >> 2);   // 36 or 37
-  const uint32_t tail = last == kObsWords ? u[kObsWords] : u[kObsWords - 1];
-  const uint32_t lower_tail = (uint32_t)__shfl_up((int)tail, 1, kWave);
-  const bool last_owned = m == 1;                      // record ends on a dword boundary
-  base[0] = m == 0 ? u[0] : (u[0] | lower_tail);
-#pragma unroll
-  for (int q = 1; q < kObsWords - 1; ++q) base[q] = u[q];
-  if (last == kObsWords) {
-    base[kObsWords - 1] = u[kObsWords - 1];
-    if (last_owned) base[kObsWords] = u[kObsWords];
-  } else if (last_owned) {
-    base[kObsWords - 1] = u[kObsWords - 1];
-  }
+  for (int q = 0; q < kObsWords - 1; ++q) base[q] = u[q];
+  if (m != 0) base[kObsWords - 1] = u[kObsWords - 1];
 }
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -387,6 +388,18 @@ struct HbmCells {
     const uint8_t* p = g + 3 * (y * S + x);
     const uint32_t tri = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
     return tri | see_through(tri);
+  }
+};
+
+// View rows straight from the HBM grid, cells outside it read as walls.
+struct HbmRows {
+  HbmCells cells;
+  int ax, ay, fx, fy;
+  __device__ __forceinline__ void load(int j, uint32_t (&c)[kView]) const {
+    const int rx = -fy, ry = fx;
+    const int bx = ax - 3 * rx + (6 - j) * fx, by = ay - 3 * ry + (6 - j) * fy;
+#pragma unroll
+    for (int i = 0; i < kView; ++i) c[i] = cells(bx + i * rx, by + i * ry);
   }
 };
 
@@ -493,14 +506,11 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
 
   const size_t rowN = (size_t)a.row * (size_t)N;
   if (a.out.obs) {
-    uint32_t w[kObsWords];
-    if (active) {
-      observe(HbmCells{g, S}, x, y, dir, carry, w);
-    } else {
-#pragma unroll
-      for (int q = 0; q < kObsWords; ++q) w[q] = 0;
-    }
-    stage_record(stage, lane, w);
+    // inactive lanes get an empty grid: every read is out of bounds (a wall)
+    uint32_t u[kObsWords + 1];
+    observe_words(HbmRows{HbmCells{g, active ? S : 0}, x, y, dir_dx(dir), dir_dy(dir)}, carry,
+                  active, lane, u);
+    store_words(stage, lane, u);
     __syncthreads();
     copy_out(stage, a.out.obs + (rowN + (size_t)e0) * kObsBytes, n_here, lane);
   }
@@ -523,28 +533,60 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
 // ---------------------------------------------------------------------------
 // Fused kernel
 // ---------------------------------------------------------------------------
-// One byte per cell in LDS: bits 0-3 type (11 = locked door), bits 4-6
-// colour, bit 7 closed door.  A 256-entry table maps codes back to triples
-// (with the see-through bit).
+// One byte per cell in LDS: four times the cell's kind, i.e. the byte
+// offset of its entry in a 64-entry table of triples (with the see-through
+// bit), so a cell costs one byte read and one table read.  Kinds: 0 empty;
+// 1-6 wall, 7-12 goal, 13-18 key, 19-24 ball, 25-30 box by colour; 31-48
+// door by state and colour; 49 lava; 50 anything else (read as unseen).
 __device__ __forceinline__ uint32_t code_of(uint32_t tri) {
-  const uint32_t type = tri & 0xF, colour = (tri >> 8) & 7, state = (tri >> 16) & 0xFF;
-  const bool door = type == kDoor;
-  const uint32_t nib = (door && state == kLocked) ? 11u : type;
-  return nib | (colour << 4) | ((door && state == kClosed) ? 0x80u : 0u);
+  const uint32_t type = tri & 0xFF, colour = (tri >> 8) & 0xFF, state = (tri >> 16) & 0xFF;
+  // first kind of each type, as two 8-entry byte tables read with v_perm:
+  // types 0-3 {50, 0, 1, 50}, 4-7 {31, 13, 19, 25}, 8-11 {7, 49, 50, 50}, 12-15 all 50
+  const uint32_t lo = __builtin_amdgcn_perm(0x19130D1Fu, 0x32010032u, type & 7);
+  const uint32_t hi = __builtin_amdgcn_perm(0x32323232u, 0x32323107u, type & 7);
+  uint32_t kind = (type < 8 ? lo : hi) & 0xFF;
+  kind = type > 15 ? 50u : kind;
+  // walls, doors, keys, balls, boxes and goals come in colours; doors in states
+  kind += ((0x1F4u >> (type & 15)) & 1u) ? colour : 0u;
+  kind += type == kDoor ? 6u * state : 0u;
+  return (kind << 2) & 0xFFu;
 }
 
-__device__ __forceinline__ uint32_t triple_of_code(uint32_t code) {
-  const uint32_t nib = code & 15, colour = (code >> 4) & 7;
+__device__ __forceinline__ uint32_t triple_of_kind(uint32_t kind) {
   uint32_t tri;
-  if (nib == 11) tri = kDoor | (colour << 8) | (kLocked << 16);
-  else if (nib == kDoor) tri = kDoor | (colour << 8) | (((code >> 7) ? kClosed : kOpen) << 16);
-  else tri = nib | (colour << 8);
+  if (kind == 0) tri = kCellEmpty;
+  else if (kind <= 6) tri = kWall | ((kind - 1) << 8);
+  else if (kind <= 12) tri = kGoal | ((kind - 7) << 8);
+  else if (kind <= 18) tri = kKey | ((kind - 13) << 8);
+  else if (kind <= 24) tri = kBall | ((kind - 19) << 8);
+  else if (kind <= 30) tri = kBox | ((kind - 25) << 8);
+  else if (kind <= 48) tri = kDoor | (((kind - 31) % 6) << 8) | (((kind - 31) / 6) << 16);
+  else if (kind == 49) tri = 9;
+  else return 0;
   return tri | see_through(tri);
 }
 
-constexpr int kTableBytes = 256 * 4;
-constexpr int kStageOff = kTableBytes;
-constexpr int kGridOff = kStageOff + kStageBytes;  // 10432, 16-aligned
+constexpr int kKinds = 64;
+
+// code of cell (x, y) of a freshly generated layout (grey walls, green
+// goal, key and locked door of the layout's colour); equals
+// code_of(layout_cell(L, x, y)) without the general switch
+__device__ __forceinline__ uint32_t layout_code(const Layout& L, int x, int y) {
+  constexpr uint32_t kWallCode = 4 * (1 + kGrey), kGoalCode = 4 * (7 + kGreen);
+  const int S = L.S;
+  uint32_t code = 0;
+  if (L.fam == kFamTwoRoom) {   // the family is uniform across the wave here
+    code = (x == L.kx && y == L.ky) ? 4u * (13u + (uint32_t)L.colour) : code;
+    code = x == L.a ? (y == L.b ? 4u * (31u + 6u * kLocked + (uint32_t)L.colour) : kWallCode) : code;
+  } else if (L.fam == kFamFourRooms) {
+    const int m = S / 2;
+    code = (y == m && x != L.c && x != L.d) ? kWallCode : code;
+    code = (x == m && y != L.a && y != L.b) ? kWallCode : code;
+  }
+  code = (x == L.gx && y == L.gy) ? kGoalCode : code;
+  const bool border = x == 0 || y == 0 || x == S - 1 || y == S - 1;
+  return border ? kWallCode : code;
+}
 // A view reaches at most 6 cells ahead and 3 to the side of an interior
 // agent, i.e. at most 5 rows and 5 columns outside an S <= 32 grid: with
 // row-major indexing that is within 5 * 32 + 5 = 165 bytes before or after
@@ -552,14 +594,33 @@ constexpr int kGridOff = kStageOff + kStageBytes;  // 10432, 16-aligned
 // so only their addresses must stay inside the allocation.
 constexpr int kMargin = 192;
 
-struct LdsCells {
-  const uint8_t* codes;   // this env's grid codes
+__device__ __forceinline__ uint32_t table_at(const uint32_t* table, uint32_t code4) {
+  return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(table) + code4);
+}
+
+// View rows from the LDS code grid: the view's row and column steps are
+// +-1 or +-S in the row-major grid, so each cell is one add away.
+struct LdsRows {
   const uint32_t* table;
-  int S;
-  __device__ __forceinline__ uint32_t operator()(int x, int y) const {
-    return table[codes[y * S + x]];
+  const uint8_t* center;   // the agent's cell
+  int R, F;                // linear steps to the agent's right and ahead
+  __device__ __forceinline__ void load(int j, uint32_t (&c)[kView]) const {
+    const uint8_t* p = center + (6 - j) * F - 3 * R;
+#pragma unroll
+    for (int i = 0; i < kView; ++i) {
+      c[i] = table_at(table, p[0]);
+      p += R;
+    }
   }
 };
+
+__device__ __forceinline__ LdsRows lds_rows(const uint32_t* table, const uint8_t* codes, int S, int x,
+                                            int y, int dir) {
+  // heading 0: ahead +1, right +S; 1: ahead +S, right -1; 2: -1, -S; 3: -S, +1
+  const int F = (dir & 1) ? ((dir == 1) ? S : -S) : ((dir == 0) ? 1 : -1);
+  const int R = (dir & 1) ? ((dir == 1) ? -1 : 1) : ((dir == 0) ? S : -S);
+  return LdsRows{table, codes + y * S + x, R, F};
+}
 
 struct FusedArgs {
   EnvTables env;
@@ -583,15 +644,23 @@ __device__ __forceinline__ int wave_excl_scan(int v, int lane, int& total) {
   return incl - v;
 }
 
+// kActions: actions come from a.actions; otherwise from the random policy.
+// On this GPU one counter tracks both outstanding loads and stores, so a
+// load consumed in the same step would also wait for every earlier record
+// store: the action of step s + 1 is therefore fetched during step s, and
+// the policy variant has no loads in its step loop at all.
+template <bool kActions>
 __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
-  extern __shared__ __align__(16) uint8_t lds[];
-  uint32_t* table = reinterpret_cast<uint32_t*>(lds);
-  uint8_t* stage = lds + kStageOff;
-  uint8_t* codes = lds + kGridOff + kMargin;
+  // static LDS (table and record stage) sits at fixed addresses, so table
+  // reads take their base as an immediate; the tile grids are dynamic
+  __shared__ __align__(16) uint32_t table[kKinds];
+  __shared__ __align__(16) uint8_t stage[kHalfStageBytes];
+  extern __shared__ __align__(16) uint8_t grids[];
+  uint8_t* codes = grids + kMargin;
   const int lane = threadIdx.x;
   const int N = a.env.n;
 
-  for (int c = lane; c < 256; c += kWave) table[c] = triple_of_code((uint32_t)c);
+  table[lane] = triple_of_kind((uint32_t)lane);   // kKinds == kWave entries
   __syncthreads();
 
   for (int tile = blockIdx.x; tile < a.tiles.n_tiles; tile += gridDim.x) {
@@ -638,9 +707,17 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
     __syncthreads();
 
     uint4 pol = make_uint4(0, 0, 0, 0);
+    uint32_t act_next = 0;
+    if (kActions && active) act_next = a.actions[e];
     for (int s = 0; s < a.k_steps; ++s) {
       const uint64_t call = a.call0 + (uint64_t)s;
-      if (!a.actions && (s == 0 || (call & 3) == 0)) pol = policy_block(seed, rid, call);
+      uint32_t act_now = 0;
+      if (kActions) {
+        act_now = act_next;
+        if (active && s + 1 < a.k_steps) act_next = a.actions[(size_t)(s + 1) * N + e];
+      } else if (s == 0 || (call & 3) == 0) {
+        pol = policy_block(seed, rid, call);
+      }
 
       const bool do_reset = active && done_prev;
       Layout L{};
@@ -662,7 +739,7 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
           uint8_t* gp = codes + bcast(my_off, r);
           const int xx = lane & 31;
           for (int yy = lane >> 5; yy < Lr.S; yy += 2)
-            if (xx < Lr.S) gp[yy * Lr.S + xx] = (uint8_t)code_of(layout_cell(Lr, xx, yy));
+            if (xx < Lr.S) gp[yy * Lr.S + xx] = (uint8_t)layout_code(Lr, xx, yy);
         }
         __syncthreads();
       }
@@ -670,10 +747,9 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
       float reward = 0.0f;
       uint32_t flags = 0, act_rec = kActionNone;
       if (active && !do_reset) {
-        const uint32_t act = a.actions ? (uint32_t)a.actions[(size_t)s * N + e]
-                                       : bounded(pick4(pol, (uint32_t)(call & 3)), 7u);
+        const uint32_t act = kActions ? act_now : bounded(pick4(pol, (uint32_t)(call & 3)), 7u);
         const int fx = x + dir_dx(dir), fy = y + dir_dy(dir);
-        const uint32_t front = table[my_codes[fy * S + fx]];
+        const uint32_t front = table_at(table, my_codes[fy * S + fx]);
         const ActResult r = intervene(act, x, y, dir, carry, front, fx, fy);
         if (r.front_changed) my_codes[fy * S + fx] = (uint8_t)code_of(r.new_front);
         t += 1;
@@ -690,16 +766,21 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
       const int row = (a.row0 + s) % a.out.rows;
       const size_t rowN = (size_t)row * (size_t)N;
       if (a.out.obs) {
-        uint32_t w[kObsWords];
-        if (active) {
-          observe(LdsCells{my_codes, table, S}, x, y, dir, carry, w);
-        } else {
+        // inactive lanes (S = 0, pose (1, 1)) read inside the guard margin
+        uint32_t u[kObsWords + 1];
+        observe_words(lds_rows(table, my_codes, S, x, y, dir), carry, active, lane & 31, u);
+        // the stage holds 32 records: lanes 0-31, then lanes 32-63 (each half
+        // starts and ends on a word boundary, so the halves are independent)
+        uint8_t* dst = a.out.obs + (rowN + (size_t)e0) * kObsBytes;
 #pragma unroll
-          for (int q = 0; q < kObsWords; ++q) w[q] = 0;
+        for (int h = 0; h < 2; ++h) {
+          const int n_half = min(32, n_here - 32 * h);
+          if (n_half <= 0) break;
+          if ((lane >> 5) == h) store_words(stage, lane & 31, u);
+          __syncthreads();
+          copy_out(stage, dst + h * kHalfStageBytes, n_half, lane);
+          __syncthreads();
         }
-        stage_record(stage, lane, w);
-        __syncthreads();
-        copy_out(stage, a.out.obs + (rowN + (size_t)e0) * kObsBytes, n_here, lane);
       }
       if (active) {
         a.out.reward[rowN + e] = reward;
@@ -714,7 +795,7 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
       const uint64_t g0 = (uint64_t)__shfl((long long)goff, 0, kWave);
       uint8_t* dst = a.st.grid + g0;
       for (int c = lane; c < tile_cells; c += kWave) {
-        const uint32_t tri = table[codes[c]];
+        const uint32_t tri = table_at(table, codes[c]);
         dst[3 * c] = (uint8_t)tri;
         dst[3 * c + 1] = (uint8_t)(tri >> 8);
         dst[3 * c + 2] = (uint8_t)(tri >> 16);
@@ -735,9 +816,13 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
 
 }  // namespace
 
-size_t fused_lds_bytes(int32_t max_tile_cells) {
-  size_t b = (size_t)kGridOff + 2 * kMargin + (size_t)max_tile_cells;
+size_t fused_dynamic_lds_bytes(int32_t max_tile_cells) {
+  const size_t b = 2 * (size_t)kMargin + (size_t)max_tile_cells;
   return (b + 15) & ~(size_t)15;
+}
+
+size_t fused_lds_bytes(int32_t max_tile_cells) {
+  return kKinds * 4 + kHalfStageBytes + fused_dynamic_lds_bytes(max_tile_cells);
 }
 
 hipError_t launch_plain(const EnvTables& env, const StateBufs& st, const uint8_t* actions,
@@ -754,13 +839,18 @@ hipError_t launch_fused(const EnvTables& env, const TileTables& tiles, const Sta
                         const TrajBufs& out, int32_t row0, int32_t grid_blocks,
                         hipStream_t stream) {
   FusedArgs a{env, tiles, st, actions, call0, k_steps, out, row0};
-  const size_t lds = fused_lds_bytes(tiles.max_tile_cells);
+  const size_t lds = fused_dynamic_lds_bytes(tiles.max_tile_cells);
+  const void* fn = actions ? reinterpret_cast<const void*>(&k_fused<true>)
+                           : reinterpret_cast<const void*>(&k_fused<false>);
   if (lds > 65536) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const hipError_t e =
+        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_fused, dim3(grid_blocks), dim3(kWave), lds, stream, a);
+  if (actions)
+    hipLaunchKernelGGL(k_fused<true>, dim3(grid_blocks), dim3(kWave), lds, stream, a);
+  else
+    hipLaunchKernelGGL(k_fused<false>, dim3(grid_blocks), dim3(kWave), lds, stream, a);
   return hipGetLastError();
 }
 

@@ -55,7 +55,8 @@ hipError_t launch_fused(const EnvTables& env, const TileTables& tiles, const Sta
                         const TrajBufs& out, int32_t row0, int32_t grid_blocks,
                         hipStream_t stream);
 
-// LDS bytes one workgroup of the fused kernel needs for a tile size.
+// LDS bytes one workgroup of the fused kernel needs for a tile size (static
+// table and record stage plus the dynamic tile grids).
 size_t fused_lds_bytes(int32_t max_tile_cells);
 
 }  // namespace gx
