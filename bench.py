@@ -31,6 +31,15 @@ RECORD_BYTES = OBS + 4 + 1 + 1          # obs + reward + flags + action per env-
 STATE_BYTES_PER_ENV = 4 * 5 + 4 + 1      # x, y, dir, t, carry + episode + done_prev
 
 
+WORKLOADS = {
+    "mixed": "mixed uneven sizes: 262144 envs (40% Empty S in {5,6,8,16}, 40% TwoRoom key/door "
+             "S in {5,6,8,16}, 20% FourRooms 19x19), random policy on device, trajectory ring in HBM",
+    "tworoom8": "65536 TwoRoom key/door 8x8, T=640, random policy on device, trajectory ring in HBM",
+    "empty8": "4096 Empty 8x8, T=256, random policy on device, trajectory ring in HBM",
+    "empty5": "16 Empty 5x5, T=100, random policy on device, trajectory ring in HBM",
+}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -61,19 +70,62 @@ def cpu_baseline(table, n_envs: int, n_steps: int) -> dict:
                       f"observations on, {dt:.1f} s"}
 
 
+def run_serving(capacity: float, n_requests: int, loads, K: int, budget_gib: int) -> list:
+    """Poisson serving at fractions of the measured fused capacity."""
+    import torch
+    from paper_2407_19396_amd import gridenv as ge
+    from paper_2407_19396_amd import workloads as wl
+
+    probe = wl.serving_requests(4000, rate_per_s=1.0, master_seed=12345)
+    ework = float(np.mean([r.n_envs * r.n_steps for r in probe]))
+    srv = ge.Server(max_tiles=16384, max_side=19)
+    budget = budget_gib << 30
+    arena = torch.empty(budget - srv.info()["device_bytes"], dtype=torch.uint8, device="cuda")
+    out = []
+    for load in loads:
+        rate = load * capacity / ework
+        reqs = wl.serving_requests(n_requests, rate, master_seed=int(load * 1000))
+        res = ge.serve_run(srv, reqs, K, budget, arena)
+        lat = res["latency_s"] * 1e3
+        wait = (res["admit_s"] - res["arrival_s"]) * 1e3
+        rec = {"load": load, "requests": n_requests, "completed": res["completed"],
+               "rate_req_per_s": rate, "mean_env_steps_per_request": ework,
+               "env_steps_per_s": res["env_steps"] / res["wall_s"], "wall_s": res["wall_s"],
+               "launches": res["launches"],
+               "host_s": {"admit": res["host_admit_s"], "step": res["host_step_s"],
+                          "wait": res["host_wait_s"]},
+               "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+               "admission_wait_ms": {"p50": float(np.percentile(wait, 50)),
+                                     "p99": float(np.percentile(wait, 99))}}
+        log(f"[bench] serving load {load}: {rec['env_steps_per_s'] / 1e9:.2f} G env-steps/s, "
+            f"latency p50 {rec['latency_ms']['p50']:.1f} ms p99 {rec['latency_ms']['p99']:.1f} ms")
+        out.append(rec)
+    srv.close()
+    del arena
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4096, help="timed environment steps of the batch")
     ap.add_argument("--warmup", type=int, default=256)
-    ap.add_argument("--envs", type=int, default=262144)
-    ap.add_argument("--K", type=int, default=0, help="steps fused per launch (0: library default)")
-    ap.add_argument("--blocks", type=int, default=0)
+    ap.add_argument("--workload", default="mixed", choices=["mixed", "tworoom8", "empty8", "empty5"])
+    ap.add_argument("--envs", type=int, default=0, help="override the workload's env count")
+    ap.add_argument("--K", type=int, default=0, help="steps fused per launch (0: autotune)")
+    ap.add_argument("--blocks", type=int, default=0, help="persistent workgroups (0: autotune or default)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner, use library defaults")
     ap.add_argument("--ring", type=int, default=0, help="trajectory ring rows (0: K)")
     ap.add_argument("--plain-steps", type=int, default=512)
+    ap.add_argument("--plain-actions", action="store_true",
+                    help="plain steps take an external action buffer instead of the device policy")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-envs", type=int, default=32768)
-    ap.add_argument("--cpu-steps", type=int, default=512)
+    ap.add_argument("--cpu-envs", type=int, default=0, help="CPU oracle sample envs (0: all)")
+    ap.add_argument("--cpu-steps", type=int, default=0, help="CPU oracle sample steps (0: --steps)")
+    ap.add_argument("--serve-requests", type=int, default=10000,
+                    help="requests per serving load level (0: skip serving)")
+    ap.add_argument("--serve-K", type=int, default=64)
+    ap.add_argument("--serve-budget-gib", type=int, default=64)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (calibrates HBM counters)")
     args = ap.parse_args()
@@ -96,18 +148,32 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copy probe: {n} bytes read and {n} bytes written by one copy kernel")
         del src, dst
-    table = wl.workload_mixed(seed=0, n=args.envs)
+    make = {"mixed": lambda: wl.workload_mixed(seed=0, n=args.envs or 262144),
+            "tworoom8": lambda: wl.workload_tworoom8(seed=0),
+            "empty8": lambda: wl.workload_empty8(seed=0),
+            "empty5": lambda: wl.workload_empty5(seed=0)}[args.workload]
+    table = make()
+    if args.envs and args.workload != "mixed":
+        table = table.subset(np.arange(args.envs) % table.n)
     env = ge.GridEnv(table)
-    if args.K or args.blocks:
+    first = ge.Traj.alloc(1, table.n)
+    stream = torch.cuda.current_stream()
+    tuned = None
+    if args.K or args.blocks or args.no_tune:
         env.set_launch(args.K or env.info()["k_default"], args.blocks)
+    else:
+        from paper_2407_19396_amd import autotune
+        probe = ge.Traj.alloc(512, table.n)
+        env.reset(first)
+        tuned = autotune.tune(env, probe, log=log)
+        del probe
+        log(f"[bench] autotuned K={tuned['K']} blocks={tuned['blocks']}")
     info = env.info()
     K = info["k_default"]
     ring = args.ring or K
     log(f"[bench] {table.name}: grid {info['grid_bytes'] / 1e6:.1f} MB, tiles {info['n_tiles']}, "
         f"LDS/WG {info['lds_bytes']} B, blocks {info['blocks']}, K {K}, ring {ring}")
     traj = ge.Traj.alloc(ring, table.n)
-    first = ge.Traj.alloc(1, table.n)
-    stream = torch.cuda.current_stream()
     env.reset(first)
     # warmup (also advances episodes away from the synchronous start)
     env.rollout(args.warmup, traj, K=K)
@@ -141,40 +207,56 @@ def main():
         lat.append(a.elapsed_time(b))
     lat = np.array(lat)
 
-    # plain kernel on the same input
+    # plain kernel on the same input, writing a ring of the same size
     plain_rate = None
     plain_lat = None
     if args.plain_steps > 0:
-        row = ge.Traj.alloc(1, table.n)
-        for _ in range(8):
-            env.step(row)
+        rows = [ge.Traj(traj.obs[r:r + 1], traj.reward[r:r + 1], traj.flags[r:r + 1], traj.action[r:r + 1])
+                for r in range(traj.rows)]
+        acts = None
+        if args.plain_actions:
+            acts = torch.from_numpy(wl.random_actions(args.plain_steps, table.n, seed=1)).to(dev)
+        for k in range(8):
+            env.step(rows[k % len(rows)])
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
-        for _ in range(args.plain_steps):
-            env.step(row)
+        for k in range(args.plain_steps):
+            env.step(rows[k % len(rows)], acts[k] if acts is not None else None)
         b.record(stream)
         torch.cuda.synchronize()
         pms = a.elapsed_time(b)
         plain_rate = table.n * args.plain_steps / (pms / 1e3)
         pl = []
-        for _ in range(64):
+        for k in range(64):
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record(stream)
-            env.step(row)
+            env.step(rows[k % len(rows)])
             b.record(stream)
             b.synchronize()
             pl.append(a.elapsed_time(b))
         plain_lat = np.array(pl)
-        log(f"[bench] plain: {plain_rate / 1e9:.2f} G env-steps/s")
+        log(f"[bench] plain: {plain_rate / 1e9:.2f} G env-steps/s, launch p50 "
+            f"{np.percentile(plain_lat, 50) * 1e3:.1f} us")
 
     per_launch_ms = ms / launches
     bytes_launch = fused_bytes(table.n, info["grid_bytes"], K)
     achieved = bytes_launch / (per_launch_ms / 1e3) / 1e9
+    from paper_2407_19396_amd import profiling
+    traffic = None
+    if args.workload == "mixed" and args.steps % K == 0:
+        traffic = profiling.traffic_bytes(os.path.join(ROOT, "profiles", "k_fused_mixed262144.txt"),
+                                          K, table.n)
+    serving = None
+    if args.serve_requests > 0 and args.workload == "mixed":
+        del traj, env
+        torch.cuda.empty_cache()
+        serving = run_serving(value, args.serve_requests, (0.5, 0.8, 0.95), args.serve_K,
+                              args.serve_budget_gib)
     cpu = None
     if not args.no_cpu:
         log("[bench] timing the CPU oracle on a sample")
-        cpu = cpu_baseline(table, min(args.cpu_envs, table.n), args.cpu_steps)
+        cpu = cpu_baseline(table, min(args.cpu_envs or table.n, table.n), args.cpu_steps or args.steps)
         log(f"[bench] cpu oracle: {cpu['value'] / 1e6:.2f} M env-steps/s on {cpu['cores']} threads")
 
     out = {
@@ -190,11 +272,10 @@ def main():
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": "mixed uneven sizes: 262144 envs (40% Empty S in {5,6,8,16}, 40% "
-                               "TwoRoom key/door S in {5,6,8,16}, 20% FourRooms 19x19), random "
-                               "policy on device, trajectory ring in HBM",
+        "config": {"workload": WORKLOADS[args.workload],
                    "n_envs": table.n, "K": K, "ring_rows": ring, "blocks": info["blocks"],
-                   "lds_bytes_per_wg": info["lds_bytes"], "global_batch": table.n},
+                   "lds_bytes_per_wg": info["lds_bytes"], "global_batch": table.n,
+                   "autotuned": tuned is not None},
         "fused_launch_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "plain": None if plain_rate is None else {
             "value": plain_rate, "unit": "env-steps/s", "steps": args.plain_steps,
@@ -202,13 +283,13 @@ def main():
                           "p99": float(np.percentile(plain_lat, 99))},
             "fused_over_plain": value / plain_rate},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_fused", "bytes_per_launch": bytes_launch,
                      "launch_ms": per_launch_ms},
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    env.close()
 
 
 if __name__ == "__main__":

@@ -21,10 +21,12 @@
  *   next call that checks the device.
  * Memory: the caller allocates and frees every state, action and output
  *   buffer (device memory of the current HIP device, e.g. torch tensors).
- *   The library owns only its context (host memory plus small device
- *   tables allocated in env_create and freed in env_destroy), never frees
- *   caller memory, and allocates nothing in env_reset / env_step /
- *   env_rollout.
+ *   The library owns only its contexts (host memory plus small device
+ *   tables allocated in env_create and freed in env_destroy) and servers
+ *   (slot pools allocated in env_server_create, freed in
+ *   env_server_destroy), never frees caller memory, and allocates nothing
+ *   in env_reset / env_step / env_rollout / env_server_admit /
+ *   env_server_step.
  * Streams: stream is a hipStream_t passed as void* (NULL = the default
  *   stream).  Calls enqueue work and return; results are valid once the
  *   stream has synchronised.  A context is not thread-safe: use it from one
@@ -54,7 +56,8 @@
  *     must be among those listed above (every generated layout is);
  *   x, y, dir, t (int32): position, heading, steps since the last reset;
  *   carry (int32), episode (uint32: resets so far), done_prev (uint8:
- *   the last step ended the episode, so the next call resets).
+ *   the last step ended the episode, so the next call resets), calls
+ *   (uint32: step calls since env_reset, the random policy's counter).
  *
  * Outputs (struct gx_traj): row r of each buffer holds n_envs entries:
  *   obs: bytes [rows][n_envs][7][7][3], view row j (0 = farthest ahead,
@@ -78,6 +81,7 @@ extern "C" {
 #define GX_ENOMEM -2   /* the context's host or device tables could not be allocated */
 #define GX_EDEVICE -3  /* a HIP call failed, or earlier GPU work faulted */
 #define GX_ESTATE -4   /* call order violated (e.g. a step before any reset) */
+#define GX_EBUSY -5    /* a server has no free tiles for the request right now */
 
 #define GX_FAMILY_EMPTY 0      /* Empty-SxS (single room), side 4..32 */
 #define GX_FAMILY_TWOROOM 1    /* DoorKey-SxS (two rooms, locked door), side 5..32 */
@@ -108,6 +112,7 @@ typedef struct {
   int32_t *x, *y, *dir, *t, *carry;
   uint32_t* episode;
   uint8_t* done_prev;
+  uint32_t* calls;
 } gx_state;
 
 /* Caller-owned device outputs; `rows` rows of n_envs entries each. */
@@ -128,7 +133,6 @@ typedef struct {
   int32_t blocks;             /* persistent workgroups of the fused kernel */
   int32_t k_default;          /* steps fused per launch when K = 0 */
   uint64_t grid_bytes;
-  uint64_t calls;             /* env_step calls + rollout steps since reset */
 } gx_info;
 
 /* Validate a batch description (families and sides of Table "envs"),
@@ -146,7 +150,7 @@ int env_info(const gx_ctx* ctx, gx_info* info);
  * 0 from the env's layout stream (Philox4x32-10 keyed by its seed, counter
  * (rng_id, episode, block, 0)), write the whole state and, when `first` is
  * not NULL, the first timestep into its row 0 (flags 4, reward 0, action
- * 0xFF).  Also restarts the context's call counter. */
+ * 0xFF).  Sets every env's call counter to 0. */
 int env_reset(gx_ctx* ctx, const gx_state* st, const gx_traj* first, void* stream);
 
 /* step(timestep, action) of Sec. 3.2.2 for every env, one kernel launch:
@@ -154,8 +158,9 @@ int env_reset(gx_ctx* ctx, const gx_state* st, const gx_traj* first, void* strea
  * first timestep of their next episode; the others apply the action and
  * return o_{t+1}, r_{t+1} and the flags.  actions: device bytes [n_envs],
  * or NULL for the uniform random policy (Philox keyed by the env seed,
- * counter (rng_id, call / 4, 1) word call % 4, call = the context's call
- * counter).  Writes output row 0 of `out`. */
+ * counter (rng_id, calls / 4, 1) word calls % 4, calls = the env's step
+ * calls since env_reset).  Every call, autoresetting ones included, adds 1
+ * to calls.  Writes output row 0 of `out`. */
 int env_step(gx_ctx* ctx, const gx_state* st, const uint8_t* actions, const gx_traj* out,
              void* stream);
 
@@ -175,6 +180,107 @@ int env_set_launch(gx_ctx* ctx, int32_t K, int32_t blocks);
 
 /* Free the context and its device tables (after the stream is idle). */
 int env_destroy(gx_ctx* ctx);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of rollout requests.
+ *
+ * A server owns a pool of max_tiles tiles of 64 env slots (their tables,
+ * state and grids, allocated once in env_server_create).  A request is a
+ * batch of its own envs with its own seed, stepped n_steps times under the
+ * random policy; it takes ceil(n_envs / 64) free tiles.  Each
+ * env_server_step launch advances every live request by up to K steps, so
+ * requests admitted while others run share the device.  A request's
+ * results equal env_create (seed, rng_id = 0..n_envs-1) + env_reset +
+ * env_rollout(n_steps, random policy) on its own envs, whatever else is
+ * being served: its env ids and its policy's call counter are its own.
+ * Step s of the request writes row s of its outputs (row stride `stride`
+ * envs; a multiple of 16 keeps the record stores vectorised).
+ * ---------------------------------------------------------------------- */
+typedef struct gx_server gx_server;
+
+typedef struct {
+  int32_t n_envs;              /* >= 1 */
+  int32_t n_steps;             /* >= 1 */
+  uint64_t seed;               /* key of every env of the request */
+  const uint8_t* family;       /* host [n_envs], read during env_server_admit */
+  const uint8_t* side;         /* host [n_envs], <= the server's max_side */
+  const int32_t* max_steps;    /* host [n_envs] */
+  uint8_t* obs;                /* device [n_steps][stride][147], or NULL */
+  float* reward;               /* device [n_steps][stride] */
+  uint8_t* flags;              /* device [n_steps][stride] */
+  uint8_t* action;             /* device [n_steps][stride] */
+  int32_t stride;              /* >= n_envs */
+} gx_request;
+
+typedef struct {
+  int32_t max_tiles, free_tiles, live_requests, max_side;
+  uint64_t device_bytes;       /* device memory the server owns */
+} gx_server_info;
+
+/* Allocate a server for up to max_tiles * 64 envs of side <= max_side. */
+int env_server_create(int32_t max_tiles, int32_t max_side, int32_t reward_mode, gx_server** out);
+
+/* Queue a request (host work only; its reset is launched by the next
+ * env_server_step).  GX_EBUSY when there are not enough free tiles now.
+ * The output buffers must stay valid until the request is released. */
+int env_server_admit(gx_server* srv, const gx_request* req, int32_t* handle);
+
+/* Launch pending admissions and one fused chunk of up to K steps for every
+ * live request on `stream`.  Writes to finished[0..*n_finished) the
+ * handles of requests whose last step is in a launch enqueued so far (at
+ * most cap per call; the rest come with later calls).  Their results are
+ * complete once the stream reaches this point. */
+int env_server_step(gx_server* srv, int32_t K, void* stream, int32_t* finished, int32_t cap,
+                    int32_t* n_finished);
+
+/* Return a finished request's tiles to the pool.  Call only after the
+ * stream has completed its last step. */
+int env_server_release(gx_server* srv, int32_t handle);
+
+int env_server_info(const gx_server* srv, gx_server_info* info);
+
+/* Free the server (after its stream is idle). */
+int env_server_destroy(gx_server* srv);
+
+/* A request of a serving run: its arrival time and its envs' configuration
+ * at index env_offset of the run's family / side / max_steps arrays. */
+typedef struct {
+  double arrival_s;            /* seconds from the start of the run, non-decreasing */
+  int32_t n_envs, n_steps;
+  uint64_t seed;
+  int64_t env_offset;
+} gx_serve_item;
+
+typedef struct {
+  int32_t K;                   /* steps per launch */
+  int32_t max_inflight;        /* launches enqueued ahead of the device */
+  int32_t keep_obs;            /* 1: requests get observation outputs */
+  uint64_t budget_bytes;       /* HBM budget: the server's pool plus request outputs */
+  uint8_t* arena;              /* device memory for request outputs */
+  uint64_t arena_bytes;
+} gx_serve_opts;
+
+typedef struct {
+  double wall_s;               /* run time */
+  uint64_t env_steps;          /* env-steps of completed requests */
+  int32_t completed, launches;
+  double admit_s;              /* host time spent admitting requests */
+  double step_s;               /* host time spent enqueuing launches */
+  double wait_s;               /* host time blocked on the device */
+} gx_serve_stats;
+
+/* Serve items in real time on an idle server: admit each request when it
+ * has arrived, in arrival order, once tiles free up and its outputs fit the
+ * budget (outputs are carved from the arena, row stride rounded up to 16
+ * envs); step every live request K steps per launch with up to
+ * max_inflight launches ahead of the device; a request completes when the
+ * host sees its last launch finish, and its tiles and outputs are then
+ * reused.  admit_s / done_s [n_items] receive admission and completion
+ * times (seconds from the start); latency = done_s - arrival_s. */
+int env_serve_run(gx_server* srv, const gx_serve_item* items, int32_t n_items,
+                  const uint8_t* family, const uint8_t* side, const int32_t* max_steps,
+                  const gx_serve_opts* opts, void* stream, double* admit_s, double* done_s,
+                  gx_serve_stats* stats);
 
 /* Static text for a status code. */
 const char* env_strerror(int status);

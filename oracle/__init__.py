@@ -50,11 +50,11 @@ class _Batch(ctypes.Structure):
                 ("reward_mode", ctypes.c_int32)]
 
 
+STATE_FIELDS = ("grid", "x", "y", "dir", "t", "carry", "episode", "done_prev", "calls")
+
+
 class _State(ctypes.Structure):
-    _fields_ = [("grid", ctypes.c_void_p), ("x", ctypes.c_void_p),
-                ("y", ctypes.c_void_p), ("dir", ctypes.c_void_p),
-                ("t", ctypes.c_void_p), ("carry", ctypes.c_void_p),
-                ("episode", ctypes.c_void_p), ("done_prev", ctypes.c_void_p)]
+    _fields_ = [(f, ctypes.c_void_p) for f in STATE_FIELDS]
 
 
 def lib():
@@ -82,7 +82,7 @@ def lib():
                                ctypes.c_int]
         L.ox_reset.restype = ctypes.c_int
         L.ox_rollout.argtypes = [ctypes.POINTER(_Batch), ctypes.POINTER(_State), ctypes.c_int32,
-                                 P, ctypes.c_uint64, ctypes.c_int32, P, P, P, P, ctypes.c_int]
+                                 P, ctypes.c_int32, P, P, P, P, ctypes.c_int]
         L.ox_rollout.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -175,17 +175,21 @@ class State:
     carry: np.ndarray
     episode: np.ndarray
     done_prev: np.ndarray
+    calls: np.ndarray = None      # u32[N] step calls since reset
+
+    def __post_init__(self):
+        if self.calls is None:
+            self.calls = np.zeros(self.x.shape[0], dtype=np.uint32)
 
     @staticmethod
     def empty(batch: Batch) -> "State":
         n = batch.n
         z = lambda dt: np.zeros(n, dtype=dt)  # noqa: E731
         return State(np.zeros(batch.grid_bytes(), dtype=np.uint8), z(np.int32), z(np.int32),
-                     z(np.int32), z(np.int32), z(np.int32), z(np.uint32), z(np.uint8))
+                     z(np.int32), z(np.int32), z(np.int32), z(np.uint32), z(np.uint8), z(np.uint32))
 
     def copy(self) -> "State":
-        return State(*(getattr(self, f).copy() for f in
-                       ("grid", "x", "y", "dir", "t", "carry", "episode", "done_prev")))
+        return State(*(getattr(self, f).copy() for f in STATE_FIELDS))
 
 
 def _cbatch(b: Batch, keep: list):
@@ -200,11 +204,10 @@ def _cbatch(b: Batch, keep: list):
 
 
 def _cstate(s: State):
-    for f in ("grid", "x", "y", "dir", "t", "carry", "episode", "done_prev"):
+    for f in STATE_FIELDS:
         a = getattr(s, f)
         assert a.flags.c_contiguous, f
-    return _State(*[getattr(s, f).ctypes.data for f in
-                    ("grid", "x", "y", "dir", "t", "carry", "episode", "done_prev")])
+    return _State(*[getattr(s, f).ctypes.data for f in STATE_FIELDS])
 
 
 @dataclass
@@ -235,10 +238,9 @@ def reset(batch: Batch, state: State, out: Outputs | None = None, nthreads: int 
 
 
 def rollout(batch: Batch, state: State, n_steps: int, actions: np.ndarray | None = None,
-            rows: int | None = None, with_obs: bool = True, nthreads: int = 0,
-            call0: int = 0) -> Outputs:
+            rows: int | None = None, with_obs: bool = True, nthreads: int = 0) -> Outputs:
     """Run n_steps steps; step k lands in output row k % rows.  Without
-    actions the random policy draws with call index call0 + k."""
+    actions the random policy draws at each env's own call count."""
     rows = n_steps if rows is None else rows
     out = Outputs.empty(rows, batch.n, with_obs)
     if actions is not None:
@@ -247,7 +249,7 @@ def rollout(batch: Batch, state: State, n_steps: int, actions: np.ndarray | None
     keep: list = []
     cb = _cbatch(batch, keep)
     cs = _cstate(state)
-    rc = lib().ox_rollout(ctypes.byref(cb), ctypes.byref(cs), n_steps, _ptr(actions), call0, rows,
+    rc = lib().ox_rollout(ctypes.byref(cb), ctypes.byref(cs), n_steps, _ptr(actions), rows,
                           _ptr(out.obs), _ptr(out.reward), _ptr(out.flags), _ptr(out.action),
                           nthreads)
     if rc != 0:

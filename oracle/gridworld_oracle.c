@@ -110,11 +110,11 @@ static uint32_t layout_word(uint64_t seed, uint32_t rng_id, uint32_t episode,
   return out[w % 4u];
 }
 
-/* Random-policy action of the call with index `call` (calls are counted
- * per context from its reset, every env advancing together): counter =
- * (rng_id, (call / 4) low 32 bits, (call / 4) high 32 bits, 1), lane
- * call % 4, uniform over the 7 actions.  The action drawn on a call that
- * autoresets is not used. */
+/* Random-policy action of an env's step call number `call` (its step calls
+ * since its reset, the autoresetting ones included): counter = (rng_id,
+ * (call / 4) low 32 bits, (call / 4) high 32 bits, 1), lane call % 4,
+ * uniform over the 7 actions.  The action drawn on a call that autoresets
+ * is not used. */
 uint32_t ox_policy_action(uint64_t seed, uint32_t rng_id, uint64_t call) {
   uint64_t block = call / 4u;
   uint32_t ctr[4] = {rng_id, (uint32_t)block, (uint32_t)(block >> 32), 1u};
@@ -339,6 +339,7 @@ typedef struct {
   int32_t *x, *y, *dir, *t, *carry;
   uint32_t *episode;
   uint8_t *done_prev;
+  uint32_t *calls;
 } ox_env_ref;
 
 static int is_pickable(int type) {
@@ -446,6 +447,7 @@ typedef struct {
   int32_t *x, *y, *dir, *t, *carry;
   uint32_t *episode;
   uint8_t *done_prev;
+  uint32_t *calls;   /* step calls since reset (the random policy's counter) */
 } ox_state;
 
 static ox_env_ref env_ref(const ox_batch *b, const ox_state *s, int i) {
@@ -454,6 +456,7 @@ static ox_env_ref env_ref(const ox_batch *b, const ox_state *s, int i) {
   e.x = s->x + i; e.y = s->y + i; e.dir = s->dir + i; e.t = s->t + i;
   e.carry = s->carry + i; e.episode = s->episode + i;
   e.done_prev = s->done_prev + i;
+  e.calls = s->calls + i;
   return e;
 }
 
@@ -480,6 +483,7 @@ int ox_reset(const ox_batch *b, const ox_state *s, uint8_t *obs, float *reward,
     *e.t = 0;
     *e.carry = O_EMPTY;
     *e.done_prev = 0;
+    *e.calls = 0;
     if (obs)
       ox_observe(e.grid, b->side[i], *e.x, *e.y, *e.dir, *e.carry,
                  obs + (size_t)147 * i);
@@ -491,10 +495,10 @@ int ox_reset(const ox_batch *b, const ox_state *s, uint8_t *obs, float *reward,
 }
 
 /* n_steps steps.  actions: [n_steps][N] bytes, or NULL for the random
- * policy, whose call index is call0 + k on step k.  Step k writes output
- * row k % rows. */
+ * policy (drawn at each env's own call count).  Step k writes output row
+ * k % rows. */
 int ox_rollout(const ox_batch *b, const ox_state *s, int32_t n_steps,
-               const uint8_t *actions, uint64_t call0, int32_t rows, uint8_t *obs,
+               const uint8_t *actions, int32_t rows, uint8_t *obs,
                float *reward, uint8_t *flags, uint8_t *action, int nthreads) {
   if (rows <= 0) return -1;
   set_threads(nthreads);
@@ -506,11 +510,12 @@ int ox_rollout(const ox_batch *b, const ox_state *s, int32_t n_steps,
       size_t row = (size_t)(k % rows);
       uint32_t a;
       if (actions) a = actions[(size_t)k * N + i];
-      else a = ox_policy_action(b->seed[i], b->rng_id[i], call0 + (uint64_t)k);
+      else a = ox_policy_action(b->seed[i], b->rng_id[i], *e.calls);
       step_one(b->family[i], b->side[i], b->max_steps[i], b->seed[i],
                b->rng_id[i], b->reward_mode, e, a,
                obs ? obs + 147 * (row * N + i) : NULL, reward + row * N + i,
                flags + row * N + i, action + row * N + i);
+      *e.calls += 1u;
     }
   }
   return 0;

@@ -89,10 +89,10 @@ __device__ __forceinline__ uint32_t pick4(uint4 v, uint32_t lane) {
   return r;
 }
 
-// Random-policy words for call block `call >> 2`: counter (id, block lo, block hi, 1).
-__device__ __forceinline__ uint4 policy_block(uint2 seed, uint32_t rng_id, uint64_t call) {
-  const uint64_t blk = call >> 2;
-  return philox10(make_uint4(rng_id, (uint32_t)blk, (uint32_t)(blk >> 32), 1u), seed);
+// Random-policy words of an env's call block `call >> 2`: counter (id,
+// block, 0, 1); call = the env's step calls since its reset.
+__device__ __forceinline__ uint4 policy_block(uint2 seed, uint32_t rng_id, uint32_t call) {
+  return philox10(make_uint4(rng_id, call >> 2, 0u, 1u), seed);
 }
 
 // ---------------------------------------------------------------------------
@@ -222,44 +222,27 @@ struct ActResult {
 
 __device__ __forceinline__ ActResult intervene(uint32_t act, int& x, int& y, int& dir, uint32_t& carry,
                                                uint32_t front, int fx, int fy) {
+  // every lane of a wave holds its own action, so the rules are evaluated
+  // as selects rather than branches
   const uint32_t type = front & 0xFF, colour = (front >> 8) & 0xFF, state = (front >> 16) & 0xFF;
-  ActResult r{front & 0xFFFFFFu, false, false};
-  if (act == kLeft) {
-    dir = (dir + 3) & 3;
-  } else if (act == kRight) {
-    dir = (dir + 1) & 3;
-  } else if (act == kForward) {
-    const bool walk = type == kEmpty || type == kGoal || (type == kDoor && state == kOpen);
-    if (walk) {
-      x = fx;
-      y = fy;
-    }
-    r.terminated = type == kGoal;
-  } else if (act == kPickup) {
-    if (carry == kCellEmpty && (type == kKey || type == kBall || type == kBox)) {
-      carry = front & 0xFFFFFFu;
-      r.new_front = kCellEmpty;
-      r.front_changed = true;
-    }
-  } else if (act == kDrop) {
-    if (carry != kCellEmpty && type == kEmpty) {
-      r.new_front = carry;
-      carry = kCellEmpty;
-      r.front_changed = true;
-    }
-  } else if (act == kToggle) {
-    if (type == kDoor) {
-      if (state == kLocked) {
-        if ((carry & 0xFF) == kKey && ((carry >> 8) & 0xFF) == colour) {
-          r.new_front = kDoor | (colour << 8) | (kOpen << 16);
-          r.front_changed = true;
-        }
-      } else {
-        r.new_front = kDoor | (colour << 8) | ((state == kOpen ? kClosed : kOpen) << 16);
-        r.front_changed = true;
-      }
-    }
-  }
+  const uint32_t front24 = front & 0xFFFFFFu;
+  dir = (dir + (act == kLeft ? 3 : (act == kRight ? 1 : 0))) & 3;
+  const bool walk = act == kForward &&
+                    (type == kEmpty || type == kGoal || (type == kDoor && state == kOpen));
+  x = walk ? fx : x;
+  y = walk ? fy : y;
+  const bool pick = act == kPickup && carry == kCellEmpty && (type == kKey || type == kBall || type == kBox);
+  const bool drop = act == kDrop && carry != kCellEmpty && type == kEmpty;
+  const bool door = act == kToggle && type == kDoor;
+  const bool unlock = door && state == kLocked && (carry & 0xFF) == kKey && ((carry >> 8) & 0xFF) == colour;
+  const bool flip = door && state != kLocked;
+  const uint32_t door_open = kDoor | (colour << 8) | (kOpen << 16);
+  const uint32_t door_flipped = kDoor | (colour << 8) | ((state == kOpen ? kClosed : kOpen) << 16);
+  ActResult r;
+  r.new_front = pick ? kCellEmpty : (drop ? carry : (unlock ? door_open : (flip ? door_flipped : front24)));
+  r.front_changed = pick || drop || unlock || flip;
+  r.terminated = act == kForward && type == kGoal;
+  carry = pick ? front24 : (drop ? kCellEmpty : carry);
   return r;
 }
 
@@ -279,17 +262,20 @@ __device__ __forceinline__ float goal_reward(int32_t t, int32_t T, int32_t mode)
 // seeds plus the see-through runs that touch a see-through seed, widened
 // by one cell on each side; the next row's seeds are the three cells ahead
 // of every visible see-through cell.  This is MiniGrid's two-pass rule in
-// bit-parallel form: the run fills are carry propagations, the downward
-// one in bit-reversed space.
+// bit-parallel form, the run fills being carry propagations.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t visible_row(uint32_t seeds, uint32_t see, uint32_t& next) {
-  const uint32_t g = seeds & see;
-  const uint32_t up = (((see + g) ^ see) | g) & see;
-  const uint32_t rs = __builtin_bitreverse32(see), rg = __builtin_bitreverse32(g);
-  const uint32_t down = __builtin_bitreverse32((((rs + rg) ^ rs) | rg) & rs);
-  const uint32_t run = up | down;
-  next = (run | (run << 1) | (run >> 1)) & 0x7Fu;
-  return seeds | next;
+// Row masks are kept in a dual form: the 7 column bits in bits 0-6 and the
+// same bits reversed in bits 25-31.  One add then fills runs towards higher
+// columns in the low half and towards lower columns in the high half (the
+// carry out of bit 6 dies in the empty bit 7, that of bit 31 leaves the
+// word), and one bit reversal merges the two directions.
+__device__ __forceinline__ uint32_t visible_row(uint32_t seeds2, uint32_t see, uint32_t& next2) {
+  const uint32_t p2 = see | __builtin_bitreverse32(see);
+  const uint32_t g2 = seeds2 & p2;
+  const uint32_t fill = (((p2 + g2) ^ p2) | g2) & p2;
+  const uint32_t run2 = fill | __builtin_bitreverse32(fill);
+  next2 = (run2 | (run2 << 1) | (run2 >> 1)) & 0xFE00007Fu;
+  return seeds2 | next2;
 }
 
 // Computes the lane's observation obs[j][i][c] (147 bytes) as the 38 words
@@ -315,7 +301,7 @@ __device__ __forceinline__ void observe_words(const Rows& rows, uint32_t carry, 
 #pragma unroll
   for (int j = kView - 1; j >= 0; --j) rows.load(j, cells[j]);
 
-  uint32_t seeds = valid ? (1u << 3) : 0u;
+  uint32_t seeds = valid ? ((1u << 3) | (1u << 28)) : 0u;   // column 3, dual form
   uint32_t later_first = 0;   // masked first cell of the row processed before (row j + 1)
   uint32_t w_hi = 0;          // record word d + 1 (word 37 is past the end: zero)
 #pragma unroll
@@ -365,13 +351,27 @@ __device__ __forceinline__ void store_words(uint8_t* stage, int slot, const uint
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-// Copies n_envs staged records (n_envs * 147 bytes) to dst.
+// Copies n_envs staged records (n_envs * 147 bytes, 1 <= n_envs <= kMaxEnvs) to
+// dst.  The aligned path issues all of a lane's 16-byte LDS reads before
+// its stores, so the reads are in flight together.
+template <int kMaxEnvs>
 __device__ __forceinline__ void copy_out(const uint8_t* stage, uint8_t* dst, int n_envs, int lane) {
+  constexpr int kMaxChunks = (kMaxEnvs * kObsBytes + 15) / 16;
+  constexpr int kPerLane = (kMaxChunks + kWave - 1) / kWave;
   const int bytes = n_envs * kObsBytes;
   if (((reinterpret_cast<uintptr_t>(dst) & 15) == 0) && (bytes & 15) == 0) {
     const u32x4* src = reinterpret_cast<const u32x4*>(stage);
     u32x4* out = reinterpret_cast<u32x4*>(dst);
-    for (int c = lane; c < (bytes >> 4); c += kWave) __builtin_nontemporal_store(src[c], out + c);
+    const int n = bytes >> 4;
+    // Reads clamp to the last chunk (n >= 1) so they need no branch.
+    u32x4 v[kPerLane];
+#pragma unroll
+    for (int i = 0; i < kPerLane; ++i) v[i] = src[min(lane + i * kWave, n - 1)];
+#pragma unroll
+    for (int i = 0; i < kPerLane; ++i) {
+      const int c = lane + i * kWave;
+      if (c < n) __builtin_nontemporal_store(v[i], out + c);
+    }
   } else {
     for (int b = lane; b < bytes; b += kWave) dst[b] = stage[b];
   }
@@ -413,7 +413,6 @@ struct PlainArgs {
   EnvTables env;
   StateBufs st;
   const uint8_t* actions;
-  uint64_t call;
   int32_t reset_all;
   TrajBufs out;
   int32_t row;
@@ -430,7 +429,7 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
 
   uint32_t fam = 0;
   int S = 5, T = 1, x = 1, y = 1, dir = 0, t = 0;
-  uint32_t carry = kCellEmpty, episode = 0, rid = 0;
+  uint32_t carry = kCellEmpty, episode = 0, rid = 0, calls = 0;
   bool done_prev = false;
   uint2 seed = make_uint2(0, 0);
   uint8_t* g = a.st.grid;
@@ -450,6 +449,7 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
       carry = (uint32_t)a.st.carry[e];
       episode = a.st.episode[e];
       done_prev = a.st.done_prev[e] != 0;
+      calls = a.st.calls[e];
     }
   }
   const bool do_reset = active && (a.reset_all || done_prev);
@@ -486,7 +486,7 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
     if (a.actions) {
       act = a.actions[e];
     } else {
-      act = bounded(pick4(policy_block(seed, rid, a.call), (uint32_t)(a.call & 3)), 7u);
+      act = bounded(pick4(policy_block(seed, rid, calls), calls & 3u), 7u);
     }
     const int fx = x + dir_dx(dir), fy = y + dir_dy(dir);
     const HbmCells cells{g, S};
@@ -512,7 +512,7 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
                   active, lane, u);
     store_words(stage, lane, u);
     __syncthreads();
-    copy_out(stage, a.out.obs + (rowN + (size_t)e0) * kObsBytes, n_here, lane);
+    copy_out<kWave>(stage, a.out.obs + (rowN + (size_t)e0) * kObsBytes, n_here, lane);
   }
   if (active && a.out.reward) {
     a.out.reward[rowN + e] = reward;
@@ -527,6 +527,7 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
     a.st.carry[e] = (int32_t)carry;
     a.st.episode[e] = episode;
     a.st.done_prev[e] = done_prev ? 1 : 0;
+    a.st.calls[e] = a.reset_all ? 0u : calls + 1u;
   }
 }
 
@@ -627,11 +628,21 @@ struct FusedArgs {
   TileTables tiles;
   StateBufs st;
   const uint8_t* actions;   // [k_steps][N] or nullptr
-  uint64_t call0;
   int32_t k_steps;
   TrajBufs out;
   int32_t row0;
+  ServeTile* serve;         // per-tile requests (serving), else nullptr
 };
+
+// The fused kernel's workgroups are single waves and all the data its lanes
+// exchange lives in LDS, whose operations a wave performs in issue order: a
+// wavefront-scope fence (no wait instruction) plus a compiler barrier is
+// enough to make one lane's LDS writes visible to the others' later reads.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __device__ __forceinline__ int wave_excl_scan(int v, int lane, int& total) {
   int incl = v;
@@ -645,11 +656,14 @@ __device__ __forceinline__ int wave_excl_scan(int v, int lane, int& total) {
 }
 
 // kActions: actions come from a.actions; otherwise from the random policy.
+// kServe: tiles belong to requests described by a.serve (serving): each runs
+// min(K, steps it has left) steps from its own counter step0, writes to its
+// own output rows and advances step0.
 // On this GPU one counter tracks both outstanding loads and stores, so a
 // load consumed in the same step would also wait for every earlier record
 // store: the action of step s + 1 is therefore fetched during step s, and
 // the policy variant has no loads in its step loop at all.
-template <bool kActions>
+template <bool kActions, bool kServe>
 __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
   // static LDS (table and record stage) sits at fixed addresses, so table
   // reads take their base as an immediate; the tile grids are dynamic
@@ -661,17 +675,49 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
   const int N = a.env.n;
 
   table[lane] = triple_of_kind((uint32_t)lane);   // kKinds == kWave entries
-  __syncthreads();
+  wave_sync();
 
   for (int tile = blockIdx.x; tile < a.tiles.n_tiles; tile += gridDim.x) {
+    // where this tile's envs live and where their records go: record of
+    // step s, lane l is at index rec_base + s * rec_step (+ l) of the outputs
     const int e0 = tile * kWave;
+    int n_here, steps;
+    uint64_t g0 = 0;
+    uint8_t *o_obs, *o_flags, *o_action;
+    float* o_reward;
+    uint32_t step0 = 0;
+    size_t rec_stride;
+    if (kServe) {
+      const ServeTile d = a.serve[tile];
+      if (!d.active || d.step0 >= d.n_steps) continue;
+      n_here = (int)d.n_envs;
+      steps = min(a.k_steps, (int)(d.n_steps - d.step0));
+      step0 = d.step0;
+      g0 = d.grid_base;
+      o_obs = d.obs;
+      o_reward = d.reward;
+      o_flags = d.flags;
+      o_action = d.action;
+      rec_stride = d.stride;
+      o_obs = o_obs ? o_obs + (size_t)d.local0 * kObsBytes : nullptr;
+      o_reward += d.local0;
+      o_flags += d.local0;
+      o_action += d.local0;
+    } else {
+      n_here = min(kWave, N - e0);
+      steps = a.k_steps;
+      o_obs = a.out.obs ? a.out.obs + (size_t)e0 * kObsBytes : nullptr;
+      o_reward = a.out.reward + e0;
+      o_flags = a.out.flags + e0;
+      o_action = a.out.action + e0;
+      rec_stride = (size_t)N;
+    }
     const int e = e0 + lane;
-    const bool active = e < N;
-    const int n_here = min(kWave, N - e0);
+    const bool active = lane < n_here;
 
     uint32_t fam = 0;
     int S = 0, T = 1, x = 1, y = 1, dir = 0, t = 0;
-    uint32_t carry = kCellEmpty, episode = 0, rid = 0;
+    uint32_t carry = kCellEmpty, episode = 0, rid = 0, calls = 0;
     bool done_prev = false;
     uint2 seed = make_uint2(0, 0);
     uint64_t goff = 0;
@@ -682,7 +728,7 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
       T = a.env.max_steps[e];
       seed = a.env.seed[e];
       rid = a.env.rng_id[e];
-      goff = a.env.grid_off[e];
+      if (!kServe) goff = a.env.grid_off[e];
       x = a.st.x[e];
       y = a.st.y[e];
       dir = a.st.dir[e];
@@ -690,13 +736,14 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
       carry = (uint32_t)a.st.carry[e];
       episode = a.st.episode[e];
       done_prev = a.st.done_prev[e] != 0;
+      calls = a.st.calls[e];
     }
     int tile_cells;
     const int my_off = wave_excl_scan(S * S, lane, tile_cells);
     uint8_t* my_codes = codes + my_off;
     // the tile's grids are contiguous in HBM: stage them as codes
+    if (!kServe) g0 = (uint64_t)__shfl((long long)goff, 0, kWave);
     {
-      const uint64_t g0 = (uint64_t)__shfl((long long)goff, 0, kWave);
       const uint8_t* src = a.st.grid + g0;
       for (int c = lane; c < tile_cells; c += kWave) {
         const uint32_t tri = (uint32_t)src[3 * c] | ((uint32_t)src[3 * c + 1] << 8) |
@@ -704,17 +751,19 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
         codes[c] = (uint8_t)code_of(tri);
       }
     }
-    __syncthreads();
+    wave_sync();
 
     uint4 pol = make_uint4(0, 0, 0, 0);
     uint32_t act_next = 0;
     if (kActions && active) act_next = a.actions[e];
-    for (int s = 0; s < a.k_steps; ++s) {
-      const uint64_t call = a.call0 + (uint64_t)s;
+    for (int s = 0; s < steps; ++s) {
+      // the env's call count; envs stepped together share it, so the policy
+      // block refresh every 4 calls is uniform across the wave in practice
+      const uint32_t call = calls + (uint32_t)s;
       uint32_t act_now = 0;
       if (kActions) {
         act_now = act_next;
-        if (active && s + 1 < a.k_steps) act_next = a.actions[(size_t)(s + 1) * N + e];
+        if (active && s + 1 < steps) act_next = a.actions[(size_t)(s + 1) * N + e];
       } else if (s == 0 || (call & 3) == 0) {
         pol = policy_block(seed, rid, call);
       }
@@ -741,13 +790,13 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
           for (int yy = lane >> 5; yy < Lr.S; yy += 2)
             if (xx < Lr.S) gp[yy * Lr.S + xx] = (uint8_t)layout_code(Lr, xx, yy);
         }
-        __syncthreads();
+        wave_sync();
       }
 
       float reward = 0.0f;
       uint32_t flags = 0, act_rec = kActionNone;
       if (active && !do_reset) {
-        const uint32_t act = kActions ? act_now : bounded(pick4(pol, (uint32_t)(call & 3)), 7u);
+        const uint32_t act = kActions ? act_now : bounded(pick4(pol, call & 3u), 7u);
         const int fx = x + dir_dx(dir), fy = y + dir_dy(dir);
         const uint32_t front = table_at(table, my_codes[fy * S + fx]);
         const ActResult r = intervene(act, x, y, dir, carry, front, fx, fy);
@@ -763,36 +812,35 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
         done_prev = false;
       }
 
-      const int row = (a.row0 + s) % a.out.rows;
-      const size_t rowN = (size_t)row * (size_t)N;
-      if (a.out.obs) {
+      const size_t row = kServe ? (size_t)(step0 + s) : (size_t)((a.row0 + s) % a.out.rows);
+      const size_t rec = row * rec_stride;   // index of lane 0's record
+      if (o_obs) {
         // inactive lanes (S = 0, pose (1, 1)) read inside the guard margin
         uint32_t u[kObsWords + 1];
         observe_words(lds_rows(table, my_codes, S, x, y, dir), carry, active, lane & 31, u);
         // the stage holds 32 records: lanes 0-31, then lanes 32-63 (each half
         // starts and ends on a word boundary, so the halves are independent)
-        uint8_t* dst = a.out.obs + (rowN + (size_t)e0) * kObsBytes;
+        uint8_t* dst = o_obs + rec * kObsBytes;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int n_half = min(32, n_here - 32 * h);
           if (n_half <= 0) break;
           if ((lane >> 5) == h) store_words(stage, lane & 31, u);
-          __syncthreads();
-          copy_out(stage, dst + h * kHalfStageBytes, n_half, lane);
-          __syncthreads();
+          wave_sync();
+          copy_out<kWave / 2>(stage, dst + h * kHalfStageBytes, n_half, lane);
+          wave_sync();
         }
       }
       if (active) {
-        a.out.reward[rowN + e] = reward;
-        a.out.flags[rowN + e] = (uint8_t)flags;
-        a.out.action[rowN + e] = (uint8_t)act_rec;
+        o_reward[rec + lane] = reward;
+        o_flags[rec + lane] = (uint8_t)flags;
+        o_action[rec + lane] = (uint8_t)act_rec;
       }
-      __syncthreads();
+      wave_sync();
     }
 
     // write the chunk's final state back
     {
-      const uint64_t g0 = (uint64_t)__shfl((long long)goff, 0, kWave);
       uint8_t* dst = a.st.grid + g0;
       for (int c = lane; c < tile_cells; c += kWave) {
         const uint32_t tri = table_at(table, codes[c]);
@@ -809,9 +857,67 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
       a.st.carry[e] = (int32_t)carry;
       a.st.episode[e] = episode;
       a.st.done_prev[e] = done_prev ? 1 : 0;
+      a.st.calls[e] = calls + (uint32_t)steps;
     }
-    __syncthreads();
+    if (kServe && lane == 0) a.serve[tile].step0 = step0 + (uint32_t)steps;
+    wave_sync();
   }
+}
+
+// ---------------------------------------------------------------------------
+// Admission of requests to a server: one workgroup per admitted tile copies
+// the tile's per-slot configuration and its descriptor from host staging
+// and resets its envs (reset(key) of Sec. 3.2.2, episode 0).
+// ---------------------------------------------------------------------------
+struct AdmitArgs {
+  EnvTables env;                 // slot tables (written here)
+  StateBufs st;                  // slot state and the grid pool
+  ServeTile* tiles;              // device descriptors (written here)
+  const ServeTile* host_tiles;   // staging, indexed by tile
+  const SlotConfig* host_slots;  // staging, indexed by slot
+  int32_t n;
+  uint32_t tile_ids[kAdmitBatch];
+};
+
+__global__ __launch_bounds__(kWave) void k_admit(AdmitArgs a) {
+  const int lane = threadIdx.x;
+  const uint32_t tile = a.tile_ids[blockIdx.x];
+  const ServeTile d = a.host_tiles[tile];
+  const bool active = lane < (int)d.n_envs;
+  const uint32_t e = tile * kWave + lane;
+  Layout L{};
+  uint8_t* g = a.st.grid;
+  if (active) {
+    const SlotConfig c = a.host_slots[e];
+    a.env.meta[e] = c.meta;
+    a.env.max_steps[e] = c.max_steps;
+    a.env.seed[e] = c.seed;
+    a.env.rng_id[e] = c.rng_id;
+    a.env.grid_off[e] = c.grid_off;
+    L = make_layout(c.meta & 0xFF, (int)((c.meta >> 8) & 0xFF), c.seed, c.rng_id, 0u);
+    g = a.st.grid + c.grid_off;
+    a.st.x[e] = L.ax;
+    a.st.y[e] = L.ay;
+    a.st.dir[e] = L.dir;
+    a.st.t[e] = 0;
+    a.st.carry[e] = (int32_t)kCellEmpty;
+    a.st.episode[e] = 0u;
+    a.st.done_prev[e] = 0;
+    a.st.calls[e] = 0u;
+  }
+  uint64_t pending = __ballot(active);
+  while (pending) {
+    const int r = __ffsll((unsigned long long)pending) - 1;
+    pending &= pending - 1;
+    const Layout Lr = bcast_layout(L, r);
+    const uint64_t gr = ((uint64_t)(uint32_t)bcast((int)(uint32_t)reinterpret_cast<uint64_t>(g), r)) |
+                        ((uint64_t)(uint32_t)bcast((int)(uint32_t)(reinterpret_cast<uint64_t>(g) >> 32), r) << 32);
+    uint8_t* gp = reinterpret_cast<uint8_t*>(gr);
+    const int xx = lane & 31;
+    for (int yy = lane >> 5; yy < Lr.S; yy += 2)
+      if (xx < Lr.S) store_triple(gp + 3 * (yy * Lr.S + xx), layout_cell(Lr, xx, yy));
+  }
+  if (lane == 0) a.tiles[tile] = d;
 }
 
 }  // namespace
@@ -826,32 +932,53 @@ size_t fused_lds_bytes(int32_t max_tile_cells) {
 }
 
 hipError_t launch_plain(const EnvTables& env, const StateBufs& st, const uint8_t* actions,
-                        uint64_t call, int reset_all, const TrajBufs& out, int32_t row,
-                        hipStream_t stream) {
-  PlainArgs a{env, st, actions, call, reset_all, out, row};
+                        int reset_all, const TrajBufs& out, int32_t row, hipStream_t stream) {
+  PlainArgs a{env, st, actions, reset_all, out, row};
   const int blocks = (env.n + kWave - 1) / kWave;
   hipLaunchKernelGGL(k_plain, dim3(blocks), dim3(kWave), 0, stream, a);
   return hipGetLastError();
 }
 
 hipError_t launch_fused(const EnvTables& env, const TileTables& tiles, const StateBufs& st,
-                        const uint8_t* actions, uint64_t call0, int32_t k_steps,
+                        const uint8_t* actions, int32_t k_steps,
                         const TrajBufs& out, int32_t row0, int32_t grid_blocks,
-                        hipStream_t stream) {
-  FusedArgs a{env, tiles, st, actions, call0, k_steps, out, row0};
+                        hipStream_t stream, ServeTile* serve) {
+  FusedArgs a{env, tiles, st, actions, k_steps, out, row0, serve};
   const size_t lds = fused_dynamic_lds_bytes(tiles.max_tile_cells);
-  const void* fn = actions ? reinterpret_cast<const void*>(&k_fused<true>)
-                           : reinterpret_cast<const void*>(&k_fused<false>);
+  const void* fn = serve ? reinterpret_cast<const void*>(&k_fused<false, true>)
+                 : actions ? reinterpret_cast<const void*>(&k_fused<true, false>)
+                           : reinterpret_cast<const void*>(&k_fused<false, false>);
   if (lds > 65536) {
     const hipError_t e =
         hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  if (actions)
-    hipLaunchKernelGGL(k_fused<true>, dim3(grid_blocks), dim3(kWave), lds, stream, a);
+  if (serve)
+    hipLaunchKernelGGL((k_fused<false, true>), dim3(grid_blocks), dim3(kWave), lds, stream, a);
+  else if (actions)
+    hipLaunchKernelGGL((k_fused<true, false>), dim3(grid_blocks), dim3(kWave), lds, stream, a);
   else
-    hipLaunchKernelGGL(k_fused<false>, dim3(grid_blocks), dim3(kWave), lds, stream, a);
+    hipLaunchKernelGGL((k_fused<false, false>), dim3(grid_blocks), dim3(kWave), lds, stream, a);
   return hipGetLastError();
+}
+
+hipError_t launch_admit(const EnvTables& env, const StateBufs& st, ServeTile* tiles,
+                        const ServeTile* host_tiles, const SlotConfig* host_slots,
+                        const uint32_t* tile_ids, int32_t n, hipStream_t stream) {
+  for (int32_t i = 0; i < n; i += kAdmitBatch) {
+    AdmitArgs a{};
+    a.env = env;
+    a.st = st;
+    a.tiles = tiles;
+    a.host_tiles = host_tiles;
+    a.host_slots = host_slots;
+    a.n = n - i < kAdmitBatch ? n - i : kAdmitBatch;
+    for (int32_t j = 0; j < a.n; ++j) a.tile_ids[j] = tile_ids[i + j];
+    hipLaunchKernelGGL(k_admit, dim3(a.n), dim3(kWave), 0, stream, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace gx

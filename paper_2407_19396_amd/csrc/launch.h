@@ -9,11 +9,11 @@ namespace gx {
 // Per-env static tables in device memory (structure of arrays).
 struct EnvTables {
   int32_t n;
-  const uint32_t* meta;       // family | side << 8
-  const int32_t* max_steps;   // truncation limit T >= 1
-  const uint2* seed;          // Philox key (lo, hi)
-  const uint32_t* rng_id;     // Philox counter word 0
-  const uint64_t* grid_off;   // byte offset of the env's [S][S][3] grid
+  uint32_t* meta;             // family | side << 8
+  int32_t* max_steps;         // truncation limit T >= 1
+  uint2* seed;                // Philox key (lo, hi)
+  uint32_t* rng_id;           // Philox counter word 0
+  uint64_t* grid_off;         // byte offset of the env's [S][S][3] grid
   int32_t reward_mode;        // 0: 1 - 0.9 t/T, 1: unit reward
 };
 
@@ -23,6 +23,7 @@ struct StateBufs {
   int32_t *x, *y, *dir, *t, *carry;
   uint32_t* episode;
   uint8_t* done_prev;
+  uint32_t* calls;     // step calls since reset: the random policy's counter
 };
 
 // Per-step outputs: row r of each buffer holds N entries.
@@ -41,19 +42,56 @@ struct TileTables {
   int32_t max_tile_cells;     // LDS bytes of the largest tile's code grids
 };
 
+// A tile of 64 slots serving one request (device memory, 64 bytes).  The
+// tile's envs are slots [tile * 64, tile * 64 + n_envs); their grids are
+// contiguous from grid_base.  The record of the request's step r for its
+// env l goes to index r * stride + l of its output buffers.
+struct alignas(64) ServeTile {
+  uint32_t active;     // 0: the tile is free
+  uint32_t n_envs;     // 1..64
+  uint64_t grid_base;  // byte offset of the tile's grids in the grid pool
+  uint8_t* obs;        // [n_steps][stride][147] or nullptr
+  float* reward;       // [n_steps][stride]
+  uint8_t* flags;
+  uint8_t* action;
+  uint32_t stride;     // envs per output row of the request (multiple of 16)
+  uint32_t local0;     // request-local index of the tile's first env
+  uint32_t step0;      // steps the request has run; advanced by the kernel
+  uint32_t n_steps;    // steps the request asked for
+};
+
+// Configuration of one server slot, staged in host memory for admission.
+struct SlotConfig {
+  uint32_t meta;       // family | side << 8
+  int32_t max_steps;
+  uint2 seed;
+  uint32_t rng_id;     // request-local env index
+  uint32_t pad;
+  uint64_t grid_off;   // byte offset of the slot's grid in the pool
+};
+
+constexpr int kAdmitBatch = 512;   // tiles per admission launch (kernel argument)
+
+// Admits tiles: copies their slot configs and descriptors from host staging
+// (coherent pinned memory the device reads directly) and resets their envs.
+hipError_t launch_admit(const EnvTables& env, const StateBufs& st, ServeTile* tiles,
+                        const ServeTile* host_tiles, const SlotConfig* host_slots,
+                        const uint32_t* tile_ids, int32_t n, hipStream_t stream);
+
 // One launch of the plain kernel: one step of every env (or the reset of
 // every env when reset_all != 0).  Writes output row `row`.
 hipError_t launch_plain(const EnvTables& env, const StateBufs& st, const uint8_t* actions,
-                        uint64_t call, int reset_all, const TrajBufs& out, int32_t row,
-                        hipStream_t stream);
+                        int reset_all, const TrajBufs& out, int32_t row, hipStream_t stream);
 
 // One launch of the fused kernel: k_steps steps of every env, state staged
 // in LDS for the whole chunk; step s (0-based within the chunk) writes row
 // (row0 + s) % rows.  actions: [k_steps][N] for this chunk, or nullptr.
+// With serve != nullptr the tiles are requests instead (see ServeTile):
+// random policy, each tile runs min(k_steps, its steps left).
 hipError_t launch_fused(const EnvTables& env, const TileTables& tiles, const StateBufs& st,
-                        const uint8_t* actions, uint64_t call0, int32_t k_steps,
+                        const uint8_t* actions, int32_t k_steps,
                         const TrajBufs& out, int32_t row0, int32_t grid_blocks,
-                        hipStream_t stream);
+                        hipStream_t stream, ServeTile* serve = nullptr);
 
 // LDS bytes one workgroup of the fused kernel needs for a tile size (static
 // table and record stage plus the dynamic tile grids).

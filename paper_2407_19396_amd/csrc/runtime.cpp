@@ -18,7 +18,6 @@ struct gx_ctx {
   int32_t n = 0;
   int32_t reward_mode = 0;
   uint64_t grid_bytes = 0;
-  uint64_t calls = 0;
   bool has_reset = false;
   // device tables
   uint32_t* d_meta = nullptr;
@@ -76,7 +75,7 @@ void free_tables(gx_ctx* c) {
 
 bool state_ok(const gx_state* st) {
   return st && st->grid && st->x && st->y && st->dir && st->t && st->carry && st->episode &&
-         st->done_prev;
+         st->done_prev && st->calls;
 }
 
 bool traj_ok(const gx_traj* tr) {
@@ -89,7 +88,8 @@ gx::EnvTables tables_of(const gx_ctx* c) {
 }
 
 gx::StateBufs state_of(const gx_state* st) {
-  return gx::StateBufs{st->grid, st->x, st->y, st->dir, st->t, st->carry, st->episode, st->done_prev};
+  return gx::StateBufs{st->grid, st->x, st->y, st->dir, st->t, st->carry, st->episode, st->done_prev,
+                       st->calls};
 }
 
 gx::TrajBufs traj_of(const gx_traj* tr) {
@@ -113,6 +113,7 @@ const char* env_strerror(int status) {
     case GX_ENOMEM: return "out of memory";
     case GX_EDEVICE: return "HIP device error";
     case GX_ESTATE: return "call order violated (reset the envs first)";
+    case GX_EBUSY: return "no free server tiles for the request now";
     default: return "unknown status";
   }
 }
@@ -200,7 +201,6 @@ int env_info(const gx_ctx* c, gx_info* info) {
   info->blocks = c->blocks;
   info->k_default = c->k_default;
   info->grid_bytes = c->grid_bytes;
-  info->calls = c->calls;
   return GX_OK;
 }
 
@@ -212,10 +212,9 @@ int env_reset(gx_ctx* c, const gx_state* st, const gx_traj* first, void* stream)
   if ((rc = device_status()) != GX_OK) return rc;
   gx::TrajBufs tb{nullptr, nullptr, nullptr, nullptr, 1};
   if (first) tb = traj_of(first);
-  if (gx::launch_plain(tables_of(c), state_of(st), nullptr, 0, 1, tb, 0,
+  if (gx::launch_plain(tables_of(c), state_of(st), nullptr, 1, tb, 0,
                        reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
     return GX_EDEVICE;
-  c->calls = 0;
   c->has_reset = true;
   return GX_OK;
 }
@@ -227,10 +226,9 @@ int env_step(gx_ctx* c, const gx_state* st, const uint8_t* actions, const gx_tra
   int rc = check_device(c);
   if (rc != GX_OK) return rc;
   if ((rc = device_status()) != GX_OK) return rc;
-  if (gx::launch_plain(tables_of(c), state_of(st), actions, c->calls, 0, traj_of(out), 0,
+  if (gx::launch_plain(tables_of(c), state_of(st), actions, 0, traj_of(out), 0,
                        reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
     return GX_EDEVICE;
-  c->calls += 1;
   return GX_OK;
 }
 
@@ -246,11 +244,10 @@ int env_rollout(gx_ctx* c, const gx_state* st, int32_t n_steps, const uint8_t* a
   for (int32_t s0 = 0; s0 < n_steps; s0 += k) {
     const int32_t ks = std::min(k, n_steps - s0);
     const uint8_t* act = actions ? actions + (size_t)s0 * (size_t)c->n : nullptr;
-    if (gx::launch_fused(tables_of(c), tiles, state_of(st), act, c->calls, ks, traj_of(traj),
+    if (gx::launch_fused(tables_of(c), tiles, state_of(st), act, ks, traj_of(traj),
                          s0 % traj->rows, c->blocks, reinterpret_cast<hipStream_t>(stream)) !=
         hipSuccess)
       return GX_EDEVICE;
-    c->calls += (uint64_t)ks;
   }
   return GX_OK;
 }

@@ -1,0 +1,468 @@
+// server.cpp -- continuous-batching request server of libgridenv.so.
+//
+// A server owns a pool of slots grouped in tiles of 64 (the fused kernel's
+// unit) with their tables, state and grid storage.  A request (its own
+// seed, env mix and step count) takes whole tiles; every env_server_step
+// call advances all live requests by up to K steps in one persistent fused
+// launch, so requests admitted while others run share the device and their
+// work overlaps.  Each request's random policy counts its own steps and its
+// env ids are request-local, so its results do not depend on what else is
+// being served (and equal a reset + rollout of the same batch on a
+// context).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <new>
+#include <set>
+#include <thread>
+#include <vector>
+
+#include "../../include/gridenv.h"
+#include "arena.h"
+#include "launch.h"
+
+namespace {
+
+constexpr int kTileEnvs = 64;
+
+bool family_side_ok(int family, int side, int max_side) {
+  if (side > max_side) return false;
+  switch (family) {
+    case GX_FAMILY_EMPTY: return side >= 4;
+    case GX_FAMILY_TWOROOM: return side >= 5;
+    case GX_FAMILY_FOURROOMS: return side >= 7 && (side & 1) == 1;
+    default: return false;
+  }
+}
+
+struct Request {
+  bool live = false;
+  int32_t n_envs = 0, n_steps = 0, done = 0;
+  std::vector<int32_t> tiles;
+};
+
+}  // namespace
+
+struct gx_server {
+  int device = 0;
+  int32_t max_tiles = 0, max_side = 0, reward_mode = 0;
+  uint64_t tile_grid_bytes = 0, device_bytes = 0;
+  int cus = 256;
+  size_t lds_per_cu = 160 * 1024;
+  // device pool
+  uint32_t* d_meta = nullptr;
+  int32_t* d_max_steps = nullptr;
+  uint2* d_seed = nullptr;
+  uint32_t* d_rng_id = nullptr;
+  uint64_t* d_grid_off = nullptr;
+  uint8_t* d_grid = nullptr;
+  int32_t *d_x = nullptr, *d_y = nullptr, *d_dir = nullptr, *d_t = nullptr, *d_carry = nullptr;
+  uint32_t* d_episode = nullptr;
+  uint8_t* d_done = nullptr;
+  uint32_t* d_calls = nullptr;
+  gx::ServeTile* d_tiles = nullptr;
+  // host staging read by the admission kernel (coherent pinned memory)
+  gx::ServeTile* h_tiles = nullptr;
+  gx::SlotConfig* h_slots = nullptr;
+  // bookkeeping
+  std::set<int32_t> free_tiles;
+  std::vector<int32_t> tile_cells;   // cells of a live tile, 0 when free
+  std::vector<Request> reqs;
+  std::vector<int32_t> free_handles;
+  std::vector<uint32_t> pending;     // tiles admitted since the last step
+  std::deque<int32_t> finished;      // requests whose last step has been launched
+  std::vector<int32_t> running;      // requests with steps left to launch
+  int32_t live = 0;
+};
+
+namespace {
+
+void free_all(gx_server* s) {
+  void* dev[] = {s->d_meta, s->d_max_steps, s->d_seed, s->d_rng_id, s->d_grid_off, s->d_grid,
+                 s->d_x, s->d_y, s->d_dir, s->d_t, s->d_carry, s->d_episode, s->d_done, s->d_calls,
+                 s->d_tiles};
+  for (void* p : dev)
+    if (p) (void)hipFree(p);
+  if (s->h_tiles) (void)hipHostFree(s->h_tiles);
+  if (s->h_slots) (void)hipHostFree(s->h_slots);
+}
+
+template <class T>
+bool dev_alloc(gx_server* s, T** p, size_t count) {
+  const size_t bytes = count * sizeof(T);
+  if (hipMalloc(reinterpret_cast<void**>(p), bytes) != hipSuccess) return false;
+  s->device_bytes += bytes;
+  return true;
+}
+
+gx::EnvTables tables_of(gx_server* s) {
+  return gx::EnvTables{s->max_tiles * kTileEnvs, s->d_meta, s->d_max_steps, s->d_seed,
+                       s->d_rng_id, s->d_grid_off, s->reward_mode};
+}
+
+gx::StateBufs state_of(gx_server* s) {
+  return gx::StateBufs{s->d_grid, s->d_x, s->d_y, s->d_dir, s->d_t, s->d_carry, s->d_episode, s->d_done,
+                       s->d_calls};
+}
+
+}  // namespace
+
+extern "C" {
+
+int env_server_create(int32_t max_tiles, int32_t max_side, int32_t reward_mode, gx_server** out) {
+  if (!out) return GX_EINVAL;
+  *out = nullptr;
+  if (max_tiles < 1 || max_tiles > (1 << 20) || max_side < 4 || max_side > 32) return GX_EINVAL;
+  if (reward_mode != 0 && reward_mode != 1) return GX_EINVAL;
+  gx_server* s = new (std::nothrow) gx_server();
+  if (!s) return GX_ENOMEM;
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return GX_EDEVICE;
+  }
+  s->max_tiles = max_tiles;
+  s->max_side = max_side;
+  s->reward_mode = reward_mode;
+  s->tile_grid_bytes = 3ull * kTileEnvs * (uint64_t)max_side * (uint64_t)max_side;
+  const size_t slots = (size_t)max_tiles * kTileEnvs;
+  bool ok = dev_alloc(s, &s->d_meta, slots) && dev_alloc(s, &s->d_max_steps, slots) &&
+            dev_alloc(s, &s->d_seed, slots) && dev_alloc(s, &s->d_rng_id, slots) &&
+            dev_alloc(s, &s->d_grid_off, slots) &&
+            dev_alloc(s, &s->d_grid, (size_t)max_tiles * s->tile_grid_bytes) &&
+            dev_alloc(s, &s->d_x, slots) && dev_alloc(s, &s->d_y, slots) &&
+            dev_alloc(s, &s->d_dir, slots) && dev_alloc(s, &s->d_t, slots) &&
+            dev_alloc(s, &s->d_carry, slots) && dev_alloc(s, &s->d_episode, slots) &&
+            dev_alloc(s, &s->d_done, slots) && dev_alloc(s, &s->d_calls, slots) &&
+            dev_alloc(s, &s->d_tiles, (size_t)max_tiles);
+  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&s->h_tiles), sizeof(gx::ServeTile) * max_tiles,
+                           hipHostMallocCoherent) == hipSuccess;
+  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&s->h_slots), sizeof(gx::SlotConfig) * slots,
+                           hipHostMallocCoherent) == hipSuccess;
+  // every descriptor starts inactive
+  ok = ok && hipMemset(s->d_tiles, 0, sizeof(gx::ServeTile) * max_tiles) == hipSuccess;
+  if (!ok) {
+    free_all(s);
+    delete s;
+    return GX_ENOMEM;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, s->device) == hipSuccess) {
+    s->cus = prop.multiProcessorCount;
+    if (prop.maxSharedMemoryPerMultiProcessor > 0) s->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor;
+  }
+  for (int32_t t = 0; t < max_tiles; ++t) s->free_tiles.insert(t);
+  s->tile_cells.assign(max_tiles, 0);
+  *out = s;
+  return GX_OK;
+}
+
+int env_server_admit(gx_server* s, const gx_request* r, int32_t* handle) {
+  if (!s || !r || !handle) return GX_EINVAL;
+  if (r->n_envs < 1 || r->n_steps < 1 || r->stride < r->n_envs || !r->family || !r->side ||
+      !r->max_steps || !r->reward || !r->flags || !r->action)
+    return GX_EINVAL;
+  for (int32_t i = 0; i < r->n_envs; ++i)
+    if (!family_side_ok(r->family[i], r->side[i], s->max_side) || r->max_steps[i] < 1) return GX_EINVAL;
+  const int32_t need = (r->n_envs + kTileEnvs - 1) / kTileEnvs;
+  if ((int32_t)s->free_tiles.size() < need) return GX_EBUSY;
+  int32_t h;
+  if (!s->free_handles.empty()) {
+    h = s->free_handles.back();
+    s->free_handles.pop_back();
+  } else {
+    h = (int32_t)s->reqs.size();
+    s->reqs.emplace_back();
+  }
+  Request& q = s->reqs[h];
+  q.live = true;
+  q.n_envs = r->n_envs;
+  q.n_steps = r->n_steps;
+  q.done = 0;
+  q.tiles.clear();
+  const uint2 seed = make_uint2((uint32_t)r->seed, (uint32_t)(r->seed >> 32));
+  for (int32_t i = 0; i < need; ++i) {
+    const int32_t t = *s->free_tiles.begin();
+    s->free_tiles.erase(s->free_tiles.begin());
+    q.tiles.push_back(t);
+    const int32_t l0 = i * kTileEnvs, n = std::min(kTileEnvs, r->n_envs - l0);
+    const uint64_t base = (uint64_t)t * s->tile_grid_bytes;
+    uint64_t off = base;
+    int32_t cells = 0;
+    for (int32_t j = 0; j < n; ++j) {
+      const int32_t S = r->side[l0 + j];
+      gx::SlotConfig& c = s->h_slots[(size_t)t * kTileEnvs + j];
+      c.meta = (uint32_t)r->family[l0 + j] | ((uint32_t)S << 8);
+      c.max_steps = r->max_steps[l0 + j];
+      c.seed = seed;
+      c.rng_id = (uint32_t)(l0 + j);
+      c.pad = 0;
+      c.grid_off = off;
+      off += 3ull * (uint64_t)S * (uint64_t)S;
+      cells += S * S;
+    }
+    gx::ServeTile& d = s->h_tiles[t];
+    d.active = 1;
+    d.n_envs = (uint32_t)n;
+    d.grid_base = base;
+    d.obs = r->obs;
+    d.reward = r->reward;
+    d.flags = r->flags;
+    d.action = r->action;
+    d.stride = (uint32_t)r->stride;
+    d.local0 = (uint32_t)l0;
+    d.step0 = 0;
+    d.n_steps = (uint32_t)r->n_steps;
+    s->tile_cells[t] = cells;
+    s->pending.push_back((uint32_t)t);
+  }
+  s->live += 1;
+  s->running.push_back(h);
+  *handle = h;
+  return GX_OK;
+}
+
+int env_server_step(gx_server* s, int32_t K, void* stream, int32_t* finished, int32_t cap,
+                    int32_t* n_finished) {
+  if (!s || K < 1 || cap < 0 || (cap > 0 && !finished) || !n_finished) return GX_EINVAL;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return GX_EDEVICE;
+  if (dev != s->device) return GX_EINVAL;
+  if (hipGetLastError() != hipSuccess) return GX_EDEVICE;
+  const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (!s->pending.empty()) {
+    if (gx::launch_admit(tables_of(s), state_of(s), s->d_tiles, s->h_tiles, s->h_slots,
+                         s->pending.data(), (int32_t)s->pending.size(), st) != hipSuccess)
+      return GX_EDEVICE;
+    s->pending.clear();
+  }
+  // launch only if some request still has steps to run
+  int32_t max_cells = 0;
+  for (int32_t h : s->running)
+    for (int32_t t : s->reqs[h].tiles) max_cells = std::max(max_cells, s->tile_cells[t]);
+  if (!s->running.empty()) {
+    const size_t lds = gx::fused_lds_bytes(max_cells);
+    const int per_cu = std::max<int>(1, std::min<int>(16, (int)(s->lds_per_cu / lds)));
+    const int32_t blocks = std::min<int32_t>(s->max_tiles, s->cus * per_cu);
+    const gx::TileTables tiles{s->max_tiles, max_cells};
+    const gx::TrajBufs none{nullptr, nullptr, nullptr, nullptr, 1};
+    if (gx::launch_fused(tables_of(s), tiles, state_of(s), nullptr, K, none, 0, blocks, st,
+                         s->d_tiles) != hipSuccess)
+      return GX_EDEVICE;
+    size_t keep = 0;
+    for (size_t i = 0; i < s->running.size(); ++i) {
+      const int32_t h = s->running[i];
+      Request& q = s->reqs[h];
+      q.done += std::min(K, q.n_steps - q.done);
+      if (q.done == q.n_steps) s->finished.push_back(h);
+      else s->running[keep++] = h;
+    }
+    s->running.resize(keep);
+  }
+  int32_t n = 0;
+  while (n < cap && !s->finished.empty()) {
+    finished[n++] = s->finished.front();
+    s->finished.pop_front();
+  }
+  *n_finished = n;
+  return GX_OK;
+}
+
+int env_server_release(gx_server* s, int32_t handle) {
+  if (!s || handle < 0 || handle >= (int32_t)s->reqs.size() || !s->reqs[handle].live) return GX_EINVAL;
+  Request& q = s->reqs[handle];
+  if (q.done < q.n_steps) return GX_ESTATE;
+  for (int32_t t : q.tiles) {
+    s->free_tiles.insert(t);
+    s->tile_cells[t] = 0;
+  }
+  q.tiles.clear();
+  q.live = false;
+  s->free_handles.push_back(handle);
+  s->live -= 1;
+  return GX_OK;
+}
+
+int env_server_info(const gx_server* s, gx_server_info* info) {
+  if (!s || !info) return GX_EINVAL;
+  info->max_tiles = s->max_tiles;
+  info->free_tiles = (int32_t)s->free_tiles.size();
+  info->live_requests = s->live;
+  info->max_side = s->max_side;
+  info->device_bytes = s->device_bytes;
+  return GX_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct Layout {
+  uint64_t reward = 0, obs = 0, flags = 0, action = 0, total = 0;
+};
+
+Layout output_layout(int32_t stride, int32_t n_steps, bool keep_obs) {
+  const uint64_t recs = (uint64_t)stride * (uint64_t)n_steps;
+  auto up = [](uint64_t x) { return (x + 255) & ~255ull; };
+  Layout l;
+  l.reward = 0;
+  l.obs = up(4 * recs);
+  l.flags = l.obs + (keep_obs ? up((uint64_t)GX_OBS_BYTES * recs) : 0);
+  l.action = l.flags + up(recs);
+  l.total = l.action + up(recs);
+  return l;
+}
+
+}  // namespace
+
+extern "C" {
+
+int env_serve_run(gx_server* s, const gx_serve_item* items, int32_t n_items, const uint8_t* family,
+                  const uint8_t* side, const int32_t* max_steps, const gx_serve_opts* o,
+                  void* stream, double* admit_s, double* done_s, gx_serve_stats* stats) {
+  if (!s || !items || n_items < 0 || !family || !side || !max_steps || !o || !admit_s || !done_s ||
+      !stats || o->K < 1 || o->max_inflight < 1 || !o->arena)
+    return GX_EINVAL;
+  if (s->live != 0) return GX_ESTATE;
+  const uint64_t budget = o->budget_bytes > s->device_bytes ? o->budget_bytes - s->device_bytes : 0;
+  const uint64_t capacity = std::min<uint64_t>(o->arena_bytes, budget) & ~255ull;
+  // every item must fit an idle server on its own, or the loop could wait forever
+  for (int32_t i = 0; i < n_items; ++i) {
+    const gx_serve_item& it = items[i];
+    if (it.n_envs < 1 || it.n_steps < 1 || it.env_offset < 0 ||
+        (i > 0 && it.arrival_s < items[i - 1].arrival_s))
+      return GX_EINVAL;
+    if ((it.n_envs + kTileEnvs - 1) / kTileEnvs > s->max_tiles) return GX_EINVAL;
+    if (output_layout((it.n_envs + 15) / 16 * 16, it.n_steps, o->keep_obs != 0).total > capacity)
+      return GX_EINVAL;
+  }
+  using clock = std::chrono::steady_clock;
+  const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  gx::Arena arena(capacity);
+  struct Live {
+    int32_t item;
+    uint64_t off, bytes;
+  };
+  std::vector<Live> by_handle;
+  std::vector<hipEvent_t> events(o->max_inflight + 1);
+  for (auto& e : events)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return GX_EDEVICE;
+  std::deque<std::pair<int32_t, std::vector<int32_t>>> inflight;   // (event index, finished handles)
+  int32_t next_event = 0;
+  std::deque<int32_t> queue;
+  int32_t next = 0, completed = 0, launches = 0;
+  uint64_t env_steps = 0;
+  std::vector<int32_t> fin(4096);
+  int rc = GX_OK;
+  double t_admit = 0, t_step = 0, t_wait = 0;
+  const auto t0 = clock::now();
+  auto now_s = [&]() { return std::chrono::duration<double>(clock::now() - t0).count(); };
+  auto retire = [&](bool wait) -> int {
+    while (!inflight.empty()) {
+      hipEvent_t ev = events[inflight.front().first];
+      const double w0 = wait ? now_s() : 0.0;
+      hipError_t q = wait ? hipEventSynchronize(ev) : hipEventQuery(ev);
+      if (wait) t_wait += now_s() - w0;
+      if (q == hipErrorNotReady) return GX_OK;
+      if (q != hipSuccess) return GX_EDEVICE;
+      const double t = now_s();
+      for (int32_t h : inflight.front().second) {
+        const Live& l = by_handle[h];
+        done_s[l.item] = t;
+        env_steps += (uint64_t)items[l.item].n_envs * (uint64_t)items[l.item].n_steps;
+        arena.release(l.off, l.bytes);
+        if (env_server_release(s, h) != GX_OK) return GX_EDEVICE;
+        ++completed;
+      }
+      inflight.pop_front();
+      wait = false;
+    }
+    return GX_OK;
+  };
+  for (int32_t i = 0; i < n_items; ++i) admit_s[i] = done_s[i] = -1.0;
+  while (completed < n_items) {
+    const double t = now_s();
+    while (next < n_items && items[next].arrival_s <= t) queue.push_back(next++);
+    // admission in arrival order while tiles and budget allow
+    const double a0 = now_s();
+    while (!queue.empty()) {
+      const gx_serve_item& it = items[queue.front()];
+      const int32_t stride = (it.n_envs + 15) / 16 * 16;
+      const Layout lay = output_layout(stride, it.n_steps, o->keep_obs != 0);
+      uint64_t off;
+      if (!arena.alloc(lay.total, &off)) break;
+      uint8_t* base = o->arena + off;
+      gx_request r;
+      r.n_envs = it.n_envs;
+      r.n_steps = it.n_steps;
+      r.seed = it.seed;
+      r.family = family + it.env_offset;
+      r.side = side + it.env_offset;
+      r.max_steps = max_steps + it.env_offset;
+      r.obs = o->keep_obs ? base + lay.obs : nullptr;
+      r.reward = reinterpret_cast<float*>(base + lay.reward);
+      r.flags = base + lay.flags;
+      r.action = base + lay.action;
+      r.stride = stride;
+      int32_t h;
+      const int a = env_server_admit(s, &r, &h);
+      if (a == GX_EBUSY) {
+        arena.release(off, lay.total);
+        break;
+      }
+      if (a != GX_OK) {
+        arena.release(off, lay.total);
+        rc = a;
+        goto out;
+      }
+      if ((int32_t)by_handle.size() <= h) by_handle.resize(h + 1);
+      by_handle[h] = Live{queue.front(), off, lay.total};
+      admit_s[queue.front()] = t;
+      queue.pop_front();
+    }
+    t_admit += now_s() - a0;
+    if (s->live > 0 && (int32_t)inflight.size() < o->max_inflight) {
+      int32_t n = 0;
+      const double s0 = now_s();
+      rc = env_server_step(s, o->K, stream, fin.data(), (int32_t)fin.size(), &n);
+      t_step += now_s() - s0;
+      if (rc != GX_OK) goto out;
+      if (hipEventRecord(events[next_event], st) != hipSuccess) {
+        rc = GX_EDEVICE;
+        goto out;
+      }
+      inflight.emplace_back(next_event, std::vector<int32_t>(fin.begin(), fin.begin() + n));
+      next_event = (next_event + 1) % (int32_t)events.size();
+      ++launches;
+    }
+    // wait for the oldest launch when the pipeline is full; otherwise poll
+    if ((rc = retire((int32_t)inflight.size() >= o->max_inflight)) != GX_OK) goto out;
+    if (s->live == 0 && queue.empty() && next < n_items) {
+      const double wait = items[next].arrival_s - now_s();
+      if (wait > 2e-4) std::this_thread::sleep_for(std::chrono::duration<double>(wait - 1e-4));
+    }
+  }
+out:
+  if (rc == GX_OK) rc = retire(true);
+  for (auto& e : events) (void)hipEventDestroy(e);
+  stats->wall_s = now_s();
+  stats->env_steps = env_steps;
+  stats->completed = completed;
+  stats->launches = launches;
+  stats->admit_s = t_admit;
+  stats->step_s = t_step;
+  stats->wait_s = t_wait;
+  return rc;
+}
+
+int env_server_destroy(gx_server* s) {
+  if (!s) return GX_EINVAL;
+  free_all(s);
+  delete s;
+  return GX_OK;
+}
+
+}  // extern "C"

@@ -18,10 +18,12 @@ from . import workloads
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgridenv.so")
 
-GX_OK, GX_EINVAL, GX_ENOMEM, GX_EDEVICE, GX_ESTATE = 0, -1, -2, -3, -4
+GX_OK, GX_EINVAL, GX_ENOMEM, GX_EDEVICE, GX_ESTATE, GX_EBUSY = 0, -1, -2, -3, -4, -5
 OBS_BYTES = 147
 EXPORTS = ("env_create", "env_sizes", "env_info", "env_reset", "env_step", "env_rollout",
-           "env_set_launch", "env_destroy", "env_strerror")
+           "env_set_launch", "env_destroy", "env_strerror",
+           "env_server_create", "env_server_admit", "env_server_step", "env_server_release",
+           "env_server_info", "env_server_destroy", "env_serve_run")
 
 
 class GxConfig(ctypes.Structure):
@@ -31,9 +33,11 @@ class GxConfig(ctypes.Structure):
                 ("seed_all", ctypes.c_uint64), ("rng_id", ctypes.c_void_p)]
 
 
+STATE_FIELDS = ("grid", "x", "y", "dir", "t", "carry", "episode", "done_prev", "calls")
+
+
 class GxState(ctypes.Structure):
-    _fields_ = [(f, ctypes.c_void_p) for f in
-                ("grid", "x", "y", "dir", "t", "carry", "episode", "done_prev")]
+    _fields_ = [(f, ctypes.c_void_p) for f in STATE_FIELDS]
 
 
 class GxTraj(ctypes.Structure):
@@ -46,7 +50,37 @@ class GxInfo(ctypes.Structure):
     _fields_ = [("n_envs", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
                 ("max_tile_cells", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
                 ("blocks", ctypes.c_int32), ("k_default", ctypes.c_int32),
-                ("grid_bytes", ctypes.c_uint64), ("calls", ctypes.c_uint64)]
+                ("grid_bytes", ctypes.c_uint64)]
+
+
+class GxRequest(ctypes.Structure):
+    _fields_ = [("n_envs", ctypes.c_int32), ("n_steps", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("family", ctypes.c_void_p), ("side", ctypes.c_void_p), ("max_steps", ctypes.c_void_p),
+                ("obs", ctypes.c_void_p), ("reward", ctypes.c_void_p), ("flags", ctypes.c_void_p),
+                ("action", ctypes.c_void_p), ("stride", ctypes.c_int32)]
+
+
+class GxServerInfo(ctypes.Structure):
+    _fields_ = [("max_tiles", ctypes.c_int32), ("free_tiles", ctypes.c_int32),
+                ("live_requests", ctypes.c_int32), ("max_side", ctypes.c_int32),
+                ("device_bytes", ctypes.c_uint64)]
+
+
+class GxServeItem(ctypes.Structure):
+    _fields_ = [("arrival_s", ctypes.c_double), ("n_envs", ctypes.c_int32), ("n_steps", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("env_offset", ctypes.c_int64)]
+
+
+class GxServeOpts(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("max_inflight", ctypes.c_int32), ("keep_obs", ctypes.c_int32),
+                ("budget_bytes", ctypes.c_uint64), ("arena", ctypes.c_void_p),
+                ("arena_bytes", ctypes.c_uint64)]
+
+
+class GxServeStats(ctypes.Structure):
+    _fields_ = [("wall_s", ctypes.c_double), ("env_steps", ctypes.c_uint64),
+                ("completed", ctypes.c_int32), ("launches", ctypes.c_int32),
+                ("admit_s", ctypes.c_double), ("step_s", ctypes.c_double), ("wait_s", ctypes.c_double)]
 
 
 class GridEnvError(RuntimeError):
@@ -76,6 +110,14 @@ def load(path: str = LIB_PATH):
     L.env_rollout.argtypes = [P, ctypes.POINTER(GxState), I32, P, ctypes.POINTER(GxTraj), I32, P]
     L.env_set_launch.argtypes = [P, I32, I32]
     L.env_destroy.argtypes = [P]
+    L.env_server_create.argtypes = [I32, I32, I32, ctypes.POINTER(P)]
+    L.env_server_admit.argtypes = [P, ctypes.POINTER(GxRequest), ctypes.POINTER(I32)]
+    L.env_server_step.argtypes = [P, I32, P, ctypes.POINTER(I32), I32, ctypes.POINTER(I32)]
+    L.env_server_release.argtypes = [P, I32]
+    L.env_server_info.argtypes = [P, ctypes.POINTER(GxServerInfo)]
+    L.env_server_destroy.argtypes = [P]
+    L.env_serve_run.argtypes = [P, ctypes.POINTER(GxServeItem), I32, P, P, P,
+                                ctypes.POINTER(GxServeOpts), P, P, P, ctypes.POINTER(GxServeStats)]
     L.env_strerror.argtypes = [ctypes.c_int]
     L.env_strerror.restype = ctypes.c_char_p
     for f in EXPORTS:
@@ -181,7 +223,7 @@ class Traj:
 class GridEnv:
     """A batch of envs on the current HIP device with its state tensors."""
 
-    FIELDS = ("grid", "x", "y", "dir", "t", "carry", "episode", "done_prev")
+    FIELDS = STATE_FIELDS
 
     def __init__(self, table: workloads.EnvTable, reward_mode: int = 0, device="cuda"):
         import torch
@@ -199,6 +241,7 @@ class GridEnv:
         self.carry = torch.zeros(n, dtype=torch.int32, device=dev)
         self.episode = torch.zeros(n, dtype=torch.int32, device=dev)   # uint32 bits
         self.done_prev = torch.zeros(n, dtype=torch.uint8, device=dev)
+        self.calls = torch.zeros(n, dtype=torch.int32, device=dev)        # uint32 bits
 
     def state(self) -> GxState:
         return GxState(*[getattr(self, f).data_ptr() for f in self.FIELDS])
@@ -223,14 +266,15 @@ class GridEnv:
     def state_numpy(self) -> dict:
         out = {f: getattr(self, f).cpu().numpy() for f in self.FIELDS}
         out["episode"] = out["episode"].view(np.uint32)
+        out["calls"] = out["calls"].view(np.uint32)
         return out
 
     def load_state(self, st: dict):
         """Copy a host state (dict of numpy arrays) into the device tensors."""
         import torch
         for f in self.FIELDS:
-            a = np.ascontiguousarray(st[f])
-            if f == "episode":
+            a = np.ascontiguousarray(st[f] if f in st else np.zeros(self.n, np.uint32))
+            if f in ("episode", "calls"):
                 a = a.astype(np.uint32).view(np.int32)
             t = torch.from_numpy(a.copy()).to(self.device)
             getattr(self, f).copy_(t.view(getattr(self, f).shape))
@@ -245,3 +289,93 @@ class GridEnv:
             self.close()
         except Exception:
             pass
+
+
+# --------------------------------------------------------------- serving
+def padded_stride(n_envs: int) -> int:
+    """Row stride (envs) of a request's outputs: a multiple of 16 keeps every
+    64-env tile's records 16-byte aligned."""
+    return -(-n_envs // 16) * 16
+
+
+class Server:
+    """Continuous-batching server (env_server_* of the C-ABI)."""
+
+    def __init__(self, max_tiles: int, max_side: int = 19, reward_mode: int = 0):
+        self.ptr = ctypes.c_void_p()
+        _check("env_server_create", load().env_server_create(max_tiles, max_side, reward_mode,
+                                                              ctypes.byref(self.ptr)))
+        self._fin = (ctypes.c_int32 * 4096)()
+
+    def admit(self, table: workloads.EnvTable, n_steps: int, out: Traj, stride: int) -> int | None:
+        """Queue a request for the envs of `table` (its first seed keys them
+        all); returns its handle, or None when no tiles are free now."""
+        fam = np.ascontiguousarray(table.family, np.uint8)
+        side = np.ascontiguousarray(table.side, np.uint8)
+        ms = np.ascontiguousarray(table.max_steps, np.int32)
+        req = GxRequest(table.n, n_steps, int(table.seed[0]), fam.ctypes.data, side.ctypes.data,
+                        ms.ctypes.data, out.obs.data_ptr() if out.obs is not None else None,
+                        out.reward.data_ptr(), out.flags.data_ptr(), out.action.data_ptr(), stride)
+        h = ctypes.c_int32()
+        rc = load().env_server_admit(self.ptr, ctypes.byref(req), ctypes.byref(h))
+        if rc == GX_EBUSY:
+            return None
+        _check("env_server_admit", rc)
+        return h.value
+
+    def step(self, K: int, stream=None) -> list[int]:
+        n = ctypes.c_int32()
+        _check("env_server_step", load().env_server_step(self.ptr, K, _stream_ptr(stream), self._fin,
+                                                         len(self._fin), ctypes.byref(n)))
+        return [self._fin[i] for i in range(n.value)]
+
+    def release(self, handle: int):
+        _check("env_server_release", load().env_server_release(self.ptr, handle))
+
+    def info(self) -> dict:
+        i = GxServerInfo()
+        _check("env_server_info", load().env_server_info(self.ptr, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in GxServerInfo._fields_}
+
+    def close(self):
+        if self.ptr:
+            _check("env_server_destroy", load().env_server_destroy(self.ptr))
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def serve_run(server: Server, requests: list, K: int, budget_bytes: int, arena, keep_obs: bool = True,
+              max_inflight: int = 2, stream=None) -> dict:
+    """Run a Poisson serving workload (workloads.serving_requests) through
+    the native serving loop; returns throughput and per-request latencies."""
+    n = len(requests)
+    items = (GxServeItem * max(n, 1))()
+    fam, side, ms = [], [], []
+    off = 0
+    for i, r in enumerate(requests):
+        items[i] = GxServeItem(r.arrival_s, r.n_envs, r.n_steps, r.seed, off)
+        fam.append(r.table.family)
+        side.append(r.table.side)
+        ms.append(r.table.max_steps)
+        off += r.n_envs
+    fam = np.ascontiguousarray(np.concatenate(fam), np.uint8)
+    side = np.ascontiguousarray(np.concatenate(side), np.uint8)
+    ms = np.ascontiguousarray(np.concatenate(ms), np.int32)
+    admit = np.zeros(n, np.float64)
+    done = np.zeros(n, np.float64)
+    opts = GxServeOpts(K, max_inflight, 1 if keep_obs else 0, budget_bytes, arena.data_ptr(),
+                       arena.numel() * arena.element_size())
+    st = GxServeStats()
+    _check("env_serve_run", load().env_serve_run(server.ptr, items, n, fam.ctypes.data, side.ctypes.data,
+                                                 ms.ctypes.data, ctypes.byref(opts), _stream_ptr(stream),
+                                                 admit.ctypes.data, done.ctypes.data, ctypes.byref(st)))
+    arrival = np.array([r.arrival_s for r in requests])
+    return {"wall_s": st.wall_s, "env_steps": st.env_steps, "completed": st.completed,
+            "launches": st.launches, "host_admit_s": st.admit_s, "host_step_s": st.step_s,
+            "host_wait_s": st.wait_s, "arrival_s": arrival, "admit_s": admit, "done_s": done,
+            "latency_s": done - arrival}

@@ -1,0 +1,144 @@
+"""rocprofv3 summaries for the fused rollout kernel.
+
+``summarize`` turns the CSV output of a kernel-trace run and of FETCH_SIZE /
+WRITE_SIZE (and optional SQ) counter runs into a short text summary for
+``profiles/``.  The HBM byte counters are calibrated against a plain
+device-to-device copy of known size recorded in the same runs (the copy
+reads and writes exactly that many bytes).  The summary ends with one
+machine-readable line that ``traffic_bytes`` reads back for the benchmark;
+it is ignored once the kernel source has changed.
+
+    python -m paper_2407_19396_amd.profiling --trace DIR --fetch DIR --write DIR
+        [--sq DIR] --copy-bytes N --K K --envs N --command "..." -o profiles/x.txt
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = os.path.join(HERE, "csrc", "kernels.hip")
+COPY_KERNEL = "copyBuffer"
+FUSED = "k_fused"
+PLAIN = "k_plain"
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _one(pattern: str) -> str:
+    hits = sorted(glob.glob(pattern))
+    if not hits:
+        raise FileNotFoundError(pattern)
+    return hits[0]
+
+
+def _counters(directory: str) -> dict:
+    """{(kernel key, counter): [values per dispatch]}"""
+    path = _one(os.path.join(directory, "*counter_collection.csv"))
+    out = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        name = r["Kernel_Name"]
+        key = FUSED if FUSED in name else PLAIN if PLAIN in name else COPY_KERNEL if COPY_KERNEL in name else None
+        if key:
+            out[(key, r["Counter_Name"])].append(float(r["Counter_Value"]))
+    return out
+
+
+def _stats(directory: str) -> dict:
+    path = _one(os.path.join(directory, "*kernel_stats.csv"))
+    out = {}
+    for r in csv.DictReader(open(path)):
+        name = r["Name"]
+        key = FUSED if FUSED in name else PLAIN if PLAIN in name else None
+        if key:
+            out[key] = {"calls": int(r["Calls"]), "avg_ns": float(r["AverageNs"]),
+                        "min_ns": float(r["MinNs"]), "max_ns": float(r["MaxNs"])}
+    return out
+
+
+def _mean(xs):
+    return sum(xs) / len(xs)
+
+
+def summarize(trace: str, fetch: str, write: str, sq: str | None, copy_bytes: int, K: int,
+              envs: int, command: str) -> str:
+    st = _stats(trace)
+    fc, wc = _counters(fetch), _counters(write)
+    copy_fetch = _mean(fc[(COPY_KERNEL, "FETCH_SIZE")]) * 1024
+    copy_write = _mean(wc[(COPY_KERNEL, "WRITE_SIZE")]) * 1024
+    f_scale, w_scale = copy_bytes / copy_fetch, copy_bytes / copy_write
+    fused_fetch = _mean(fc[(FUSED, "FETCH_SIZE")]) * 1024 * f_scale
+    fused_write = _mean(wc[(FUSED, "WRITE_SIZE")]) * 1024 * w_scale
+    lines = [
+        "# k_fused on the mixed 262144-env workload (rocprofv3)",
+        "",
+        f"command: {command}",
+        f"kernel source sha256[:16]: {kernel_source_hash()}",
+        f"steps per launch K = {K}, envs = {envs}",
+        "",
+        "## kernel trace (--kernel-trace --stats)",
+    ]
+    for k in (FUSED, PLAIN):
+        if k in st:
+            s = st[k]
+            lines.append(f"{k}: calls {s['calls']}, average {s['avg_ns'] / 1e3:.1f} us, "
+                         f"min {s['min_ns'] / 1e3:.1f} us, max {s['max_ns'] / 1e3:.1f} us")
+    lines += [
+        "",
+        "## HBM traffic (--pmc FETCH_SIZE, then --pmc WRITE_SIZE; KiB per dispatch)",
+        f"copy probe of {copy_bytes} bytes: FETCH_SIZE {copy_fetch / 1024:.0f} KiB, "
+        f"WRITE_SIZE {copy_write / 1024:.0f} KiB -> scale fetch x{f_scale:.3f}, write x{w_scale:.3f}",
+        f"k_fused per launch: fetch {fused_fetch / 1e6:.1f} MB, write {fused_write / 1e6:.1f} MB (scaled)",
+    ]
+    if sq:
+        qc = _counters(sq)
+        wave_steps = envs / 64 * K
+        lines += ["", "## SQ counters per launch (and per wave-step of 64 env-steps)"]
+        for (k, c), v in sorted(qc.items()):
+            if k == FUSED:
+                lines.append(f"{c}: {_mean(v):.4g} ({_mean(v) / wave_steps:.1f} per wave-step)")
+    lines += ["", f"machine: traffic_bytes_per_launch={fused_fetch + fused_write:.0f} K={K} envs={envs} "
+                  f"kernel={kernel_source_hash()} avg_ns={st.get(FUSED, {}).get('avg_ns', 0):.0f}"]
+    return "\n".join(lines) + "\n"
+
+
+def traffic_bytes(profile_path: str, K: int, envs: int) -> float | None:
+    """Calibrated HBM bytes per fused launch from a committed summary, or
+    None if it is missing or was taken for another kernel source, K or size."""
+    if not os.path.exists(profile_path):
+        return None
+    for line in open(profile_path):
+        if line.startswith("machine:"):
+            kv = dict(tok.split("=", 1) for tok in line.split()[1:])
+            if kv.get("kernel") == kernel_source_hash() and int(kv["K"]) == K and int(kv["envs"]) == envs:
+                return float(kv["traffic_bytes_per_launch"])
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--sq")
+    ap.add_argument("--copy-bytes", type=int, required=True)
+    ap.add_argument("--K", type=int, required=True)
+    ap.add_argument("--envs", type=int, required=True)
+    ap.add_argument("--command", required=True)
+    ap.add_argument("-o", "--out", required=True)
+    a = ap.parse_args()
+    text = summarize(a.trace, a.fetch, a.write, a.sq, a.copy_bytes, a.K, a.envs, a.command)
+    with open(a.out, "w") as f:
+        f.write(text)
+    print(text)
+
+
+if __name__ == "__main__":
+    main()

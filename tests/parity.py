@@ -8,7 +8,7 @@ import numpy as np
 import oracle as ox
 from paper_2407_19396_amd import workloads as wl
 
-FIELDS = ("grid", "x", "y", "dir", "t", "carry", "episode", "done_prev")
+FIELDS = ("grid", "x", "y", "dir", "t", "carry", "episode", "done_prev", "calls")
 
 
 def ox_batch(table: wl.EnvTable, reward_mode: int = 0) -> ox.Batch:

@@ -1,0 +1,40 @@
+"""HIP graph capture of env_rollout (it allocates and synchronises
+nothing): every replay, with eager work and synchronisations in between,
+equals the same rollout run eagerly."""
+import numpy as np
+import pytest
+
+import parity as P
+from paper_2407_19396_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("K", [16, 64])
+def test_graph_replays_match_eager(K):
+    import torch
+    from paper_2407_19396_amd import gridenv as ge
+    table = wl.mixed_table(3000, seed=3, mix_seed=4)
+    eager = ge.GridEnv(table)
+    eager.reset()
+    tr_e = ge.Traj.alloc(K, table.n)
+    graph = ge.GridEnv(table)
+    graph.reset()
+    tr_g = ge.Traj.alloc(K, table.n)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        graph.rollout(K, tr_g, K=K)
+    noise = torch.zeros(1 << 20, device="cuda")
+    for replay in range(4):
+        eager.rollout(K, tr_e, K=K)
+        g.replay()
+        noise.add_(1.0)                      # eager work between replays
+        torch.cuda.synchronize()
+        for f in ("obs", "reward", "flags", "action"):
+            np.testing.assert_array_equal(P.to_np(getattr(tr_g, f)), P.to_np(getattr(tr_e, f)),
+                                          err_msg=f"replay {replay}: {f}")
+        se, sg = eager.state_numpy(), graph.state_numpy()
+        for f in P.FIELDS:
+            np.testing.assert_array_equal(sg[f], se[f], err_msg=f"replay {replay}: state {f}")
+    assert (eager.state_numpy()["calls"] == 4 * K).all()

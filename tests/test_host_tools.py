@@ -1,0 +1,52 @@
+"""Host-side logic that needs no GPU: launch-shape candidates of the
+autotuner, the profile summary reader, and the workload generators."""
+import numpy as np
+import pytest
+
+from paper_2407_19396_amd import autotune, profiling
+from paper_2407_19396_amd import workloads as wl
+
+
+def test_block_candidates_include_full_occupancy_and_whole_rounds():
+    c = autotune.block_candidates(n_tiles=4096, lds_bytes=18432, cus=256)
+    assert 2048 in c                      # 8 per CU fill the LDS and make exactly 2 rounds
+    assert all(b <= 8 * 256 for b in c)
+    assert 4096 // 3 + 1 in c or 1366 in c
+    c = autotune.block_candidates(n_tiles=10, lds_bytes=18432, cus=256)
+    assert max(c) == 10                   # never more workgroups than tiles
+
+
+def test_traffic_is_read_only_for_the_same_kernel(tmp_path):
+    p = tmp_path / "k.txt"
+    h = profiling.kernel_source_hash()
+    p.write_text(f"# x\nmachine: traffic_bytes_per_launch=123 K=512 envs=262144 kernel={h} avg_ns=1\n")
+    assert profiling.traffic_bytes(str(p), 512, 262144) == 123.0
+    assert profiling.traffic_bytes(str(p), 256, 262144) is None
+    assert profiling.traffic_bytes(str(p), 512, 1000) is None
+    p.write_text("machine: traffic_bytes_per_launch=123 K=512 envs=262144 kernel=0000 avg_ns=1\n")
+    assert profiling.traffic_bytes(str(p), 512, 262144) is None
+    assert profiling.traffic_bytes(str(tmp_path / "missing.txt"), 512, 262144) is None
+
+
+def test_mixed_workload_composition():
+    t = wl.workload_mixed(seed=0)
+    assert t.n == 262144
+    frac = np.bincount(t.family, minlength=3) / t.n
+    assert abs(frac[0] - 0.4) < 0.01 and abs(frac[1] - 0.4) < 0.01 and abs(frac[2] - 0.2) < 0.01
+    assert set(np.unique(t.side[t.family != 2])) == {5, 6, 8, 16}
+    assert set(np.unique(t.side[t.family == 2])) == {19}
+    assert (t.max_steps[t.family == 0] == 4 * t.side[t.family == 0].astype(int) ** 2).all()
+    assert (t.max_steps[t.family == 1] == 10 * t.side[t.family == 1].astype(int) ** 2).all()
+    assert (t.max_steps[t.family == 2] == 100).all()
+
+
+def test_serving_requests_shape():
+    reqs = wl.serving_requests(3000, rate_per_s=1000.0, master_seed=1)
+    n = np.array([r.n_envs for r in reqs])
+    steps = np.array([r.n_steps for r in reqs])
+    arr = np.array([r.arrival_s for r in reqs])
+    assert n.min() >= 1 and n.max() <= 8192 and 700 < n.mean() < 1150   # log-uniform, E ~ 909
+    assert steps.min() >= 64 and steps.max() <= 1024
+    assert (np.diff(arr) > 0).all() and 2.5 < arr[-1] < 3.5            # Poisson at 1000/s
+    assert all(r.table.n == r.n_envs and (r.table.seed == r.seed).all() for r in reqs[:50])
+    assert len({r.seed for r in reqs}) == len(reqs)

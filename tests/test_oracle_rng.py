@@ -61,7 +61,10 @@ def test_policy_rollout_uses_call_index(ox):
     b = ox.Batch(t.family, t.side, t.max_steps, t.seed, t.rng_id)
     s = ox.State.empty(b)
     ox.reset(b, s)
-    out = ox.rollout(b, s, 9, call0=5)
+    assert (s.calls == 0).all()
+    s.calls[:] = 5                    # a state can carry any call count
+    out = ox.rollout(b, s, 9)
+    assert (s.calls == 14).all()
     for k in range(9):
         for i in range(3):
             if out.flags[k, i] & 4:
