@@ -25,6 +25,8 @@ OPEN, CLOSED, LOCKED = 0, 1, 2
 FLAG_TERMINATED, FLAG_TRUNCATED, FLAG_FIRST = 1, 2, 4
 ACTION_NONE = 0xFF
 FAMILY_EMPTY, FAMILY_TWOROOM, FAMILY_FOURROOMS = 0, 1, 2
+FAMILY_LAVAGAP, FAMILY_CROSSINGS, FAMILY_DISTSHIFT = 3, 4, 5
+LAVA = 9
 OBS_BYTES = 147
 
 
@@ -47,7 +49,7 @@ class _Batch(ctypes.Structure):
                 ("family", ctypes.c_void_p), ("side", ctypes.c_void_p),
                 ("max_steps", ctypes.c_void_p), ("seed", ctypes.c_void_p),
                 ("rng_id", ctypes.c_void_p), ("grid_off", ctypes.c_void_p),
-                ("reward_mode", ctypes.c_int32)]
+                ("reward_mode", ctypes.c_int32), ("param", ctypes.c_void_p)]
 
 
 STATE_FIELDS = ("grid", "x", "y", "dir", "t", "carry", "episode", "done_prev", "calls")
@@ -69,10 +71,10 @@ def lib():
         L.ox_uniform.restype = ctypes.c_uint32
         L.ox_policy_action.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64]
         L.ox_policy_action.restype = ctypes.c_uint32
-        L.ox_side_ok.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.ox_side_ok.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.ox_side_ok.restype = ctypes.c_int
-        L.ox_layout.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32,
-                                ctypes.c_uint32, P, P, P, P]
+        L.ox_layout.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                ctypes.c_uint32, ctypes.c_uint32, P, P, P, P]
         L.ox_layout.restype = ctypes.c_int
         L.ox_observe.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                  ctypes.c_int32, P]
@@ -109,15 +111,15 @@ def policy_action(seed: int, rng_id: int, call: int) -> int:
     return int(lib().ox_policy_action(seed, rng_id, call))
 
 
-def side_ok(family: int, side: int) -> bool:
-    return bool(lib().ox_side_ok(family, side))
+def side_ok(family: int, side: int, param: int = 0) -> bool:
+    return bool(lib().ox_side_ok(family, side, param))
 
 
-def layout(family: int, side: int, seed: int, rng_id: int, episode: int):
+def layout(family: int, side: int, seed: int, rng_id: int, episode: int, param: int = 0):
     """Start state of one env: (grid [S][S][3] uint8, x, y, dir)."""
     g = np.zeros((side, side, 3), dtype=np.uint8)
     x, y, d = (ctypes.c_int(), ctypes.c_int(), ctypes.c_int())
-    rc = lib().ox_layout(family, side, seed, rng_id, episode, _ptr(g),
+    rc = lib().ox_layout(family, side, param, seed, rng_id, episode, _ptr(g),
                          ctypes.addressof(x), ctypes.addressof(y), ctypes.addressof(d))
     if rc != 0:
         raise ValueError(f"layout failed ({rc}) for family={family} side={side}")
@@ -149,6 +151,7 @@ class Batch:
     seed: np.ndarray        # u64[N]
     rng_id: np.ndarray      # u32[N]
     reward_mode: int = 0
+    param: np.ndarray | None = None   # u8[N] family parameter (Crossings N, DistShift k)
 
     @property
     def n(self) -> int:
@@ -199,8 +202,10 @@ def _cbatch(b: Batch, keep: list):
             np.ascontiguousarray(b.seed, dtype=np.uint64),
             np.ascontiguousarray(b.rng_id, dtype=np.uint32),
             b.grid_offsets()]
-    keep.extend(arrs)
-    return _Batch(b.n, *[a.ctypes.data for a in arrs], b.reward_mode)
+    param = None if b.param is None else np.ascontiguousarray(b.param, dtype=np.uint8)
+    keep.extend(arrs + [param])
+    return _Batch(b.n, *[a.ctypes.data for a in arrs], b.reward_mode,
+                  None if param is None else param.ctypes.data)
 
 
 def _cstate(s: State):

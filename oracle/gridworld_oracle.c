@@ -24,7 +24,10 @@
  *   - the first-person symbolic observation (Table "observations",
  *     symbolic_first_person, R = 7) with MiniGrid's occlusion rule, since
  *     Sec. 3.2.1 states the environments match MiniGrid exactly;
- *   - the Empty, DoorKey (two rooms) and FourRooms families (Table "envs").
+ *   - the Empty, DoorKey (two rooms) and FourRooms families (Table "envs"),
+ *     and the lava families LavaGap, Crossings and DistShift with the
+ *     goal-or-lava reward R2 of Table "envs" (lava: -1 and termination,
+ *     Tables "rewards" and "terminations", on_lava_fall).
  *
  * Every point the paper leaves open is fixed by a documented reading; the
  * readings are listed next to each function.  Parity status of each
@@ -51,7 +54,8 @@ enum { D_OPEN = 0, D_CLOSED = 1, D_LOCKED = 2 };
 /* actions (MiniGrid order): left, right, forward, pickup, drop, toggle, done */
 enum { A_LEFT = 0, A_RIGHT = 1, A_FORWARD = 2, A_PICKUP = 3, A_DROP = 4,
        A_TOGGLE = 5, A_DONE = 6 };
-enum { FAM_EMPTY = 0, FAM_TWOROOM = 1, FAM_FOURROOMS = 2 };
+enum { FAM_EMPTY = 0, FAM_TWOROOM = 1, FAM_FOURROOMS = 2, FAM_LAVAGAP = 3,
+       FAM_CROSSINGS = 4, FAM_DISTSHIFT = 5 };
 
 #define OX_FLAG_TERMINATED 1u
 #define OX_FLAG_TRUNCATED 2u
@@ -158,13 +162,19 @@ static uint32_t count_empty(const uint8_t *g, int S, int x0, int x1, int y0,
   return n;
 }
 
-/* Side limits of each family. */
-int ox_side_ok(int family, int side) {
+/* Side (and parameter) limits of each family.  The parameter is the
+ * number of lava rivers of Crossings (at most 8 and at most S - 3) and the
+ * variant (1 or 2) of DistShift; the other families ignore it. */
+int ox_side_ok(int family, int side, int param) {
   if (side > 32) return 0;
   switch (family) {
     case FAM_EMPTY: return side >= 4;
     case FAM_TWOROOM: return side >= 5;
     case FAM_FOURROOMS: return side >= 7 && (side % 2) == 1;
+    case FAM_LAVAGAP: return side >= 5;
+    case FAM_CROSSINGS:
+      return side >= 5 && (side % 2) == 1 && param >= 1 && param <= 8 && param <= side - 3;
+    case FAM_DISTSHIFT: return side >= 6 && (param == 1 || param == 2);
   }
   return 0;
 }
@@ -188,13 +198,33 @@ int ox_side_ok(int family, int side) {
 /*   (m, m+1+u(m-1)), (1+u(m-1), m), (m+1+u(m-1), m); goal uniform     */
 /*   over all empty cells, agent uniform over the remaining empty      */
 /*   cells; direction uniform.                                          */
+/* The lava families start the agent at (1, 1) facing east with the    */
+/* goal in a fixed corner, as MiniGrid's versions of them do:          */
+/* LavaGap(S): goal (S-2, S-2); lava column c = 2 + u(S-4), full over  */
+/*   rows 1..S-2 except the gap row 1 + u(S-2).                         */
+/* Crossings(S odd, N rivers): goal (S-2, S-2).  Candidate rivers are  */
+/*   the columns x = 2, 4, .., S-3 then the rows y = 2, 4, .., S-3;     */
+/*   N of them are chosen by a partial Fisher-Yates shuffle (step k    */
+/*   swaps candidate k with candidate k + u(M - k), M = S - 3).  Each   */
+/*   chosen river is a full lava line across the interior.  The rivers */
+/*   cut the interior into a lattice of rooms; a monotone path of room */
+/*   moves from the top-left room to the bottom-right one is drawn one */
+/*   move at a time (east with probability rv / (rv + rh), rv and rh   */
+/*   the columns and rows still to cross: u(rv + rh) < rv), and each   */
+/*   move opens one cell of the river it crosses, uniform along the    */
+/*   current room's side (position drawn right after the move).        */
+/* DistShift(S, k): goal (S-2, 1); lava on rows 1 and r2 (r2 = 2 for   */
+/*   k = 1, S - 2 for k = 2) over columns 3..S-3; no random draws.     */
 /* Pinned by: structural invariants, uniformity tests and the hand     */
 /* layouts in tests; agreement with MiniGrid's own generators: parity  */
 /* unpinned (MiniGrid is not available).                               */
 /* ------------------------------------------------------------------ */
-int ox_layout(int family, int S, uint64_t seed, uint32_t rng_id,
+static void crossings(uint8_t *grid, int S, int N, uint64_t seed,
+                      uint32_t rng_id, uint32_t episode, uint32_t *w);
+
+int ox_layout(int family, int S, int param, uint64_t seed, uint32_t rng_id,
               uint32_t episode, uint8_t *grid, int *ax, int *ay, int *adir) {
-  if (!ox_side_ok(family, S)) return -1;
+  if (!ox_side_ok(family, S, param)) return -1;
   uint32_t w = 0;
 #define DRAW(n) ox_uniform(layout_word(seed, rng_id, episode, w++), (uint32_t)(n))
   for (int y = 0; y < S; ++y)
@@ -222,7 +252,7 @@ int ox_layout(int family, int S, uint64_t seed, uint32_t rng_id,
     n = count_empty(grid, S, 1, c - 1, 1, S - 2);
     if (kth_empty(grid, S, 1, c - 1, 1, S - 2, DRAW(n), ax, ay)) return -2;
     *adir = (int)DRAW(4);
-  } else {
+  } else if (family == FAM_FOURROOMS) {
     int m = S / 2;
     for (int i = 0; i < S; ++i) {
       put(grid, S, m, i, O_WALL, C_GREY, 0);
@@ -243,9 +273,73 @@ int ox_layout(int family, int S, uint64_t seed, uint32_t rng_id,
     n = count_empty(grid, S, 1, S - 2, 1, S - 2);
     if (kth_empty(grid, S, 1, S - 2, 1, S - 2, DRAW(n), ax, ay)) return -2;
     *adir = (int)DRAW(4);
+  } else {
+    *ax = 1; *ay = 1; *adir = 0;
+    if (family == FAM_LAVAGAP) {
+      put(grid, S, S - 2, S - 2, O_GOAL, C_GREEN, 0);
+      int c = 2 + (int)DRAW(S - 4);
+      int gap = 1 + (int)DRAW(S - 2);
+      for (int y = 1; y <= S - 2; ++y)
+        if (y != gap) put(grid, S, c, y, O_LAVA, C_RED, 0);
+    } else if (family == FAM_CROSSINGS) {
+      put(grid, S, S - 2, S - 2, O_GOAL, C_GREEN, 0);
+      crossings(grid, S, param, seed, rng_id, episode, &w);
+    } else {
+      put(grid, S, S - 2, 1, O_GOAL, C_GREEN, 0);
+      int r2 = param == 1 ? 2 : S - 2;
+      for (int x = 3; x <= S - 3; ++x) {
+        put(grid, S, x, 1, O_LAVA, C_RED, 0);
+        put(grid, S, x, r2, O_LAVA, C_RED, 0);
+      }
+    }
   }
 #undef DRAW
   return 0;
+}
+
+/* Crossings(S, N) body: draws continue the layout stream at word *w. */
+static void crossings(uint8_t *grid, int S, int N, uint64_t seed,
+                      uint32_t rng_id, uint32_t episode, uint32_t *w) {
+#define DRAW(n) ox_uniform(layout_word(seed, rng_id, episode, (*w)++), (uint32_t)(n))
+  /* candidates: columns 2, 4, .., S-3 (coded as +x), then rows (coded -y) */
+  int cand[32], M = 0;
+  for (int x = 2; x <= S - 3; x += 2) cand[M++] = x;
+  for (int y = 2; y <= S - 3; y += 2) cand[M++] = -y;
+  for (int k = 0; k < N; ++k) {
+    int r = k + (int)DRAW(M - k);
+    int tmp = cand[k]; cand[k] = cand[r]; cand[r] = tmp;
+  }
+  /* the chosen columns and rows, ascending, framed by the border */
+  int vlim[34], hlim[34], nv = 0, nh = 0;
+  vlim[0] = 0; hlim[0] = 0;
+  for (int v = 1; v <= S - 2; ++v)
+    for (int k = 0; k < N; ++k) {
+      if (cand[k] == v) vlim[++nv] = v;
+      if (cand[k] == -v) hlim[++nh] = v;
+    }
+  vlim[nv + 1] = S - 1; hlim[nh + 1] = S - 1;
+  for (int i = 1; i <= nv; ++i)
+    for (int y = 1; y <= S - 2; ++y) put(grid, S, vlim[i], y, O_LAVA, C_RED, 0);
+  for (int j = 1; j <= nh; ++j)
+    for (int x = 1; x <= S - 2; ++x) put(grid, S, x, hlim[j], O_LAVA, C_RED, 0);
+  /* the path: room (ci, rj) starts at (0, 0) and ends at (nv, nh) */
+  int ci = 0, rj = 0;
+  for (int q = 0; q < N; ++q) {
+    int rv = nv - ci, rh = nh - rj;
+    int east = (int)DRAW(rv + rh) < rv;
+    if (east) {
+      int lo = hlim[rj], hi = hlim[rj + 1];
+      int y = lo + 1 + (int)DRAW(hi - lo - 1);
+      put(grid, S, vlim[ci + 1], y, O_EMPTY, 0, 0);
+      ci += 1;
+    } else {
+      int lo = vlim[ci], hi = vlim[ci + 1];
+      int x = lo + 1 + (int)DRAW(hi - lo - 1);
+      put(grid, S, x, hlim[rj + 1], O_EMPTY, 0, 0);
+      rj += 1;
+    }
+  }
+#undef DRAW
 }
 
 /* ------------------------------------------------------------------ */
@@ -354,15 +448,20 @@ static int is_pickable(int type) {
 /* Otherwise: intervention I(s, a) (turn, forward with collision,     */
 /* pickup, drop, toggle with colour-matched keys; App. A), transition */
 /* (identity for these families), observation O(s'), reward R, and    */
-/* termination (goal reached) plus truncation at t = T.               */
+/* termination (goal reached or lava entered) plus truncation at t = T.*/
+/* Lava (Table "entities") is walked onto like an empty cell and ends  */
+/* the episode with reward -1 (R2 of Table "envs"; on_lava_fall of     */
+/* Tables "rewards" and "terminations"), in both reward modes: the     */
+/* time discount of Eq. (1) applies to the goal reward only.           */
 /* ------------------------------------------------------------------ */
-static void step_one(int family, int S, int32_t T, uint64_t seed,
+static void step_one(int family, int S, int param, int32_t T, uint64_t seed,
                      uint32_t rng_id, int reward_mode, ox_env_ref e,
                      uint32_t action, uint8_t *obs, float *reward,
                      uint8_t *flags, uint8_t *rec_action) {
   if (*e.done_prev) {
     *e.episode += 1u;
-    ox_layout(family, S, seed, rng_id, *e.episode, e.grid, e.x, e.y, e.dir);
+    ox_layout(family, S, param, seed, rng_id, *e.episode, e.grid, e.x, e.y,
+              e.dir);
     *e.t = 0;
     *e.carry = O_EMPTY;
     *e.done_prev = 0;
@@ -375,16 +474,17 @@ static void step_one(int family, int S, int32_t T, uint64_t seed,
   int dir = *e.dir;
   int fx = *e.x + DIR_X[dir], fy = *e.y + DIR_Y[dir];
   uint8_t *front = cell(e.grid, S, fx, fy);
-  int terminated = 0;
+  int terminated = 0, lava = 0;
   switch (action) {
     case A_LEFT: *e.dir = (dir + 3) % 4; break;
     case A_RIGHT: *e.dir = (dir + 1) % 4; break;
     case A_FORWARD: {
       int type = front[0];
-      int walkable = type == O_EMPTY || type == O_GOAL ||
+      int walkable = type == O_EMPTY || type == O_GOAL || type == O_LAVA ||
                      (type == O_DOOR && front[2] == D_OPEN);
       if (walkable) { *e.x = fx; *e.y = fy; }
       if (type == O_GOAL) terminated = 1;
+      if (type == O_LAVA) terminated = lava = 1;
       break;
     }
     case A_PICKUP:
@@ -416,7 +516,8 @@ static void step_one(int family, int S, int32_t T, uint64_t seed,
   }
   *e.t += 1;
   int truncated = *e.t >= T;
-  *reward = terminated ? ox_goal_reward(*e.t, T, reward_mode) : 0.0f;
+  if (lava) *reward = -1.0f;
+  else *reward = terminated ? ox_goal_reward(*e.t, T, reward_mode) : 0.0f;
   *flags = (uint8_t)((terminated ? OX_FLAG_TERMINATED : 0) |
                      (truncated ? OX_FLAG_TRUNCATED : 0));
   *rec_action = (uint8_t)action;
@@ -426,7 +527,7 @@ static void step_one(int family, int S, int32_t T, uint64_t seed,
 
 /* ------------------------------------------------------------------ */
 /* Batch entry points (SoA, host memory).  Per env i:                  */
-/*   family[i], side[i], max_steps[i], seed[i], rng_id[i],            */
+/*   family[i], side[i], param[i], max_steps[i], seed[i], rng_id[i],  */
 /*   grid + grid_off[i] ([side][side][3]),                             */
 /*   x, y, dir, t, carry, episode, done_prev.                          */
 /* Outputs are [N] rows; obs rows are 147 bytes; obs may be NULL.      */
@@ -440,6 +541,7 @@ typedef struct {
   const uint32_t *rng_id;
   const uint64_t *grid_off;
   int32_t reward_mode;
+  const uint8_t *param;   /* per env family parameter, or NULL (all 0) */
 } ox_batch;
 
 typedef struct {
@@ -449,6 +551,8 @@ typedef struct {
   uint8_t *done_prev;
   uint32_t *calls;   /* step calls since reset (the random policy's counter) */
 } ox_state;
+
+#define PARAM(b, i) ((b)->param ? (int)(b)->param[i] : 0)
 
 static ox_env_ref env_ref(const ox_batch *b, const ox_state *s, int i) {
   ox_env_ref e;
@@ -472,14 +576,14 @@ static void set_threads(int nthreads) {
 int ox_reset(const ox_batch *b, const ox_state *s, uint8_t *obs, float *reward,
              uint8_t *flags, uint8_t *action, int nthreads) {
   for (int i = 0; i < b->n; ++i)
-    if (!ox_side_ok(b->family[i], b->side[i])) return -1;
+    if (!ox_side_ok(b->family[i], b->side[i], PARAM(b, i))) return -1;
   set_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 64) if (nthreads > 0)
   for (int i = 0; i < b->n; ++i) {
     ox_env_ref e = env_ref(b, s, i);
     *e.episode = 0;
-    ox_layout(b->family[i], b->side[i], b->seed[i], b->rng_id[i], 0, e.grid,
-              e.x, e.y, e.dir);
+    ox_layout(b->family[i], b->side[i], PARAM(b, i), b->seed[i], b->rng_id[i],
+              0, e.grid, e.x, e.y, e.dir);
     *e.t = 0;
     *e.carry = O_EMPTY;
     *e.done_prev = 0;
@@ -511,8 +615,8 @@ int ox_rollout(const ox_batch *b, const ox_state *s, int32_t n_steps,
       uint32_t a;
       if (actions) a = actions[(size_t)k * N + i];
       else a = ox_policy_action(b->seed[i], b->rng_id[i], *e.calls);
-      step_one(b->family[i], b->side[i], b->max_steps[i], b->seed[i],
-               b->rng_id[i], b->reward_mode, e, a,
+      step_one(b->family[i], b->side[i], PARAM(b, i), b->max_steps[i],
+               b->seed[i], b->rng_id[i], b->reward_mode, e, a,
                obs ? obs + 147 * (row * N + i) : NULL, reward + row * N + i,
                flags + row * N + i, action + row * N + i);
       *e.calls += 1u;

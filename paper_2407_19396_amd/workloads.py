@@ -7,8 +7,9 @@ streams.  It holds none of the environment dynamics, so both sides of a
 parity check can use it without sharing any of the method's arithmetic.
 
 The workloads stand in for the paper's MiniGrid tasks (NAVIX, Table
-"envs": Empty-5x5 / 8x8 / 16x16, DoorKey-5x5 ... 16x16, FourRooms), which
-are generated procedurally, so no dataset is involved.
+"envs": Empty-5x5 / 8x8 / 16x16, DoorKey-5x5 ... 16x16, FourRooms, and the
+lava tasks LavaGap-S5/6/7, Crossings-S9N1/2/3 and S11N5, DistShift1/2),
+which are generated procedurally, so no dataset is involved.
 """
 from __future__ import annotations
 
@@ -17,18 +18,21 @@ from dataclasses import dataclass
 import numpy as np
 
 FAMILY_EMPTY, FAMILY_TWOROOM, FAMILY_FOURROOMS = 0, 1, 2
-FAMILY_NAMES = {FAMILY_EMPTY: "Empty", FAMILY_TWOROOM: "TwoRoom", FAMILY_FOURROOMS: "FourRooms"}
+FAMILY_LAVAGAP, FAMILY_CROSSINGS, FAMILY_DISTSHIFT = 3, 4, 5
+FAMILY_NAMES = {FAMILY_EMPTY: "Empty", FAMILY_TWOROOM: "TwoRoom", FAMILY_FOURROOMS: "FourRooms",
+                FAMILY_LAVAGAP: "LavaGap", FAMILY_CROSSINGS: "Crossings",
+                FAMILY_DISTSHIFT: "DistShift"}
 N_ACTIONS = 7
 
 
 def default_max_steps(family: int, side: int) -> int:
-    """MiniGrid's default step limits for each family: 4*S^2 (Empty),
-    10*S^2 (DoorKey), 100 (FourRooms)."""
-    if family == FAMILY_EMPTY:
-        return 4 * side * side
+    """MiniGrid's default step limits for each family: 4*S^2 (Empty and
+    the lava families), 10*S^2 (DoorKey), 100 (FourRooms)."""
     if family == FAMILY_TWOROOM:
         return 10 * side * side
-    return 100
+    if family == FAMILY_FOURROOMS:
+        return 100
+    return 4 * side * side
 
 
 @dataclass
@@ -40,6 +44,11 @@ class EnvTable:
     seed: np.ndarray       # u64[N]
     rng_id: np.ndarray     # u32[N]
     name: str = ""
+    param: np.ndarray | None = None   # u8[N]: Crossings rivers, DistShift variant (else 0)
+
+    def __post_init__(self):
+        if self.param is None:
+            self.param = np.zeros(self.family.shape[0], dtype=np.uint8)
 
     @property
     def n(self) -> int:
@@ -48,10 +57,11 @@ class EnvTable:
     def subset(self, idx) -> "EnvTable":
         idx = np.asarray(idx)
         return EnvTable(self.family[idx].copy(), self.side[idx].copy(), self.max_steps[idx].copy(),
-                        self.seed[idx].copy(), self.rng_id[idx].copy(), self.name + "[subset]")
+                        self.seed[idx].copy(), self.rng_id[idx].copy(), self.name + "[subset]",
+                        self.param[idx].copy())
 
 
-def _table(family, side, seed: int, name: str, max_steps=None) -> EnvTable:
+def _table(family, side, seed: int, name: str, max_steps=None, param=0) -> EnvTable:
     family = np.asarray(family, dtype=np.uint8)
     side = np.asarray(side, dtype=np.uint8)
     n = family.shape[0]
@@ -60,14 +70,30 @@ def _table(family, side, seed: int, name: str, max_steps=None) -> EnvTable:
                              dtype=np.int32)
     else:
         max_steps = np.broadcast_to(np.asarray(max_steps, dtype=np.int32), (n,)).copy()
+    param = np.broadcast_to(np.asarray(param, dtype=np.uint8), (n,)).copy()
     return EnvTable(family, side, max_steps, np.full(n, seed, dtype=np.uint64),
-                    np.arange(n, dtype=np.uint32), name)
+                    np.arange(n, dtype=np.uint32), name, param)
 
 
-def uniform_table(n: int, family: int, side: int, seed: int = 0, max_steps=None) -> EnvTable:
-    """n envs of one family and side."""
+def uniform_table(n: int, family: int, side: int, seed: int = 0, max_steps=None,
+                  param: int = 0) -> EnvTable:
+    """n envs of one family, side and family parameter."""
     return _table(np.full(n, family), np.full(n, side), seed,
-                  f"{FAMILY_NAMES[family]}-{side}x{side} x{n}", max_steps)
+                  f"{FAMILY_NAMES[family]}-{side}x{side}/{param} x{n}", max_steps, param)
+
+
+# the lava tasks of the paper's environment table: (family, side, param)
+LAVA_TASKS = [(FAMILY_LAVAGAP, 5, 0), (FAMILY_LAVAGAP, 6, 0), (FAMILY_LAVAGAP, 7, 0),
+              (FAMILY_CROSSINGS, 9, 1), (FAMILY_CROSSINGS, 9, 2), (FAMILY_CROSSINGS, 9, 3),
+              (FAMILY_CROSSINGS, 11, 5), (FAMILY_DISTSHIFT, 6, 1), (FAMILY_DISTSHIFT, 8, 2)]
+
+
+def lava_table(n: int, seed: int = 0, mix_seed: int = 54321) -> EnvTable:
+    """The lava tasks in equal shares, drawn i.i.d. per env from a seeded
+    generator."""
+    rng = np.random.default_rng(mix_seed)
+    pick = np.array(LAVA_TASKS)[rng.integers(0, len(LAVA_TASKS), n)]
+    return _table(pick[:, 0], pick[:, 1], seed, f"lava x{n}", None, pick[:, 2])
 
 
 def mixed_table(n: int, seed: int = 0, mix_seed: int = 12345) -> EnvTable:
@@ -103,7 +129,12 @@ def workload_mixed(seed: int = 0, n: int = 262144) -> EnvTable:
     return mixed_table(n, seed)
 
 
-WORKLOAD_STEPS = {"empty5": 100, "empty8": 1000, "tworoom8": 2048, "mixed": 4096}
+def workload_lava(seed: int = 0, n: int = 262144) -> EnvTable:
+    """262144 envs of the lava tasks (fused persistent launch, 4096 steps)."""
+    return lava_table(n, seed)
+
+
+WORKLOAD_STEPS = {"empty5": 100, "empty8": 1000, "tworoom8": 2048, "mixed": 4096, "lava": 4096}
 
 
 def random_actions(n_steps: int, n_envs: int, seed: int) -> np.ndarray:

@@ -5,14 +5,14 @@ from __future__ import annotations
 
 import numpy as np
 
-EMPTY, WALL, DOOR, KEY, GOAL = 1, 2, 4, 5, 8
+EMPTY, WALL, DOOR, KEY, GOAL, LAVA = 1, 2, 4, 5, 8, 9
 COLOURS = {"r": 0, "g": 1, "b": 2, "p": 3, "y": 4, "e": 5}
 DIRS = {">": 0, "v": 1, "<": 2, "^": 3}
 
 
 def parse(picture: str):
     """Grid [S][S][3] from rows of space-separated tokens:
-    ``#`` wall, ``.`` empty, ``G`` goal, ``K<c>`` key of colour c,
+    ``#`` wall, ``.`` empty, ``G`` goal, ``~`` lava, ``K<c>`` key of colour c,
     ``D<c><s>`` door of colour c in state s (0 open, 1 closed, 2 locked),
     ``> v < ^`` the agent (on an empty cell) facing east/south/west/north.
     Returns (grid, x, y, dir); x, y, dir are None without an agent."""
@@ -29,6 +29,8 @@ def parse(picture: str):
                 g[y, x] = (EMPTY, 0, 0)
             elif tok == "G":
                 g[y, x] = (GOAL, 1, 0)
+            elif tok == "~":
+                g[y, x] = (LAVA, 0, 0)
             elif tok[0] == "K":
                 g[y, x] = (KEY, COLOURS[tok[1]], 0)
             elif tok[0] == "D":
@@ -57,12 +59,13 @@ def rotate_world(grid: np.ndarray, x: int, y: int, d: int):
 
 
 def one_env(ox, picture: str, carry: int = EMPTY, t: int = 0, T: int = 100, family: int = 1,
-            seed: int = 0, episode: int = 0, reward_mode: int = 0):
+            seed: int = 0, episode: int = 0, reward_mode: int = 0, param: int = 0):
     """A single-env oracle batch whose state is the given picture."""
     g, x, y, d = parse(picture)
     S = g.shape[0]
     b = ox.Batch(np.array([family], np.uint8), np.array([S], np.uint8), np.array([T], np.int32),
-                 np.array([seed], np.uint64), np.array([0], np.uint32), reward_mode)
+                 np.array([seed], np.uint64), np.array([0], np.uint32), reward_mode,
+                 np.array([param], np.uint8))
     s = ox.State(g.reshape(-1).copy(), np.array([x], np.int32), np.array([y], np.int32),
                  np.array([d], np.int32), np.array([t], np.int32), np.array([carry], np.int32),
                  np.array([episode], np.uint32), np.array([0], np.uint8))
@@ -71,3 +74,21 @@ def one_env(ox, picture: str, carry: int = EMPTY, t: int = 0, T: int = 100, fami
 
 def grid_of(state, S: int, off: int = 0) -> np.ndarray:
     return state.grid[off:off + 3 * S * S].reshape(S, S, 3)
+
+
+def reachable(grid: np.ndarray, start, goal) -> bool:
+    """Breadth-first search over cells that are neither wall nor lava."""
+    S = grid.shape[0]
+    seen = {start}
+    todo = [start]
+    while todo:
+        x, y = todo.pop()
+        if (x, y) == goal:
+            return True
+        for dx, dy in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+            nx, ny = x + dx, y + dy
+            if 0 <= nx < S and 0 <= ny < S and (nx, ny) not in seen and \
+                    grid[ny, nx, 0] not in (WALL, LAVA):
+                seen.add((nx, ny))
+                todo.append((nx, ny))
+    return False
