@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 OBS = 147
 RECORD_BYTES = OBS + 4 + 1 + 1          # obs + reward + flags + action per env-step
-STATE_BYTES_PER_ENV = 4 * 5 + 4 + 1      # x, y, dir, t, carry + episode + done_prev
+STATE_BYTES_PER_ENV = 4 * 5 + 4 + 1 + 4  # x, y, dir, t, carry + episode + done_prev + calls
 
 
 WORKLOADS = {
@@ -37,6 +37,8 @@ WORKLOADS = {
     "tworoom8": "65536 TwoRoom key/door 8x8, T=640, random policy on device, trajectory ring in HBM",
     "empty8": "4096 Empty 8x8, T=256, random policy on device, trajectory ring in HBM",
     "empty5": "16 Empty 5x5, T=100, random policy on device, trajectory ring in HBM",
+    "lava": "lava tasks: 262144 envs in equal shares of LavaGap S5/S6/S7, Crossings S9N1/S9N2/S9N3/"
+            "S11N5, DistShift1 (6x6), DistShift2 (8x8), random policy on device, trajectory ring in HBM",
 }
 
 
@@ -54,7 +56,7 @@ def cpu_baseline(table, n_envs: int, n_steps: int) -> dict:
     import oracle as ox
     from paper_2407_19396_amd import workloads as wl
     sub = table.subset(np.arange(n_envs))
-    b = ox.Batch(sub.family, sub.side, sub.max_steps, sub.seed, sub.rng_id)
+    b = ox.Batch(sub.family, sub.side, sub.max_steps, sub.seed, sub.rng_id, 0, sub.param)
     s = ox.State.empty(b)
     threads = os.cpu_count() or 1
     try:
@@ -110,7 +112,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4096, help="timed environment steps of the batch")
     ap.add_argument("--warmup", type=int, default=256)
-    ap.add_argument("--workload", default="mixed", choices=["mixed", "tworoom8", "empty8", "empty5"])
+    ap.add_argument("--workload", default="mixed", choices=sorted(WORKLOADS))
     ap.add_argument("--envs", type=int, default=0, help="override the workload's env count")
     ap.add_argument("--K", type=int, default=0, help="steps fused per launch (0: autotune)")
     ap.add_argument("--blocks", type=int, default=0, help="persistent workgroups (0: autotune or default)")
@@ -151,9 +153,10 @@ def main():
     make = {"mixed": lambda: wl.workload_mixed(seed=0, n=args.envs or 262144),
             "tworoom8": lambda: wl.workload_tworoom8(seed=0),
             "empty8": lambda: wl.workload_empty8(seed=0),
-            "empty5": lambda: wl.workload_empty5(seed=0)}[args.workload]
+            "empty5": lambda: wl.workload_empty5(seed=0),
+            "lava": lambda: wl.workload_lava(seed=0, n=args.envs or 262144)}[args.workload]
     table = make()
-    if args.envs and args.workload != "mixed":
+    if args.envs and args.workload not in ("mixed", "lava"):
         table = table.subset(np.arange(args.envs) % table.n)
     env = ge.GridEnv(table)
     first = ge.Traj.alloc(1, table.n)

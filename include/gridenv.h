@@ -11,7 +11,11 @@
  * the action with -1 and the reward with 0.  Inside a step the systems of
  * Table "systems" (App. A) apply in order: intervention (the action),
  * transition (identity for these families), observation, reward,
- * termination.
+ * termination.  The families are those of Table "envs" with a static
+ * world: Empty, DoorKey, FourRooms (reward R1) and the lava families
+ * LavaGap, Crossings, DistShift (reward R2).  An episode terminates on
+ * reaching the goal or walking into lava (Tables "rewards" and
+ * "terminations": on_goal_reached, on_lava_fall).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -37,14 +41,14 @@
  * Encoding (MiniGrid's canonical indices; Table "components": Tag, Colour,
  * State; Table "observations": symbolic encodings)
  *   cell triple (type, colour, state): type 0 unseen, 1 empty, 2 wall,
- *   4 door, 5 key, 8 goal; colour 0 red, 1 green, 2 blue, 3 purple,
- *   4 yellow, 5 grey; door state 0 open, 1 closed, 2 locked.
+ *   4 door, 5 key, 8 goal, 9 lava; colour 0 red, 1 green, 2 blue,
+ *   3 purple, 4 yellow, 5 grey; door state 0 open, 1 closed, 2 locked.
  *   Walls are (2,5,0), empty cells (1,0,0), the goal (8,1,0), keys (5,c,0),
- *   doors (4,c,s).
+ *   doors (4,c,s), lava (9,0,0).
  *   actions: 0 turn left, 1 turn right, 2 forward, 3 pickup, 4 drop,
  *   5 toggle, 6 done; any other value acts as 6 (no effect).
  *   heading: 0 east (+x), 1 south (+y), 2 west (-x), 3 north (-y).
- *   flags bits: 1 terminated (goal reached), 2 truncated (t reached T),
+ *   flags bits: 1 terminated (goal or lava reached), 2 truncated (t reached T),
  *   4 first step of an episode (reset).
  *   carry: packed triple type | colour << 8 | state << 16 of the held
  *   object; an empty hand is 1 (the triple (1,0,0)).
@@ -77,15 +81,21 @@ extern "C" {
 #endif
 
 #define GX_OK 0
-#define GX_EINVAL -1   /* invalid argument: NULL pointer, bad size, family or side */
+#define GX_EINVAL -1   /* invalid argument: NULL pointer, bad size, family, side or param */
 #define GX_ENOMEM -2   /* the context's host or device tables could not be allocated */
 #define GX_EDEVICE -3  /* a HIP call failed, or earlier GPU work faulted */
 #define GX_ESTATE -4   /* call order violated (e.g. a step before any reset) */
 #define GX_EBUSY -5    /* a server has no free tiles for the request right now */
 
+/* Families (Table "envs").  The lava families start the agent at (1, 1)
+ * facing east; walking into lava gives reward -1 in both reward modes. */
 #define GX_FAMILY_EMPTY 0      /* Empty-SxS (single room), side 4..32 */
 #define GX_FAMILY_TWOROOM 1    /* DoorKey-SxS (two rooms, locked door), side 5..32 */
 #define GX_FAMILY_FOURROOMS 2  /* FourRooms, odd side 7..31 */
+#define GX_FAMILY_LAVAGAP 3    /* LavaGap-SS: a lava column with one gap, side 5..32 */
+#define GX_FAMILY_CROSSINGS 4  /* Crossings-SSNN: param = N lava rivers, 1..min(8, S-3),
+                                  odd side 5..31 */
+#define GX_FAMILY_DISTSHIFT 5  /* DistShift: param = variant 1 or 2, side 6..32 */
 
 #define GX_OBS_BYTES 147
 
@@ -100,6 +110,7 @@ typedef struct {
                                   reward) */
   const uint8_t* family;       /* [n_envs] GX_FAMILY_* */
   const uint8_t* side;         /* [n_envs] grid side S (height = width) */
+  const uint8_t* param;        /* [n_envs] family parameter, or NULL: all 0 */
   const int32_t* max_steps;    /* [n_envs] truncation limit T >= 1 */
   const uint64_t* seed;        /* [n_envs] RNG key per env, or NULL: seed_all */
   uint64_t seed_all;
@@ -204,6 +215,7 @@ typedef struct {
   uint64_t seed;               /* key of every env of the request */
   const uint8_t* family;       /* host [n_envs], read during env_server_admit */
   const uint8_t* side;         /* host [n_envs], <= the server's max_side */
+  const uint8_t* param;        /* host [n_envs] family parameter, or NULL: all 0 */
   const int32_t* max_steps;    /* host [n_envs] */
   uint8_t* obs;                /* device [n_steps][stride][147], or NULL */
   float* reward;               /* device [n_steps][stride] */
@@ -243,7 +255,8 @@ int env_server_info(const gx_server* srv, gx_server_info* info);
 int env_server_destroy(gx_server* srv);
 
 /* A request of a serving run: its arrival time and its envs' configuration
- * at index env_offset of the run's family / side / max_steps arrays. */
+ * at index env_offset of the run's family / side / param / max_steps arrays
+ * (param may be NULL: all 0). */
 typedef struct {
   double arrival_s;            /* seconds from the start of the run, non-decreasing */
   int32_t n_envs, n_steps;
@@ -278,8 +291,9 @@ typedef struct {
  * reused.  admit_s / done_s [n_items] receive admission and completion
  * times (seconds from the start); latency = done_s - arrival_s. */
 int env_serve_run(gx_server* srv, const gx_serve_item* items, int32_t n_items,
-                  const uint8_t* family, const uint8_t* side, const int32_t* max_steps,
-                  const gx_serve_opts* opts, void* stream, double* admit_s, double* done_s,
+                  const uint8_t* family, const uint8_t* side, const uint8_t* param,
+                  const int32_t* max_steps, const gx_serve_opts* opts, void* stream,
+                  double* admit_s, double* done_s,
                   gx_serve_stats* stats);
 
 /* Static text for a status code. */

@@ -36,7 +36,8 @@ constexpr int kObsWords = 37;                       // ceil(147 / 4)
 
 // Cell triples are packed as type | colour << 8 | state << 16 (MiniGrid's
 // object, colour and state indices).  Bit 31 marks a see-through cell.
-constexpr uint32_t kEmpty = 1, kWall = 2, kDoor = 4, kKey = 5, kBall = 6, kBox = 7, kGoal = 8;
+constexpr uint32_t kEmpty = 1, kWall = 2, kDoor = 4, kKey = 5, kBall = 6, kBox = 7, kGoal = 8,
+                   kLava = 9;
 constexpr uint32_t kGreen = 1, kGrey = 5;
 constexpr uint32_t kOpen = 0, kClosed = 1, kLocked = 2;
 constexpr uint32_t kSeeBit = 1u << 31;
@@ -48,7 +49,10 @@ constexpr uint32_t kFlagTerminated = 1, kFlagTruncated = 2, kFlagFirst = 4;
 constexpr uint32_t kActionNone = 0xFF;
 
 enum : uint32_t { kLeft = 0, kRight = 1, kForward = 2, kPickup = 3, kDrop = 4, kToggle = 5 };
-enum : uint32_t { kFamEmpty = 0, kFamTwoRoom = 1, kFamFourRooms = 2 };
+enum : uint32_t {
+  kFamEmpty = 0, kFamTwoRoom = 1, kFamFourRooms = 2,
+  kFamLavaGap = 3, kFamCrossings = 4, kFamDistShift = 5
+};
 
 __device__ __forceinline__ uint32_t see_through(uint32_t tri) {
   const uint32_t type = tri & 0xFF, state = (tri >> 16) & 0xFF;
@@ -103,12 +107,105 @@ __device__ __forceinline__ uint4 policy_block(uint2 seed, uint32_t rng_id, uint3
 // ---------------------------------------------------------------------------
 struct Layout {
   int fam, S;
-  int a, b, c, d;      // TwoRoom: a = wall column, b = door row; FourRooms: the 4 openings
+  int a, b, c, d;      // TwoRoom: a = wall column, b = door row; FourRooms: the 4 openings;
+                       // LavaGap: a = lava column, b = gap row; DistShift: a = second lava row
   int colour;          // TwoRoom door / key colour
   int kx, ky;          // TwoRoom key
   int gx, gy;          // goal
   int ax, ay, dir;     // agent
+  uint32_t vmask, hmask;   // Crossings: river columns / rows (bit = coordinate)
+  uint64_t vopen, hopen;   // Crossings: opening row of each river column, opening column
+                           // of each river row, 5 bits each in ascending river order
 };
+
+// Layout-stream draws taken in order, one Philox block per 4 words.
+struct DrawStream {
+  uint2 seed;
+  uint32_t id, episode, w;
+  uint4 block;
+  __device__ __forceinline__ uint32_t next(uint32_t n) {
+    if ((w & 3u) == 0) block = philox10(make_uint4(id, episode, w >> 2, 0u), seed);
+    const uint32_t r = bounded(pick4(block, w & 3u), n);
+    ++w;
+    return r;
+  }
+};
+
+// position of the k-th (0-based) set bit of m
+__device__ __forceinline__ int kth_bit(uint32_t m, int k) {
+  for (int i = 0; i < k; ++i) m &= m - 1u;
+  return __builtin_ctz(m);
+}
+
+// Crossings(S, N): N of the M = S - 3 candidate rivers (columns 2, 4, ..,
+// S - 3, then rows 2, 4, .., S - 3) by a partial Fisher-Yates shuffle, then
+// a monotone path of room moves, each opening one cell of the river it
+// crosses (Table "envs", Crossings; lava of Table "entities").  The shuffle
+// keeps only the positions it touched: entry k records that position
+// mkey[k] now holds candidate mval[k].
+constexpr int kMaxRivers = 8;
+
+struct Rivers {
+  uint32_t vmask, hmask;
+  uint64_t vopen, hopen;
+};
+
+__device__ __noinline__ Rivers crossings_layout(int S, int N, uint2 seed, uint32_t rng_id,
+                                                uint32_t episode) {
+  DrawStream ds{seed, rng_id, episode, 0u, make_uint4(0, 0, 0, 0)};
+  const int M = S - 3, h = M / 2;
+  int mkey[kMaxRivers], mval[kMaxRivers];
+  Rivers R{0u, 0u, 0ull, 0ull};
+#pragma unroll
+  for (int k = 0; k < kMaxRivers; ++k) {
+    if (k < N) {
+      const int r = k + (int)ds.next((uint32_t)(M - k));
+      int vk = k, vr = r;
+#pragma unroll
+      for (int j = 0; j < k; ++j) {
+        vk = mkey[j] == k ? mval[j] : vk;
+        vr = mkey[j] == r ? mval[j] : vr;
+      }
+      mkey[k] = r;
+      mval[k] = vk;
+      if (vr < h) R.vmask |= 1u << (2 + 2 * vr);
+      else R.hmask |= 1u << (2 + 2 * (vr - h));
+    }
+  }
+  const int nv = __builtin_popcount(R.vmask), nh = __builtin_popcount(R.hmask);
+  int ci = 0, rj = 0;
+  for (int q = 0; q < N; ++q) {
+    const int rv = nv - ci, rh = nh - rj;
+    if ((int)ds.next((uint32_t)(rv + rh)) < rv) {
+      const int lo = rj == 0 ? 0 : kth_bit(R.hmask, rj - 1);
+      const int hi = rj == nh ? S - 1 : kth_bit(R.hmask, rj);
+      const uint64_t y = (uint64_t)(lo + 1 + (int)ds.next((uint32_t)(hi - lo - 1)));
+      R.vopen |= y << (5 * ci);
+      ++ci;
+    } else {
+      const int lo = ci == 0 ? 0 : kth_bit(R.vmask, ci - 1);
+      const int hi = ci == nv ? S - 1 : kth_bit(R.vmask, ci);
+      const uint64_t x = (uint64_t)(lo + 1 + (int)ds.next((uint32_t)(hi - lo - 1)));
+      R.hopen |= x << (5 * rj);
+      ++rj;
+    }
+  }
+  return R;
+}
+
+// whether interior cell (x, y) of a Crossings layout is lava
+__device__ __forceinline__ bool crossings_lava(const Layout& L, int x, int y) {
+  bool lava = false;
+  if ((L.vmask >> x) & 1u) {
+    const int rank = __builtin_popcount(L.vmask & ((1u << x) - 1u));
+    lava = y != (int)((L.vopen >> (5 * rank)) & 31u);
+  }
+  if ((L.hmask >> y) & 1u) {
+    const int rank = __builtin_popcount(L.hmask & ((1u << y) - 1u));
+    lava = lava || x != (int)((L.hopen >> (5 * rank)) & 31u);
+  }
+  return lava;
+}
 
 __device__ __forceinline__ void fourrooms_cell(int S, int m, int g1, int g2, int g3, int g4,
                                                uint32_t idx, int& x, int& y) {
@@ -134,9 +231,11 @@ __device__ __forceinline__ void fourrooms_cell(int S, int m, int g1, int g2, int
   x = 1;
 }
 
-__device__ Layout make_layout(uint32_t fam, int S, uint2 seed, uint32_t rng_id, uint32_t episode) {
-  const uint4 w0 = philox10(make_uint4(rng_id, episode, 0u, 0u), seed);
-  const uint4 w1 = philox10(make_uint4(rng_id, episode, 1u, 0u), seed);
+// meta = family | side << 8 | parameter << 16 (Crossings: rivers; DistShift:
+// variant).  The lava families start at (1, 1) facing east.
+__device__ Layout make_layout(uint32_t meta, uint2 seed, uint32_t rng_id, uint32_t episode) {
+  const uint32_t fam = meta & 0xFF;
+  const int S = (int)((meta >> 8) & 0xFF), param = (int)((meta >> 16) & 0xFF);
   Layout L;
   L.fam = (int)fam;
   L.S = S;
@@ -145,6 +244,29 @@ __device__ Layout make_layout(uint32_t fam, int S, uint2 seed, uint32_t rng_id, 
   L.kx = L.ky = -1;
   L.gx = S - 2;
   L.gy = S - 2;
+  L.vmask = L.hmask = 0;
+  L.vopen = L.hopen = 0;
+  if (fam >= kFamLavaGap) {
+    L.ax = L.ay = 1;
+    L.dir = 0;
+    if (fam == kFamLavaGap) {
+      const uint4 w0 = philox10(make_uint4(rng_id, episode, 0u, 0u), seed);
+      L.a = 2 + (int)bounded(w0.x, (uint32_t)(S - 4));
+      L.b = 1 + (int)bounded(w0.y, (uint32_t)(S - 2));
+    } else if (fam == kFamCrossings) {
+      const Rivers R = crossings_layout(S, param, seed, rng_id, episode);
+      L.vmask = R.vmask;
+      L.hmask = R.hmask;
+      L.vopen = R.vopen;
+      L.hopen = R.hopen;
+    } else {
+      L.gy = 1;
+      L.a = param == 1 ? 2 : S - 2;
+    }
+    return L;
+  }
+  const uint4 w0 = philox10(make_uint4(rng_id, episode, 0u, 0u), seed);
+  const uint4 w1 = philox10(make_uint4(rng_id, episode, 1u, 0u), seed);
   if (fam == kFamEmpty) {
     const int w = S - 2;
     const uint32_t k = bounded(w0.x, (uint32_t)(w * w - 1));   // interior minus the last (goal) cell
@@ -193,6 +315,12 @@ __device__ __forceinline__ uint32_t layout_cell(const Layout& L, int x, int y) {
     const int m = S / 2;
     if (x == m) return (y == L.a || y == L.b) ? kCellEmpty : kCellWall;
     if (y == m) return (x == L.c || x == L.d) ? kCellEmpty : kCellWall;
+  } else if (L.fam == kFamLavaGap) {
+    if (x == L.a && y != L.b) return kLava;
+  } else if (L.fam == kFamCrossings) {
+    if (crossings_lava(L, x, y)) return kLava;
+  } else if (L.fam == kFamDistShift) {
+    if ((y == 1 || y == L.a) && x >= 3 && x <= S - 3) return kLava;
   }
   return kCellEmpty;
 }
@@ -207,6 +335,12 @@ __device__ __forceinline__ Layout bcast_layout(const Layout& L, int r) {
   o.kx = bcast(L.kx, r); o.ky = bcast(L.ky, r);
   o.gx = bcast(L.gx, r); o.gy = bcast(L.gy, r);
   o.ax = o.ay = o.dir = 0;
+  o.vmask = (uint32_t)bcast((int)L.vmask, r);
+  o.hmask = (uint32_t)bcast((int)L.hmask, r);
+  o.vopen = (uint64_t)(uint32_t)bcast((int)(uint32_t)L.vopen, r) |
+            ((uint64_t)(uint32_t)bcast((int)(L.vopen >> 32), r) << 32);
+  o.hopen = (uint64_t)(uint32_t)bcast((int)(uint32_t)L.hopen, r) |
+            ((uint64_t)(uint32_t)bcast((int)(L.hopen >> 32), r) << 32);
   return o;
 }
 
@@ -218,6 +352,7 @@ struct ActResult {
   uint32_t new_front;
   bool front_changed;
   bool terminated;
+  bool lava;   // terminated by walking into lava
 };
 
 __device__ __forceinline__ ActResult intervene(uint32_t act, int& x, int& y, int& dir, uint32_t& carry,
@@ -227,8 +362,8 @@ __device__ __forceinline__ ActResult intervene(uint32_t act, int& x, int& y, int
   const uint32_t type = front & 0xFF, colour = (front >> 8) & 0xFF, state = (front >> 16) & 0xFF;
   const uint32_t front24 = front & 0xFFFFFFu;
   dir = (dir + (act == kLeft ? 3 : (act == kRight ? 1 : 0))) & 3;
-  const bool walk = act == kForward &&
-                    (type == kEmpty || type == kGoal || (type == kDoor && state == kOpen));
+  const bool walk = act == kForward && (type == kEmpty || type == kGoal || type == kLava ||
+                                        (type == kDoor && state == kOpen));
   x = walk ? fx : x;
   y = walk ? fy : y;
   const bool pick = act == kPickup && carry == kCellEmpty && (type == kKey || type == kBall || type == kBox);
@@ -241,7 +376,8 @@ __device__ __forceinline__ ActResult intervene(uint32_t act, int& x, int& y, int
   ActResult r;
   r.new_front = pick ? kCellEmpty : (drop ? carry : (unlock ? door_open : (flip ? door_flipped : front24)));
   r.front_changed = pick || drop || unlock || flip;
-  r.terminated = act == kForward && type == kGoal;
+  r.lava = act == kForward && type == kLava;
+  r.terminated = (act == kForward && type == kGoal) || r.lava;
   carry = pick ? front24 : (drop ? kCellEmpty : carry);
   return r;
 }
@@ -253,6 +389,12 @@ __device__ __forceinline__ float goal_reward(int32_t t, int32_t T, int32_t mode)
   const float q = __fdiv_rn((float)t, (float)T);
   const float p = __fmul_rn(0.9f, q);
   return __fsub_rn(1.0f, p);
+}
+
+// Reward of a step: -1 for walking into lava (R2 of Table "envs", in both
+// modes), the goal reward on reaching the goal, else 0.
+__device__ __forceinline__ float step_reward(const ActResult& r, int32_t t, int32_t T, int32_t mode) {
+  return r.lava ? -1.0f : (r.terminated ? goal_reward(t, T, mode) : 0.0f);
 }
 
 // ---------------------------------------------------------------------------
@@ -427,14 +569,14 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
   const bool active = e < N;
   const int n_here = min(kWave, N - e0);
 
-  uint32_t fam = 0;
+  uint32_t fam = 0, meta = 0;
   int S = 5, T = 1, x = 1, y = 1, dir = 0, t = 0;
   uint32_t carry = kCellEmpty, episode = 0, rid = 0, calls = 0;
   bool done_prev = false;
   uint2 seed = make_uint2(0, 0);
   uint8_t* g = a.st.grid;
   if (active) {
-    const uint32_t meta = a.env.meta[e];
+    meta = a.env.meta[e];
     fam = meta & 0xFF;
     S = (int)((meta >> 8) & 0xFF);
     T = a.env.max_steps[e];
@@ -456,7 +598,7 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
   Layout L{};
   if (do_reset) {
     episode = a.reset_all ? 0u : episode + 1u;
-    L = make_layout(fam, S, seed, rid, episode);
+    L = make_layout(meta, seed, rid, episode);
     x = L.ax;
     y = L.ay;
     dir = L.dir;
@@ -495,7 +637,7 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
     if (r.front_changed) store_triple(g + 3 * (fy * S + fx), r.new_front);
     t += 1;
     const bool trunc = t >= T;
-    reward = r.terminated ? goal_reward(t, T, a.env.reward_mode) : 0.0f;
+    reward = step_reward(r, t, T, a.env.reward_mode);
     flags = (r.terminated ? kFlagTerminated : 0u) | (trunc ? kFlagTruncated : 0u);
     done_prev = r.terminated || trunc;
     act_rec = act & 0xFF;
@@ -570,10 +712,10 @@ __device__ __forceinline__ uint32_t triple_of_kind(uint32_t kind) {
 constexpr int kKinds = 64;
 
 // code of cell (x, y) of a freshly generated layout (grey walls, green
-// goal, key and locked door of the layout's colour); equals
+// goal, key and locked door of the layout's colour, red lava); equals
 // code_of(layout_cell(L, x, y)) without the general switch
 __device__ __forceinline__ uint32_t layout_code(const Layout& L, int x, int y) {
-  constexpr uint32_t kWallCode = 4 * (1 + kGrey), kGoalCode = 4 * (7 + kGreen);
+  constexpr uint32_t kWallCode = 4 * (1 + kGrey), kGoalCode = 4 * (7 + kGreen), kLavaCode = 4 * 49;
   const int S = L.S;
   uint32_t code = 0;
   if (L.fam == kFamTwoRoom) {   // the family is uniform across the wave here
@@ -583,6 +725,12 @@ __device__ __forceinline__ uint32_t layout_code(const Layout& L, int x, int y) {
     const int m = S / 2;
     code = (y == m && x != L.c && x != L.d) ? kWallCode : code;
     code = (x == m && y != L.a && y != L.b) ? kWallCode : code;
+  } else if (L.fam == kFamLavaGap) {
+    code = (x == L.a && y != L.b) ? kLavaCode : code;
+  } else if (L.fam == kFamCrossings) {
+    code = crossings_lava(L, x, y) ? kLavaCode : code;
+  } else if (L.fam == kFamDistShift) {
+    code = ((y == 1 || y == L.a) && x >= 3 && x <= S - 3) ? kLavaCode : code;
   }
   code = (x == L.gx && y == L.gy) ? kGoalCode : code;
   const bool border = x == 0 || y == 0 || x == S - 1 || y == S - 1;
@@ -715,14 +863,14 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
     const int e = e0 + lane;
     const bool active = lane < n_here;
 
-    uint32_t fam = 0;
+    uint32_t fam = 0, meta = 0;
     int S = 0, T = 1, x = 1, y = 1, dir = 0, t = 0;
     uint32_t carry = kCellEmpty, episode = 0, rid = 0, calls = 0;
     bool done_prev = false;
     uint2 seed = make_uint2(0, 0);
     uint64_t goff = 0;
     if (active) {
-      const uint32_t meta = a.env.meta[e];
+      meta = a.env.meta[e];
       fam = meta & 0xFF;
       S = (int)((meta >> 8) & 0xFF);
       T = a.env.max_steps[e];
@@ -772,7 +920,7 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
       Layout L{};
       if (do_reset) {
         episode += 1u;
-        L = make_layout(fam, S, seed, rid, episode);
+        L = make_layout(meta, seed, rid, episode);
         x = L.ax;
         y = L.ay;
         dir = L.dir;
@@ -803,7 +951,7 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
         if (r.front_changed) my_codes[fy * S + fx] = (uint8_t)code_of(r.new_front);
         t += 1;
         const bool trunc = t >= T;
-        reward = r.terminated ? goal_reward(t, T, a.env.reward_mode) : 0.0f;
+        reward = step_reward(r, t, T, a.env.reward_mode);
         flags = (r.terminated ? kFlagTerminated : 0u) | (trunc ? kFlagTruncated : 0u);
         done_prev = r.terminated || trunc;
         act_rec = act & 0xFF;
@@ -894,7 +1042,7 @@ __global__ __launch_bounds__(kWave) void k_admit(AdmitArgs a) {
     a.env.seed[e] = c.seed;
     a.env.rng_id[e] = c.rng_id;
     a.env.grid_off[e] = c.grid_off;
-    L = make_layout(c.meta & 0xFF, (int)((c.meta >> 8) & 0xFF), c.seed, c.rng_id, 0u);
+    L = make_layout(c.meta, c.seed, c.rng_id, 0u);
     g = a.st.grid + c.grid_off;
     a.st.x[e] = L.ax;
     a.st.y[e] = L.ay;

@@ -72,6 +72,22 @@ struct SlotConfig {
 
 constexpr int kAdmitBatch = 512;   // tiles per admission launch (kernel argument)
 
+// Whether (family, side, param) describes a valid env with side <= max_side
+// (the families of Table "envs"; param: Crossings rivers, DistShift variant).
+inline bool family_ok(int family, int side, int param, int max_side) {
+  if (side > max_side || side > 32) return false;
+  switch (family) {
+    case 0: return side >= 4;                                  // Empty
+    case 1: return side >= 5;                                  // DoorKey
+    case 2: return side >= 7 && (side & 1) == 1;               // FourRooms
+    case 3: return side >= 5;                                  // LavaGap
+    case 4: return side >= 5 && (side & 1) == 1 && param >= 1 && param <= 8 &&
+                   param <= side - 3;                          // Crossings
+    case 5: return side >= 6 && (param == 1 || param == 2);    // DistShift
+    default: return false;
+  }
+}
+
 // Admits tiles: copies their slot configs and descriptors from host staging
 // (coherent pinned memory the device reads directly) and resets their envs.
 hipError_t launch_admit(const EnvTables& env, const StateBufs& st, ServeTile* tiles,

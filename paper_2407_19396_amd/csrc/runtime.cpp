@@ -36,16 +36,6 @@ namespace {
 
 constexpr int kTileEnvs = 64;
 
-bool side_ok(int family, int side) {
-  if (side > 32) return false;
-  switch (family) {
-    case GX_FAMILY_EMPTY: return side >= 4;
-    case GX_FAMILY_TWOROOM: return side >= 5;
-    case GX_FAMILY_FOURROOMS: return side >= 7 && (side & 1) == 1;
-    default: return false;
-  }
-}
-
 // Reports (and clears) a pending asynchronous error of earlier GPU work.
 int device_status() {
   const hipError_t e = hipGetLastError();
@@ -133,9 +123,9 @@ int env_create(const gx_config* cfg, gx_ctx** out) {
   std::vector<uint64_t> grid_off(n);
   uint64_t off = 0;
   for (int32_t i = 0; i < n; ++i) {
-    const int fam = cfg->family[i], S = cfg->side[i];
-    if (!side_ok(fam, S) || cfg->max_steps[i] < 1) return GX_EINVAL;
-    meta[i] = (uint32_t)fam | ((uint32_t)S << 8);
+    const int fam = cfg->family[i], S = cfg->side[i], P = cfg->param ? cfg->param[i] : 0;
+    if (!gx::family_ok(fam, S, P, 32) || cfg->max_steps[i] < 1) return GX_EINVAL;
+    meta[i] = (uint32_t)fam | ((uint32_t)S << 8) | ((uint32_t)P << 16);
     max_steps[i] = cfg->max_steps[i];
     const uint64_t sd = cfg->seed ? cfg->seed[i] : cfg->seed_all;
     seed[i] = make_uint2((uint32_t)sd, (uint32_t)(sd >> 32));

@@ -29,16 +29,6 @@ namespace {
 
 constexpr int kTileEnvs = 64;
 
-bool family_side_ok(int family, int side, int max_side) {
-  if (side > max_side) return false;
-  switch (family) {
-    case GX_FAMILY_EMPTY: return side >= 4;
-    case GX_FAMILY_TWOROOM: return side >= 5;
-    case GX_FAMILY_FOURROOMS: return side >= 7 && (side & 1) == 1;
-    default: return false;
-  }
-}
-
 struct Request {
   bool live = false;
   int32_t n_envs = 0, n_steps = 0, done = 0;
@@ -166,7 +156,9 @@ int env_server_admit(gx_server* s, const gx_request* r, int32_t* handle) {
       !r->max_steps || !r->reward || !r->flags || !r->action)
     return GX_EINVAL;
   for (int32_t i = 0; i < r->n_envs; ++i)
-    if (!family_side_ok(r->family[i], r->side[i], s->max_side) || r->max_steps[i] < 1) return GX_EINVAL;
+    if (!gx::family_ok(r->family[i], r->side[i], r->param ? r->param[i] : 0, s->max_side) ||
+        r->max_steps[i] < 1)
+      return GX_EINVAL;
   const int32_t need = (r->n_envs + kTileEnvs - 1) / kTileEnvs;
   if ((int32_t)s->free_tiles.size() < need) return GX_EBUSY;
   int32_t h;
@@ -195,7 +187,8 @@ int env_server_admit(gx_server* s, const gx_request* r, int32_t* handle) {
     for (int32_t j = 0; j < n; ++j) {
       const int32_t S = r->side[l0 + j];
       gx::SlotConfig& c = s->h_slots[(size_t)t * kTileEnvs + j];
-      c.meta = (uint32_t)r->family[l0 + j] | ((uint32_t)S << 8);
+      c.meta = (uint32_t)r->family[l0 + j] | ((uint32_t)S << 8) |
+               ((uint32_t)(r->param ? r->param[l0 + j] : 0) << 16);
       c.max_steps = r->max_steps[l0 + j];
       c.seed = seed;
       c.rng_id = (uint32_t)(l0 + j);
@@ -321,8 +314,9 @@ Layout output_layout(int32_t stride, int32_t n_steps, bool keep_obs) {
 extern "C" {
 
 int env_serve_run(gx_server* s, const gx_serve_item* items, int32_t n_items, const uint8_t* family,
-                  const uint8_t* side, const int32_t* max_steps, const gx_serve_opts* o,
-                  void* stream, double* admit_s, double* done_s, gx_serve_stats* stats) {
+                  const uint8_t* side, const uint8_t* param, const int32_t* max_steps,
+                  const gx_serve_opts* o, void* stream, double* admit_s, double* done_s,
+                  gx_serve_stats* stats) {
   if (!s || !items || n_items < 0 || !family || !side || !max_steps || !o || !admit_s || !done_s ||
       !stats || o->K < 1 || o->max_inflight < 1 || !o->arena)
     return GX_EINVAL;
@@ -401,6 +395,7 @@ int env_serve_run(gx_server* s, const gx_serve_item* items, int32_t n_items, con
       r.seed = it.seed;
       r.family = family + it.env_offset;
       r.side = side + it.env_offset;
+      r.param = param ? param + it.env_offset : nullptr;
       r.max_steps = max_steps + it.env_offset;
       r.obs = o->keep_obs ? base + lay.obs : nullptr;
       r.reward = reinterpret_cast<float*>(base + lay.reward);

@@ -28,7 +28,7 @@ EXPORTS = ("env_create", "env_sizes", "env_info", "env_reset", "env_step", "env_
 
 class GxConfig(ctypes.Structure):
     _fields_ = [("n_envs", ctypes.c_int32), ("reward_mode", ctypes.c_int32),
-                ("family", ctypes.c_void_p), ("side", ctypes.c_void_p),
+                ("family", ctypes.c_void_p), ("side", ctypes.c_void_p), ("param", ctypes.c_void_p),
                 ("max_steps", ctypes.c_void_p), ("seed", ctypes.c_void_p),
                 ("seed_all", ctypes.c_uint64), ("rng_id", ctypes.c_void_p)]
 
@@ -55,7 +55,8 @@ class GxInfo(ctypes.Structure):
 
 class GxRequest(ctypes.Structure):
     _fields_ = [("n_envs", ctypes.c_int32), ("n_steps", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("family", ctypes.c_void_p), ("side", ctypes.c_void_p), ("max_steps", ctypes.c_void_p),
+                ("family", ctypes.c_void_p), ("side", ctypes.c_void_p), ("param", ctypes.c_void_p),
+                ("max_steps", ctypes.c_void_p),
                 ("obs", ctypes.c_void_p), ("reward", ctypes.c_void_p), ("flags", ctypes.c_void_p),
                 ("action", ctypes.c_void_p), ("stride", ctypes.c_int32)]
 
@@ -116,7 +117,7 @@ def load(path: str = LIB_PATH):
     L.env_server_release.argtypes = [P, I32]
     L.env_server_info.argtypes = [P, ctypes.POINTER(GxServerInfo)]
     L.env_server_destroy.argtypes = [P]
-    L.env_serve_run.argtypes = [P, ctypes.POINTER(GxServeItem), I32, P, P, P,
+    L.env_serve_run.argtypes = [P, ctypes.POINTER(GxServeItem), I32, P, P, P, P,
                                 ctypes.POINTER(GxServeOpts), P, P, P, ctypes.POINTER(GxServeStats)]
     L.env_strerror.argtypes = [ctypes.c_int]
     L.env_strerror.restype = ctypes.c_char_p
@@ -149,8 +150,9 @@ def env_create(table: workloads.EnvTable, reward_mode: int = 0) -> int:
     ms = np.ascontiguousarray(table.max_steps, np.int32)
     seed = np.ascontiguousarray(table.seed, np.uint64)
     rid = np.ascontiguousarray(table.rng_id, np.uint32)
-    cfg = GxConfig(table.n, reward_mode, fam.ctypes.data, side.ctypes.data, ms.ctypes.data,
-                   seed.ctypes.data, 0, rid.ctypes.data)
+    par = np.ascontiguousarray(table.param, np.uint8)
+    cfg = GxConfig(table.n, reward_mode, fam.ctypes.data, side.ctypes.data, par.ctypes.data,
+                   ms.ctypes.data, seed.ctypes.data, 0, rid.ctypes.data)
     ctx = ctypes.c_void_p()
     _check("env_create", load().env_create(ctypes.byref(cfg), ctypes.byref(ctx)))
     return ctx.value
@@ -313,8 +315,10 @@ class Server:
         fam = np.ascontiguousarray(table.family, np.uint8)
         side = np.ascontiguousarray(table.side, np.uint8)
         ms = np.ascontiguousarray(table.max_steps, np.int32)
+        par = np.ascontiguousarray(table.param, np.uint8)
         req = GxRequest(table.n, n_steps, int(table.seed[0]), fam.ctypes.data, side.ctypes.data,
-                        ms.ctypes.data, out.obs.data_ptr() if out.obs is not None else None,
+                        par.ctypes.data, ms.ctypes.data,
+                        out.obs.data_ptr() if out.obs is not None else None,
                         out.reward.data_ptr(), out.flags.data_ptr(), out.action.data_ptr(), stride)
         h = ctypes.c_int32()
         rc = load().env_server_admit(self.ptr, ctypes.byref(req), ctypes.byref(h))
@@ -355,16 +359,18 @@ def serve_run(server: Server, requests: list, K: int, budget_bytes: int, arena, 
     the native serving loop; returns throughput and per-request latencies."""
     n = len(requests)
     items = (GxServeItem * max(n, 1))()
-    fam, side, ms = [], [], []
+    fam, side, par, ms = [], [], [], []
     off = 0
     for i, r in enumerate(requests):
         items[i] = GxServeItem(r.arrival_s, r.n_envs, r.n_steps, r.seed, off)
         fam.append(r.table.family)
         side.append(r.table.side)
+        par.append(r.table.param)
         ms.append(r.table.max_steps)
         off += r.n_envs
     fam = np.ascontiguousarray(np.concatenate(fam), np.uint8)
     side = np.ascontiguousarray(np.concatenate(side), np.uint8)
+    par = np.ascontiguousarray(np.concatenate(par), np.uint8)
     ms = np.ascontiguousarray(np.concatenate(ms), np.int32)
     admit = np.zeros(n, np.float64)
     done = np.zeros(n, np.float64)
@@ -372,7 +378,8 @@ def serve_run(server: Server, requests: list, K: int, budget_bytes: int, arena, 
                        arena.numel() * arena.element_size())
     st = GxServeStats()
     _check("env_serve_run", load().env_serve_run(server.ptr, items, n, fam.ctypes.data, side.ctypes.data,
-                                                 ms.ctypes.data, ctypes.byref(opts), _stream_ptr(stream),
+                                                 par.ctypes.data, ms.ctypes.data, ctypes.byref(opts),
+                                                 _stream_ptr(stream),
                                                  admit.ctypes.data, done.ctypes.data, ctypes.byref(st)))
     arrival = np.array([r.arrival_s for r in requests])
     return {"wall_s": st.wall_s, "env_steps": st.env_steps, "completed": st.completed,

@@ -12,7 +12,8 @@ FIELDS = ("grid", "x", "y", "dir", "t", "carry", "episode", "done_prev", "calls"
 
 
 def ox_batch(table: wl.EnvTable, reward_mode: int = 0) -> ox.Batch:
-    return ox.Batch(table.family, table.side, table.max_steps, table.seed, table.rng_id, reward_mode)
+    return ox.Batch(table.family, table.side, table.max_steps, table.seed, table.rng_id, reward_mode,
+                    table.param)
 
 
 def to_np(t):

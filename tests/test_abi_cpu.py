@@ -36,30 +36,39 @@ def test_strerror():
     assert ge.env_strerror(-99) == "unknown status"
 
 
-def _cfg(family, side, max_steps, n=None, reward_mode=0):
+def _cfg(family, side, max_steps, n=None, reward_mode=0, param=None):
     family = np.asarray(family, np.uint8)
     side = np.asarray(side, np.uint8)
     max_steps = np.asarray(max_steps, np.int32)
-    keep = (family, side, max_steps)
+    param = None if param is None else np.asarray(param, np.uint8)
+    keep = (family, side, max_steps, param)
     n = len(family) if n is None else n
-    return ge.GxConfig(n, reward_mode, family.ctypes.data, side.ctypes.data, max_steps.ctypes.data,
+    return ge.GxConfig(n, reward_mode, family.ctypes.data, side.ctypes.data,
+                       None if param is None else param.ctypes.data, max_steps.ctypes.data,
                        None, 0, None), keep
 
 
-@pytest.mark.parametrize("family,side,T,n,mode", [
-    ([0], [3], [10], None, 0),          # Empty needs side >= 4
-    ([1], [4], [10], None, 0),          # TwoRoom needs side >= 5
-    ([2], [8], [10], None, 0),          # FourRooms needs an odd side
-    ([2], [5], [10], None, 0),          # FourRooms needs side >= 7
-    ([0], [33], [10], None, 0),         # side <= 32
-    ([3], [8], [10], None, 0),          # unknown family
-    ([0], [8], [0], None, 0),           # max_steps >= 1
-    ([0], [8], [10], 0, 0),             # n_envs >= 1
-    ([0], [8], [10], None, 2),          # reward mode 0 or 1
+@pytest.mark.parametrize("family,side,T,n,mode,param", [
+    ([0], [3], [10], None, 0, None),          # Empty needs side >= 4
+    ([1], [4], [10], None, 0, None),          # TwoRoom needs side >= 5
+    ([2], [8], [10], None, 0, None),          # FourRooms needs an odd side
+    ([2], [5], [10], None, 0, None),          # FourRooms needs side >= 7
+    ([0], [33], [10], None, 0, None),         # side <= 32
+    ([6], [8], [10], None, 0, None),          # unknown family
+    ([3], [4], [10], None, 0, None),          # LavaGap needs side >= 5
+    ([4], [9], [10], None, 0, None),          # Crossings needs N >= 1 (NULL param: 0)
+    ([4], [10], [10], None, 0, [2]),          # Crossings needs an odd side
+    ([4], [9], [10], None, 0, [7]),           # Crossings needs N <= S - 3
+    ([4], [31], [10], None, 0, [9]),          # Crossings needs N <= 8
+    ([5], [8], [10], None, 0, [0]),           # DistShift variant 1 or 2
+    ([5], [5], [10], None, 0, [1]),           # DistShift needs side >= 6
+    ([0], [8], [0], None, 0, None),           # max_steps >= 1
+    ([0], [8], [10], 0, 0, None),             # n_envs >= 1
+    ([0], [8], [10], None, 2, None),          # reward mode 0 or 1
 ])
-def test_create_rejects_bad_configs(family, side, T, n, mode):
+def test_create_rejects_bad_configs(family, side, T, n, mode, param):
     lib = ge.load()
-    cfg, keep = _cfg(family, side, T, n, mode)
+    cfg, keep = _cfg(family, side, T, n, mode, param)
     ctx = ctypes.c_void_p(1)
     assert lib.env_create(ctypes.byref(cfg), ctypes.byref(ctx)) == ge.GX_EINVAL
     assert ctx.value is None

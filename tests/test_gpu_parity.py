@@ -35,6 +35,8 @@ def tables():
         "fourrooms19": wl.uniform_table(512, wl.FAMILY_FOURROOMS, 19, seed=6),
         "mixed": wl.mixed_table(3000, seed=7, mix_seed=8),
         "all_sides": all_sides_table(),
+        "lava": wl.lava_table(3000, seed=21, mix_seed=22),
+        "lava_all": lava_all_table(),
     }
 
 
@@ -52,6 +54,24 @@ def all_sides_table():
                        np.full(len(fam), 77, np.uint64), np.arange(len(fam), dtype=np.uint32), "all sides")
 
 
+def lava_all_table():
+    """Every valid (side, parameter) of the lava families, three envs each."""
+    fam, side, par = [], [], []
+    for S in range(5, 33):
+        fam.append(3); side.append(S); par.append(0)
+    for S in range(5, 32, 2):
+        for N in range(1, min(8, S - 3) + 1):
+            fam.append(4); side.append(S); par.append(N)
+    for S in range(6, 33):
+        for k in (1, 2):
+            fam.append(5); side.append(S); par.append(k)
+    fam, side, par = np.array(fam * 3), np.array(side * 3), np.array(par * 3)
+    ms = np.array([wl.default_max_steps(int(f), int(s)) for f, s in zip(fam, side)]) // 16 + 1
+    return wl.EnvTable(fam.astype(np.uint8), side.astype(np.uint8), ms.astype(np.int32),
+                       np.full(len(fam), 91, np.uint64), np.arange(len(fam), dtype=np.uint32),
+                       "lava all", par.astype(np.uint8))
+
+
 @pytest.mark.parametrize("name", list(tables()))
 def test_reset_parity(ge, name):
     table = tables()[name]
@@ -62,7 +82,8 @@ def test_reset_parity(ge, name):
 
 
 @pytest.mark.parametrize("name,steps", [("empty5", 100), ("empty8", 300), ("tworoom8", 300),
-                                        ("fourrooms19", 250), ("mixed", 300), ("all_sides", 200)])
+                                        ("fourrooms19", 250), ("mixed", 300), ("all_sides", 200),
+                                        ("lava", 300), ("lava_all", 200)])
 @pytest.mark.parametrize("policy", [False, True])
 def test_plain_step_parity(ge, name, steps, policy):
     import torch
@@ -82,7 +103,8 @@ def test_plain_step_parity(ge, name, steps, policy):
 
 
 @pytest.mark.parametrize("name,steps", [("empty5", 100), ("empty8", 300), ("tworoom8", 300),
-                                        ("fourrooms19", 250), ("mixed", 300), ("all_sides", 200)])
+                                        ("fourrooms19", 250), ("mixed", 300), ("all_sides", 200),
+                                        ("lava", 300), ("lava_all", 200)])
 @pytest.mark.parametrize("K", [1, 7, 64])
 @pytest.mark.parametrize("policy", [False, True])
 def test_fused_rollout_parity(ge, name, steps, K, policy):
@@ -207,3 +229,33 @@ def test_rollouts_are_deterministic(ge):
     np.testing.assert_array_equal(outs[0][1], outs[1][1])
     for f in P.FIELDS:
         np.testing.assert_array_equal(outs[0][2][f], outs[1][2][f])
+
+
+def test_crossings_layouts_many_seeds(ge):
+    """Reset of 20000 Crossings envs over every valid (side, rivers), each
+    with its own seed: grids, poses and first observations equal the
+    oracle's (the device shuffle and path draws are the oracle's)."""
+    rng = np.random.default_rng(5)
+    combos = [(S, N) for S in range(5, 32, 2) for N in range(1, min(8, S - 3) + 1)]
+    pick = np.array(combos)[rng.integers(0, len(combos), 20000)]
+    n = len(pick)
+    table = wl.EnvTable(np.full(n, 4, np.uint8), pick[:, 0].astype(np.uint8),
+                        np.full(n, 50, np.int32), rng.integers(0, 2 ** 63, n).astype(np.uint64),
+                        np.arange(n, dtype=np.uint32), "crossings seeds", pick[:, 1].astype(np.uint8))
+    env, first = make(ge, table)
+    b, s, ref = P.oracle_reset(table)
+    P.assert_rows_equal(first, ref, what="crossings reset")
+    P.assert_state_equal(env, s, "crossings reset")
+
+
+def test_unit_reward_mode_lava(ge):
+    import torch
+    table = wl.lava_table(2048, seed=17, mix_seed=18)
+    env, _ = make(ge, table, reward_mode=1)
+    b, s, _ = P.oracle_reset(table, reward_mode=1)
+    ref = ox.rollout(b, s, 200, None, nthreads=8)
+    traj = ge.Traj.alloc(200, table.n)
+    env.rollout(200, traj, K=32)
+    torch.cuda.synchronize()
+    P.assert_rows_equal(traj, ref, what="unit reward, lava")
+    assert set(np.unique(ref.reward)) == {-1.0, 0.0, 1.0}

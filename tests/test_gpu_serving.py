@@ -73,7 +73,8 @@ def run_mix(ge, reqs, K, max_tiles, per_step=8):
 
 def oracle_of(r):
     b = ox.Batch(r.table.family, r.table.side, r.table.max_steps,
-                 np.full(r.n_envs, r.seed, np.uint64), np.arange(r.n_envs, dtype=np.uint32))
+                 np.full(r.n_envs, r.seed, np.uint64), np.arange(r.n_envs, dtype=np.uint32), 0,
+                 r.table.param)
     s = ox.State.empty(b)
     ox.reset(b, s)
     return ox.rollout(b, s, r.n_steps, None, nthreads=16)
@@ -140,3 +141,20 @@ def test_native_serving_loop_completes_everything():
     info = srv.info()
     assert info["live_requests"] == 0 and info["free_tiles"] == 256
     srv.close()
+
+
+def test_lava_requests_equal_oracle():
+    """Requests of the lava tasks through the server (admission resets
+    them on the device) equal the oracle's reset + rollout."""
+    import torch
+    from paper_2407_19396_amd import gridenv as ge
+    rng = np.random.default_rng(3)
+    reqs = []
+    for i in range(6):
+        n = int(rng.integers(1, 300))
+        t = wl.lava_table(n, seed=int(rng.integers(0, 2 ** 62)), mix_seed=i)
+        reqs.append(wl.Request(i, 0.0, n, int(rng.integers(20, 120)), int(t.seed[0]), t))
+    outs, _, info = run_mix(ge, reqs, 32, max_tiles=8)
+    assert info["live_requests"] == 0
+    for i, r in enumerate(reqs):
+        P.assert_rows_equal(crop(outs[i], r.n_envs), oracle_of(r), what=f"lava request {i}")
