@@ -25,8 +25,9 @@ OPEN, CLOSED, LOCKED = 0, 1, 2
 FLAG_TERMINATED, FLAG_TRUNCATED, FLAG_FIRST = 1, 2, 4
 ACTION_NONE = 0xFF
 FAMILY_EMPTY, FAMILY_TWOROOM, FAMILY_FOURROOMS = 0, 1, 2
-FAMILY_LAVAGAP, FAMILY_CROSSINGS, FAMILY_DISTSHIFT = 3, 4, 5
-LAVA = 9
+FAMILY_LAVAGAP, FAMILY_CROSSINGS, FAMILY_DISTSHIFT, FAMILY_DYNOBS = 3, 4, 5, 6
+BALL, LAVA = 6, 9
+MAX_OBST = 8
 OBS_BYTES = 147
 
 
@@ -52,7 +53,7 @@ class _Batch(ctypes.Structure):
                 ("reward_mode", ctypes.c_int32), ("param", ctypes.c_void_p)]
 
 
-STATE_FIELDS = ("grid", "x", "y", "dir", "t", "carry", "episode", "done_prev", "calls")
+STATE_FIELDS = ("grid", "x", "y", "dir", "t", "carry", "episode", "done_prev", "calls", "obst")
 
 
 class _State(ctypes.Structure):
@@ -74,7 +75,7 @@ def lib():
         L.ox_side_ok.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.ox_side_ok.restype = ctypes.c_int
         L.ox_layout.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
-                                ctypes.c_uint32, ctypes.c_uint32, P, P, P, P]
+                                ctypes.c_uint32, ctypes.c_uint32, P, P, P, P, P]
         L.ox_layout.restype = ctypes.c_int
         L.ox_observe.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                  ctypes.c_int32, P]
@@ -115,14 +116,19 @@ def side_ok(family: int, side: int, param: int = 0) -> bool:
     return bool(lib().ox_side_ok(family, side, param))
 
 
-def layout(family: int, side: int, seed: int, rng_id: int, episode: int, param: int = 0):
-    """Start state of one env: (grid [S][S][3] uint8, x, y, dir)."""
+def layout(family: int, side: int, seed: int, rng_id: int, episode: int, param: int = 0,
+           with_obst: bool = False):
+    """Start state of one env: (grid [S][S][3] uint8, x, y, dir), plus the
+    obstacle list u8[16] (x, y per ball, 0xFF unused) with with_obst."""
     g = np.zeros((side, side, 3), dtype=np.uint8)
+    ob = np.zeros(2 * MAX_OBST, dtype=np.uint8)
     x, y, d = (ctypes.c_int(), ctypes.c_int(), ctypes.c_int())
     rc = lib().ox_layout(family, side, param, seed, rng_id, episode, _ptr(g),
-                         ctypes.addressof(x), ctypes.addressof(y), ctypes.addressof(d))
+                         ctypes.addressof(x), ctypes.addressof(y), ctypes.addressof(d), _ptr(ob))
     if rc != 0:
         raise ValueError(f"layout failed ({rc}) for family={family} side={side}")
+    if with_obst:
+        return g, x.value, y.value, d.value, ob
     return g, x.value, y.value, d.value
 
 
@@ -179,17 +185,21 @@ class State:
     episode: np.ndarray
     done_prev: np.ndarray
     calls: np.ndarray = None      # u32[N] step calls since reset
+    obst: np.ndarray = None       # u8[N * 16] obstacle positions (x, y per ball, 0xFF unused)
 
     def __post_init__(self):
         if self.calls is None:
             self.calls = np.zeros(self.x.shape[0], dtype=np.uint32)
+        if self.obst is None:
+            self.obst = np.full(self.x.shape[0] * 2 * MAX_OBST, 0xFF, dtype=np.uint8)
 
     @staticmethod
     def empty(batch: Batch) -> "State":
         n = batch.n
         z = lambda dt: np.zeros(n, dtype=dt)  # noqa: E731
         return State(np.zeros(batch.grid_bytes(), dtype=np.uint8), z(np.int32), z(np.int32),
-                     z(np.int32), z(np.int32), z(np.int32), z(np.uint32), z(np.uint8), z(np.uint32))
+                     z(np.int32), z(np.int32), z(np.int32), z(np.uint32), z(np.uint8), z(np.uint32),
+                     np.full(n * 2 * MAX_OBST, 0xFF, dtype=np.uint8))
 
     def copy(self) -> "State":
         return State(*(getattr(self, f).copy() for f in STATE_FIELDS))

@@ -27,7 +27,10 @@
  *   - the Empty, DoorKey (two rooms) and FourRooms families (Table "envs"),
  *     and the lava families LavaGap, Crossings and DistShift with the
  *     goal-or-lava reward R2 of Table "envs" (lava: -1 and termination,
- *     Tables "rewards" and "terminations", on_lava_fall).
+ *     Tables "rewards" and "terminations", on_lava_fall);
+ *   - Dynamic-Obstacles (Table "envs", reward R3; Fig. 1): balls that move
+ *     at random every step, the first family whose transition system is
+ *     not the identity (Table "systems").
  *
  * Every point the paper leaves open is fixed by a documented reading; the
  * readings are listed next to each function.  Parity status of each
@@ -55,7 +58,8 @@ enum { D_OPEN = 0, D_CLOSED = 1, D_LOCKED = 2 };
 enum { A_LEFT = 0, A_RIGHT = 1, A_FORWARD = 2, A_PICKUP = 3, A_DROP = 4,
        A_TOGGLE = 5, A_DONE = 6 };
 enum { FAM_EMPTY = 0, FAM_TWOROOM = 1, FAM_FOURROOMS = 2, FAM_LAVAGAP = 3,
-       FAM_CROSSINGS = 4, FAM_DISTSHIFT = 5 };
+       FAM_CROSSINGS = 4, FAM_DISTSHIFT = 5, FAM_DYNOBS = 6 };
+#define OX_MAX_OBST 8
 
 #define OX_FLAG_TERMINATED 1u
 #define OX_FLAG_TRUNCATED 2u
@@ -163,8 +167,10 @@ static uint32_t count_empty(const uint8_t *g, int S, int x0, int x1, int y0,
 }
 
 /* Side (and parameter) limits of each family.  The parameter is the
- * number of lava rivers of Crossings (at most 8 and at most S - 3) and the
- * variant (1 or 2) of DistShift; the other families ignore it. */
+ * number of lava rivers of Crossings (at most 8 and at most S - 3), the
+ * variant (1 or 2) of DistShift and the number of obstacles (1 to 8, leaving
+ * two free interior cells) of Dynamic-Obstacles; the other families ignore
+ * it. */
 int ox_side_ok(int family, int side, int param) {
   if (side > 32) return 0;
   switch (family) {
@@ -175,6 +181,9 @@ int ox_side_ok(int family, int side, int param) {
     case FAM_CROSSINGS:
       return side >= 5 && (side % 2) == 1 && param >= 1 && param <= 8 && param <= side - 3;
     case FAM_DISTSHIFT: return side >= 6 && (param == 1 || param == 2);
+    case FAM_DYNOBS:
+      return side >= 5 && param >= 1 && param <= OX_MAX_OBST &&
+             param <= (side - 2) * (side - 2) - 2;
   }
   return 0;
 }
@@ -215,6 +224,10 @@ int ox_side_ok(int family, int side, int param) {
 /*   current room's side (position drawn right after the move).        */
 /* DistShift(S, k): goal (S-2, 1); lava on rows 1 and r2 (r2 = 2 for   */
 /*   k = 1, S - 2 for k = 2) over columns 3..S-3; no random draws.     */
+/* Dynamic-Obstacles(S, n): goal (S-2, S-2); n blue balls, ball b at   */
+/*   the k-th empty interior cell other than the agent's, k uniform,    */
+/*   placed in order b = 0..n-1; their positions are listed in obst     */
+/*   (x, y per ball, 0xFF for unused slots and other families).         */
 /* Pinned by: structural invariants, uniformity tests and the hand     */
 /* layouts in tests; agreement with MiniGrid's own generators: parity  */
 /* unpinned (MiniGrid is not available).                               */
@@ -223,8 +236,10 @@ static void crossings(uint8_t *grid, int S, int N, uint64_t seed,
                       uint32_t rng_id, uint32_t episode, uint32_t *w);
 
 int ox_layout(int family, int S, int param, uint64_t seed, uint32_t rng_id,
-              uint32_t episode, uint8_t *grid, int *ax, int *ay, int *adir) {
+              uint32_t episode, uint8_t *grid, int *ax, int *ay, int *adir,
+              uint8_t *obst) {
   if (!ox_side_ok(family, S, param)) return -1;
+  if (obst) memset(obst, 0xFF, 2 * OX_MAX_OBST);
   uint32_t w = 0;
 #define DRAW(n) ox_uniform(layout_word(seed, rng_id, episode, w++), (uint32_t)(n))
   for (int y = 0; y < S; ++y)
@@ -284,6 +299,17 @@ int ox_layout(int family, int S, int param, uint64_t seed, uint32_t rng_id,
     } else if (family == FAM_CROSSINGS) {
       put(grid, S, S - 2, S - 2, O_GOAL, C_GREEN, 0);
       crossings(grid, S, param, seed, rng_id, episode, &w);
+    } else if (family == FAM_DYNOBS) {
+      put(grid, S, S - 2, S - 2, O_GOAL, C_GREEN, 0);
+      for (int b = 0; b < param; ++b) {
+        /* empty interior cells other than the agent's (1, 1), row-major */
+        uint32_t n = count_empty(grid, S, 1, S - 2, 1, S - 2) - 1u;
+        uint32_t k = DRAW(n) + 1u;   /* skip the agent's cell, the first empty one */
+        int bx, by;
+        if (kth_empty(grid, S, 1, S - 2, 1, S - 2, k, &bx, &by)) return -2;
+        put(grid, S, bx, by, O_BALL, C_BLUE, 0);
+        if (obst) { obst[2 * b] = (uint8_t)bx; obst[2 * b + 1] = (uint8_t)by; }
+      }
     } else {
       put(grid, S, S - 2, 1, O_GOAL, C_GREEN, 0);
       int r2 = param == 1 ? 2 : S - 2;
@@ -434,10 +460,46 @@ typedef struct {
   uint32_t *episode;
   uint8_t *done_prev;
   uint32_t *calls;
+  uint8_t *obst;   /* 16 bytes: obstacle positions (Dynamic-Obstacles) */
 } ox_env_ref;
 
 static int is_pickable(int type) {
   return type == O_KEY || type == O_BALL || type == O_BOX;
+}
+
+/* ------------------------------------------------------------------ */
+/* Transition system of Dynamic-Obstacles (Table "systems"; Fig. 1):  */
+/* each ball, in list order, moves to a uniformly drawn empty cell of */
+/* the 8 around it that the agent does not occupy, drawn as the k-th  */
+/* such cell in row-major order, k = u(count) of its word; with no    */
+/* such cell it stays.  Ball b's word: key = seed, counter = (rng_id, */
+/* call, b / 4, 2), lane b % 4, call = the env's step-call count.     */
+/* Pinned by hand-worked moves, uniformity and invariant tests.       */
+/* ------------------------------------------------------------------ */
+static void move_obstacles(uint8_t *grid, int S, int n, int ax, int ay,
+                           uint8_t *obst, uint64_t seed, uint32_t rng_id,
+                           uint32_t call) {
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  for (int b = 0; b < n; ++b) {
+    uint32_t ctr[4] = {rng_id, call, (uint32_t)(b / 4), 2u}, out[4];
+    ox_philox4x32_10(ctr, key, out);
+    uint32_t word = out[b % 4];
+    int bx = obst[2 * b], by = obst[2 * b + 1];
+    int cx[8], cy[8], count = 0;
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        int x = bx + dx, y = by + dy;
+        if ((dx == 0 && dy == 0) || (x == ax && y == ay)) continue;
+        if (cell(grid, S, x, y)[0] != O_EMPTY) continue;
+        cx[count] = x; cy[count] = y; ++count;
+      }
+    if (count == 0) continue;
+    uint32_t k = ox_uniform(word, (uint32_t)count);
+    put(grid, S, bx, by, O_EMPTY, 0, 0);
+    put(grid, S, cx[k], cy[k], O_BALL, C_BLUE, 0);
+    obst[2 * b] = (uint8_t)cx[k];
+    obst[2 * b + 1] = (uint8_t)cy[k];
+  }
 }
 
 /* ------------------------------------------------------------------ */
@@ -453,6 +515,11 @@ static int is_pickable(int type) {
 /* the episode with reward -1 (R2 of Table "envs"; on_lava_fall of     */
 /* Tables "rewards" and "terminations"), in both reward modes: the     */
 /* time discount of Eq. (1) applies to the goal reward only.           */
+/* Dynamic-Obstacles (R3): the env has three actions (any other acts   */
+/* as turn left); the cell ahead is checked first, then the balls     */
+/* move (the transition system), then the action applies; moving       */
+/* forward when that cell held a ball or a wall ends the episode with  */
+/* reward -1, as MiniGrid's version does.                              */
 /* ------------------------------------------------------------------ */
 static void step_one(int family, int S, int param, int32_t T, uint64_t seed,
                      uint32_t rng_id, int reward_mode, ox_env_ref e,
@@ -461,7 +528,7 @@ static void step_one(int family, int S, int param, int32_t T, uint64_t seed,
   if (*e.done_prev) {
     *e.episode += 1u;
     ox_layout(family, S, param, seed, rng_id, *e.episode, e.grid, e.x, e.y,
-              e.dir);
+              e.dir, e.obst);
     *e.t = 0;
     *e.carry = O_EMPTY;
     *e.done_prev = 0;
@@ -474,7 +541,12 @@ static void step_one(int family, int S, int param, int32_t T, uint64_t seed,
   int dir = *e.dir;
   int fx = *e.x + DIR_X[dir], fy = *e.y + DIR_Y[dir];
   uint8_t *front = cell(e.grid, S, fx, fy);
-  int terminated = 0, lava = 0;
+  int terminated = 0, lava = 0, blocked = 0;
+  if (family == FAM_DYNOBS) {
+    if (action > A_FORWARD) action = A_LEFT;   /* three actions only */
+    blocked = front[0] != O_EMPTY && front[0] != O_GOAL;
+    move_obstacles(e.grid, S, param, *e.x, *e.y, e.obst, seed, rng_id, *e.calls);
+  }
   switch (action) {
     case A_LEFT: *e.dir = (dir + 3) % 4; break;
     case A_RIGHT: *e.dir = (dir + 1) % 4; break;
@@ -516,6 +588,7 @@ static void step_one(int family, int S, int param, int32_t T, uint64_t seed,
   }
   *e.t += 1;
   int truncated = *e.t >= T;
+  if (blocked && action == A_FORWARD) terminated = lava = 1;
   if (lava) *reward = -1.0f;
   else *reward = terminated ? ox_goal_reward(*e.t, T, reward_mode) : 0.0f;
   *flags = (uint8_t)((terminated ? OX_FLAG_TERMINATED : 0) |
@@ -550,6 +623,7 @@ typedef struct {
   uint32_t *episode;
   uint8_t *done_prev;
   uint32_t *calls;   /* step calls since reset (the random policy's counter) */
+  uint8_t *obst;     /* [N][16] obstacle positions (x, y per ball, 0xFF unused) */
 } ox_state;
 
 #define PARAM(b, i) ((b)->param ? (int)(b)->param[i] : 0)
@@ -561,6 +635,7 @@ static ox_env_ref env_ref(const ox_batch *b, const ox_state *s, int i) {
   e.carry = s->carry + i; e.episode = s->episode + i;
   e.done_prev = s->done_prev + i;
   e.calls = s->calls + i;
+  e.obst = s->obst + (size_t)16 * i;
   return e;
 }
 
@@ -583,7 +658,7 @@ int ox_reset(const ox_batch *b, const ox_state *s, uint8_t *obs, float *reward,
     ox_env_ref e = env_ref(b, s, i);
     *e.episode = 0;
     ox_layout(b->family[i], b->side[i], PARAM(b, i), b->seed[i], b->rng_id[i],
-              0, e.grid, e.x, e.y, e.dir);
+              0, e.grid, e.x, e.y, e.dir, e.obst);
     *e.t = 0;
     *e.carry = O_EMPTY;
     *e.done_prev = 0;

@@ -5,14 +5,15 @@ from __future__ import annotations
 
 import numpy as np
 
-EMPTY, WALL, DOOR, KEY, GOAL, LAVA = 1, 2, 4, 5, 8, 9
+EMPTY, WALL, DOOR, KEY, BALL, GOAL, LAVA = 1, 2, 4, 5, 6, 8, 9
 COLOURS = {"r": 0, "g": 1, "b": 2, "p": 3, "y": 4, "e": 5}
 DIRS = {">": 0, "v": 1, "<": 2, "^": 3}
 
 
 def parse(picture: str):
     """Grid [S][S][3] from rows of space-separated tokens:
-    ``#`` wall, ``.`` empty, ``G`` goal, ``~`` lava, ``K<c>`` key of colour c,
+    ``#`` wall, ``.`` empty, ``G`` goal, ``~`` lava, ``o`` blue ball,
+    ``K<c>`` key of colour c,
     ``D<c><s>`` door of colour c in state s (0 open, 1 closed, 2 locked),
     ``> v < ^`` the agent (on an empty cell) facing east/south/west/north.
     Returns (grid, x, y, dir); x, y, dir are None without an agent."""
@@ -31,6 +32,8 @@ def parse(picture: str):
                 g[y, x] = (GOAL, 1, 0)
             elif tok == "~":
                 g[y, x] = (LAVA, 0, 0)
+            elif tok == "o":
+                g[y, x] = (BALL, 2, 0)
             elif tok[0] == "K":
                 g[y, x] = (KEY, COLOURS[tok[1]], 0)
             elif tok[0] == "D":
@@ -59,16 +62,24 @@ def rotate_world(grid: np.ndarray, x: int, y: int, d: int):
 
 
 def one_env(ox, picture: str, carry: int = EMPTY, t: int = 0, T: int = 100, family: int = 1,
-            seed: int = 0, episode: int = 0, reward_mode: int = 0, param: int = 0):
-    """A single-env oracle batch whose state is the given picture."""
+            seed: int = 0, episode: int = 0, reward_mode: int = 0, param: int = 0,
+            obst=None, calls: int = 0):
+    """A single-env oracle batch whose state is the given picture; obst lists
+    the balls' (x, y) in their move order (default: row-major order)."""
     g, x, y, d = parse(picture)
     S = g.shape[0]
     b = ox.Batch(np.array([family], np.uint8), np.array([S], np.uint8), np.array([T], np.int32),
                  np.array([seed], np.uint64), np.array([0], np.uint32), reward_mode,
                  np.array([param], np.uint8))
+    if obst is None:
+        obst = [(int(bx), int(by)) for by, bx in np.argwhere(g[:, :, 0] == BALL)]
+    ob = np.full(16, 0xFF, np.uint8)
+    for i, (bx, by) in enumerate(obst):
+        ob[2 * i], ob[2 * i + 1] = bx, by
     s = ox.State(g.reshape(-1).copy(), np.array([x], np.int32), np.array([y], np.int32),
                  np.array([d], np.int32), np.array([t], np.int32), np.array([carry], np.int32),
-                 np.array([episode], np.uint32), np.array([0], np.uint8))
+                 np.array([episode], np.uint32), np.array([0], np.uint8),
+                 np.array([calls], np.uint32), ob)
     return b, s
 
 
