@@ -50,7 +50,8 @@ class _Batch(ctypes.Structure):
                 ("family", ctypes.c_void_p), ("side", ctypes.c_void_p),
                 ("max_steps", ctypes.c_void_p), ("seed", ctypes.c_void_p),
                 ("rng_id", ctypes.c_void_p), ("grid_off", ctypes.c_void_p),
-                ("reward_mode", ctypes.c_int32), ("param", ctypes.c_void_p)]
+                ("reward_mode", ctypes.c_int32), ("param", ctypes.c_void_p),
+                ("obs_mode", ctypes.c_int32)]
 
 
 STATE_FIELDS = ("grid", "x", "y", "dir", "t", "carry", "episode", "done_prev", "calls", "obst")
@@ -79,6 +80,8 @@ def lib():
         L.ox_layout.restype = ctypes.c_int
         L.ox_observe.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                  ctypes.c_int32, P]
+        L.ox_observe_categorical.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_int, ctypes.c_int32, P]
         L.ox_goal_reward.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int]
         L.ox_goal_reward.restype = ctypes.c_float
         L.ox_reset.argtypes = [ctypes.POINTER(_Batch), ctypes.POINTER(_State), P, P, P, P,
@@ -140,6 +143,14 @@ def observe(grid: np.ndarray, x: int, y: int, d: int, carry: int = EMPTY) -> np.
     return obs
 
 
+def observe_categorical(grid: np.ndarray, x: int, y: int, d: int, carry: int = EMPTY) -> np.ndarray:
+    """categorical_first_person view [7][7] (row j, column i) of one env."""
+    g = np.ascontiguousarray(grid, dtype=np.uint8)
+    obs = np.zeros((7, 7), dtype=np.uint8)
+    lib().ox_observe_categorical(_ptr(g), g.shape[0], x, y, d, carry, _ptr(obs))
+    return obs
+
+
 def goal_reward(t: int, T: int, reward_mode: int = 0) -> float:
     return float(np.float32(lib().ox_goal_reward(t, T, reward_mode)))
 
@@ -158,6 +169,7 @@ class Batch:
     rng_id: np.ndarray      # u32[N]
     reward_mode: int = 0
     param: np.ndarray | None = None   # u8[N] family parameter (Crossings N, DistShift k)
+    obs_mode: int = 0                 # 0 symbolic_first_person [7][7][3], 1 categorical [7][7]
 
     @property
     def n(self) -> int:
@@ -215,7 +227,7 @@ def _cbatch(b: Batch, keep: list):
     param = None if b.param is None else np.ascontiguousarray(b.param, dtype=np.uint8)
     keep.extend(arrs + [param])
     return _Batch(b.n, *[a.ctypes.data for a in arrs], b.reward_mode,
-                  None if param is None else param.ctypes.data)
+                  None if param is None else param.ctypes.data, b.obs_mode)
 
 
 def _cstate(s: State):
@@ -233,15 +245,16 @@ class Outputs:
     action: np.ndarray       # u8[rows][N]
 
     @staticmethod
-    def empty(rows: int, n: int, with_obs: bool = True) -> "Outputs":
-        return Outputs(np.zeros((rows, n, 7, 7, 3), dtype=np.uint8) if with_obs else None,
+    def empty(rows: int, n: int, with_obs: bool = True, obs_mode: int = 0) -> "Outputs":
+        shape = (rows, n, 7, 7, 3) if obs_mode == 0 else (rows, n, 7, 7)
+        return Outputs(np.zeros(shape, dtype=np.uint8) if with_obs else None,
                        np.zeros((rows, n), dtype=np.float32),
                        np.zeros((rows, n), dtype=np.uint8),
                        np.zeros((rows, n), dtype=np.uint8))
 
 
 def reset(batch: Batch, state: State, out: Outputs | None = None, nthreads: int = 0) -> Outputs:
-    out = out or Outputs.empty(1, batch.n)
+    out = out or Outputs.empty(1, batch.n, obs_mode=batch.obs_mode)
     keep: list = []
     cb = _cbatch(batch, keep)
     cs = _cstate(state)
@@ -257,7 +270,7 @@ def rollout(batch: Batch, state: State, n_steps: int, actions: np.ndarray | None
     """Run n_steps steps; step k lands in output row k % rows.  Without
     actions the random policy draws at each env's own call count."""
     rows = n_steps if rows is None else rows
-    out = Outputs.empty(rows, batch.n, with_obs)
+    out = Outputs.empty(rows, batch.n, with_obs, batch.obs_mode)
     if actions is not None:
         actions = np.ascontiguousarray(actions, dtype=np.uint8)
         assert actions.shape == (n_steps, batch.n), actions.shape

@@ -10,9 +10,9 @@
  * It shares no code, header, table or constant with the GPU library.
  *
  * What it follows:
- *   - the timestep protocol and autoreset (Sec. 3.2.2, "Stateful and fully
- *     jittable": timestep tuple, reset pads action -1 / reward 0, step
- *     autoresets when done);
+ *   - the timestep protocol and autoreset (Sec. 3.2.2: the timestep tuple,
+ *     the reset padding the action with -1 and the reward with 0, and a
+ *     step that resets by itself once the episode has ended);
  *   - the systems in their order: intervention, transition, observation,
  *     reward, termination (Table "systems"; App. A);
  *   - the entities and components (Tables "components", "entities"):
@@ -438,6 +438,28 @@ void ox_observe(const uint8_t *grid, int S, int ax, int ay, int dir,
     }
 }
 
+/* categorical_first_person (Table "observations"): the entity-id grid  */
+/* of the same 7x7 view, [j][i], one byte per cell: the type index of a  */
+/* visible cell, 0 where unseen; the agent's cell shows the carried      */
+/* object's type (1 for an empty hand).  Pinned by the type channels of  */
+/* the hand-worked views in tests/golden/.                               */
+void ox_observe_categorical(const uint8_t *grid, int S, int ax, int ay, int dir,
+                            int32_t carry, uint8_t *obs /* [7][7] */) {
+  uint8_t sym[OX_VIEW * OX_VIEW * 3];
+  ox_observe(grid, S, ax, ay, dir, carry, sym);
+  for (int k = 0; k < OX_VIEW * OX_VIEW; ++k) obs[k] = sym[3 * k];
+}
+
+/* bytes of one observation record in a mode: 0 symbolic_first_person,
+ * 1 categorical_first_person */
+static size_t obs_bytes(int mode) { return mode == 1 ? 49 : 147; }
+
+static void emit_obs(int mode, const uint8_t *grid, int S, int ax, int ay, int dir,
+                     int32_t carry, uint8_t *obs) {
+  if (mode == 1) ox_observe_categorical(grid, S, ax, ay, dir, carry, obs);
+  else ox_observe(grid, S, ax, ay, dir, carry, obs);
+}
+
 /* ------------------------------------------------------------------ */
 /* Reward R (Sec. 3.2.1, Eq. (1); Table "rewards", on_goal_reached),  */
 /* in fp32, three separately rounded operations:                       */
@@ -522,7 +544,7 @@ static void move_obstacles(uint8_t *grid, int S, int n, int ax, int ay,
 /* reward -1, as MiniGrid's version does.                              */
 /* ------------------------------------------------------------------ */
 static void step_one(int family, int S, int param, int32_t T, uint64_t seed,
-                     uint32_t rng_id, int reward_mode, ox_env_ref e,
+                     uint32_t rng_id, int reward_mode, int obs_mode, ox_env_ref e,
                      uint32_t action, uint8_t *obs, float *reward,
                      uint8_t *flags, uint8_t *rec_action) {
   if (*e.done_prev) {
@@ -532,7 +554,7 @@ static void step_one(int family, int S, int param, int32_t T, uint64_t seed,
     *e.t = 0;
     *e.carry = O_EMPTY;
     *e.done_prev = 0;
-    if (obs) ox_observe(e.grid, S, *e.x, *e.y, *e.dir, *e.carry, obs);
+    if (obs) emit_obs(obs_mode, e.grid, S, *e.x, *e.y, *e.dir, *e.carry, obs);
     *reward = 0.0f;
     *flags = OX_FLAG_FIRST;
     *rec_action = OX_ACTION_NONE;
@@ -595,7 +617,7 @@ static void step_one(int family, int S, int param, int32_t T, uint64_t seed,
                      (truncated ? OX_FLAG_TRUNCATED : 0));
   *rec_action = (uint8_t)action;
   *e.done_prev = (uint8_t)(terminated || truncated);
-  if (obs) ox_observe(e.grid, S, *e.x, *e.y, *e.dir, *e.carry, obs);
+  if (obs) emit_obs(obs_mode, e.grid, S, *e.x, *e.y, *e.dir, *e.carry, obs);
 }
 
 /* ------------------------------------------------------------------ */
@@ -603,7 +625,8 @@ static void step_one(int family, int S, int param, int32_t T, uint64_t seed,
 /*   family[i], side[i], param[i], max_steps[i], seed[i], rng_id[i],  */
 /*   grid + grid_off[i] ([side][side][3]),                             */
 /*   x, y, dir, t, carry, episode, done_prev.                          */
-/* Outputs are [N] rows; obs rows are 147 bytes; obs may be NULL.      */
+/* Outputs are [N] rows; obs records are 147 bytes (49 in the          */
+/* categorical mode); obs may be NULL.                                 */
 /* nthreads > 0 runs envs in parallel with OpenMP (timing mode).       */
 /* ------------------------------------------------------------------ */
 typedef struct {
@@ -615,6 +638,7 @@ typedef struct {
   const uint64_t *grid_off;
   int32_t reward_mode;
   const uint8_t *param;   /* per env family parameter, or NULL (all 0) */
+  int32_t obs_mode;       /* 0 symbolic_first_person, 1 categorical_first_person */
 } ox_batch;
 
 typedef struct {
@@ -664,8 +688,8 @@ int ox_reset(const ox_batch *b, const ox_state *s, uint8_t *obs, float *reward,
     *e.done_prev = 0;
     *e.calls = 0;
     if (obs)
-      ox_observe(e.grid, b->side[i], *e.x, *e.y, *e.dir, *e.carry,
-                 obs + (size_t)147 * i);
+      emit_obs(b->obs_mode, e.grid, b->side[i], *e.x, *e.y, *e.dir, *e.carry,
+               obs + obs_bytes(b->obs_mode) * i);
     if (reward) reward[i] = 0.0f;
     if (flags) flags[i] = OX_FLAG_FIRST;
     if (action) action[i] = OX_ACTION_NONE;
@@ -691,8 +715,9 @@ int ox_rollout(const ox_batch *b, const ox_state *s, int32_t n_steps,
       if (actions) a = actions[(size_t)k * N + i];
       else a = ox_policy_action(b->seed[i], b->rng_id[i], *e.calls);
       step_one(b->family[i], b->side[i], PARAM(b, i), b->max_steps[i],
-               b->seed[i], b->rng_id[i], b->reward_mode, e, a,
-               obs ? obs + 147 * (row * N + i) : NULL, reward + row * N + i,
+               b->seed[i], b->rng_id[i], b->reward_mode, b->obs_mode, e, a,
+               obs ? obs + obs_bytes(b->obs_mode) * (row * N + i) : NULL,
+               reward + row * N + i,
                flags + row * N + i, action + row * N + i);
       *e.calls += 1u;
     }

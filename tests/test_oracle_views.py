@@ -159,3 +159,35 @@ def test_open_field_sees_everything(ox):
         exp[:, :] = (1, 0, 0)
         exp[6, 3] = (5, 3, 0)
         np.testing.assert_array_equal(o, exp)
+
+
+@pytest.mark.parametrize("case", _cases(), ids=lambda c: c["name"][:2])
+def test_hand_worked_categorical_views(ox, case):
+    """categorical_first_person (Table 'observations'): the hand-worked
+    views' type channel, one byte per cell."""
+    g, x, y, d = gt.parse("\n".join(case["picture"]))
+    obs = ox.observe_categorical(g, x, y, d, gt.carry_of(*case["carry"]))
+    np.testing.assert_array_equal(obs, np.array(case["type"]))
+
+
+def test_categorical_batches_record_49_bytes(ox):
+    """A categorical batch writes 49-byte records at 49 * (row * N + i) and
+    its dynamics equal the symbolic batch's (only the record differs)."""
+    from paper_2407_19396_amd import workloads as wl
+    t = wl.mixed_table(300, seed=5, mix_seed=6)
+    outs, states = [], []
+    for mode in (0, 1):
+        b = ox.Batch(t.family, t.side, t.max_steps, t.seed, t.rng_id, 0, t.param, mode)
+        s = ox.State.empty(b)
+        first = ox.reset(b, s)
+        out = ox.rollout(b, s, 40, None)
+        outs.append((first, out))
+        states.append(s)
+    (f0, o0), (f1, o1) = outs
+    assert o1.obs.shape == (40, 300, 7, 7) and f1.obs.shape == (1, 300, 7, 7)
+    np.testing.assert_array_equal(o1.obs, o0.obs[..., 0])
+    np.testing.assert_array_equal(f1.obs, f0.obs[..., 0])
+    for f in ("reward", "flags", "action"):
+        np.testing.assert_array_equal(getattr(o1, f), getattr(o0, f))
+    for f in ox.STATE_FIELDS:
+        np.testing.assert_array_equal(getattr(states[1], f), getattr(states[0], f))
