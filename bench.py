@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 OBS = 147
 RECORD_BYTES = OBS + 4 + 1 + 1          # obs + reward + flags + action per env-step
-STATE_BYTES_PER_ENV = 4 * 5 + 4 + 1 + 4  # x, y, dir, t, carry + episode + done_prev + calls
+STATE_BYTES_PER_ENV = 4 * 5 + 4 + 1 + 4 + 16  # x, y, dir, t, carry + episode + done_prev + calls + obstacles
 
 
 WORKLOADS = {
@@ -39,6 +39,8 @@ WORKLOADS = {
     "empty5": "16 Empty 5x5, T=100, random policy on device, trajectory ring in HBM",
     "lava": "lava tasks: 262144 envs in equal shares of LavaGap S5/S6/S7, Crossings S9N1/S9N2/S9N3/"
             "S11N5, DistShift1 (6x6), DistShift2 (8x8), random policy on device, trajectory ring in HBM",
+    "dynobs": "Dynamic-Obstacles tasks: 262144 envs in equal shares of 5x5 (2 balls), 6x6 (3), 8x8 (4), "
+              "16x16 (8), random policy on device, trajectory ring in HBM",
 }
 
 
@@ -46,10 +48,11 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def fused_bytes(n_envs: int, grid_bytes: int, k: int) -> float:
+def fused_bytes(n_envs: int, grid_bytes: int, k: int, obs_bytes: int = OBS) -> float:
     """Algorithmic HBM bytes of one fused launch of k steps: every record
     written once, the state (grids + scalars) read and written once."""
-    return n_envs * k * RECORD_BYTES + 2.0 * (grid_bytes + STATE_BYTES_PER_ENV * n_envs)
+    record = obs_bytes + 4 + 1 + 1
+    return n_envs * k * record + 2.0 * (grid_bytes + STATE_BYTES_PER_ENV * n_envs)
 
 
 def cpu_baseline(table, n_envs: int, n_steps: int) -> dict:
@@ -72,7 +75,8 @@ def cpu_baseline(table, n_envs: int, n_steps: int) -> dict:
                       f"observations on, {dt:.1f} s"}
 
 
-def run_serving(capacity: float, n_requests: int, loads, K: int, budget_gib: int) -> list:
+def run_serving(capacity: float, n_requests: int, loads, K: int, budget_gib: int,
+                inflight: int = 2) -> list:
     """Poisson serving at fractions of the measured fused capacity."""
     import torch
     from paper_2407_19396_amd import gridenv as ge
@@ -87,7 +91,7 @@ def run_serving(capacity: float, n_requests: int, loads, K: int, budget_gib: int
     for load in loads:
         rate = load * capacity / ework
         reqs = wl.serving_requests(n_requests, rate, master_seed=int(load * 1000))
-        res = ge.serve_run(srv, reqs, K, budget, arena)
+        res = ge.serve_run(srv, reqs, K, budget, arena, max_inflight=inflight)
         lat = res["latency_s"] * 1e3
         wait = (res["admit_s"] - res["arrival_s"]) * 1e3
         rec = {"load": load, "requests": n_requests, "completed": res["completed"],
@@ -119,6 +123,10 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner, use library defaults")
     ap.add_argument("--ring", type=int, default=0, help="trajectory ring rows (0: K)")
     ap.add_argument("--plain-steps", type=int, default=512)
+    ap.add_argument("--obs", default="symbolic", choices=["symbolic", "categorical"],
+                    help="observation function: symbolic (147 B) or categorical (49 B) first person")
+    ap.add_argument("--graph", action="store_true",
+                    help="capture the timed rollout in a HIP graph and time its replay")
     ap.add_argument("--plain-actions", action="store_true",
                     help="plain steps take an external action buffer instead of the device policy")
     ap.add_argument("--no-cpu", action="store_true")
@@ -127,6 +135,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests per serving load level (0: skip serving)")
     ap.add_argument("--serve-K", type=int, default=64)
+    ap.add_argument("--serve-inflight", type=int, default=2, help="launches enqueued ahead of the device")
+    ap.add_argument("--serve-loads", default="0.5,0.8,0.95")
     ap.add_argument("--serve-budget-gib", type=int, default=64)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device-to-device copy of this size first (calibrates HBM counters)")
@@ -154,19 +164,22 @@ def main():
             "tworoom8": lambda: wl.workload_tworoom8(seed=0),
             "empty8": lambda: wl.workload_empty8(seed=0),
             "empty5": lambda: wl.workload_empty5(seed=0),
-            "lava": lambda: wl.workload_lava(seed=0, n=args.envs or 262144)}[args.workload]
+            "lava": lambda: wl.workload_lava(seed=0, n=args.envs or 262144),
+            "dynobs": lambda: wl.workload_dynobs(seed=0, n=args.envs or 262144)}[args.workload]
     table = make()
-    if args.envs and args.workload not in ("mixed", "lava"):
+    if args.envs and args.workload not in ("mixed", "lava", "dynobs"):
         table = table.subset(np.arange(args.envs) % table.n)
-    env = ge.GridEnv(table)
-    first = ge.Traj.alloc(1, table.n)
+    obs_mode = 1 if args.obs == "categorical" else 0
+    obs_bytes = 49 if obs_mode else OBS
+    env = ge.GridEnv(table, obs_mode=obs_mode)
+    first = ge.Traj.alloc(1, table.n, obs_mode=obs_mode)
     stream = torch.cuda.current_stream()
     tuned = None
     if args.K or args.blocks or args.no_tune:
         env.set_launch(args.K or env.info()["k_default"], args.blocks)
     else:
         from paper_2407_19396_amd import autotune
-        probe = ge.Traj.alloc(512, table.n)
+        probe = ge.Traj.alloc(512, table.n, obs_mode=obs_mode)
         env.reset(first)
         tuned = autotune.tune(env, probe, log=log)
         del probe
@@ -176,19 +189,31 @@ def main():
     ring = args.ring or K
     log(f"[bench] {table.name}: grid {info['grid_bytes'] / 1e6:.1f} MB, tiles {info['n_tiles']}, "
         f"LDS/WG {info['lds_bytes']} B, blocks {info['blocks']}, K {K}, ring {ring}")
-    traj = ge.Traj.alloc(ring, table.n)
+    traj = ge.Traj.alloc(ring, table.n, obs_mode=obs_mode)
     env.reset(first)
     # warmup (also advances episodes away from the synchronous start)
     env.rollout(args.warmup, traj, K=K)
     torch.cuda.synchronize()
     log("[bench] warmup done")
 
-    # timed fused run
+    # timed fused run (optionally as the replay of a captured graph)
+    graph = None
+    if args.graph:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            env.rollout(args.steps, traj, K=K)
+        graph.replay()                      # one untimed replay
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        log("[bench] rollout captured in a HIP graph")
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     start.record(stream)
-    env.rollout(args.steps, traj, K=K)
+    if graph is not None:
+        graph.replay()
+    else:
+        env.rollout(args.steps, traj, K=K)
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -243,19 +268,20 @@ def main():
             f"{np.percentile(plain_lat, 50) * 1e3:.1f} us")
 
     per_launch_ms = ms / launches
-    bytes_launch = fused_bytes(table.n, info["grid_bytes"], K)
+    bytes_launch = fused_bytes(table.n, info["grid_bytes"], K, obs_bytes)
     achieved = bytes_launch / (per_launch_ms / 1e3) / 1e9
     from paper_2407_19396_amd import profiling
     traffic = None
-    if args.workload == "mixed" and args.steps % K == 0:
+    if args.workload == "mixed" and args.steps % K == 0 and obs_mode == 0:
         traffic = profiling.traffic_bytes(os.path.join(ROOT, "profiles", "k_fused_mixed262144.txt"),
                                           K, table.n)
     serving = None
-    if args.serve_requests > 0 and args.workload == "mixed":
+    if args.serve_requests > 0 and args.workload == "mixed" and obs_mode == 0:
         del traj, env
         torch.cuda.empty_cache()
-        serving = run_serving(value, args.serve_requests, (0.5, 0.8, 0.95), args.serve_K,
-                              args.serve_budget_gib)
+        loads = tuple(float(x) for x in args.serve_loads.split(","))
+        serving = run_serving(value, args.serve_requests, loads, args.serve_K,
+                              args.serve_budget_gib, args.serve_inflight)
     cpu = None
     if not args.no_cpu:
         log("[bench] timing the CPU oracle on a sample")
@@ -278,7 +304,8 @@ def main():
         "config": {"workload": WORKLOADS[args.workload],
                    "n_envs": table.n, "K": K, "ring_rows": ring, "blocks": info["blocks"],
                    "lds_bytes_per_wg": info["lds_bytes"], "global_batch": table.n,
-                   "autotuned": tuned is not None},
+                   "autotuned": tuned is not None, "hip_graph": graph is not None,
+                   "observation": args.obs},
         "fused_launch_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "plain": None if plain_rate is None else {
             "value": plain_rate, "unit": "env-steps/s", "steps": args.plain_steps,

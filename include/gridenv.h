@@ -11,11 +11,13 @@
  * the action with -1 and the reward with 0.  Inside a step the systems of
  * Table "systems" (App. A) apply in order: intervention (the action),
  * transition (identity for these families), observation, reward,
- * termination.  The families are those of Table "envs" with a static
- * world: Empty, DoorKey, FourRooms (reward R1) and the lava families
- * LavaGap, Crossings, DistShift (reward R2).  An episode terminates on
- * reaching the goal or walking into lava (Tables "rewards" and
- * "terminations": on_goal_reached, on_lava_fall).
+ * termination.  The families are those of Table "envs": Empty, DoorKey,
+ * FourRooms (reward R1), the lava families LavaGap, Crossings, DistShift
+ * (reward R2) and Dynamic-Obstacles (reward R3), whose balls move every
+ * step (its transition system).  An episode terminates on reaching the
+ * goal or walking into lava (Tables "rewards" and "terminations":
+ * on_goal_reached, on_lava_fall), or, in Dynamic-Obstacles, on stepping
+ * forward at a ball or wall.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -41,10 +43,10 @@
  * Encoding (MiniGrid's canonical indices; Table "components": Tag, Colour,
  * State; Table "observations": symbolic encodings)
  *   cell triple (type, colour, state): type 0 unseen, 1 empty, 2 wall,
- *   4 door, 5 key, 8 goal, 9 lava; colour 0 red, 1 green, 2 blue,
+ *   4 door, 5 key, 6 ball, 8 goal, 9 lava; colour 0 red, 1 green, 2 blue,
  *   3 purple, 4 yellow, 5 grey; door state 0 open, 1 closed, 2 locked.
  *   Walls are (2,5,0), empty cells (1,0,0), the goal (8,1,0), keys (5,c,0),
- *   doors (4,c,s), lava (9,0,0).
+ *   doors (4,c,s), lava (9,0,0), obstacles (6,2,0).
  *   actions: 0 turn left, 1 turn right, 2 forward, 3 pickup, 4 drop,
  *   5 toggle, 6 done; any other value acts as 6 (no effect).
  *   heading: 0 east (+x), 1 south (+y), 2 west (-x), 3 north (-y).
@@ -61,11 +63,14 @@
  *   x, y, dir, t (int32): position, heading, steps since the last reset;
  *   carry (int32), episode (uint32: resets so far), done_prev (uint8:
  *   the last step ended the episode, so the next call resets), calls
- *   (uint32: step calls since env_reset, the random policy's counter).
+ *   (uint32: step calls since env_reset, the random policy's counter),
+ *   obst (bytes [16] per env: the Dynamic-Obstacles balls' x, y in their
+ *   move order, 0xFF for unused slots and for the other families).
  *
  * Outputs (struct gx_traj): row r of each buffer holds n_envs entries:
  *   obs: bytes [rows][n_envs][7][7][3], view row j (0 = farthest ahead,
  *     6 = the agent's row), view column i (0 = the agent's left), channel;
+ *     [rows][n_envs][7][7] (the type channel) in the categorical mode;
  *     may be NULL to skip observations;
  *   reward: float [rows][n_envs]; flags, action: bytes [rows][n_envs]
  *     (action is the action applied, 0xFF on reset steps).
@@ -87,8 +92,9 @@ extern "C" {
 #define GX_ESTATE -4   /* call order violated (e.g. a step before any reset) */
 #define GX_EBUSY -5    /* a server has no free tiles for the request right now */
 
-/* Families (Table "envs").  The lava families start the agent at (1, 1)
- * facing east; walking into lava gives reward -1 in both reward modes. */
+/* Families (Table "envs").  The lava families and Dynamic-Obstacles start
+ * the agent at (1, 1) facing east; walking into lava gives reward -1 in
+ * both reward modes. */
 #define GX_FAMILY_EMPTY 0      /* Empty-SxS (single room), side 4..32 */
 #define GX_FAMILY_TWOROOM 1    /* DoorKey-SxS (two rooms, locked door), side 5..32 */
 #define GX_FAMILY_FOURROOMS 2  /* FourRooms, odd side 7..31 */
@@ -96,8 +102,13 @@ extern "C" {
 #define GX_FAMILY_CROSSINGS 4  /* Crossings-SSNN: param = N lava rivers, 1..min(8, S-3),
                                   odd side 5..31 */
 #define GX_FAMILY_DISTSHIFT 5  /* DistShift: param = variant 1 or 2, side 6..32 */
+#define GX_FAMILY_DYNOBS 6     /* Dynamic-Obstacles: param = balls 1..8 (at most
+                                  (S-2)^2 - 2), side 5..32; three actions (any
+                                  other acts as 0); every step the balls move at
+                                  random first; forward at a ball or wall: -1, end */
 
-#define GX_OBS_BYTES 147
+#define GX_OBS_BYTES 147      /* symbolic first-person record */
+#define GX_OBS_CAT_BYTES 49   /* categorical first-person record */
 
 typedef struct gx_ctx gx_ctx;
 
@@ -108,6 +119,11 @@ typedef struct {
                                   (Sec. 3.2.1, Eq. (1), t counted after the
                                   step, fp32); 1: r = 1 (the paper's Markovian
                                   reward) */
+  int32_t obs_mode;            /* observation function (Table "observations"):
+                                  0 symbolic_first_person, records [7][7][3]
+                                  (147 bytes); 1 categorical_first_person,
+                                  records [7][7] of type ids (49 bytes), the
+                                  same view and occlusion */
   const uint8_t* family;       /* [n_envs] GX_FAMILY_* */
   const uint8_t* side;         /* [n_envs] grid side S (height = width) */
   const uint8_t* param;        /* [n_envs] family parameter, or NULL: all 0 */
@@ -124,6 +140,7 @@ typedef struct {
   uint32_t* episode;
   uint8_t* done_prev;
   uint32_t* calls;
+  uint8_t* obst;               /* [n_envs][16], 16-byte aligned */
 } gx_state;
 
 /* Caller-owned device outputs; `rows` rows of n_envs entries each. */

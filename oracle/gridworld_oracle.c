@@ -496,6 +496,7 @@ static int is_pickable(int type) {
 /* such cell in row-major order, k = u(count) of its word; with no    */
 /* such cell it stays.  Ball b's word: key = seed, counter = (rng_id, */
 /* call, b / 4, 2), lane b % 4, call = the env's step-call count.     */
+/* A list entry off the interior (a malformed state) does not move.   */
 /* Pinned by hand-worked moves, uniformity and invariant tests.       */
 /* ------------------------------------------------------------------ */
 static void move_obstacles(uint8_t *grid, int S, int n, int ax, int ay,
@@ -508,6 +509,7 @@ static void move_obstacles(uint8_t *grid, int S, int n, int ax, int ay,
     uint32_t word = out[b % 4];
     int bx = obst[2 * b], by = obst[2 * b + 1];
     int cx[8], cy[8], count = 0;
+    if (bx < 1 || by < 1 || bx > S - 2 || by > S - 2) continue;   /* malformed entry */
     for (int dy = -1; dy <= 1; ++dy)
       for (int dx = -1; dx <= 1; ++dx) {
         int x = bx + dx, y = by + dy;

@@ -33,6 +33,8 @@ constexpr int kObsBytes = kView * kView * 3;        // 147
 constexpr int kStageBytes = kWave * kObsBytes;      // 9408, a multiple of 16
 constexpr int kHalfStageBytes = kStageBytes / 2;    // 4704, a multiple of 16
 constexpr int kObsWords = 37;                       // ceil(147 / 4)
+constexpr int kCatBytes = kView * kView;            // categorical record: 49
+constexpr int kCatWords = 13;                       // ceil(49 / 4)
 
 // Cell triples are packed as type | colour << 8 | state << 16 (MiniGrid's
 // object, colour and state indices).  Bit 31 marks a see-through cell.
@@ -41,6 +43,7 @@ constexpr uint32_t kEmpty = 1, kWall = 2, kDoor = 4, kKey = 5, kBall = 6, kBox =
 constexpr uint32_t kGreen = 1, kGrey = 5;
 constexpr uint32_t kOpen = 0, kClosed = 1, kLocked = 2;
 constexpr uint32_t kSeeBit = 1u << 31;
+constexpr uint32_t kSeeBits = 0xFE000000u;   // see flags of view columns 0-6 at bits 31-25
 constexpr uint32_t kCellWall = kWall | (kGrey << 8);
 constexpr uint32_t kCellEmpty = kEmpty;
 constexpr uint32_t kCellGoal = kGoal | (kGreen << 8);
@@ -51,8 +54,11 @@ constexpr uint32_t kActionNone = 0xFF;
 enum : uint32_t { kLeft = 0, kRight = 1, kForward = 2, kPickup = 3, kDrop = 4, kToggle = 5 };
 enum : uint32_t {
   kFamEmpty = 0, kFamTwoRoom = 1, kFamFourRooms = 2,
-  kFamLavaGap = 3, kFamCrossings = 4, kFamDistShift = 5
+  kFamLavaGap = 3, kFamCrossings = 4, kFamDistShift = 5, kFamDynObs = 6
 };
+constexpr int kMaxObst = 8;
+constexpr uint32_t kBlue = 2;
+constexpr uint32_t kCellBall = kBall | (kBlue << 8);
 
 __device__ __forceinline__ uint32_t see_through(uint32_t tri) {
   const uint32_t type = tri & 0xFF, state = (tri >> 16) & 0xFF;
@@ -116,7 +122,26 @@ struct Layout {
   uint32_t vmask, hmask;   // Crossings: river columns / rows (bit = coordinate)
   uint64_t vopen, hopen;   // Crossings: opening row of each river column, opening column
                            // of each river row, 5 bits each in ascending river order
+  uint32_t ob[4];          // Dynamic-Obstacles: ball b at bytes 2b (x), 2b + 1 (y); 0xFF unused
 };
+
+// (x, y) of ball b from a packed obstacle list
+__device__ __forceinline__ uint32_t obst_at(const uint32_t (&ob)[4], int b) {
+  return (ob[b >> 1] >> (16 * (b & 1))) & 0xFFFFu;
+}
+
+__device__ __forceinline__ void obst_set(uint32_t (&ob)[4], int b, uint32_t x, uint32_t y) {
+  const int sh = 16 * (b & 1);
+  ob[b >> 1] = (ob[b >> 1] & ~(0xFFFFu << sh)) | ((x | (y << 8)) << sh);
+}
+
+__device__ __forceinline__ bool is_ball(const Layout& L, int x, int y) {
+  const uint32_t xy = (uint32_t)x | ((uint32_t)y << 8);
+  bool hit = false;
+#pragma unroll
+  for (int b = 0; b < kMaxObst; ++b) hit = hit || obst_at(L.ob, b) == xy;
+  return hit;
+}
 
 // Layout-stream draws taken in order, one Philox block per 4 words.
 struct DrawStream {
@@ -207,28 +232,46 @@ __device__ __forceinline__ bool crossings_lava(const Layout& L, int x, int y) {
   return lava;
 }
 
+// q = k / w, r = k % w for k < 2^16 and 1 <= w <= 32.  The single-precision
+// quotient is within a few ulp of k / w, far less than the 1 / w distance
+// between its fractional part and the next integer when k % w != 0; when
+// k % w == 0 it may fall just short of q, which the correction repairs.
+__device__ __forceinline__ void small_divmod(uint32_t k, uint32_t w, uint32_t& q, uint32_t& r) {
+  q = (uint32_t)((float)k * __builtin_amdgcn_rcpf((float)w));
+  r = k - q * w;
+  const bool under = r >= w;
+  q += under ? 1u : 0u;
+  r -= under ? w : 0u;
+}
+
+// idx-th free cell, row-major, of a four-room grid of side S = 2m + 1 with
+// openings (m, g1), (m, g2) in the vertical wall (g1 < m < g2) and
+// (g3, m), (g4, m) in the horizontal one.  Rows other than m hold S - 3 free
+// cells (the wall column removed), S - 2 in the opening rows g1 and g2; row
+// m holds the two openings.
 __device__ __forceinline__ void fourrooms_cell(int S, int m, int g1, int g2, int g3, int g4,
                                                uint32_t idx, int& x, int& y) {
-  // idx-th free cell, row-major, of a four-room grid with openings
-  // (m, g1), (m, g2) in the vertical wall and (g3, m), (g4, m) in the horizontal one
-  y = 1;
-  for (int yy = 1; yy <= S - 2; ++yy) {
-    const uint32_t cnt = yy == m ? 2u : (uint32_t)(S - 2) - ((yy == g1 || yy == g2) ? 0u : 1u);
-    if (idx < cnt) {
-      y = yy;
-      if (yy == m) {
-        x = idx == 0 ? g3 : g4;
-      } else if (yy == g1 || yy == g2) {
-        x = 1 + (int)idx;
-      } else {
-        x = 1 + (int)idx;
-        if (x >= m) x += 1;
-      }
-      return;
-    }
-    idx -= cnt;
+  const uint32_t W = (uint32_t)(S - 3);
+  const uint32_t top = (uint32_t)(m - 1) * W + 1u;   // free cells in rows 1 .. m-1
+  if (idx - top < 2u) {                              // row m
+    y = m;
+    x = idx == top ? g3 : g4;
+    return;
   }
-  x = 1;
+  const bool low = idx >= top;
+  const int row0 = low ? m + 1 : 1, gap = low ? g2 : g1;
+  const uint32_t k = low ? idx - top - 2u : idx;
+  const uint32_t before = (uint32_t)(gap - row0) * W;   // cells in the rows above the gap row
+  if (k - before <= W) {                                // the gap row: every interior cell
+    y = gap;
+    x = 1 + (int)(k - before);
+    return;
+  }
+  uint32_t q, r;
+  small_divmod(k < before ? k : k - 1u, W, q, r);
+  y = row0 + (int)q;
+  x = 1 + (int)r;
+  x += x >= m ? 1 : 0;
 }
 
 // meta = family | side << 8 | parameter << 16 (Crossings: rivers; DistShift:
@@ -246,6 +289,40 @@ __device__ Layout make_layout(uint32_t meta, uint2 seed, uint32_t rng_id, uint32
   L.gy = S - 2;
   L.vmask = L.hmask = 0;
   L.vopen = L.hopen = 0;
+  L.ob[0] = L.ob[1] = L.ob[2] = L.ob[3] = 0xFFFFFFFFu;
+  if (fam == kFamDynObs) {
+    // balls in order, ball b at the draw-b-th free interior cell other than
+    // the agent's (1, 1): linear interior index c with c - #{earlier balls
+    // <= c} = draw + 1, found by iterating c = draw + 1 + #{balls <= c}
+    L.ax = L.ay = 1;
+    L.dir = 0;
+    const uint32_t w = (uint32_t)(S - 2);
+    const uint4 w0 = philox10(make_uint4(rng_id, episode, 0u, 0u), seed);
+    const uint4 w1 = param > 4 ? philox10(make_uint4(rng_id, episode, 1u, 0u), seed)
+                               : make_uint4(0, 0, 0, 0);
+    uint32_t p[kMaxObst];
+#pragma unroll
+    for (int b = 0; b < kMaxObst; ++b) {
+      p[b] = 0xFFFFu;
+      if (b < param) {
+        const uint32_t word = pick4(b < 4 ? w0 : w1, (uint32_t)(b & 3));
+        const uint32_t k = bounded(word, w * w - 2u - (uint32_t)b);
+        uint32_t c = k + 1u;
+#pragma unroll
+        for (int it = 0; it < b; ++it) {
+          uint32_t below = 0;
+#pragma unroll
+          for (int j = 0; j < b; ++j) below += p[j] <= c ? 1u : 0u;
+          c = k + 1u + below;
+        }
+        p[b] = c;
+        uint32_t q, r;
+        small_divmod(c, w, q, r);
+        obst_set(L.ob, b, 1u + r, 1u + q);
+      }
+    }
+    return L;
+  }
   if (fam >= kFamLavaGap) {
     L.ax = L.ay = 1;
     L.dir = 0;
@@ -270,8 +347,10 @@ __device__ Layout make_layout(uint32_t meta, uint2 seed, uint32_t rng_id, uint32
   if (fam == kFamEmpty) {
     const int w = S - 2;
     const uint32_t k = bounded(w0.x, (uint32_t)(w * w - 1));   // interior minus the last (goal) cell
-    L.ax = 1 + (int)(k % (uint32_t)w);
-    L.ay = 1 + (int)(k / (uint32_t)w);
+    uint32_t q, r;
+    small_divmod(k, (uint32_t)w, q, r);
+    L.ax = 1 + (int)r;
+    L.ay = 1 + (int)q;
     L.dir = (int)bounded(w0.y, 4u);
   } else if (fam == kFamTwoRoom) {
     L.a = 2 + (int)bounded(w0.x, (uint32_t)(S - 4));
@@ -279,12 +358,15 @@ __device__ Layout make_layout(uint32_t meta, uint2 seed, uint32_t rng_id, uint32
     L.colour = (int)bounded(w0.z, 6u);
     const uint32_t lw = (uint32_t)(L.a - 1), n = lw * (uint32_t)(S - 2);
     const uint32_t kk = bounded(w0.w, n);
-    L.kx = 1 + (int)(kk % lw);
-    L.ky = 1 + (int)(kk / lw);
+    uint32_t q, r;
+    small_divmod(kk, lw, q, r);
+    L.kx = 1 + (int)r;
+    L.ky = 1 + (int)q;
     uint32_t ka = bounded(w1.x, n - 1u);
     ka += ka >= kk ? 1u : 0u;
-    L.ax = 1 + (int)(ka % lw);
-    L.ay = 1 + (int)(ka / lw);
+    small_divmod(ka, lw, q, r);
+    L.ax = 1 + (int)r;
+    L.ay = 1 + (int)q;
     L.dir = (int)bounded(w1.y, 4u);
   } else {
     const int m = S / 2;
@@ -321,6 +403,8 @@ __device__ __forceinline__ uint32_t layout_cell(const Layout& L, int x, int y) {
     if (crossings_lava(L, x, y)) return kLava;
   } else if (L.fam == kFamDistShift) {
     if ((y == 1 || y == L.a) && x >= 3 && x <= S - 3) return kLava;
+  } else if (L.fam == kFamDynObs) {
+    if (is_ball(L, x, y)) return kCellBall;
   }
   return kCellEmpty;
 }
@@ -341,6 +425,8 @@ __device__ __forceinline__ Layout bcast_layout(const Layout& L, int r) {
             ((uint64_t)(uint32_t)bcast((int)(L.vopen >> 32), r) << 32);
   o.hopen = (uint64_t)(uint32_t)bcast((int)(uint32_t)L.hopen, r) |
             ((uint64_t)(uint32_t)bcast((int)(L.hopen >> 32), r) << 32);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) o.ob[i] = (uint32_t)bcast((int)L.ob[i], r);
   return o;
 }
 
@@ -352,7 +438,8 @@ struct ActResult {
   uint32_t new_front;
   bool front_changed;
   bool terminated;
-  bool lava;   // terminated by walking into lava
+  bool penalty;   // ended with reward -1: walked into lava, or (Dynamic-Obstacles)
+                  // stepped forward at a ball or wall
 };
 
 __device__ __forceinline__ ActResult intervene(uint32_t act, int& x, int& y, int& dir, uint32_t& carry,
@@ -376,10 +463,53 @@ __device__ __forceinline__ ActResult intervene(uint32_t act, int& x, int& y, int
   ActResult r;
   r.new_front = pick ? kCellEmpty : (drop ? carry : (unlock ? door_open : (flip ? door_flipped : front24)));
   r.front_changed = pick || drop || unlock || flip;
-  r.lava = act == kForward && type == kLava;
-  r.terminated = (act == kForward && type == kGoal) || r.lava;
+  r.penalty = act == kForward && type == kLava;
+  r.terminated = (act == kForward && type == kGoal) || r.penalty;
   carry = pick ? front24 : (drop ? kCellEmpty : carry);
   return r;
+}
+
+// ---------------------------------------------------------------------------
+// Transition system of Dynamic-Obstacles (Table "systems"; Fig. 1): every
+// ball, in list order, moves to a uniformly drawn empty cell of the 8
+// around it that the agent does not occupy (the k-th in row-major order,
+// k = u(count) of its word), or stays if there is none.  Ball b's word:
+// key = seed, counter (rng_id, call, b / 4, 2), lane b % 4.  Cells: the
+// grid accessor reads "is empty" and writes a ball or an empty cell.  List
+// entries off the interior (only a malformed state has them) do not move.
+// ---------------------------------------------------------------------------
+template <class Grid>
+__device__ __forceinline__ void move_obstacles(const Grid& g, int n, int ax, int ay, uint32_t (&ob)[4],
+                                               uint2 seed, uint32_t rng_id, uint32_t call) {
+  uint4 blk = make_uint4(0, 0, 0, 0);
+#pragma unroll
+  for (int b = 0; b < kMaxObst; ++b) {
+    if (b < n) {
+      if ((b & 3) == 0) blk = philox10(make_uint4(rng_id, call, (uint32_t)(b >> 2), 2u), seed);
+      const uint32_t word = pick4(blk, (uint32_t)(b & 3));
+      const uint32_t pos = obst_at(ob, b);
+      const int bx = (int)(pos & 0xFF), by = (int)(pos >> 8);
+      // an entry off the interior (a malformed state) is left alone, so no
+      // access ever leaves the env's grid
+      const bool inside = bx >= 1 && by >= 1 && bx <= g.S - 2 && by <= g.S - 2;
+      uint32_t mask = 0;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int dx = (i < 3) ? i - 1 : (i < 5 ? (i == 3 ? -1 : 1) : i - 6);
+        const int dy = (i < 3) ? -1 : (i < 5 ? 0 : 1);
+        const bool free = inside && g.empty(bx + dx, by + dy) && !(bx + dx == ax && by + dy == ay);
+        mask |= free ? (1u << i) : 0u;
+      }
+      if (mask) {
+        const int i = kth_bit(mask, (int)bounded(word, (uint32_t)__builtin_popcount(mask)));
+        const int dx = (i < 3) ? i - 1 : (i < 5 ? (i == 3 ? -1 : 1) : i - 6);
+        const int dy = (i < 3) ? -1 : (i < 5 ? 0 : 1);
+        g.put_empty(bx, by);
+        g.put_ball(bx + dx, by + dy);
+        obst_set(ob, b, (uint32_t)(bx + dx), (uint32_t)(by + dy));
+      }
+    }
+  }
 }
 
 // Reward of Eq. (1) in the time-discounted form 1 - 0.9 * (t / T), t after
@@ -391,10 +521,11 @@ __device__ __forceinline__ float goal_reward(int32_t t, int32_t T, int32_t mode)
   return __fsub_rn(1.0f, p);
 }
 
-// Reward of a step: -1 for walking into lava (R2 of Table "envs", in both
-// modes), the goal reward on reaching the goal, else 0.
+// Reward of a step: -1 for walking into lava (R2 of Table "envs") or, in
+// Dynamic-Obstacles, for stepping forward at a ball or wall (R3), in both
+// modes; the goal reward on reaching the goal; else 0.
 __device__ __forceinline__ float step_reward(const ActResult& r, int32_t t, int32_t T, int32_t mode) {
-  return r.lava ? -1.0f : (r.terminated ? goal_reward(t, T, mode) : 0.0f);
+  return r.penalty ? -1.0f : (r.terminated ? goal_reward(t, T, mode) : 0.0f);
 }
 
 // ---------------------------------------------------------------------------
@@ -423,8 +554,8 @@ __device__ __forceinline__ uint32_t visible_row(uint32_t seeds2, uint32_t see, u
 // Computes the lane's observation obs[j][i][c] (147 bytes) as the 38 words
 // u[0..37] it occupies once placed at byte 147 * slot of a record stage
 // (slot = the lane's position in the staged group; slot 0 starts a group).
-// rows.load(j, c) fills c[i] with the triple of view cell (i, j), kSeeBit set
-// when it is see-through.  Lanes with valid == false produce zeros (their
+// rows.load_all(c) fills c[j][i] with the triple of view cell (i, j) and, when
+// it is see-through, bit 31 - i set (no other bit of the top byte).  Lanes with valid == false produce zeros (their
 // loader must still be safe to call).
 //
 // Records are realigned to their byte offset with byte permutes.  A word
@@ -432,75 +563,99 @@ __device__ __forceinline__ uint32_t visible_row(uint32_t seeds2, uint32_t see, u
 // record starting mid-word already holds the lower record's tail, received
 // by a cross-lane shuffle; store_words writes exactly the words a record
 // owns.
-template <class Rows>
+template <bool kCat, class Rows>
 __device__ __forceinline__ void observe_words(const Rows& rows, uint32_t carry, bool valid, int slot,
                                               uint32_t (&u)[kObsWords + 1]) {
-  const uint32_t m = (uint32_t)(kObsBytes * slot) & 3u;
+  constexpr int kBytes = kCat ? kCatBytes : kObsBytes;
+  constexpr int kWords = kCat ? kCatWords : kObsWords;
+  const uint32_t m = (uint32_t)(kBytes * slot) & 3u;
   const uint32_t realign = 0x07060504u - m * 0x01010101u;
 
   // all 49 reads first: they are independent and stay in flight together
   uint32_t cells[kView][kView];
-#pragma unroll
-  for (int j = kView - 1; j >= 0; --j) rows.load(j, cells[j]);
+  rows.load_all(cells);
 
   uint32_t seeds = valid ? ((1u << 3) | (1u << 28)) : 0u;   // column 3, dual form
-  uint32_t later_first = 0;   // masked first cell of the row processed before (row j + 1)
-  uint32_t w_hi = 0;          // record word d + 1 (word 37 is past the end: zero)
+  // masked first cells of the row processed before (row j + 1); zero past
+  // the record's end
+  uint32_t later[3] = {0u, 0u, 0u};
+  uint32_t w_hi = 0;          // record word d + 1 (zero past the end)
 #pragma unroll
   for (int j = kView - 1; j >= 0; --j) {
     uint32_t (&c)[kView] = cells[j];
-    // see-through bits, bit i = column i: each funnel shift moves one flag in
-    uint32_t see = 0;
-#pragma unroll
-    for (int i = kView - 1; i >= 0; --i) see = __builtin_amdgcn_alignbit(see, c[i], 31);
+    // see-through bits: cell i carries its flag at bit 31 - i, so the row's
+    // flags are one OR away, already in the high half of the dual form
+    const uint32_t see = ((c[0] | c[1] | c[2]) | (c[3] | c[4] | c[5]) | c[6]) & kSeeBits;
     uint32_t next;
     const uint32_t vis = visible_row(seeds, see, next);
     seeds = next;
 #pragma unroll
     for (int i = 0; i < kView; ++i) c[i] &= (uint32_t)(((int32_t)(vis << (31 - i))) >> 31);
     if (j == kView - 1) c[3] = valid ? carry : 0u;   // the agent's cell shows what it carries
-    // record words whose lower cell lies in this row; word d spans cells
-    // 4d/3 and 4d/3 + 1 (byte b belongs to cell b / 3)
 #pragma unroll
-    for (int d = kObsWords - 1; d >= 0; --d) {
-      const int k = (4 * d) / 3;
-      if (k / kView != j) continue;
-      const int i = k - kView * j, off = (4 * d) % 3;
-      const uint32_t sel = off == 0 ? 0x04020100u : (off == 1 ? 0x05040201u : 0x06050402u);
-      const uint32_t wd = __builtin_amdgcn_perm(i + 1 < kView ? c[i + 1] : later_first, c[i], sel);
+    for (int d = kWords - 1; d >= 0; --d) {
+      uint32_t wd;
+      if (kCat) {
+        // word d holds the types of cells 4d .. 4d + 3 (byte b = cell b)
+        const int k = 4 * d;
+        if (k / kView != j) continue;
+        const int i = k - kView * j;
+        const uint32_t c0 = c[i];
+        const uint32_t c1 = i + 1 < kView ? c[i + 1] : later[i + 1 - kView];
+        const uint32_t c2 = i + 2 < kView ? c[i + 2] : later[i + 2 - kView];
+        const uint32_t c3 = i + 3 < kView ? c[i + 3] : later[i + 3 - kView];
+        wd = __builtin_amdgcn_perm(__builtin_amdgcn_perm(c3, c2, 0x0C0C0400u),
+                                   __builtin_amdgcn_perm(c1, c0, 0x0C0C0400u), 0x05040100u);
+      } else {
+        // word d spans cells 4d/3 and 4d/3 + 1 (byte b belongs to cell b / 3)
+        const int k = (4 * d) / 3;
+        if (k / kView != j) continue;
+        const int i = k - kView * j, off = (4 * d) % 3;
+        const uint32_t sel = off == 0 ? 0x04020100u : (off == 1 ? 0x05040201u : 0x06050402u);
+        wd = __builtin_amdgcn_perm(i + 1 < kView ? c[i + 1] : later[0], c[i], sel);
+      }
       u[d + 1] = __builtin_amdgcn_perm(w_hi, wd, realign);
       w_hi = wd;
     }
-    later_first = c[0];
+    later[0] = c[0];
+    later[1] = c[1];
+    later[2] = c[2];
   }
   u[0] = __builtin_amdgcn_perm(w_hi, 0u, realign);
-  // the word a record shares with the next one: u[36] when the record starts
-  // on a word boundary, u[37] when it starts two or three bytes in
-  const uint32_t tail = m == 0 ? u[kObsWords - 1] : u[kObsWords];
+  // the word a record shares with the next one (the one holding the next
+  // record's first byte): symbolic u[36] when the record starts on a word
+  // boundary, u[37] when it starts two or three bytes in; categorical u[12]
+  const uint32_t tail = kCat ? u[kCatWords - 1] : (m == 0 ? u[kObsWords - 1] : u[kObsWords]);
   const uint32_t lower_tail = (uint32_t)__shfl_up((int)tail, 1, kWave);
   if (m != 0) u[0] |= lower_tail;
 }
 
-// Writes the words a record owns (see observe_words) at stage + 147 * slot.
+// Writes the words a record owns (see observe_words) at stage + bytes * slot:
+// all but the word holding the next record's first byte, which that record
+// writes (symbolic: the next record starts inside word 36 unless m == 1 puts
+// it at word 37; categorical: inside word 12 unless m == 3).
+template <bool kCat>
 __device__ __forceinline__ void store_words(uint8_t* stage, int slot, const uint32_t (&u)[kObsWords + 1]) {
-  const uint32_t s = (uint32_t)(kObsBytes * slot);
+  constexpr int kBytes = kCat ? kCatBytes : kObsBytes;
+  constexpr int kWords = kCat ? kCatWords : kObsWords;
+  const uint32_t s = (uint32_t)(kBytes * slot);
   const uint32_t m = s & 3u;
   uint32_t* base = reinterpret_cast<uint32_t*>(stage) + (s >> 2);
 #pragma unroll
-  for (int q = 0; q < kObsWords - 1; ++q) base[q] = u[q];
-  if (m != 0) base[kObsWords - 1] = u[kObsWords - 1];
+  for (int q = 0; q < kWords - 1; ++q) base[q] = u[q];
+  if (kCat ? m == 3 : m != 0) base[kWords - 1] = u[kWords - 1];
 }
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-// Copies n_envs staged records (n_envs * 147 bytes, 1 <= n_envs <= kMaxEnvs) to
+// Copies n_envs staged records of kBytes bytes (1 <= n_envs <= kMaxEnvs) to
 // dst.  The aligned path issues all of a lane's 16-byte LDS reads before
 // its stores, so the reads are in flight together.
-template <int kMaxEnvs>
+template <int kMaxEnvs, int kBytes>
 __device__ __forceinline__ void copy_out(const uint8_t* stage, uint8_t* dst, int n_envs, int lane) {
-  constexpr int kMaxChunks = (kMaxEnvs * kObsBytes + 15) / 16;
+  constexpr int kMaxChunks = (kMaxEnvs * kBytes + 15) / 16;
   constexpr int kPerLane = (kMaxChunks + kWave - 1) / kWave;
-  const int bytes = n_envs * kObsBytes;
+  const int bytes = n_envs * kBytes;
   if (((reinterpret_cast<uintptr_t>(dst) & 15) == 0) && (bytes & 15) == 0) {
     const u32x4* src = reinterpret_cast<const u32x4*>(stage);
     u32x4* out = reinterpret_cast<u32x4*>(dst);
@@ -522,14 +677,15 @@ __device__ __forceinline__ void copy_out(const uint8_t* stage, uint8_t* dst, int
 // ---------------------------------------------------------------------------
 // Plain kernel
 // ---------------------------------------------------------------------------
+// Cell (x, y) for view column i: the triple, plus bit 31 - i if see-through.
 struct HbmCells {
   const uint8_t* g;
   int S;
-  __device__ __forceinline__ uint32_t operator()(int x, int y) const {
+  __device__ __forceinline__ uint32_t operator()(int x, int y, int i) const {
     if ((unsigned)x >= (unsigned)S || (unsigned)y >= (unsigned)S) return kCellWall;
     const uint8_t* p = g + 3 * (y * S + x);
     const uint32_t tri = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
-    return tri | see_through(tri);
+    return tri | (see_through(tri) >> i);
   }
 };
 
@@ -541,7 +697,11 @@ struct HbmRows {
     const int rx = -fy, ry = fx;
     const int bx = ax - 3 * rx + (6 - j) * fx, by = ay - 3 * ry + (6 - j) * fy;
 #pragma unroll
-    for (int i = 0; i < kView; ++i) c[i] = cells(bx + i * rx, by + i * ry);
+    for (int i = 0; i < kView; ++i) c[i] = cells(bx + i * rx, by + i * ry, i);
+  }
+  __device__ __forceinline__ void load_all(uint32_t (&c)[kView][kView]) const {
+#pragma unroll
+    for (int j = kView - 1; j >= 0; --j) load(j, c[j]);
   }
 };
 
@@ -550,6 +710,15 @@ __device__ __forceinline__ void store_triple(uint8_t* p, uint32_t tri) {
   p[1] = (uint8_t)(tri >> 8);
   p[2] = (uint8_t)(tri >> 16);
 }
+
+// Grid accessors for the obstacle transition: HBM triples, LDS codes.
+struct HbmGrid {
+  uint8_t* g;
+  int S;
+  __device__ __forceinline__ bool empty(int x, int y) const { return g[3 * (y * S + x)] == kEmpty; }
+  __device__ __forceinline__ void put_empty(int x, int y) const { store_triple(g + 3 * (y * S + x), kCellEmpty); }
+  __device__ __forceinline__ void put_ball(int x, int y) const { store_triple(g + 3 * (y * S + x), kCellBall); }
+};
 
 struct PlainArgs {
   EnvTables env;
@@ -575,6 +744,7 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
   bool done_prev = false;
   uint2 seed = make_uint2(0, 0);
   uint8_t* g = a.st.grid;
+  uint32_t ob[4] = {~0u, ~0u, ~0u, ~0u};
   if (active) {
     meta = a.env.meta[e];
     fam = meta & 0xFF;
@@ -592,6 +762,10 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
       episode = a.st.episode[e];
       done_prev = a.st.done_prev[e] != 0;
       calls = a.st.calls[e];
+      if (fam == kFamDynObs) {
+        const uint4 o4 = *reinterpret_cast<const uint4*>(a.st.obst + 16 * (size_t)e);
+        ob[0] = o4.x; ob[1] = o4.y; ob[2] = o4.z; ob[3] = o4.w;
+      }
     }
   }
   const bool do_reset = active && (a.reset_all || done_prev);
@@ -604,6 +778,8 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
     dir = L.dir;
     t = 0;
     carry = kCellEmpty;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ob[i] = L.ob[i];
   }
   // the wave writes every resetting env's new grid together, 32 cells a row
   uint64_t pending = __ballot(do_reset);
@@ -632,8 +808,18 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
     }
     const int fx = x + dir_dx(dir), fy = y + dir_dy(dir);
     const HbmCells cells{g, S};
-    const uint32_t front = cells(fx, fy);
-    const ActResult r = intervene(act, x, y, dir, carry, front, fx, fy);
+    uint32_t front = cells(fx, fy, 0);
+    bool blocked = false;
+    if (fam == kFamDynObs) {
+      // three actions; the cell ahead is judged before the balls move
+      act = act > kForward ? kLeft : act;
+      blocked = (front & 0xFF) != kEmpty && (front & 0xFF) != kGoal;
+      move_obstacles(HbmGrid{g, S}, (int)((meta >> 16) & 0xFF), x, y, ob, seed, rid, calls);
+      front = cells(fx, fy, 0);
+    }
+    ActResult r = intervene(act, x, y, dir, carry, front, fx, fy);
+    r.penalty = r.penalty || (blocked && act == kForward);
+    r.terminated = r.terminated || r.penalty;
     if (r.front_changed) store_triple(g + 3 * (fy * S + fx), r.new_front);
     t += 1;
     const bool trunc = t >= T;
@@ -650,11 +836,18 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
   if (a.out.obs) {
     // inactive lanes get an empty grid: every read is out of bounds (a wall)
     uint32_t u[kObsWords + 1];
-    observe_words(HbmRows{HbmCells{g, active ? S : 0}, x, y, dir_dx(dir), dir_dy(dir)}, carry,
-                  active, lane, u);
-    store_words(stage, lane, u);
-    __syncthreads();
-    copy_out<kWave>(stage, a.out.obs + (rowN + (size_t)e0) * kObsBytes, n_here, lane);
+    const HbmRows rows{HbmCells{g, active ? S : 0}, x, y, dir_dx(dir), dir_dy(dir)};
+    if (a.env.obs_mode == 1) {
+      observe_words<true>(rows, carry, active, lane, u);
+      store_words<true>(stage, lane, u);
+      __syncthreads();
+      copy_out<kWave, kCatBytes>(stage, a.out.obs + (rowN + (size_t)e0) * kCatBytes, n_here, lane);
+    } else {
+      observe_words<false>(rows, carry, active, lane, u);
+      store_words<false>(stage, lane, u);
+      __syncthreads();
+      copy_out<kWave, kObsBytes>(stage, a.out.obs + (rowN + (size_t)e0) * kObsBytes, n_here, lane);
+    }
   }
   if (active && a.out.reward) {
     a.out.reward[rowN + e] = reward;
@@ -670,6 +863,8 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
     a.st.episode[e] = episode;
     a.st.done_prev[e] = done_prev ? 1 : 0;
     a.st.calls[e] = a.reset_all ? 0u : calls + 1u;
+    if (fam == kFamDynObs || do_reset)
+      *reinterpret_cast<uint4*>(a.st.obst + 16 * (size_t)e) = make_uint4(ob[0], ob[1], ob[2], ob[3]);
   }
 }
 
@@ -677,8 +872,9 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
 // Fused kernel
 // ---------------------------------------------------------------------------
 // One byte per cell in LDS: four times the cell's kind, i.e. the byte
-// offset of its entry in a 64-entry table of triples (with the see-through
-// bit), so a cell costs one byte read and one table read.  Kinds: 0 empty;
+// offset of its entry in 64-entry tables of triples, so a cell costs one byte
+// read and one table read.  There is one table per view column i, whose
+// entries carry the see-through flag at bit 31 - i.  Kinds: 0 empty;
 // 1-6 wall, 7-12 goal, 13-18 key, 19-24 ball, 25-30 box by colour; 31-48
 // door by state and colour; 49 lava; 50 anything else (read as unseen).
 __device__ __forceinline__ uint32_t code_of(uint32_t tri) {
@@ -731,6 +927,8 @@ __device__ __forceinline__ uint32_t layout_code(const Layout& L, int x, int y) {
     code = crossings_lava(L, x, y) ? kLavaCode : code;
   } else if (L.fam == kFamDistShift) {
     code = ((y == 1 || y == L.a) && x >= 3 && x <= S - 3) ? kLavaCode : code;
+  } else if (L.fam == kFamDynObs) {
+    code = is_ball(L, x, y) ? 4u * (19u + kBlue) : code;
   }
   code = (x == L.gx && y == L.gy) ? kGoalCode : code;
   const bool border = x == 0 || y == 0 || x == S - 1 || y == S - 1;
@@ -743,23 +941,39 @@ __device__ __forceinline__ uint32_t layout_code(const Layout& L, int x, int y) {
 // so only their addresses must stay inside the allocation.
 constexpr int kMargin = 192;
 
+// dynamic LDS of a fused workgroup: the largest tile's grids plus both margins
+__host__ __device__ inline size_t tile_lds_bytes(int32_t max_tile_cells) {
+  const size_t b = 2 * (size_t)kMargin + (size_t)max_tile_cells;
+  return (b + 15) & ~(size_t)15;
+}
+
 __device__ __forceinline__ uint32_t table_at(const uint32_t* table, uint32_t code4) {
   return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(table) + code4);
 }
 
 // View rows from the LDS code grid: the view's row and column steps are
-// +-1 or +-S in the row-major grid, so each cell is one add away.
+// +-1 or +-S in the row-major grid, so each cell is one add away.  All 49
+// codes are read before any table lookup, so the lookups wait on the code
+// reads in bulk rather than one dependent pair at a time.
 struct LdsRows {
   const uint32_t* table;
   const uint8_t* center;   // the agent's cell
   int R, F;                // linear steps to the agent's right and ahead
-  __device__ __forceinline__ void load(int j, uint32_t (&c)[kView]) const {
-    const uint8_t* p = center + (6 - j) * F - 3 * R;
+  __device__ __forceinline__ void load_all(uint32_t (&c)[kView][kView]) const {
+    uint32_t code[kView][kView];
 #pragma unroll
-    for (int i = 0; i < kView; ++i) {
-      c[i] = table_at(table, p[0]);
-      p += R;
+    for (int j = kView - 1; j >= 0; --j) {
+      const uint8_t* p = center + (6 - j) * F - 3 * R;
+#pragma unroll
+      for (int i = 0; i < kView; ++i) {
+        code[j][i] = p[0];
+        p += R;
+      }
     }
+#pragma unroll
+    for (int j = kView - 1; j >= 0; --j)
+#pragma unroll
+      for (int i = 0; i < kView; ++i) c[j][i] = table_at(table + kKinds * i, code[j][i]);
   }
 };
 
@@ -770,6 +984,14 @@ __device__ __forceinline__ LdsRows lds_rows(const uint32_t* table, const uint8_t
   const int R = (dir & 1) ? ((dir == 1) ? -1 : 1) : ((dir == 0) ? S : -S);
   return LdsRows{table, codes + y * S + x, R, F};
 }
+
+struct LdsGrid {
+  uint8_t* g;
+  int S;
+  __device__ __forceinline__ bool empty(int x, int y) const { return g[y * S + x] == 0; }
+  __device__ __forceinline__ void put_empty(int x, int y) const { g[y * S + x] = 0; }
+  __device__ __forceinline__ void put_ball(int x, int y) const { g[y * S + x] = (uint8_t)(4u * (19u + kBlue)); }
+};
 
 struct FusedArgs {
   EnvTables env;
@@ -815,14 +1037,27 @@ template <bool kActions, bool kServe>
 __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
   // static LDS (table and record stage) sits at fixed addresses, so table
   // reads take their base as an immediate; the tile grids are dynamic
-  __shared__ __align__(16) uint32_t table[kKinds];
+  __shared__ __align__(16) uint32_t table[kKinds * kView];
   __shared__ __align__(16) uint8_t stage[kHalfStageBytes];
   extern __shared__ __align__(16) uint8_t grids[];
   uint8_t* codes = grids + kMargin;
   const int lane = threadIdx.x;
   const int N = a.env.n;
 
-  table[lane] = triple_of_kind((uint32_t)lane);   // kKinds == kWave entries
+  {
+    const uint32_t t = triple_of_kind((uint32_t)lane);   // kKinds == kWave entries
+#pragma unroll
+    for (int i = 0; i < kView; ++i) table[kKinds * i + lane] = (t & ~kSeeBit) | ((t & kSeeBit) >> i);
+  }
+  // Every byte a view may read holds a code from here on: the margins and
+  // any space past a small tile are cleared once (code 0, an empty cell),
+  // and the kernel only ever writes codes.  An arbitrary byte would index
+  // the tables off an entry boundary and could set another column's
+  // see-through flag, which the row's combined flags would then pick up.
+  {
+    const uint32_t words = (uint32_t)(tile_lds_bytes(a.tiles.max_tile_cells) >> 2);
+    for (uint32_t w = (uint32_t)lane; w < words; w += kWave) reinterpret_cast<uint32_t*>(grids)[w] = 0u;
+  }
   wave_sync();
 
   for (int tile = blockIdx.x; tile < a.tiles.n_tiles; tile += gridDim.x) {
@@ -854,7 +1089,7 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
     } else {
       n_here = min(kWave, N - e0);
       steps = a.k_steps;
-      o_obs = a.out.obs ? a.out.obs + (size_t)e0 * kObsBytes : nullptr;
+      o_obs = a.out.obs ? a.out.obs + (size_t)e0 * (a.env.obs_mode == 1 ? kCatBytes : kObsBytes) : nullptr;
       o_reward = a.out.reward + e0;
       o_flags = a.out.flags + e0;
       o_action = a.out.action + e0;
@@ -869,6 +1104,7 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
     bool done_prev = false;
     uint2 seed = make_uint2(0, 0);
     uint64_t goff = 0;
+    uint32_t ob[4] = {~0u, ~0u, ~0u, ~0u};
     if (active) {
       meta = a.env.meta[e];
       fam = meta & 0xFF;
@@ -885,6 +1121,8 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
       episode = a.st.episode[e];
       done_prev = a.st.done_prev[e] != 0;
       calls = a.st.calls[e];
+      const uint4 o4 = *reinterpret_cast<const uint4*>(a.st.obst + 16 * (size_t)e);
+      ob[0] = o4.x; ob[1] = o4.y; ob[2] = o4.z; ob[3] = o4.w;
     }
     int tile_cells;
     const int my_off = wave_excl_scan(S * S, lane, tile_cells);
@@ -926,6 +1164,8 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
         dir = L.dir;
         t = 0;
         carry = kCellEmpty;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ob[i] = L.ob[i];
       }
       uint64_t pending = __ballot(do_reset);
       if (pending) {
@@ -934,9 +1174,19 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
           pending &= pending - 1;
           const Layout Lr = bcast_layout(L, r);
           uint8_t* gp = codes + bcast(my_off, r);
-          const int xx = lane & 31;
-          for (int yy = lane >> 5; yy < Lr.S; yy += 2)
-            if (xx < Lr.S) gp[yy * Lr.S + xx] = (uint8_t)layout_code(Lr, xx, yy);
+          // the grid's cells in row-major order, 64 at a time, one per lane
+          const uint32_t Sr = (uint32_t)Lr.S;
+          uint32_t yy, xx, dy, dx;
+          small_divmod((uint32_t)lane, Sr, yy, xx);
+          small_divmod((uint32_t)kWave, Sr, dy, dx);
+          for (uint32_t c = (uint32_t)lane; c < Sr * Sr; c += kWave) {
+            gp[c] = (uint8_t)layout_code(Lr, (int)xx, (int)yy);
+            xx += dx;
+            yy += dy;
+            const bool wrap = xx >= Sr;
+            xx -= wrap ? Sr : 0u;
+            yy += wrap ? 1u : 0u;
+          }
         }
         wave_sync();
       }
@@ -944,10 +1194,20 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
       float reward = 0.0f;
       uint32_t flags = 0, act_rec = kActionNone;
       if (active && !do_reset) {
-        const uint32_t act = kActions ? act_now : bounded(pick4(pol, call & 3u), 7u);
+        uint32_t act = kActions ? act_now : bounded(pick4(pol, call & 3u), 7u);
         const int fx = x + dir_dx(dir), fy = y + dir_dy(dir);
-        const uint32_t front = table_at(table, my_codes[fy * S + fx]);
-        const ActResult r = intervene(act, x, y, dir, carry, front, fx, fy);
+        uint32_t front = table_at(table, my_codes[fy * S + fx]);
+        bool blocked = false;
+        if (fam == kFamDynObs) {
+          // three actions; the cell ahead is judged before the balls move
+          act = act > kForward ? kLeft : act;
+          blocked = (front & 0xFF) != kEmpty && (front & 0xFF) != kGoal;
+          move_obstacles(LdsGrid{my_codes, S}, (int)((meta >> 16) & 0xFF), x, y, ob, seed, rid, call);
+          front = table_at(table, my_codes[fy * S + fx]);
+        }
+        ActResult r = intervene(act, x, y, dir, carry, front, fx, fy);
+        r.penalty = r.penalty || (blocked && act == kForward);
+        r.terminated = r.terminated || r.penalty;
         if (r.front_changed) my_codes[fy * S + fx] = (uint8_t)code_of(r.new_front);
         t += 1;
         const bool trunc = t >= T;
@@ -962,10 +1222,18 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
 
       const size_t row = kServe ? (size_t)(step0 + s) : (size_t)((a.row0 + s) % a.out.rows);
       const size_t rec = row * rec_stride;   // index of lane 0's record
-      if (o_obs) {
+      if (o_obs && !kServe && a.env.obs_mode == 1) {
+        // categorical records (49 bytes): the stage holds all 64 at once
+        uint32_t u[kObsWords + 1];
+        observe_words<true>(lds_rows(table, my_codes, S, x, y, dir), carry, active, lane, u);
+        store_words<true>(stage, lane, u);
+        wave_sync();
+        copy_out<kWave, kCatBytes>(stage, o_obs + rec * kCatBytes, n_here, lane);
+        wave_sync();
+      } else if (o_obs) {
         // inactive lanes (S = 0, pose (1, 1)) read inside the guard margin
         uint32_t u[kObsWords + 1];
-        observe_words(lds_rows(table, my_codes, S, x, y, dir), carry, active, lane & 31, u);
+        observe_words<false>(lds_rows(table, my_codes, S, x, y, dir), carry, active, lane & 31, u);
         // the stage holds 32 records: lanes 0-31, then lanes 32-63 (each half
         // starts and ends on a word boundary, so the halves are independent)
         uint8_t* dst = o_obs + rec * kObsBytes;
@@ -973,9 +1241,9 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
         for (int h = 0; h < 2; ++h) {
           const int n_half = min(32, n_here - 32 * h);
           if (n_half <= 0) break;
-          if ((lane >> 5) == h) store_words(stage, lane & 31, u);
+          if ((lane >> 5) == h) store_words<false>(stage, lane & 31, u);
           wave_sync();
-          copy_out<kWave / 2>(stage, dst + h * kHalfStageBytes, n_half, lane);
+          copy_out<kWave / 2, kObsBytes>(stage, dst + h * kHalfStageBytes, n_half, lane);
           wave_sync();
         }
       }
@@ -1006,6 +1274,7 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
       a.st.episode[e] = episode;
       a.st.done_prev[e] = done_prev ? 1 : 0;
       a.st.calls[e] = calls + (uint32_t)steps;
+      *reinterpret_cast<uint4*>(a.st.obst + 16 * (size_t)e) = make_uint4(ob[0], ob[1], ob[2], ob[3]);
     }
     if (kServe && lane == 0) a.serve[tile].step0 = step0 + (uint32_t)steps;
     wave_sync();
@@ -1052,6 +1321,7 @@ __global__ __launch_bounds__(kWave) void k_admit(AdmitArgs a) {
     a.st.episode[e] = 0u;
     a.st.done_prev[e] = 0;
     a.st.calls[e] = 0u;
+    *reinterpret_cast<uint4*>(a.st.obst + 16 * (size_t)e) = make_uint4(L.ob[0], L.ob[1], L.ob[2], L.ob[3]);
   }
   uint64_t pending = __ballot(active);
   while (pending) {
@@ -1070,13 +1340,10 @@ __global__ __launch_bounds__(kWave) void k_admit(AdmitArgs a) {
 
 }  // namespace
 
-size_t fused_dynamic_lds_bytes(int32_t max_tile_cells) {
-  const size_t b = 2 * (size_t)kMargin + (size_t)max_tile_cells;
-  return (b + 15) & ~(size_t)15;
-}
+size_t fused_dynamic_lds_bytes(int32_t max_tile_cells) { return tile_lds_bytes(max_tile_cells); }
 
 size_t fused_lds_bytes(int32_t max_tile_cells) {
-  return kKinds * 4 + kHalfStageBytes + fused_dynamic_lds_bytes(max_tile_cells);
+  return kKinds * kView * 4 + kHalfStageBytes + fused_dynamic_lds_bytes(max_tile_cells);
 }
 
 hipError_t launch_plain(const EnvTables& env, const StateBufs& st, const uint8_t* actions,

@@ -9,12 +9,13 @@ namespace gx {
 // Per-env static tables in device memory (structure of arrays).
 struct EnvTables {
   int32_t n;
-  uint32_t* meta;             // family | side << 8
+  uint32_t* meta;             // family | side << 8 | family parameter << 16
   int32_t* max_steps;         // truncation limit T >= 1
   uint2* seed;                // Philox key (lo, hi)
   uint32_t* rng_id;           // Philox counter word 0
   uint64_t* grid_off;         // byte offset of the env's [S][S][3] grid
   int32_t reward_mode;        // 0: 1 - 0.9 t/T, 1: unit reward
+  int32_t obs_mode;           // 0: symbolic first person (147 B), 1: categorical (49 B)
 };
 
 // Caller-owned state (device pointers).
@@ -24,6 +25,7 @@ struct StateBufs {
   uint32_t* episode;
   uint8_t* done_prev;
   uint32_t* calls;     // step calls since reset: the random policy's counter
+  uint8_t* obst;       // [N][16] obstacle positions (x, y per ball, 0xFF unused)
 };
 
 // Per-step outputs: row r of each buffer holds N entries.
@@ -84,6 +86,8 @@ inline bool family_ok(int family, int side, int param, int max_side) {
     case 4: return side >= 5 && (side & 1) == 1 && param >= 1 && param <= 8 &&
                    param <= side - 3;                          // Crossings
     case 5: return side >= 6 && (param == 1 || param == 2);    // DistShift
+    case 6: return side >= 5 && param >= 1 && param <= 8 &&
+                   param <= (side - 2) * (side - 2) - 2;       // Dynamic-Obstacles
     default: return false;
   }
 }

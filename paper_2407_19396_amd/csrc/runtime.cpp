@@ -17,6 +17,7 @@ struct gx_ctx {
   int device = 0;
   int32_t n = 0;
   int32_t reward_mode = 0;
+  int32_t obs_mode = 0;
   uint64_t grid_bytes = 0;
   bool has_reset = false;
   // device tables
@@ -65,7 +66,8 @@ void free_tables(gx_ctx* c) {
 
 bool state_ok(const gx_state* st) {
   return st && st->grid && st->x && st->y && st->dir && st->t && st->carry && st->episode &&
-         st->done_prev && st->calls;
+         st->done_prev && st->calls && st->obst &&
+         (reinterpret_cast<uintptr_t>(st->obst) & 15) == 0;
 }
 
 bool traj_ok(const gx_traj* tr) {
@@ -74,12 +76,12 @@ bool traj_ok(const gx_traj* tr) {
 
 gx::EnvTables tables_of(const gx_ctx* c) {
   return gx::EnvTables{c->n, c->d_meta, c->d_max_steps, c->d_seed, c->d_rng_id, c->d_grid_off,
-                       c->reward_mode};
+                       c->reward_mode, c->obs_mode};
 }
 
 gx::StateBufs state_of(const gx_state* st) {
   return gx::StateBufs{st->grid, st->x, st->y, st->dir, st->t, st->carry, st->episode, st->done_prev,
-                       st->calls};
+                       st->calls, st->obst};
 }
 
 gx::TrajBufs traj_of(const gx_traj* tr) {
@@ -113,6 +115,7 @@ int env_create(const gx_config* cfg, gx_ctx** out) {
   *out = nullptr;
   if (!cfg || cfg->n_envs < 1 || !cfg->family || !cfg->side || !cfg->max_steps) return GX_EINVAL;
   if (cfg->reward_mode != 0 && cfg->reward_mode != 1) return GX_EINVAL;
+  if (cfg->obs_mode != 0 && cfg->obs_mode != 1) return GX_EINVAL;
   const int32_t n = cfg->n_envs;
   // the grid of a tile must fit the LDS of one workgroup; side <= 32 and
   // 64 envs per tile bound it at 64 KiB of cells
@@ -141,6 +144,7 @@ int env_create(const gx_config* cfg, gx_ctx** out) {
   }
   c->n = n;
   c->reward_mode = cfg->reward_mode;
+  c->obs_mode = cfg->obs_mode;
   c->grid_bytes = off;
   c->n_tiles = (n + kTileEnvs - 1) / kTileEnvs;
   for (int32_t t = 0; t < c->n_tiles; ++t) {

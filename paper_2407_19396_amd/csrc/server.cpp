@@ -54,6 +54,7 @@ struct gx_server {
   uint32_t* d_episode = nullptr;
   uint8_t* d_done = nullptr;
   uint32_t* d_calls = nullptr;
+  uint8_t* d_obst = nullptr;
   gx::ServeTile* d_tiles = nullptr;
   // host staging read by the admission kernel (coherent pinned memory)
   gx::ServeTile* h_tiles = nullptr;
@@ -74,7 +75,7 @@ namespace {
 void free_all(gx_server* s) {
   void* dev[] = {s->d_meta, s->d_max_steps, s->d_seed, s->d_rng_id, s->d_grid_off, s->d_grid,
                  s->d_x, s->d_y, s->d_dir, s->d_t, s->d_carry, s->d_episode, s->d_done, s->d_calls,
-                 s->d_tiles};
+                 s->d_obst, s->d_tiles};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   if (s->h_tiles) (void)hipHostFree(s->h_tiles);
@@ -91,12 +92,12 @@ bool dev_alloc(gx_server* s, T** p, size_t count) {
 
 gx::EnvTables tables_of(gx_server* s) {
   return gx::EnvTables{s->max_tiles * kTileEnvs, s->d_meta, s->d_max_steps, s->d_seed,
-                       s->d_rng_id, s->d_grid_off, s->reward_mode};
+                       s->d_rng_id, s->d_grid_off, s->reward_mode, 0};
 }
 
 gx::StateBufs state_of(gx_server* s) {
   return gx::StateBufs{s->d_grid, s->d_x, s->d_y, s->d_dir, s->d_t, s->d_carry, s->d_episode, s->d_done,
-                       s->d_calls};
+                       s->d_calls, s->d_obst};
 }
 
 }  // namespace
@@ -127,6 +128,7 @@ int env_server_create(int32_t max_tiles, int32_t max_side, int32_t reward_mode, 
             dev_alloc(s, &s->d_dir, slots) && dev_alloc(s, &s->d_t, slots) &&
             dev_alloc(s, &s->d_carry, slots) && dev_alloc(s, &s->d_episode, slots) &&
             dev_alloc(s, &s->d_done, slots) && dev_alloc(s, &s->d_calls, slots) &&
+            dev_alloc(s, &s->d_obst, slots * 16) &&
             dev_alloc(s, &s->d_tiles, (size_t)max_tiles);
   ok = ok && hipHostMalloc(reinterpret_cast<void**>(&s->h_tiles), sizeof(gx::ServeTile) * max_tiles,
                            hipHostMallocCoherent) == hipSuccess;

@@ -27,13 +27,13 @@ EXPORTS = ("env_create", "env_sizes", "env_info", "env_reset", "env_step", "env_
 
 
 class GxConfig(ctypes.Structure):
-    _fields_ = [("n_envs", ctypes.c_int32), ("reward_mode", ctypes.c_int32),
+    _fields_ = [("n_envs", ctypes.c_int32), ("reward_mode", ctypes.c_int32), ("obs_mode", ctypes.c_int32),
                 ("family", ctypes.c_void_p), ("side", ctypes.c_void_p), ("param", ctypes.c_void_p),
                 ("max_steps", ctypes.c_void_p), ("seed", ctypes.c_void_p),
                 ("seed_all", ctypes.c_uint64), ("rng_id", ctypes.c_void_p)]
 
 
-STATE_FIELDS = ("grid", "x", "y", "dir", "t", "carry", "episode", "done_prev", "calls")
+STATE_FIELDS = ("grid", "x", "y", "dir", "t", "carry", "episode", "done_prev", "calls", "obst")
 
 
 class GxState(ctypes.Structure):
@@ -144,14 +144,14 @@ def _stream_ptr(stream) -> int | None:
 
 
 # --------------------------------------------------------------- C names
-def env_create(table: workloads.EnvTable, reward_mode: int = 0) -> int:
+def env_create(table: workloads.EnvTable, reward_mode: int = 0, obs_mode: int = 0) -> int:
     fam = np.ascontiguousarray(table.family, np.uint8)
     side = np.ascontiguousarray(table.side, np.uint8)
     ms = np.ascontiguousarray(table.max_steps, np.int32)
     seed = np.ascontiguousarray(table.seed, np.uint64)
     rid = np.ascontiguousarray(table.rng_id, np.uint32)
     par = np.ascontiguousarray(table.param, np.uint8)
-    cfg = GxConfig(table.n, reward_mode, fam.ctypes.data, side.ctypes.data, par.ctypes.data,
+    cfg = GxConfig(table.n, reward_mode, obs_mode, fam.ctypes.data, side.ctypes.data, par.ctypes.data,
                    ms.ctypes.data, seed.ctypes.data, 0, rid.ctypes.data)
     ctx = ctypes.c_void_p()
     _check("env_create", load().env_create(ctypes.byref(cfg), ctypes.byref(ctx)))
@@ -198,17 +198,18 @@ def env_destroy(ctx: int):
 # --------------------------------------------------------------- tensors
 @dataclass
 class Traj:
-    """Device output rows: obs [rows][N][7][7][3] u8 (or None), reward f32,
-    flags u8, action u8 [rows][N]."""
+    """Device output rows: obs [rows][N][7][7][3] u8 ([rows][N][7][7] in the
+    categorical mode, or None), reward f32, flags u8, action u8 [rows][N]."""
     obs: object
     reward: object
     flags: object
     action: object
 
     @staticmethod
-    def alloc(rows: int, n: int, device="cuda", with_obs: bool = True) -> "Traj":
+    def alloc(rows: int, n: int, device="cuda", with_obs: bool = True, obs_mode: int = 0) -> "Traj":
         import torch
-        return Traj(torch.zeros((rows, n, 7, 7, 3), dtype=torch.uint8, device=device) if with_obs else None,
+        shape = (rows, n, 7, 7, 3) if obs_mode == 0 else (rows, n, 7, 7)
+        return Traj(torch.zeros(shape, dtype=torch.uint8, device=device) if with_obs else None,
                     torch.zeros((rows, n), dtype=torch.float32, device=device),
                     torch.zeros((rows, n), dtype=torch.uint8, device=device),
                     torch.zeros((rows, n), dtype=torch.uint8, device=device))
@@ -227,11 +228,12 @@ class GridEnv:
 
     FIELDS = STATE_FIELDS
 
-    def __init__(self, table: workloads.EnvTable, reward_mode: int = 0, device="cuda"):
+    def __init__(self, table: workloads.EnvTable, reward_mode: int = 0, device="cuda", obs_mode: int = 0):
         import torch
         self.table = table
+        self.obs_mode = obs_mode
         self.device = torch.device(device)
-        self.ctx = env_create(table, reward_mode)
+        self.ctx = env_create(table, reward_mode, obs_mode)
         grid_bytes, n = env_sizes(self.ctx)
         self.n = n
         dev = self.device
@@ -244,6 +246,7 @@ class GridEnv:
         self.episode = torch.zeros(n, dtype=torch.int32, device=dev)   # uint32 bits
         self.done_prev = torch.zeros(n, dtype=torch.uint8, device=dev)
         self.calls = torch.zeros(n, dtype=torch.int32, device=dev)        # uint32 bits
+        self.obst = torch.full((n * 16,), 0xFF, dtype=torch.uint8, device=dev)
 
     def state(self) -> GxState:
         return GxState(*[getattr(self, f).data_ptr() for f in self.FIELDS])
@@ -275,7 +278,12 @@ class GridEnv:
         """Copy a host state (dict of numpy arrays) into the device tensors."""
         import torch
         for f in self.FIELDS:
-            a = np.ascontiguousarray(st[f] if f in st else np.zeros(self.n, np.uint32))
+            if f in st:
+                a = np.ascontiguousarray(st[f])
+            elif f == "obst":
+                a = np.full(self.n * 16, 0xFF, np.uint8)
+            else:
+                a = np.zeros(self.n, np.uint32)
             if f in ("episode", "calls"):
                 a = a.astype(np.uint32).view(np.int32)
             t = torch.from_numpy(a.copy()).to(self.device)

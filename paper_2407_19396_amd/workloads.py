@@ -18,16 +18,16 @@ from dataclasses import dataclass
 import numpy as np
 
 FAMILY_EMPTY, FAMILY_TWOROOM, FAMILY_FOURROOMS = 0, 1, 2
-FAMILY_LAVAGAP, FAMILY_CROSSINGS, FAMILY_DISTSHIFT = 3, 4, 5
+FAMILY_LAVAGAP, FAMILY_CROSSINGS, FAMILY_DISTSHIFT, FAMILY_DYNOBS = 3, 4, 5, 6
 FAMILY_NAMES = {FAMILY_EMPTY: "Empty", FAMILY_TWOROOM: "TwoRoom", FAMILY_FOURROOMS: "FourRooms",
                 FAMILY_LAVAGAP: "LavaGap", FAMILY_CROSSINGS: "Crossings",
-                FAMILY_DISTSHIFT: "DistShift"}
+                FAMILY_DISTSHIFT: "DistShift", FAMILY_DYNOBS: "Dynamic-Obstacles"}
 N_ACTIONS = 7
 
 
 def default_max_steps(family: int, side: int) -> int:
-    """MiniGrid's default step limits for each family: 4*S^2 (Empty and
-    the lava families), 10*S^2 (DoorKey), 100 (FourRooms)."""
+    """MiniGrid's default step limits for each family: 4*S^2 (Empty, the
+    lava families and Dynamic-Obstacles), 10*S^2 (DoorKey), 100 (FourRooms)."""
     if family == FAMILY_TWOROOM:
         return 10 * side * side
     if family == FAMILY_FOURROOMS:
@@ -129,12 +129,30 @@ def workload_mixed(seed: int = 0, n: int = 262144) -> EnvTable:
     return mixed_table(n, seed)
 
 
+# the Dynamic-Obstacles tasks of the paper's environment table: (side, balls)
+DYNOBS_TASKS = [(5, 2), (6, 3), (8, 4), (16, 8)]
+
+
+def dynobs_table(n: int, seed: int = 0, mix_seed: int = 777) -> EnvTable:
+    """The Dynamic-Obstacles tasks in equal shares, i.i.d. per env."""
+    rng = np.random.default_rng(mix_seed)
+    pick = np.array(DYNOBS_TASKS)[rng.integers(0, len(DYNOBS_TASKS), n)]
+    return _table(np.full(n, FAMILY_DYNOBS), pick[:, 0], seed, f"dynamic obstacles x{n}", None,
+                  pick[:, 1])
+
+
+def workload_dynobs(seed: int = 0, n: int = 262144) -> EnvTable:
+    """262144 envs of the Dynamic-Obstacles tasks (fused, 4096 steps)."""
+    return dynobs_table(n, seed)
+
+
 def workload_lava(seed: int = 0, n: int = 262144) -> EnvTable:
     """262144 envs of the lava tasks (fused persistent launch, 4096 steps)."""
     return lava_table(n, seed)
 
 
-WORKLOAD_STEPS = {"empty5": 100, "empty8": 1000, "tworoom8": 2048, "mixed": 4096, "lava": 4096}
+WORKLOAD_STEPS = {"empty5": 100, "empty8": 1000, "tworoom8": 2048, "mixed": 4096, "lava": 4096,
+                  "dynobs": 4096}
 
 
 def random_actions(n_steps: int, n_envs: int, seed: int) -> np.ndarray:

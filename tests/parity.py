@@ -8,12 +8,12 @@ import numpy as np
 import oracle as ox
 from paper_2407_19396_amd import workloads as wl
 
-FIELDS = ("grid", "x", "y", "dir", "t", "carry", "episode", "done_prev", "calls")
+FIELDS = ("grid", "x", "y", "dir", "t", "carry", "episode", "done_prev", "calls", "obst")
 
 
-def ox_batch(table: wl.EnvTable, reward_mode: int = 0) -> ox.Batch:
+def ox_batch(table: wl.EnvTable, reward_mode: int = 0, obs_mode: int = 0) -> ox.Batch:
     return ox.Batch(table.family, table.side, table.max_steps, table.seed, table.rng_id, reward_mode,
-                    table.param)
+                    table.param, obs_mode)
 
 
 def to_np(t):
@@ -32,10 +32,11 @@ def assert_rows_equal(gpu, ref: ox.Outputs, rows=None, what=""):
         g_obs = to_np(gpu.obs)[rows]
         r_obs = ref.obs[rows]
         if not np.array_equal(g_obs, r_obs):
-            bad = np.argwhere((g_obs != r_obs).any(axis=(-1, -2, -3)))
+            bad = np.argwhere((g_obs != r_obs).reshape(g_obs.shape[0], g_obs.shape[1], -1).any(axis=-1))
             k, e = bad[0][:2]
             raise AssertionError(f"obs mismatch {what} at row {k} env {e} ({len(bad)} records):\n"
-                                 f"gpu types\n{g_obs[k, e, :, :, 0]}\noracle types\n{r_obs[k, e, :, :, 0]}")
+                                 f"gpu\n{g_obs[k, e, ..., 0] if g_obs.ndim == 5 else g_obs[k, e]}\n"
+                                 f"oracle\n{r_obs[k, e, ..., 0] if r_obs.ndim == 5 else r_obs[k, e]}")
 
 
 def assert_state_equal(env, ref: ox.State, what=""):
@@ -49,8 +50,8 @@ def assert_state_equal(env, ref: ox.State, what=""):
                                  f"oracle {r.reshape(-1)[idx]}")
 
 
-def oracle_reset(table: wl.EnvTable, reward_mode: int = 0):
-    b = ox_batch(table, reward_mode)
+def oracle_reset(table: wl.EnvTable, reward_mode: int = 0, obs_mode: int = 0):
+    b = ox_batch(table, reward_mode, obs_mode)
     s = ox.State.empty(b)
     first = ox.reset(b, s, nthreads=8)
     return b, s, first

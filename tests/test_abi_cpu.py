@@ -36,14 +36,14 @@ def test_strerror():
     assert ge.env_strerror(-99) == "unknown status"
 
 
-def _cfg(family, side, max_steps, n=None, reward_mode=0, param=None):
+def _cfg(family, side, max_steps, n=None, reward_mode=0, param=None, obs_mode=0):
     family = np.asarray(family, np.uint8)
     side = np.asarray(side, np.uint8)
     max_steps = np.asarray(max_steps, np.int32)
     param = None if param is None else np.asarray(param, np.uint8)
     keep = (family, side, max_steps, param)
     n = len(family) if n is None else n
-    return ge.GxConfig(n, reward_mode, family.ctypes.data, side.ctypes.data,
+    return ge.GxConfig(n, reward_mode, obs_mode, family.ctypes.data, side.ctypes.data,
                        None if param is None else param.ctypes.data, max_steps.ctypes.data,
                        None, 0, None), keep
 
@@ -69,6 +69,15 @@ def _cfg(family, side, max_steps, n=None, reward_mode=0, param=None):
 def test_create_rejects_bad_configs(family, side, T, n, mode, param):
     lib = ge.load()
     cfg, keep = _cfg(family, side, T, n, mode, param)
+    ctx = ctypes.c_void_p(1)
+    assert lib.env_create(ctypes.byref(cfg), ctypes.byref(ctx)) == ge.GX_EINVAL
+    assert ctx.value is None
+
+
+@pytest.mark.parametrize("obs_mode", [-1, 2, 3])
+def test_create_rejects_bad_observation_modes(obs_mode):
+    lib = ge.load()
+    cfg, keep = _cfg([0], [8], [10], obs_mode=obs_mode)
     ctx = ctypes.c_void_p(1)
     assert lib.env_create(ctypes.byref(cfg), ctypes.byref(ctx)) == ge.GX_EINVAL
     assert ctx.value is None

@@ -37,6 +37,8 @@ def tables():
         "all_sides": all_sides_table(),
         "lava": wl.lava_table(3000, seed=21, mix_seed=22),
         "lava_all": lava_all_table(),
+        "dynobs": wl.dynobs_table(3000, seed=41, mix_seed=42),
+        "dynobs_all": dynobs_all_table(),
     }
 
 
@@ -52,6 +54,19 @@ def all_sides_table():
     ms = np.array([wl.default_max_steps(int(f), int(s)) for f, s in zip(fam, side)]) // 8 + 1
     return wl.EnvTable(fam.astype(np.uint8), side.astype(np.uint8), ms.astype(np.int32),
                        np.full(len(fam), 77, np.uint64), np.arange(len(fam), dtype=np.uint32), "all sides")
+
+
+def dynobs_all_table():
+    """Every side 5..32 of Dynamic-Obstacles with 1..8 balls, two envs each."""
+    side, par = [], []
+    for S in range(5, 33):
+        for n in range(1, min(8, (S - 2) ** 2 - 2) + 1):
+            side.append(S); par.append(n)
+    side, par = np.array(side * 2), np.array(par * 2)
+    ms = np.array([wl.default_max_steps(6, int(s)) for s in side]) // 16 + 1
+    return wl.EnvTable(np.full(len(side), 6, np.uint8), side.astype(np.uint8), ms.astype(np.int32),
+                       np.full(len(side), 93, np.uint64), np.arange(len(side), dtype=np.uint32),
+                       "dynobs all", par.astype(np.uint8))
 
 
 def lava_all_table():
@@ -83,7 +98,8 @@ def test_reset_parity(ge, name):
 
 @pytest.mark.parametrize("name,steps", [("empty5", 100), ("empty8", 300), ("tworoom8", 300),
                                         ("fourrooms19", 250), ("mixed", 300), ("all_sides", 200),
-                                        ("lava", 300), ("lava_all", 200)])
+                                        ("lava", 300), ("lava_all", 200), ("dynobs", 300),
+                                        ("dynobs_all", 150)])
 @pytest.mark.parametrize("policy", [False, True])
 def test_plain_step_parity(ge, name, steps, policy):
     import torch
@@ -104,7 +120,8 @@ def test_plain_step_parity(ge, name, steps, policy):
 
 @pytest.mark.parametrize("name,steps", [("empty5", 100), ("empty8", 300), ("tworoom8", 300),
                                         ("fourrooms19", 250), ("mixed", 300), ("all_sides", 200),
-                                        ("lava", 300), ("lava_all", 200)])
+                                        ("lava", 300), ("lava_all", 200), ("dynobs", 300),
+                                        ("dynobs_all", 150)])
 @pytest.mark.parametrize("K", [1, 7, 64])
 @pytest.mark.parametrize("policy", [False, True])
 def test_fused_rollout_parity(ge, name, steps, K, policy):
@@ -259,3 +276,42 @@ def test_unit_reward_mode_lava(ge):
     torch.cuda.synchronize()
     P.assert_rows_equal(traj, ref, what="unit reward, lava")
     assert set(np.unique(ref.reward)) == {-1.0, 0.0, 1.0}
+
+
+@pytest.mark.parametrize("name", ["mixed", "lava", "dynobs", "all_sides"])
+@pytest.mark.parametrize("kernel", ["plain", "fused"])
+def test_categorical_observation_parity(ge, name, kernel):
+    """categorical_first_person records (49 bytes) through both kernels."""
+    import torch
+    table = tables()[name]
+    env = ge.GridEnv(table, obs_mode=1)
+    first = ge.Traj.alloc(1, table.n, obs_mode=1)
+    env.reset(first)
+    b, s, ref0 = P.oracle_reset(table, obs_mode=1)
+    P.assert_rows_equal(first, ref0, what=f"categorical reset {name}")
+    steps = 120
+    ref = ox.rollout(b, s, steps, None, nthreads=8)
+    traj = ge.Traj.alloc(steps, table.n, obs_mode=1)
+    if kernel == "fused":
+        env.rollout(steps, traj, K=32)
+    else:
+        for k in range(steps):
+            env.step(ge.Traj(traj.obs[k:k + 1], traj.reward[k:k + 1], traj.flags[k:k + 1],
+                             traj.action[k:k + 1]))
+    torch.cuda.synchronize()
+    P.assert_rows_equal(traj, ref, what=f"categorical {kernel} {name}")
+    P.assert_state_equal(env, s, f"categorical {kernel} {name}")
+
+
+@pytest.mark.parametrize("n", [1, 63, 65, 130])
+def test_categorical_ragged(ge, n):
+    import torch
+    table = wl.mixed_table(n, seed=n + 7, mix_seed=n + 8)
+    env = ge.GridEnv(table, obs_mode=1)
+    env.reset(ge.Traj.alloc(1, n, obs_mode=1))
+    b, s, _ = P.oracle_reset(table, obs_mode=1)
+    ref = ox.rollout(b, s, 30, None, nthreads=8)
+    traj = ge.Traj.alloc(30, n, obs_mode=1)
+    env.rollout(30, traj, K=8)
+    torch.cuda.synchronize()
+    P.assert_rows_equal(traj, ref, what=f"categorical n={n}")

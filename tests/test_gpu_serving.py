@@ -143,18 +143,20 @@ def test_native_serving_loop_completes_everything():
     srv.close()
 
 
-def test_lava_requests_equal_oracle():
-    """Requests of the lava tasks through the server (admission resets
-    them on the device) equal the oracle's reset + rollout."""
+def test_lava_and_obstacle_requests_equal_oracle():
+    """Requests of the lava and Dynamic-Obstacles tasks through the server
+    (admission resets them on the device) equal the oracle's reset +
+    rollout."""
     import torch
     from paper_2407_19396_amd import gridenv as ge
     rng = np.random.default_rng(3)
     reqs = []
-    for i in range(6):
+    for i in range(8):
         n = int(rng.integers(1, 300))
-        t = wl.lava_table(n, seed=int(rng.integers(0, 2 ** 62)), mix_seed=i)
+        make = wl.lava_table if i % 2 == 0 else wl.dynobs_table
+        t = make(n, seed=int(rng.integers(0, 2 ** 62)), mix_seed=i)
         reqs.append(wl.Request(i, 0.0, n, int(rng.integers(20, 120)), int(t.seed[0]), t))
-    outs, _, info = run_mix(ge, reqs, 32, max_tiles=8)
+    outs, _, info = run_mix(ge, reqs, 32, max_tiles=10)
     assert info["live_requests"] == 0
     for i, r in enumerate(reqs):
         P.assert_rows_equal(crop(outs[i], r.n_envs), oracle_of(r), what=f"lava request {i}")

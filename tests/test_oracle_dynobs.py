@@ -318,3 +318,19 @@ def test_brute_force_invariants(ox):
                 else:
                     assert out.reward[0, i] == 0
             alive &= (out.flags[0] & 1) == 0
+
+
+def test_malformed_list_entries_do_not_move(ox):
+    """An obstacle list holding fewer balls than the family parameter (a
+    malformed state): entries off the interior are left alone and no cell
+    outside the grid is touched."""
+    b, s = dyn_env(ox, POCKET, obst=[(2, 2)], n=3, seed=4)
+    s.obst[2:6] = [0xFF, 0xFF, 0, 9]          # (255, 255) and (0, 9): off the interior
+    before = s.obst.copy()
+    grid_before = s.grid.copy()
+    ox.step(b, s, [0])
+    g = gt.grid_of(s, 7)
+    assert balls(g) == {(3, 2)}
+    np.testing.assert_array_equal(s.obst[2:6], before[2:6])
+    changed = np.nonzero(s.grid != grid_before)[0] // 3
+    assert set(changed.tolist()) == {2 * 7 + 2, 2 * 7 + 3}
