@@ -1060,7 +1060,8 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
   }
   wave_sync();
 
-  for (int tile = blockIdx.x; tile < a.tiles.n_tiles; tile += gridDim.x) {
+  for (int it = blockIdx.x; it < a.tiles.n_tiles; it += gridDim.x) {
+    const int tile = a.tiles.list ? (int)a.tiles.list[it] : it;
     // where this tile's envs live and where their records go: record of
     // step s, lane l is at index rec_base + s * rec_step (+ l) of the outputs
     const int e0 = tile * kWave;

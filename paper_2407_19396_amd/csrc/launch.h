@@ -42,6 +42,7 @@ struct TrajBufs {
 struct TileTables {
   int32_t n_tiles;
   int32_t max_tile_cells;     // LDS bytes of the largest tile's code grids
+  const uint32_t* list;       // tile ids to run, n_tiles of them (serving), or nullptr: 0..n_tiles-1
 };
 
 // A tile of 64 slots serving one request (device memory, 64 bytes).  The

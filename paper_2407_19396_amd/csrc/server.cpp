@@ -28,6 +28,7 @@
 namespace {
 
 constexpr int kTileEnvs = 64;
+constexpr int kLists = 8;   // tile lists kept for launches still in flight
 
 struct Request {
   bool live = false;
@@ -59,6 +60,11 @@ struct gx_server {
   // host staging read by the admission kernel (coherent pinned memory)
   gx::ServeTile* h_tiles = nullptr;
   gx::SlotConfig* h_slots = nullptr;
+  // the tile lists of the last kLists launches (read by the fused kernel
+  // from coherent pinned memory); a list is reused once its launch is done
+  uint32_t* h_lists = nullptr;
+  hipEvent_t list_done[kLists] = {};
+  int64_t launches = 0;
   // bookkeeping
   std::set<int32_t> free_tiles;
   std::vector<int32_t> tile_cells;   // cells of a live tile, 0 when free
@@ -80,6 +86,9 @@ void free_all(gx_server* s) {
     if (p) (void)hipFree(p);
   if (s->h_tiles) (void)hipHostFree(s->h_tiles);
   if (s->h_slots) (void)hipHostFree(s->h_slots);
+  if (s->h_lists) (void)hipHostFree(s->h_lists);
+  for (hipEvent_t& e : s->list_done)
+    if (e) (void)hipEventDestroy(e);
 }
 
 template <class T>
@@ -134,6 +143,10 @@ int env_server_create(int32_t max_tiles, int32_t max_side, int32_t reward_mode, 
                            hipHostMallocCoherent) == hipSuccess;
   ok = ok && hipHostMalloc(reinterpret_cast<void**>(&s->h_slots), sizeof(gx::SlotConfig) * slots,
                            hipHostMallocCoherent) == hipSuccess;
+  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&s->h_lists),
+                           sizeof(uint32_t) * (size_t)max_tiles * kLists, hipHostMallocCoherent) == hipSuccess;
+  for (hipEvent_t& e : s->list_done)
+    ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
   // every descriptor starts inactive
   ok = ok && hipMemset(s->d_tiles, 0, sizeof(gx::ServeTile) * max_tiles) == hipSuccess;
   if (!ok) {
@@ -234,19 +247,38 @@ int env_server_step(gx_server* s, int32_t K, void* stream, int32_t* finished, in
       return GX_EDEVICE;
     s->pending.clear();
   }
-  // launch only if some request still has steps to run
-  int32_t max_cells = 0;
-  for (int32_t h : s->running)
-    for (int32_t t : s->reqs[h].tiles) max_cells = std::max(max_cells, s->tile_cells[t]);
+  // launch only if some request still has steps to run: the live tiles,
+  // those of requests with the most steps left first, so that the blocks
+  // that finish early pick up the short ones
   if (!s->running.empty()) {
+    std::sort(s->running.begin(), s->running.end(), [s](int32_t a, int32_t b) {
+      const Request &qa = s->reqs[a], &qb = s->reqs[b];
+      return qa.n_steps - qa.done > qb.n_steps - qb.done;
+    });
+    const int slot = (int)(s->launches % kLists);
+    const hipError_t q = hipEventQuery(s->list_done[slot]);
+    if (q == hipErrorNotReady) {
+      if (hipEventSynchronize(s->list_done[slot]) != hipSuccess) return GX_EDEVICE;
+    } else if (q != hipSuccess) {
+      return GX_EDEVICE;
+    }
+    uint32_t* list = s->h_lists + (size_t)slot * s->max_tiles;
+    int32_t n = 0, max_cells = 0;
+    for (int32_t h : s->running)
+      for (int32_t t : s->reqs[h].tiles) {
+        list[n++] = (uint32_t)t;
+        max_cells = std::max(max_cells, s->tile_cells[t]);
+      }
     const size_t lds = gx::fused_lds_bytes(max_cells);
     const int per_cu = std::max<int>(1, std::min<int>(16, (int)(s->lds_per_cu / lds)));
-    const int32_t blocks = std::min<int32_t>(s->max_tiles, s->cus * per_cu);
-    const gx::TileTables tiles{s->max_tiles, max_cells};
+    const int32_t blocks = std::min<int32_t>(n, s->cus * per_cu);
+    const gx::TileTables tiles{n, max_cells, list};
     const gx::TrajBufs none{nullptr, nullptr, nullptr, nullptr, 1};
     if (gx::launch_fused(tables_of(s), tiles, state_of(s), nullptr, K, none, 0, blocks, st,
                          s->d_tiles) != hipSuccess)
       return GX_EDEVICE;
+    if (hipEventRecord(s->list_done[slot], st) != hipSuccess) return GX_EDEVICE;
+    ++s->launches;
     size_t keep = 0;
     for (size_t i = 0; i < s->running.size(); ++i) {
       const int32_t h = s->running[i];

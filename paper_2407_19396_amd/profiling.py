@@ -27,8 +27,8 @@ FUSED = "k_fused"
 PLAIN = "k_plain"
 
 
-def kernel_source_hash() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
+def kernel_source_hash(path: str = KERNEL_SOURCE) -> str:
+    with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
@@ -67,8 +67,11 @@ def _mean(xs):
     return sum(xs) / len(xs)
 
 
-def summarize(trace: str, fetch: str, write: str, sq: str | None, copy_bytes: int, K: int,
-              envs: int, command: str) -> str:
+def summarize(trace: str, fetch: str, write: str, sq, copy_bytes: int, K: int,
+              envs: int, command: str, source: str = KERNEL_SOURCE) -> str:
+    """sq: a directory or a list of directories of SQ counter runs; source:
+    the kernel source the profiled library was built from."""
+    kernel = kernel_source_hash(source)
     st = _stats(trace)
     fc, wc = _counters(fetch), _counters(write)
     copy_fetch = _mean(fc[(COPY_KERNEL, "FETCH_SIZE")]) * 1024
@@ -80,7 +83,7 @@ def summarize(trace: str, fetch: str, write: str, sq: str | None, copy_bytes: in
         "# k_fused on the mixed 262144-env workload (rocprofv3)",
         "",
         f"command: {command}",
-        f"kernel source sha256[:16]: {kernel_source_hash()}",
+        f"kernel source sha256[:16]: {kernel}",
         f"steps per launch K = {K}, envs = {envs}",
         "",
         "## kernel trace (--kernel-trace --stats)",
@@ -98,14 +101,15 @@ def summarize(trace: str, fetch: str, write: str, sq: str | None, copy_bytes: in
         f"k_fused per launch: fetch {fused_fetch / 1e6:.1f} MB, write {fused_write / 1e6:.1f} MB (scaled)",
     ]
     if sq:
-        qc = _counters(sq)
         wave_steps = envs / 64 * K
         lines += ["", "## SQ counters per launch (and per wave-step of 64 env-steps)"]
-        for (k, c), v in sorted(qc.items()):
-            if k == FUSED:
-                lines.append(f"{c}: {_mean(v):.4g} ({_mean(v) / wave_steps:.1f} per wave-step)")
+        for d in ([sq] if isinstance(sq, str) else sq):
+            qc = _counters(d)
+            for (k, c), v in sorted(qc.items()):
+                if k == FUSED:
+                    lines.append(f"{c}: {_mean(v):.4g} ({_mean(v) / wave_steps:.1f} per wave-step)")
     lines += ["", f"machine: traffic_bytes_per_launch={fused_fetch + fused_write:.0f} K={K} envs={envs} "
-                  f"kernel={kernel_source_hash()} avg_ns={st.get(FUSED, {}).get('avg_ns', 0):.0f}"]
+                  f"kernel={kernel} avg_ns={st.get(FUSED, {}).get('avg_ns', 0):.0f}"]
     return "\n".join(lines) + "\n"
 
 
@@ -127,14 +131,15 @@ def main():
     ap.add_argument("--trace", required=True)
     ap.add_argument("--fetch", required=True)
     ap.add_argument("--write", required=True)
-    ap.add_argument("--sq")
+    ap.add_argument("--sq", action="append", help="SQ counter run directory (repeatable)")
+    ap.add_argument("--source", default=KERNEL_SOURCE, help="kernel source the profiled build used")
     ap.add_argument("--copy-bytes", type=int, required=True)
     ap.add_argument("--K", type=int, required=True)
     ap.add_argument("--envs", type=int, required=True)
     ap.add_argument("--command", required=True)
     ap.add_argument("-o", "--out", required=True)
     a = ap.parse_args()
-    text = summarize(a.trace, a.fetch, a.write, a.sq, a.copy_bytes, a.K, a.envs, a.command)
+    text = summarize(a.trace, a.fetch, a.write, a.sq, a.copy_bytes, a.K, a.envs, a.command, a.source)
     with open(a.out, "w") as f:
         f.write(text)
     print(text)
