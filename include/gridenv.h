@@ -249,16 +249,18 @@ typedef struct {
 /* Allocate a server for up to max_tiles * 64 envs of side <= max_side. */
 int env_server_create(int32_t max_tiles, int32_t max_side, int32_t reward_mode, gx_server** out);
 
-/* Queue a request (host work only; its reset is launched by the next
- * env_server_step).  GX_EBUSY when there are not enough free tiles now.
+/* Queue a request (host work only; the next env_server_step's launch resets
+ * its envs before their first step).  GX_EBUSY when there are not enough
+ * free tiles now.
  * The output buffers must stay valid until the request is released. */
 int env_server_admit(gx_server* srv, const gx_request* req, int32_t* handle);
 
-/* Launch pending admissions and one fused chunk of up to K steps for every
- * live request on `stream`.  Writes to finished[0..*n_finished) the
- * handles of requests whose last step is in a launch enqueued so far (at
- * most cap per call; the rest come with later calls).  Their results are
- * complete once the stream reaches this point. */
+/* Launch one fused chunk of up to K steps for every live request on
+ * `stream` (newly admitted requests are reset first, in the same launch).
+ * Writes to finished[0..*n_finished) the handles of requests whose last step
+ * is in a launch enqueued so far (at most cap per call; the rest come with
+ * later calls).  Their results are complete once the stream reaches this
+ * point. */
 int env_server_step(gx_server* srv, int32_t K, void* stream, int32_t* finished, int32_t cap,
                     int32_t* n_finished);
 

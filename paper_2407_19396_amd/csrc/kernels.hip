@@ -993,6 +993,31 @@ struct LdsGrid {
   __device__ __forceinline__ void put_ball(int x, int y) const { g[y * S + x] = (uint8_t)(4u * (19u + kBlue)); }
 };
 
+// Writes the code grids of the freshly laid-out envs in `pending` (a lane
+// mask; each such lane holds its Layout) into LDS at codes + its offset: the
+// whole wave fills one grid at a time, 64 cells per pass in row-major order.
+__device__ __forceinline__ void fill_layouts(uint64_t pending, const Layout& L, uint8_t* codes, int my_off,
+                                             int lane) {
+  while (pending) {
+    const int r = __ffsll((unsigned long long)pending) - 1;
+    pending &= pending - 1;
+    const Layout Lr = bcast_layout(L, r);
+    uint8_t* gp = codes + bcast(my_off, r);
+    const uint32_t Sr = (uint32_t)Lr.S;
+    uint32_t yy, xx, dy, dx;
+    small_divmod((uint32_t)lane, Sr, yy, xx);
+    small_divmod((uint32_t)kWave, Sr, dy, dx);
+    for (uint32_t c = (uint32_t)lane; c < Sr * Sr; c += kWave) {
+      gp[c] = (uint8_t)layout_code(Lr, (int)xx, (int)yy);
+      xx += dx;
+      yy += dy;
+      const bool wrap = xx >= Sr;
+      xx -= wrap ? Sr : 0u;
+      yy += wrap ? 1u : 0u;
+    }
+  }
+}
+
 struct FusedArgs {
   EnvTables env;
   TileTables tiles;
@@ -1001,7 +1026,9 @@ struct FusedArgs {
   int32_t k_steps;
   TrajBufs out;
   int32_t row0;
-  ServeTile* serve;         // per-tile requests (serving), else nullptr
+  ServeTile* serve;               // per-tile requests (serving), else nullptr
+  const ServeTile* host_tiles;    // serving: staging of newly admitted tiles (pinned host memory)
+  const SlotConfig* host_slots;   // serving: their slot configurations
 };
 
 // The fused kernel's workgroups are single waves and all the data its lanes
@@ -1061,7 +1088,12 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
   wave_sync();
 
   for (int it = blockIdx.x; it < a.tiles.n_tiles; it += gridDim.x) {
-    const int tile = a.tiles.list ? (int)a.tiles.list[it] : it;
+    // serving lists mark a newly admitted tile with the top bit: its
+    // descriptor and slot configurations are still in host staging and its
+    // envs are reset here (episode 0) before its first step
+    const uint32_t entry = a.tiles.list ? a.tiles.list[it] : (uint32_t)it;
+    const int tile = (int)(entry & 0x7FFFFFFFu);
+    const bool fresh = kServe && (entry >> 31) != 0;
     // where this tile's envs live and where their records go: record of
     // step s, lane l is at index rec_base + s * rec_step (+ l) of the outputs
     const int e0 = tile * kWave;
@@ -1072,7 +1104,8 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
     uint32_t step0 = 0;
     size_t rec_stride;
     if (kServe) {
-      const ServeTile d = a.serve[tile];
+      const ServeTile d = fresh ? a.host_tiles[tile] : a.serve[tile];
+      if (fresh && lane == 0) a.serve[tile] = d;   // the device copy later launches read
       if (!d.active || d.step0 >= d.n_steps) continue;
       n_here = (int)d.n_envs;
       steps = min(a.k_steps, (int)(d.n_steps - d.step0));
@@ -1106,7 +1139,27 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
     uint2 seed = make_uint2(0, 0);
     uint64_t goff = 0;
     uint32_t ob[4] = {~0u, ~0u, ~0u, ~0u};
-    if (active) {
+    Layout L0{};
+    if (active && fresh) {
+      const SlotConfig c = a.host_slots[e];
+      meta = c.meta;
+      T = c.max_steps;
+      seed = c.seed;
+      rid = c.rng_id;
+      a.env.meta[e] = c.meta;
+      a.env.max_steps[e] = c.max_steps;
+      a.env.seed[e] = c.seed;
+      a.env.rng_id[e] = c.rng_id;
+      a.env.grid_off[e] = c.grid_off;
+      fam = meta & 0xFF;
+      S = (int)((meta >> 8) & 0xFF);
+      L0 = make_layout(meta, seed, rid, 0u);
+      x = L0.ax;
+      y = L0.ay;
+      dir = L0.dir;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ob[i] = L0.ob[i];
+    } else if (active) {
       meta = a.env.meta[e];
       fam = meta & 0xFF;
       S = (int)((meta >> 8) & 0xFF);
@@ -1128,9 +1181,12 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
     int tile_cells;
     const int my_off = wave_excl_scan(S * S, lane, tile_cells);
     uint8_t* my_codes = codes + my_off;
-    // the tile's grids are contiguous in HBM: stage them as codes
+    // the tile's grids are contiguous in HBM: stage them as codes (a fresh
+    // tile's are laid out here instead)
     if (!kServe) g0 = (uint64_t)__shfl((long long)goff, 0, kWave);
-    {
+    if (fresh) {
+      fill_layouts(__ballot(active), L0, codes, my_off, lane);
+    } else {
       const uint8_t* src = a.st.grid + g0;
       for (int c = lane; c < tile_cells; c += kWave) {
         const uint32_t tri = (uint32_t)src[3 * c] | ((uint32_t)src[3 * c + 1] << 8) |
@@ -1168,27 +1224,9 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) ob[i] = L.ob[i];
       }
-      uint64_t pending = __ballot(do_reset);
+      const uint64_t pending = __ballot(do_reset);
       if (pending) {
-        while (pending) {
-          const int r = __ffsll((unsigned long long)pending) - 1;
-          pending &= pending - 1;
-          const Layout Lr = bcast_layout(L, r);
-          uint8_t* gp = codes + bcast(my_off, r);
-          // the grid's cells in row-major order, 64 at a time, one per lane
-          const uint32_t Sr = (uint32_t)Lr.S;
-          uint32_t yy, xx, dy, dx;
-          small_divmod((uint32_t)lane, Sr, yy, xx);
-          small_divmod((uint32_t)kWave, Sr, dy, dx);
-          for (uint32_t c = (uint32_t)lane; c < Sr * Sr; c += kWave) {
-            gp[c] = (uint8_t)layout_code(Lr, (int)xx, (int)yy);
-            xx += dx;
-            yy += dy;
-            const bool wrap = xx >= Sr;
-            xx -= wrap ? Sr : 0u;
-            yy += wrap ? 1u : 0u;
-          }
-        }
+        fill_layouts(pending, L, codes, my_off, lane);
         wave_sync();
       }
 
@@ -1282,63 +1320,6 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
   }
 }
 
-// ---------------------------------------------------------------------------
-// Admission of requests to a server: one workgroup per admitted tile copies
-// the tile's per-slot configuration and its descriptor from host staging
-// and resets its envs (reset(key) of Sec. 3.2.2, episode 0).
-// ---------------------------------------------------------------------------
-struct AdmitArgs {
-  EnvTables env;                 // slot tables (written here)
-  StateBufs st;                  // slot state and the grid pool
-  ServeTile* tiles;              // device descriptors (written here)
-  const ServeTile* host_tiles;   // staging, indexed by tile
-  const SlotConfig* host_slots;  // staging, indexed by slot
-  int32_t n;
-  uint32_t tile_ids[kAdmitBatch];
-};
-
-__global__ __launch_bounds__(kWave) void k_admit(AdmitArgs a) {
-  const int lane = threadIdx.x;
-  const uint32_t tile = a.tile_ids[blockIdx.x];
-  const ServeTile d = a.host_tiles[tile];
-  const bool active = lane < (int)d.n_envs;
-  const uint32_t e = tile * kWave + lane;
-  Layout L{};
-  uint8_t* g = a.st.grid;
-  if (active) {
-    const SlotConfig c = a.host_slots[e];
-    a.env.meta[e] = c.meta;
-    a.env.max_steps[e] = c.max_steps;
-    a.env.seed[e] = c.seed;
-    a.env.rng_id[e] = c.rng_id;
-    a.env.grid_off[e] = c.grid_off;
-    L = make_layout(c.meta, c.seed, c.rng_id, 0u);
-    g = a.st.grid + c.grid_off;
-    a.st.x[e] = L.ax;
-    a.st.y[e] = L.ay;
-    a.st.dir[e] = L.dir;
-    a.st.t[e] = 0;
-    a.st.carry[e] = (int32_t)kCellEmpty;
-    a.st.episode[e] = 0u;
-    a.st.done_prev[e] = 0;
-    a.st.calls[e] = 0u;
-    *reinterpret_cast<uint4*>(a.st.obst + 16 * (size_t)e) = make_uint4(L.ob[0], L.ob[1], L.ob[2], L.ob[3]);
-  }
-  uint64_t pending = __ballot(active);
-  while (pending) {
-    const int r = __ffsll((unsigned long long)pending) - 1;
-    pending &= pending - 1;
-    const Layout Lr = bcast_layout(L, r);
-    const uint64_t gr = ((uint64_t)(uint32_t)bcast((int)(uint32_t)reinterpret_cast<uint64_t>(g), r)) |
-                        ((uint64_t)(uint32_t)bcast((int)(uint32_t)(reinterpret_cast<uint64_t>(g) >> 32), r) << 32);
-    uint8_t* gp = reinterpret_cast<uint8_t*>(gr);
-    const int xx = lane & 31;
-    for (int yy = lane >> 5; yy < Lr.S; yy += 2)
-      if (xx < Lr.S) store_triple(gp + 3 * (yy * Lr.S + xx), layout_cell(Lr, xx, yy));
-  }
-  if (lane == 0) a.tiles[tile] = d;
-}
-
 }  // namespace
 
 size_t fused_dynamic_lds_bytes(int32_t max_tile_cells) { return tile_lds_bytes(max_tile_cells); }
@@ -1358,8 +1339,9 @@ hipError_t launch_plain(const EnvTables& env, const StateBufs& st, const uint8_t
 hipError_t launch_fused(const EnvTables& env, const TileTables& tiles, const StateBufs& st,
                         const uint8_t* actions, int32_t k_steps,
                         const TrajBufs& out, int32_t row0, int32_t grid_blocks,
-                        hipStream_t stream, ServeTile* serve) {
-  FusedArgs a{env, tiles, st, actions, k_steps, out, row0, serve};
+                        hipStream_t stream, ServeTile* serve, const ServeTile* host_tiles,
+                        const SlotConfig* host_slots) {
+  FusedArgs a{env, tiles, st, actions, k_steps, out, row0, serve, host_tiles, host_slots};
   const size_t lds = fused_dynamic_lds_bytes(tiles.max_tile_cells);
   const void* fn = serve ? reinterpret_cast<const void*>(&k_fused<false, true>)
                  : actions ? reinterpret_cast<const void*>(&k_fused<true, false>)
@@ -1376,25 +1358,6 @@ hipError_t launch_fused(const EnvTables& env, const TileTables& tiles, const Sta
   else
     hipLaunchKernelGGL((k_fused<false, false>), dim3(grid_blocks), dim3(kWave), lds, stream, a);
   return hipGetLastError();
-}
-
-hipError_t launch_admit(const EnvTables& env, const StateBufs& st, ServeTile* tiles,
-                        const ServeTile* host_tiles, const SlotConfig* host_slots,
-                        const uint32_t* tile_ids, int32_t n, hipStream_t stream) {
-  for (int32_t i = 0; i < n; i += kAdmitBatch) {
-    AdmitArgs a{};
-    a.env = env;
-    a.st = st;
-    a.tiles = tiles;
-    a.host_tiles = host_tiles;
-    a.host_slots = host_slots;
-    a.n = n - i < kAdmitBatch ? n - i : kAdmitBatch;
-    for (int32_t j = 0; j < a.n; ++j) a.tile_ids[j] = tile_ids[i + j];
-    hipLaunchKernelGGL(k_admit, dim3(a.n), dim3(kWave), 0, stream, a);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
 }
 
 }  // namespace gx

@@ -63,7 +63,8 @@ struct alignas(64) ServeTile {
   uint32_t n_steps;    // steps the request asked for
 };
 
-// Configuration of one server slot, staged in host memory for admission.
+// Configuration of one server slot, staged in pinned host memory until the
+// first launch that runs its tile copies it to the device tables.
 struct SlotConfig {
   uint32_t meta;       // family | side << 8
   int32_t max_steps;
@@ -73,7 +74,6 @@ struct SlotConfig {
   uint64_t grid_off;   // byte offset of the slot's grid in the pool
 };
 
-constexpr int kAdmitBatch = 512;   // tiles per admission launch (kernel argument)
 
 // Whether (family, side, param) describes a valid env with side <= max_side
 // (the families of Table "envs"; param: Crossings rivers, DistShift variant).
@@ -93,12 +93,6 @@ inline bool family_ok(int family, int side, int param, int max_side) {
   }
 }
 
-// Admits tiles: copies their slot configs and descriptors from host staging
-// (coherent pinned memory the device reads directly) and resets their envs.
-hipError_t launch_admit(const EnvTables& env, const StateBufs& st, ServeTile* tiles,
-                        const ServeTile* host_tiles, const SlotConfig* host_slots,
-                        const uint32_t* tile_ids, int32_t n, hipStream_t stream);
-
 // One launch of the plain kernel: one step of every env (or the reset of
 // every env when reset_all != 0).  Writes output row `row`.
 hipError_t launch_plain(const EnvTables& env, const StateBufs& st, const uint8_t* actions,
@@ -112,7 +106,8 @@ hipError_t launch_plain(const EnvTables& env, const StateBufs& st, const uint8_t
 hipError_t launch_fused(const EnvTables& env, const TileTables& tiles, const StateBufs& st,
                         const uint8_t* actions, int32_t k_steps,
                         const TrajBufs& out, int32_t row0, int32_t grid_blocks,
-                        hipStream_t stream, ServeTile* serve = nullptr);
+                        hipStream_t stream, ServeTile* serve = nullptr,
+                        const ServeTile* host_tiles = nullptr, const SlotConfig* host_slots = nullptr);
 
 // LDS bytes one workgroup of the fused kernel needs for a tile size (static
 // table and record stage plus the dynamic tile grids).

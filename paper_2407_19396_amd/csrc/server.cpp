@@ -57,7 +57,8 @@ struct gx_server {
   uint32_t* d_calls = nullptr;
   uint8_t* d_obst = nullptr;
   gx::ServeTile* d_tiles = nullptr;
-  // host staging read by the admission kernel (coherent pinned memory)
+  // host staging of newly admitted tiles, read by their first fused launch
+  // (coherent pinned memory)
   gx::ServeTile* h_tiles = nullptr;
   gx::SlotConfig* h_slots = nullptr;
   // the tile lists of the last kLists launches (read by the fused kernel
@@ -70,7 +71,7 @@ struct gx_server {
   std::vector<int32_t> tile_cells;   // cells of a live tile, 0 when free
   std::vector<Request> reqs;
   std::vector<int32_t> free_handles;
-  std::vector<uint32_t> pending;     // tiles admitted since the last step
+  std::vector<uint8_t> fresh;        // 1: admitted, not yet in a launch
   std::deque<int32_t> finished;      // requests whose last step has been launched
   std::vector<int32_t> running;      // requests with steps left to launch
   int32_t live = 0;
@@ -161,6 +162,7 @@ int env_server_create(int32_t max_tiles, int32_t max_side, int32_t reward_mode, 
   }
   for (int32_t t = 0; t < max_tiles; ++t) s->free_tiles.insert(t);
   s->tile_cells.assign(max_tiles, 0);
+  s->fresh.assign(max_tiles, 0);
   *out = s;
   return GX_OK;
 }
@@ -225,7 +227,7 @@ int env_server_admit(gx_server* s, const gx_request* r, int32_t* handle) {
     d.step0 = 0;
     d.n_steps = (uint32_t)r->n_steps;
     s->tile_cells[t] = cells;
-    s->pending.push_back((uint32_t)t);
+    s->fresh[t] = 1;
   }
   s->live += 1;
   s->running.push_back(h);
@@ -241,12 +243,6 @@ int env_server_step(gx_server* s, int32_t K, void* stream, int32_t* finished, in
   if (dev != s->device) return GX_EINVAL;
   if (hipGetLastError() != hipSuccess) return GX_EDEVICE;
   const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  if (!s->pending.empty()) {
-    if (gx::launch_admit(tables_of(s), state_of(s), s->d_tiles, s->h_tiles, s->h_slots,
-                         s->pending.data(), (int32_t)s->pending.size(), st) != hipSuccess)
-      return GX_EDEVICE;
-    s->pending.clear();
-  }
   // launch only if some request still has steps to run: the live tiles,
   // those of requests with the most steps left first, so that the blocks
   // that finish early pick up the short ones
@@ -264,9 +260,12 @@ int env_server_step(gx_server* s, int32_t K, void* stream, int32_t* finished, in
     }
     uint32_t* list = s->h_lists + (size_t)slot * s->max_tiles;
     int32_t n = 0, max_cells = 0;
+    // a tile admitted since the last launch carries the top bit: that launch
+    // takes its descriptor and slots from host staging and resets its envs
     for (int32_t h : s->running)
       for (int32_t t : s->reqs[h].tiles) {
-        list[n++] = (uint32_t)t;
+        list[n++] = (uint32_t)t | (s->fresh[t] ? 0x80000000u : 0u);
+        s->fresh[t] = 0;
         max_cells = std::max(max_cells, s->tile_cells[t]);
       }
     const size_t lds = gx::fused_lds_bytes(max_cells);
@@ -275,7 +274,7 @@ int env_server_step(gx_server* s, int32_t K, void* stream, int32_t* finished, in
     const gx::TileTables tiles{n, max_cells, list};
     const gx::TrajBufs none{nullptr, nullptr, nullptr, nullptr, 1};
     if (gx::launch_fused(tables_of(s), tiles, state_of(s), nullptr, K, none, 0, blocks, st,
-                         s->d_tiles) != hipSuccess)
+                         s->d_tiles, s->h_tiles, s->h_slots) != hipSuccess)
       return GX_EDEVICE;
     if (hipEventRecord(s->list_done[slot], st) != hipSuccess) return GX_EDEVICE;
     ++s->launches;
