@@ -82,6 +82,9 @@ def lib():
                                  ctypes.c_int32, P]
         L.ox_observe_categorical.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                              ctypes.c_int, ctypes.c_int32, P]
+        L.ox_observe_full.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P]
+        L.ox_observe_full_categorical.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                  ctypes.c_int, P]
         L.ox_goal_reward.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int]
         L.ox_goal_reward.restype = ctypes.c_float
         L.ox_reset.argtypes = [ctypes.POINTER(_Batch), ctypes.POINTER(_State), P, P, P, P,
@@ -151,6 +154,22 @@ def observe_categorical(grid: np.ndarray, x: int, y: int, d: int, carry: int = E
     return obs
 
 
+def observe_full(grid: np.ndarray, x: int, y: int, d: int) -> np.ndarray:
+    """symbolic observation [S][S][3] (row y, column x, channel) of one env."""
+    g = np.ascontiguousarray(grid, dtype=np.uint8)
+    obs = np.zeros_like(g)
+    lib().ox_observe_full(_ptr(g), g.shape[0], x, y, d, _ptr(obs))
+    return obs
+
+
+def observe_full_categorical(grid: np.ndarray, x: int, y: int, d: int) -> np.ndarray:
+    """categorical observation [S][S] (row y, column x) of one env."""
+    g = np.ascontiguousarray(grid, dtype=np.uint8)
+    obs = np.zeros(g.shape[:2], dtype=np.uint8)
+    lib().ox_observe_full_categorical(_ptr(g), g.shape[0], x, y, d, _ptr(obs))
+    return obs
+
+
 def goal_reward(t: int, T: int, reward_mode: int = 0) -> float:
     return float(np.float32(lib().ox_goal_reward(t, T, reward_mode)))
 
@@ -169,7 +188,8 @@ class Batch:
     rng_id: np.ndarray      # u32[N]
     reward_mode: int = 0
     param: np.ndarray | None = None   # u8[N] family parameter (Crossings N, DistShift k)
-    obs_mode: int = 0                 # 0 symbolic_first_person [7][7][3], 1 categorical [7][7]
+    obs_mode: int = 0                 # 0 symbolic_first_person [7][7][3], 1 categorical_first_person
+                                      # [7][7], 2 symbolic [S][S][3], 3 categorical [S][S]
 
     @property
     def n(self) -> int:
@@ -184,6 +204,24 @@ class Batch:
 
     def grid_bytes(self) -> int:
         return int((3 * self.side.astype(np.uint64) ** 2).sum())
+
+    def obs_row_bytes(self) -> int:
+        """Bytes of one output row of observations in this batch's mode."""
+        return obs_row_bytes(self.obs_mode, self.n, self.grid_bytes())
+
+
+def obs_row_bytes(obs_mode: int, n: int, grid_bytes: int) -> int:
+    """First-person rows hold n records of 147 or 49 bytes; whole-grid rows
+    are packed like the grids: sum 3 S^2 (symbolic) or sum S^2 bytes."""
+    return {0: 147 * n, 1: 49 * n, 2: grid_bytes, 3: grid_bytes // 3}[obs_mode]
+
+
+def full_record(row: np.ndarray, obs_mode: int, grid_off: int, S: int) -> np.ndarray:
+    """One env's whole-grid record inside an output row (modes 2 and 3)."""
+    if obs_mode == 2:
+        return row[grid_off:grid_off + 3 * S * S].reshape(S, S, 3)
+    o = grid_off // 3
+    return row[o:o + S * S].reshape(S, S)
 
 
 @dataclass
@@ -239,14 +277,16 @@ def _cstate(s: State):
 
 @dataclass
 class Outputs:
-    obs: np.ndarray | None   # u8[rows][N][7][7][3]
+    obs: np.ndarray | None   # u8[rows][N][7][7][3], [rows][N][7][7] or [rows][row bytes]
     reward: np.ndarray       # f32[rows][N]
     flags: np.ndarray        # u8[rows][N]
     action: np.ndarray       # u8[rows][N]
 
     @staticmethod
-    def empty(rows: int, n: int, with_obs: bool = True, obs_mode: int = 0) -> "Outputs":
-        shape = (rows, n, 7, 7, 3) if obs_mode == 0 else (rows, n, 7, 7)
+    def empty(rows: int, n: int, with_obs: bool = True, obs_mode: int = 0,
+              row_bytes: int = 0) -> "Outputs":
+        """row_bytes: bytes of one observation row in the whole-grid modes."""
+        shape = {0: (rows, n, 7, 7, 3), 1: (rows, n, 7, 7)}.get(obs_mode, (rows, row_bytes))
         return Outputs(np.zeros(shape, dtype=np.uint8) if with_obs else None,
                        np.zeros((rows, n), dtype=np.float32),
                        np.zeros((rows, n), dtype=np.uint8),
@@ -254,7 +294,7 @@ class Outputs:
 
 
 def reset(batch: Batch, state: State, out: Outputs | None = None, nthreads: int = 0) -> Outputs:
-    out = out or Outputs.empty(1, batch.n, obs_mode=batch.obs_mode)
+    out = out or Outputs.empty(1, batch.n, obs_mode=batch.obs_mode, row_bytes=batch.obs_row_bytes())
     keep: list = []
     cb = _cbatch(batch, keep)
     cs = _cstate(state)
@@ -270,7 +310,7 @@ def rollout(batch: Batch, state: State, n_steps: int, actions: np.ndarray | None
     """Run n_steps steps; step k lands in output row k % rows.  Without
     actions the random policy draws at each env's own call count."""
     rows = n_steps if rows is None else rows
-    out = Outputs.empty(rows, batch.n, with_obs, batch.obs_mode)
+    out = Outputs.empty(rows, batch.n, with_obs, batch.obs_mode, batch.obs_row_bytes())
     if actions is not None:
         actions = np.ascontiguousarray(actions, dtype=np.uint8)
         assert actions.shape == (n_steps, batch.n), actions.shape

@@ -23,7 +23,9 @@
  *     the paper defaults to (reward_mode 1);
  *   - the first-person symbolic observation (Table "observations",
  *     symbolic_first_person, R = 7) with MiniGrid's occlusion rule, since
- *     Sec. 3.2.1 states the environments match MiniGrid exactly;
+ *     Sec. 3.2.1 states the environments match MiniGrid exactly, and the
+ *     other observation functions of that table except the RGB ones:
+ *     categorical_first_person, symbolic and categorical;
  *   - the Empty, DoorKey (two rooms) and FourRooms families (Table "envs"),
  *     and the lava families LavaGap, Crossings and DistShift with the
  *     goal-or-lava reward R2 of Table "envs" (lava: -1 and termination,
@@ -450,13 +452,47 @@ void ox_observe_categorical(const uint8_t *grid, int S, int ax, int ay, int dir,
   for (int k = 0; k < OX_VIEW * OX_VIEW; ++k) obs[k] = sym[3 * k];
 }
 
-/* bytes of one observation record in a mode: 0 symbolic_first_person,
- * 1 categorical_first_person */
-static size_t obs_bytes(int mode) { return mode == 1 ? 49 : 147; }
+/* symbolic (Table "observations"): the whole grid in the canonical      */
+/* encoding, [S][S][3] in the grid's own layout, with the agent drawn on */
+/* its cell as (agent 10, red 0, heading), the way MiniGrid encodes a    */
+/* fully observed grid; what the agent carries is not shown.  Pinned by  */
+/* the hand-worked grid in tests/golden/ and by agreement with the       */
+/* first-person view at every visible cell.                              */
+void ox_observe_full(const uint8_t *grid, int S, int ax, int ay, int dir,
+                     uint8_t *obs /* [S][S][3] */) {
+  for (int y = 0; y < S; ++y)
+    for (int x = 0; x < S; ++x) {
+      const uint8_t *c = grid + 3 * (y * S + x);
+      uint8_t *o = obs + 3 * (y * S + x);
+      if (x == ax && y == ay) {
+        o[0] = O_AGENT; o[1] = C_RED; o[2] = (uint8_t)dir;
+      } else {
+        o[0] = c[0]; o[1] = c[1]; o[2] = c[2];
+      }
+    }
+}
 
+/* categorical (Table "observations"): the entity-id grid [S][S], one    */
+/* byte per cell: the type index of every cell, the agent's cell 10.     */
+/* Pinned like the symbolic grid above.                                  */
+void ox_observe_full_categorical(const uint8_t *grid, int S, int ax, int ay, int dir,
+                                 uint8_t *obs /* [S][S] */) {
+  (void)dir;
+  for (int y = 0; y < S; ++y)
+    for (int x = 0; x < S; ++x)
+      obs[y * S + x] = (x == ax && y == ay) ? (uint8_t)O_AGENT : grid[3 * (y * S + x)];
+}
+
+/* Observation modes: 0 symbolic_first_person, 1 categorical_first_person, */
+/* 2 symbolic, 3 categorical.  The first-person records of one output row  */
+/* are [N][147] or [N][49]; the whole-grid records are packed like the     */
+/* grids, env i's at grid_off(i) (symbolic) or grid_off(i) / 3             */
+/* (categorical) of a row of sum 3 S^2 or sum S^2 bytes.                   */
 static void emit_obs(int mode, const uint8_t *grid, int S, int ax, int ay, int dir,
                      int32_t carry, uint8_t *obs) {
   if (mode == 1) ox_observe_categorical(grid, S, ax, ay, dir, carry, obs);
+  else if (mode == 2) ox_observe_full(grid, S, ax, ay, dir, obs);
+  else if (mode == 3) ox_observe_full_categorical(grid, S, ax, ay, dir, obs);
   else ox_observe(grid, S, ax, ay, dir, carry, obs);
 }
 
@@ -627,8 +663,8 @@ static void step_one(int family, int S, int param, int32_t T, uint64_t seed,
 /*   family[i], side[i], param[i], max_steps[i], seed[i], rng_id[i],  */
 /*   grid + grid_off[i] ([side][side][3]),                             */
 /*   x, y, dir, t, carry, episode, done_prev.                          */
-/* Outputs are [N] rows; obs records are 147 bytes (49 in the          */
-/* categorical mode); obs may be NULL.                                 */
+/* Outputs are [N] rows; obs records as emit_obs describes; obs may be */
+/* NULL.                                                               */
 /* nthreads > 0 runs envs in parallel with OpenMP (timing mode).       */
 /* ------------------------------------------------------------------ */
 typedef struct {
@@ -640,7 +676,8 @@ typedef struct {
   const uint64_t *grid_off;
   int32_t reward_mode;
   const uint8_t *param;   /* per env family parameter, or NULL (all 0) */
-  int32_t obs_mode;       /* 0 symbolic_first_person, 1 categorical_first_person */
+  int32_t obs_mode;       /* 0 symbolic_first_person, 1 categorical_first_person,
+                             2 symbolic, 3 categorical */
 } ox_batch;
 
 typedef struct {
@@ -653,6 +690,25 @@ typedef struct {
 } ox_state;
 
 #define PARAM(b, i) ((b)->param ? (int)(b)->param[i] : 0)
+
+/* bytes of one output row of observations */
+static size_t obs_row_bytes(const ox_batch *b) {
+  if (b->obs_mode == 0 || b->obs_mode == 1) return (size_t)b->n * (b->obs_mode == 1 ? 49 : 147);
+  size_t cells = 0;
+  for (int i = 0; i < b->n; ++i) cells += (size_t)b->side[i] * b->side[i];
+  return b->obs_mode == 2 ? 3 * cells : cells;
+}
+
+/* env i's record in output row `row` */
+static uint8_t *obs_at(const ox_batch *b, uint8_t *obs, size_t row_bytes, size_t row, int i) {
+  uint8_t *r = obs + row * row_bytes;
+  switch (b->obs_mode) {
+    case 1: return r + (size_t)49 * i;
+    case 2: return r + b->grid_off[i];
+    case 3: return r + b->grid_off[i] / 3;
+    default: return r + (size_t)147 * i;
+  }
+}
 
 static ox_env_ref env_ref(const ox_batch *b, const ox_state *s, int i) {
   ox_env_ref e;
@@ -679,6 +735,7 @@ int ox_reset(const ox_batch *b, const ox_state *s, uint8_t *obs, float *reward,
   for (int i = 0; i < b->n; ++i)
     if (!ox_side_ok(b->family[i], b->side[i], PARAM(b, i))) return -1;
   set_threads(nthreads);
+  const size_t row_bytes = obs_row_bytes(b);
 #pragma omp parallel for schedule(dynamic, 64) if (nthreads > 0)
   for (int i = 0; i < b->n; ++i) {
     ox_env_ref e = env_ref(b, s, i);
@@ -691,7 +748,7 @@ int ox_reset(const ox_batch *b, const ox_state *s, uint8_t *obs, float *reward,
     *e.calls = 0;
     if (obs)
       emit_obs(b->obs_mode, e.grid, b->side[i], *e.x, *e.y, *e.dir, *e.carry,
-               obs + obs_bytes(b->obs_mode) * i);
+               obs_at(b, obs, row_bytes, 0, i));
     if (reward) reward[i] = 0.0f;
     if (flags) flags[i] = OX_FLAG_FIRST;
     if (action) action[i] = OX_ACTION_NONE;
@@ -708,6 +765,7 @@ int ox_rollout(const ox_batch *b, const ox_state *s, int32_t n_steps,
   if (rows <= 0) return -1;
   set_threads(nthreads);
   const size_t N = (size_t)b->n;
+  const size_t row_bytes = obs_row_bytes(b);
 #pragma omp parallel for schedule(dynamic, 64) if (nthreads > 0)
   for (int i = 0; i < b->n; ++i) {
     ox_env_ref e = env_ref(b, s, i);
@@ -718,7 +776,7 @@ int ox_rollout(const ox_batch *b, const ox_state *s, int32_t n_steps,
       else a = ox_policy_action(b->seed[i], b->rng_id[i], *e.calls);
       step_one(b->family[i], b->side[i], PARAM(b, i), b->max_steps[i],
                b->seed[i], b->rng_id[i], b->reward_mode, b->obs_mode, e, a,
-               obs ? obs + obs_bytes(b->obs_mode) * (row * N + i) : NULL,
+               obs ? obs_at(b, obs, row_bytes, row, i) : NULL,
                reward + row * N + i,
                flags + row * N + i, action + row * N + i);
       *e.calls += 1u;
