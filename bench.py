@@ -48,6 +48,9 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+OBS_MODES = {"symbolic": 0, "categorical": 1, "symbolic_grid": 2, "categorical_grid": 3}
+
+
 def fused_bytes(n_envs: int, grid_bytes: int, k: int, obs_bytes: int = OBS) -> float:
     """Algorithmic HBM bytes of one fused launch of k steps: every record
     written once, the state (grids + scalars) read and written once."""
@@ -123,8 +126,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner, use library defaults")
     ap.add_argument("--ring", type=int, default=0, help="trajectory ring rows (0: K)")
     ap.add_argument("--plain-steps", type=int, default=512)
-    ap.add_argument("--obs", default="symbolic", choices=["symbolic", "categorical"],
-                    help="observation function: symbolic (147 B) or categorical (49 B) first person")
+    ap.add_argument("--obs", default="symbolic", choices=list(OBS_MODES),
+                    help="observation function: symbolic (147 B) or categorical (49 B) first person, "
+                         "or the whole grid: symbolic_grid (3 S^2 B) or categorical_grid (S^2 B)")
     ap.add_argument("--graph", action="store_true",
                     help="capture the timed rollout in a HIP graph and time its replay")
     ap.add_argument("--plain-actions", action="store_true",
@@ -169,17 +173,18 @@ def main():
     table = make()
     if args.envs and args.workload not in ("mixed", "lava", "dynobs"):
         table = table.subset(np.arange(args.envs) % table.n)
-    obs_mode = 1 if args.obs == "categorical" else 0
-    obs_bytes = 49 if obs_mode else OBS
+    obs_mode = OBS_MODES[args.obs]
     env = ge.GridEnv(table, obs_mode=obs_mode)
-    first = ge.Traj.alloc(1, table.n, obs_mode=obs_mode)
+    # observation bytes per env-step (the mean record size in the whole-grid modes)
+    obs_bytes = env.info()["obs_row_bytes"] / table.n
+    first = env.traj(1)
     stream = torch.cuda.current_stream()
     tuned = None
     if args.K or args.blocks or args.no_tune:
         env.set_launch(args.K or env.info()["k_default"], args.blocks)
     else:
         from paper_2407_19396_amd import autotune
-        probe = ge.Traj.alloc(512, table.n, obs_mode=obs_mode)
+        probe = env.traj(512)
         env.reset(first)
         tuned = autotune.tune(env, probe, log=log)
         del probe
@@ -189,7 +194,7 @@ def main():
     ring = args.ring or K
     log(f"[bench] {table.name}: grid {info['grid_bytes'] / 1e6:.1f} MB, tiles {info['n_tiles']}, "
         f"LDS/WG {info['lds_bytes']} B, blocks {info['blocks']}, K {K}, ring {ring}")
-    traj = ge.Traj.alloc(ring, table.n, obs_mode=obs_mode)
+    traj = env.traj(ring)
     env.reset(first)
     # warmup (also advances episodes away from the synchronous start)
     env.rollout(args.warmup, traj, K=K)

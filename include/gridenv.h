@@ -68,10 +68,17 @@
  *   move order, 0xFF for unused slots and for the other families).
  *
  * Outputs (struct gx_traj): row r of each buffer holds n_envs entries:
- *   obs: bytes [rows][n_envs][7][7][3], view row j (0 = farthest ahead,
- *     6 = the agent's row), view column i (0 = the agent's left), channel;
- *     [rows][n_envs][7][7] (the type channel) in the categorical mode;
- *     may be NULL to skip observations;
+ *   obs: row r is env_info's obs_row_bytes bytes; may be NULL to skip
+ *     observations.  By obs_mode:
+ *     0 symbolic_first_person: [n_envs][7][7][3], view row j (0 = farthest
+ *       ahead, 6 = the agent's row), view column i (0 = the agent's left),
+ *       channel;
+ *     1 categorical_first_person: [n_envs][7][7], the type channel of 0;
+ *     2 symbolic: env i's whole grid [S_i][S_i][3] at byte grid_off(i) of
+ *       the row (rows are packed like the grid buffer), the agent drawn over
+ *       its cell as (10, 0, heading) (MiniGrid's fully observed encoding;
+ *       the carried object is not shown);
+ *     3 categorical: the type channel of 2, [S_i][S_i] at grid_off(i) / 3;
  *   reward: float [rows][n_envs]; flags, action: bytes [rows][n_envs]
  *     (action is the action applied, 0xFF on reset steps).
  */
@@ -123,7 +130,9 @@ typedef struct {
                                   0 symbolic_first_person, records [7][7][3]
                                   (147 bytes); 1 categorical_first_person,
                                   records [7][7] of type ids (49 bytes), the
-                                  same view and occlusion */
+                                  same view and occlusion; 2 symbolic, the
+                                  whole grid [S][S][3]; 3 categorical, the
+                                  whole grid's type ids [S][S] */
   const uint8_t* family;       /* [n_envs] GX_FAMILY_* */
   const uint8_t* side;         /* [n_envs] grid side S (height = width) */
   const uint8_t* param;        /* [n_envs] family parameter, or NULL: all 0 */
@@ -161,6 +170,7 @@ typedef struct {
   int32_t blocks;             /* persistent workgroups of the fused kernel */
   int32_t k_default;          /* steps fused per launch when K = 0 */
   uint64_t grid_bytes;
+  uint64_t obs_row_bytes;     /* bytes of one row of observation outputs */
 } gx_info;
 
 /* Validate a batch description (families and sides of Table "envs"),

@@ -646,6 +646,16 @@ __device__ __forceinline__ void store_words(uint8_t* stage, int slot, const uint
   if (kCat ? m == 3 : m != 0) base[kWords - 1] = u[kWords - 1];
 }
 
+// Both kernels' workgroups are single waves and all the data its lanes
+// exchange lives in LDS, whose operations a wave performs in issue order: a
+// wavefront-scope fence (no wait instruction) plus a compiler barrier is
+// enough to make one lane's LDS writes visible to the others' later reads.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // Copies n_envs staged records of kBytes bytes (1 <= n_envs <= kMaxEnvs) to
@@ -673,6 +683,80 @@ __device__ __forceinline__ void copy_out(const uint8_t* stage, uint8_t* dst, int
     for (int b = lane; b < bytes; b += kWave) dst[b] = stage[b];
   }
 }
+
+// ---------------------------------------------------------------------------
+// Whole-grid observations (Table "observations": symbolic [S][S][3] and
+// categorical [S][S]), MiniGrid's fully observed encoding: every cell's
+// triple (or type) with the agent drawn over its own cell as (10, red,
+// heading).  A wave's records are contiguous in the output row, exactly like
+// its envs' grids, so the wave writes them as one byte range [0, n): window
+// by window, the lanes fill the LDS stage a word at a time (fill(o) returns
+// output bytes o..o+3; o may fall outside [0, n) at the window edges, where
+// the bytes are never stored), every lane then writes its agent's bytes over
+// its cell, and the window leaves as 16-byte aligned stores; bytes outside
+// [0, n) belong to neighbouring waves' records and are left alone.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kAgent = 10;
+
+template <int kWin, class Fill>
+__device__ __forceinline__ void emit_grids(uint8_t* dst, int64_t n, uint8_t* stage, int lane, bool has_agent,
+                                           int64_t agent_o, uint32_t agent_bytes, int agent_len,
+                                           const Fill& fill) {
+  static_assert(kWin % 16 == 0, "stage windows are whole 16-byte chunks");
+  const uintptr_t d0 = reinterpret_cast<uintptr_t>(dst), d1 = d0 + (uintptr_t)n;
+  uint32_t* words = reinterpret_cast<uint32_t*>(stage);
+  for (uintptr_t A = d0 & ~(uintptr_t)15; A < d1; A += kWin) {
+    const int win = (int)min((uintptr_t)kWin, (d1 - A + 15) & ~(uintptr_t)15);
+    const int64_t rel = (int64_t)A - (int64_t)d0;   // output byte of stage byte 0, >= -15
+    for (int q = lane; q < (win >> 2); q += kWave) words[q] = fill(rel + 4 * q);
+    wave_sync();
+    if (has_agent) {
+      for (int k = 0; k < agent_len; ++k) {
+        const int64_t p = agent_o + k - rel;
+        if (p >= 0 && p < win) stage[p] = (uint8_t)(agent_bytes >> (8 * k));
+      }
+    }
+    wave_sync();
+    for (int c = lane; c < (win >> 4); c += kWave) {
+      const uintptr_t a = A + 16 * (uintptr_t)c;
+      if (a >= d0 && a + 16 <= d1) {
+        __builtin_nontemporal_store(reinterpret_cast<const u32x4*>(stage)[c], reinterpret_cast<u32x4*>(a));
+      } else {
+        for (int b = 0; b < 16; ++b)
+          if (a + b >= d0 && a + b < d1) reinterpret_cast<uint8_t*>(a)[b] = stage[16 * c + b];
+      }
+    }
+    wave_sync();
+  }
+}
+
+// Fill of symbolic records from the HBM grids (the plain kernel): output
+// byte o is byte o of the wave's grid block of n bytes.
+struct FillHbmSymbolic {
+  const uint8_t* src;
+  int64_t n;
+  __device__ __forceinline__ uint32_t operator()(int64_t o) const {
+    uint32_t w = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (o + k >= 0 && o + k < n) w |= (uint32_t)src[o + k] << (8 * k);
+    return w;
+  }
+};
+
+// Categorical records from the HBM grids: output byte o is the type channel
+// of cell o of the wave's block of n cells.
+struct FillHbmCategorical {
+  const uint8_t* src;
+  int64_t n;
+  __device__ __forceinline__ uint32_t operator()(int64_t o) const {
+    uint32_t w = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (o + k >= 0 && o + k < n) w |= (uint32_t)src[3 * (o + k)] << (8 * k);
+    return w;
+  }
+};
 
 // ---------------------------------------------------------------------------
 // Plain kernel
@@ -744,6 +828,7 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
   bool done_prev = false;
   uint2 seed = make_uint2(0, 0);
   uint8_t* g = a.st.grid;
+  uint64_t goff = 0;
   uint32_t ob[4] = {~0u, ~0u, ~0u, ~0u};
   if (active) {
     meta = a.env.meta[e];
@@ -752,7 +837,8 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
     T = a.env.max_steps[e];
     seed = a.env.seed[e];
     rid = a.env.rng_id[e];
-    g = a.st.grid + a.env.grid_off[e];
+    goff = a.env.grid_off[e];
+    g = a.st.grid + goff;
     if (!a.reset_all) {
       x = a.st.x[e];
       y = a.st.y[e];
@@ -833,7 +919,24 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
   }
 
   const size_t rowN = (size_t)a.row * (size_t)N;
-  if (a.out.obs) {
+  if (a.out.obs && a.env.obs_mode >= 2) {
+    // whole-grid records: the step's grid writes by every lane (resets,
+    // doors, keys, balls) must be visible before the wave copies the grids
+    __threadfence_block();
+    __syncthreads();
+    const uint64_t G0 = (uint64_t)__shfl((long long)goff, 0, kWave);
+    const uint64_t end = active ? goff + 3ull * (uint64_t)(S * S) : 0ull;
+    const int64_t n = (int64_t)((uint64_t)__shfl((long long)end, n_here - 1, kWave) - G0);
+    const int64_t cell = (int64_t)(goff - G0) / 3 + y * S + x;   // the agent's cell in the block
+    const uint8_t* src = a.st.grid + G0;
+    uint8_t* dst = a.out.obs + (size_t)a.row * a.out.obs_row;
+    if (a.env.obs_mode == 3)
+      emit_grids<kStageBytes>(dst + G0 / 3, n / 3, stage, lane, active, cell, kAgent, 1,
+                              FillHbmCategorical{src, n / 3});
+    else
+      emit_grids<kStageBytes>(dst + G0, n, stage, lane, active, 3 * cell, kAgent | ((uint32_t)dir << 16), 3,
+                              FillHbmSymbolic{src, n});
+  } else if (a.out.obs) {
     // inactive lanes get an empty grid: every read is out of bounds (a wall)
     uint32_t u[kObsWords + 1];
     const HbmRows rows{HbmCells{g, active ? S : 0}, x, y, dir_dx(dir), dir_dy(dir)};
@@ -993,6 +1096,35 @@ struct LdsGrid {
   __device__ __forceinline__ void put_ball(int x, int y) const { g[y * S + x] = (uint8_t)(4u * (19u + kBlue)); }
 };
 
+// Fills of whole-grid records from the tile's LDS codes (the fused kernel):
+// output byte o of the tile's symbolic block is byte o % 3 of cell o / 3's
+// triple; the categorical block holds one type per cell.  Edge reads reach
+// at most 15 cells before or after the tile, inside the cleared margins.
+struct FillLdsSymbolic {
+  const uint32_t* table;   // view column 0's table (see flag at bit 31)
+  const uint8_t* codes;
+  __device__ __forceinline__ uint32_t operator()(int64_t o) const {
+    const int oi = (int)o;
+    const int c = (oi + 48) / 3 - 16;   // floor(oi / 3) for oi >= -48
+    const int r = oi - 3 * c;
+    const uint64_t v = (uint64_t)(table_at(table, codes[c]) & 0xFFFFFFu) |
+                       ((uint64_t)(table_at(table, codes[c + 1]) & 0xFFFFFFu) << 24);
+    return (uint32_t)(v >> (8 * r));
+  }
+};
+
+struct FillLdsCategorical {
+  const uint32_t* table;
+  const uint8_t* codes;
+  __device__ __forceinline__ uint32_t operator()(int64_t o) const {
+    const int oi = (int)o;
+    uint32_t w = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w |= (table_at(table, codes[oi + k]) & 0xFFu) << (8 * k);
+    return w;
+  }
+};
+
 // Writes the code grids of the freshly laid-out envs in `pending` (a lane
 // mask; each such lane holds its Layout) into LDS at codes + its offset: the
 // whole wave fills one grid at a time, 64 cells per pass in row-major order.
@@ -1030,16 +1162,6 @@ struct FusedArgs {
   const ServeTile* host_tiles;    // serving: staging of newly admitted tiles (pinned host memory)
   const SlotConfig* host_slots;   // serving: their slot configurations
 };
-
-// The fused kernel's workgroups are single waves and all the data its lanes
-// exchange lives in LDS, whose operations a wave performs in issue order: a
-// wavefront-scope fence (no wait instruction) plus a compiler barrier is
-// enough to make one lane's LDS writes visible to the others' later reads.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 __device__ __forceinline__ int wave_excl_scan(int v, int lane, int& total) {
   int incl = v;
@@ -1261,7 +1383,18 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
 
       const size_t row = kServe ? (size_t)(step0 + s) : (size_t)((a.row0 + s) % a.out.rows);
       const size_t rec = row * rec_stride;   // index of lane 0's record
-      if (o_obs && !kServe && a.env.obs_mode == 1) {
+      if (o_obs && !kServe && a.env.obs_mode >= 2) {
+        // whole-grid records, packed like the tile's grids (from g0)
+        wave_sync();   // every lane's grid writes of this step
+        const int64_t cell = my_off + y * S + x;   // the agent's cell in the tile
+        uint8_t* dst = a.out.obs + row * a.out.obs_row;
+        if (a.env.obs_mode == 3)
+          emit_grids<kHalfStageBytes>(dst + g0 / 3, tile_cells, stage, lane, active, cell, kAgent, 1,
+                                      FillLdsCategorical{table, codes});
+        else
+          emit_grids<kHalfStageBytes>(dst + g0, 3 * (int64_t)tile_cells, stage, lane, active, 3 * cell,
+                                      kAgent | ((uint32_t)dir << 16), 3, FillLdsSymbolic{table, codes});
+      } else if (o_obs && !kServe && a.env.obs_mode == 1) {
         // categorical records (49 bytes): the stage holds all 64 at once
         uint32_t u[kObsWords + 1];
         observe_words<true>(lds_rows(table, my_codes, S, x, y, dir), carry, active, lane, u);

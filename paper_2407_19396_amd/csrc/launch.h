@@ -15,7 +15,8 @@ struct EnvTables {
   uint32_t* rng_id;           // Philox counter word 0
   uint64_t* grid_off;         // byte offset of the env's [S][S][3] grid
   int32_t reward_mode;        // 0: 1 - 0.9 t/T, 1: unit reward
-  int32_t obs_mode;           // 0: symbolic first person (147 B), 1: categorical (49 B)
+  int32_t obs_mode;           // 0: symbolic first person (147 B), 1: categorical first
+                              // person (49 B), 2: symbolic whole grid, 3: categorical whole grid
 };
 
 // Caller-owned state (device pointers).
@@ -30,11 +31,12 @@ struct StateBufs {
 
 // Per-step outputs: row r of each buffer holds N entries.
 struct TrajBufs {
-  uint8_t* obs;     // [rows][N][147] or nullptr
+  uint8_t* obs;     // [rows][N][147], [rows][N][49], or whole-grid rows of obs_row bytes; or nullptr
   float* reward;    // [rows][N]
   uint8_t* flags;   // [rows][N]
   uint8_t* action;  // [rows][N]
   int32_t rows;
+  uint64_t obs_row = 0;   // bytes of one whole-grid observation row (sum 3 S^2 or sum S^2)
 };
 
 // Fused rollout tiling: tile i covers envs [i*64, i*64+64) (the last is

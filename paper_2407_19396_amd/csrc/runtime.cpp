@@ -70,6 +70,16 @@ bool state_ok(const gx_state* st) {
          (reinterpret_cast<uintptr_t>(st->obst) & 15) == 0;
 }
 
+// bytes of one output row of observations
+uint64_t obs_row_bytes(const gx_ctx* c) {
+  switch (c->obs_mode) {
+    case 1: return (uint64_t)c->n * GX_OBS_CAT_BYTES;
+    case 2: return c->grid_bytes;
+    case 3: return c->grid_bytes / 3;
+    default: return (uint64_t)c->n * GX_OBS_BYTES;
+  }
+}
+
 bool traj_ok(const gx_traj* tr) {
   return tr && tr->reward && tr->flags && tr->action && tr->rows >= 1;
 }
@@ -84,8 +94,8 @@ gx::StateBufs state_of(const gx_state* st) {
                        st->calls, st->obst};
 }
 
-gx::TrajBufs traj_of(const gx_traj* tr) {
-  return gx::TrajBufs{tr->obs, tr->reward, tr->flags, tr->action, tr->rows};
+gx::TrajBufs traj_of(const gx_ctx* c, const gx_traj* tr) {
+  return gx::TrajBufs{tr->obs, tr->reward, tr->flags, tr->action, tr->rows, obs_row_bytes(c)};
 }
 
 int check_device(const gx_ctx* c) {
@@ -115,7 +125,7 @@ int env_create(const gx_config* cfg, gx_ctx** out) {
   *out = nullptr;
   if (!cfg || cfg->n_envs < 1 || !cfg->family || !cfg->side || !cfg->max_steps) return GX_EINVAL;
   if (cfg->reward_mode != 0 && cfg->reward_mode != 1) return GX_EINVAL;
-  if (cfg->obs_mode != 0 && cfg->obs_mode != 1) return GX_EINVAL;
+  if (cfg->obs_mode < 0 || cfg->obs_mode > 3) return GX_EINVAL;
   const int32_t n = cfg->n_envs;
   // the grid of a tile must fit the LDS of one workgroup; side <= 32 and
   // 64 envs per tile bound it at 64 KiB of cells
@@ -195,6 +205,7 @@ int env_info(const gx_ctx* c, gx_info* info) {
   info->blocks = c->blocks;
   info->k_default = c->k_default;
   info->grid_bytes = c->grid_bytes;
+  info->obs_row_bytes = obs_row_bytes(c);
   return GX_OK;
 }
 
@@ -205,7 +216,7 @@ int env_reset(gx_ctx* c, const gx_state* st, const gx_traj* first, void* stream)
   if (rc != GX_OK) return rc;
   if ((rc = device_status()) != GX_OK) return rc;
   gx::TrajBufs tb{nullptr, nullptr, nullptr, nullptr, 1};
-  if (first) tb = traj_of(first);
+  if (first) tb = traj_of(c, first);
   if (gx::launch_plain(tables_of(c), state_of(st), nullptr, 1, tb, 0,
                        reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
     return GX_EDEVICE;
@@ -220,7 +231,7 @@ int env_step(gx_ctx* c, const gx_state* st, const uint8_t* actions, const gx_tra
   int rc = check_device(c);
   if (rc != GX_OK) return rc;
   if ((rc = device_status()) != GX_OK) return rc;
-  if (gx::launch_plain(tables_of(c), state_of(st), actions, 0, traj_of(out), 0,
+  if (gx::launch_plain(tables_of(c), state_of(st), actions, 0, traj_of(c, out), 0,
                        reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
     return GX_EDEVICE;
   return GX_OK;
@@ -238,7 +249,7 @@ int env_rollout(gx_ctx* c, const gx_state* st, int32_t n_steps, const uint8_t* a
   for (int32_t s0 = 0; s0 < n_steps; s0 += k) {
     const int32_t ks = std::min(k, n_steps - s0);
     const uint8_t* act = actions ? actions + (size_t)s0 * (size_t)c->n : nullptr;
-    if (gx::launch_fused(tables_of(c), tiles, state_of(st), act, ks, traj_of(traj),
+    if (gx::launch_fused(tables_of(c), tiles, state_of(st), act, ks, traj_of(c, traj),
                          s0 % traj->rows, c->blocks, reinterpret_cast<hipStream_t>(stream)) !=
         hipSuccess)
       return GX_EDEVICE;

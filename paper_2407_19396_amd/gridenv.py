@@ -50,7 +50,7 @@ class GxInfo(ctypes.Structure):
     _fields_ = [("n_envs", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
                 ("max_tile_cells", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
                 ("blocks", ctypes.c_int32), ("k_default", ctypes.c_int32),
-                ("grid_bytes", ctypes.c_uint64)]
+                ("grid_bytes", ctypes.c_uint64), ("obs_row_bytes", ctypes.c_uint64)]
 
 
 class GxRequest(ctypes.Structure):
@@ -198,17 +198,19 @@ def env_destroy(ctx: int):
 # --------------------------------------------------------------- tensors
 @dataclass
 class Traj:
-    """Device output rows: obs [rows][N][7][7][3] u8 ([rows][N][7][7] in the
-    categorical mode, or None), reward f32, flags u8, action u8 [rows][N]."""
+    """Device output rows: obs u8 [rows][N][7][7][3] (mode 0), [rows][N][7][7]
+    (mode 1) or [rows][row_bytes] (whole-grid modes 2 and 3, records packed
+    like the grids), or None; reward f32, flags u8, action u8 [rows][N]."""
     obs: object
     reward: object
     flags: object
     action: object
 
     @staticmethod
-    def alloc(rows: int, n: int, device="cuda", with_obs: bool = True, obs_mode: int = 0) -> "Traj":
+    def alloc(rows: int, n: int, device="cuda", with_obs: bool = True, obs_mode: int = 0,
+              row_bytes: int = 0) -> "Traj":
         import torch
-        shape = (rows, n, 7, 7, 3) if obs_mode == 0 else (rows, n, 7, 7)
+        shape = {0: (rows, n, 7, 7, 3), 1: (rows, n, 7, 7)}.get(obs_mode, (rows, row_bytes))
         return Traj(torch.zeros(shape, dtype=torch.uint8, device=device) if with_obs else None,
                     torch.zeros((rows, n), dtype=torch.float32, device=device),
                     torch.zeros((rows, n), dtype=torch.uint8, device=device),
@@ -250,6 +252,11 @@ class GridEnv:
 
     def state(self) -> GxState:
         return GxState(*[getattr(self, f).data_ptr() for f in self.FIELDS])
+
+    def traj(self, rows: int, with_obs: bool = True) -> Traj:
+        """Output rows shaped for this context's observation mode."""
+        return Traj.alloc(rows, self.n, self.device, with_obs, self.obs_mode,
+                          int(self.info()["obs_row_bytes"]))
 
     def reset(self, first: Traj | None = None, stream=None):
         env_reset(self.ctx, self.state(), first.c() if first is not None else None, stream)
