@@ -979,7 +979,8 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
 // read and one table read.  There is one table per view column i, whose
 // entries carry the see-through flag at bit 31 - i.  Kinds: 0 empty;
 // 1-6 wall, 7-12 goal, 13-18 key, 19-24 ball, 25-30 box by colour; 31-48
-// door by state and colour; 49 lava; 50 anything else (read as unseen).
+// door by state and colour; 49 lava; 50 anything else (read as unseen);
+// 51-54 the agent by heading (whole-grid records only).
 __device__ __forceinline__ uint32_t code_of(uint32_t tri) {
   const uint32_t type = tri & 0xFF, colour = (tri >> 8) & 0xFF, state = (tri >> 16) & 0xFF;
   // first kind of each type, as two 8-entry byte tables read with v_perm:
@@ -994,6 +995,10 @@ __device__ __forceinline__ uint32_t code_of(uint32_t tri) {
   return (kind << 2) & 0xFFu;
 }
 
+// kinds 51-54: the agent facing east, south, west, north; they exist only
+// while whole-grid records are written
+constexpr uint32_t kAgentKind = 51;
+
 __device__ __forceinline__ uint32_t triple_of_kind(uint32_t kind) {
   uint32_t tri;
   if (kind == 0) tri = kCellEmpty;
@@ -1004,6 +1009,7 @@ __device__ __forceinline__ uint32_t triple_of_kind(uint32_t kind) {
   else if (kind <= 30) tri = kBox | ((kind - 25) << 8);
   else if (kind <= 48) tri = kDoor | (((kind - 31) % 6) << 8) | (((kind - 31) / 6) << 16);
   else if (kind == 49) tri = 9;
+  else if (kind >= kAgentKind && kind < kAgentKind + 4) return kAgent | ((kind - kAgentKind) << 16);
   else return 0;
   return tri | see_through(tri);
 }
@@ -1096,34 +1102,71 @@ struct LdsGrid {
   __device__ __forceinline__ void put_ball(int x, int y) const { g[y * S + x] = (uint8_t)(4u * (19u + kBlue)); }
 };
 
-// Fills of whole-grid records from the tile's LDS codes (the fused kernel):
-// output byte o of the tile's symbolic block is byte o % 3 of cell o / 3's
-// triple; the categorical block holds one type per cell.  Edge reads reach
-// at most 15 cells before or after the tile, inside the cleared margins.
-struct FillLdsSymbolic {
-  const uint32_t* table;   // view column 0's table (see flag at bit 31)
-  const uint8_t* codes;
-  __device__ __forceinline__ uint32_t operator()(int64_t o) const {
-    const int oi = (int)o;
-    const int c = (oi + 48) / 3 - 16;   // floor(oi / 3) for oi >= -48
-    const int r = oi - 3 * c;
-    const uint64_t v = (uint64_t)(table_at(table, codes[c]) & 0xFFFFFFu) |
-                       ((uint64_t)(table_at(table, codes[c + 1]) & 0xFFFFFFu) << 24);
-    return (uint32_t)(v >> (8 * r));
-  }
-};
-
-struct FillLdsCategorical {
-  const uint32_t* table;
-  const uint8_t* codes;
-  __device__ __forceinline__ uint32_t operator()(int64_t o) const {
-    const int oi = (int)o;
-    uint32_t w = 0;
+// Whole-grid records straight from the tile's LDS codes (the fused kernel).
+// The agents are drawn into the codes beforehand (kinds 51-54, one per
+// heading) and removed afterwards, so every output byte is a function of
+// the codes alone and needs no staging: the lanes walk the tile's record
+// block [0, n) in aligned units held in registers and store each once.
+// Symbolic: 16-byte units, at most 6 cells each (18 triple bytes, taken
+// from offset r < 3); categorical: 4-byte units of 4 cells, so that
+// neighbouring lanes read neighbouring code words.  Units at the block's
+// two ends store only their bytes inside [0, n) (the rest belong to the
+// neighbouring tiles' records); their reads reach at most 15 cells before
+// or after the tile, inside the cleared margins.
+template <bool kCat>
+__device__ __forceinline__ void emit_tile_grids(uint8_t* dst, int n_cells, const uint32_t* table,
+                                                const uint8_t* codes, int lane) {
+  constexpr int kUnit = kCat ? 4 : 16;
+  const int64_t n = kCat ? n_cells : 3 * (int64_t)n_cells;
+  const uintptr_t d0 = reinterpret_cast<uintptr_t>(dst), d1 = d0 + (uintptr_t)n;
+  const uintptr_t A = d0 & ~(uintptr_t)(kUnit - 1);
+  const int rel = (int)((int64_t)A - (int64_t)d0);   // in [1 - kUnit, 0]
+  const int units = (int)((d1 - A + kUnit - 1) / kUnit);
+  for (int q = lane; q < units; q += kWave) {
+    const int o = rel + kUnit * q;   // output byte of the unit's first byte
+    const uintptr_t a = A + (uintptr_t)(kUnit * q);
+    if (kCat) {
+      // the unit's 4 codes: one aligned word, or two and a byte shift
+      const int lo = o & ~3, sh = o & 3;
+      const uint32_t* cw = reinterpret_cast<const uint32_t*>(codes + lo);
+      const uint32_t c4 = __builtin_amdgcn_alignbyte(cw[1], cw[0], (uint32_t)sh);
+      uint32_t ty[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) w |= (table_at(table, codes[oi + k]) & 0xFFu) << (8 * k);
-    return w;
+      for (int k = 0; k < 4; ++k) ty[k] = table_at(table, (c4 >> (8 * k)) & 0xFFu);
+      // bytes 0 of the four entries
+      const uint32_t w = __builtin_amdgcn_perm(__builtin_amdgcn_perm(ty[3], ty[2], 0x0c0c0400u),
+                                               __builtin_amdgcn_perm(ty[1], ty[0], 0x0c0c0400u), 0x05040100u);
+      if (a >= d0 && a + 4 <= d1) {
+        __builtin_nontemporal_store(w, reinterpret_cast<uint32_t*>(a));
+      } else {
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          if (a + b >= d0 && a + b < d1) reinterpret_cast<uint8_t*>(a)[b] = (uint8_t)(w >> (8 * b));
+      }
+    } else {
+      const int c = (o + 48) / 3 - 16;   // floor(o / 3) for o >= -48
+      const uint32_t r = (uint32_t)(o - 3 * c);
+      uint32_t t[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) t[k] = table_at(table, codes[c + k]) & 0xFFFFFFu;
+      // the 18 bytes t0..t5 as words, then bytes r..r+15 of them
+      const uint32_t s0 = t[0] | (t[1] << 24), s1 = (t[1] >> 8) | (t[2] << 16),
+                     s2 = (t[2] >> 16) | (t[3] << 8), s3 = t[4] | (t[5] << 24), s4 = t[5] >> 8;
+      u32x4 w;
+      w.x = __builtin_amdgcn_alignbyte(s1, s0, r);
+      w.y = __builtin_amdgcn_alignbyte(s2, s1, r);
+      w.z = __builtin_amdgcn_alignbyte(s3, s2, r);
+      w.w = __builtin_amdgcn_alignbyte(s4, s3, r);
+      if (a >= d0 && a + 16 <= d1) {
+        __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(a));
+      } else {
+#pragma unroll
+        for (int b = 0; b < 16; ++b)
+          if (a + b >= d0 && a + b < d1) reinterpret_cast<uint8_t*>(a)[b] = (uint8_t)(w[b >> 2] >> (8 * (b & 3)));
+      }
+    }
   }
-};
+}
 
 // Writes the code grids of the freshly laid-out envs in `pending` (a lane
 // mask; each such lane holds its Layout) into LDS at codes + its offset: the
@@ -1384,16 +1427,20 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
       const size_t row = kServe ? (size_t)(step0 + s) : (size_t)((a.row0 + s) % a.out.rows);
       const size_t rec = row * rec_stride;   // index of lane 0's record
       if (o_obs && !kServe && a.env.obs_mode >= 2) {
-        // whole-grid records, packed like the tile's grids (from g0)
-        wave_sync();   // every lane's grid writes of this step
-        const int64_t cell = my_off + y * S + x;   // the agent's cell in the tile
+        // whole-grid records, packed like the tile's grids (from g0): the
+        // agents are drawn into the codes for the copy and then removed
+        uint8_t* at = my_codes + y * S + x;
+        uint8_t under = 0;
+        if (active) {
+          under = *at;
+          *at = (uint8_t)(4u * (kAgentKind + (uint32_t)dir));
+        }
+        wave_sync();   // every lane's grid writes of this step, and the agents
         uint8_t* dst = a.out.obs + row * a.out.obs_row;
-        if (a.env.obs_mode == 3)
-          emit_grids<kHalfStageBytes>(dst + g0 / 3, tile_cells, stage, lane, active, cell, kAgent, 1,
-                                      FillLdsCategorical{table, codes});
-        else
-          emit_grids<kHalfStageBytes>(dst + g0, 3 * (int64_t)tile_cells, stage, lane, active, 3 * cell,
-                                      kAgent | ((uint32_t)dir << 16), 3, FillLdsSymbolic{table, codes});
+        if (a.env.obs_mode == 3) emit_tile_grids<true>(dst + g0 / 3, tile_cells, table, codes, lane);
+        else emit_tile_grids<false>(dst + g0, tile_cells, table, codes, lane);
+        wave_sync();
+        if (active) *at = under;
       } else if (o_obs && !kServe && a.env.obs_mode == 1) {
         // categorical records (49 bytes): the stage holds all 64 at once
         uint32_t u[kObsWords + 1];
