@@ -87,11 +87,11 @@ def lib():
                                                   ctypes.c_int, P]
         L.ox_goal_reward.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int]
         L.ox_goal_reward.restype = ctypes.c_float
-        L.ox_reset.argtypes = [ctypes.POINTER(_Batch), ctypes.POINTER(_State), P, P, P, P,
+        L.ox_reset.argtypes = [ctypes.POINTER(_Batch), ctypes.POINTER(_State), P, P, P, P, P,
                                ctypes.c_int]
         L.ox_reset.restype = ctypes.c_int
         L.ox_rollout.argtypes = [ctypes.POINTER(_Batch), ctypes.POINTER(_State), ctypes.c_int32,
-                                 P, ctypes.c_int32, P, P, P, P, ctypes.c_int]
+                                 P, ctypes.c_int32, P, P, P, P, P, ctypes.c_int]
         L.ox_rollout.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -281,6 +281,7 @@ class Outputs:
     reward: np.ndarray       # f32[rows][N]
     flags: np.ndarray        # u8[rows][N]
     action: np.ndarray       # u8[rows][N]
+    mission: np.ndarray = None   # u8[rows][N]: GoToDoor's target colour, 0xFF without a mission
 
     @staticmethod
     def empty(rows: int, n: int, with_obs: bool = True, obs_mode: int = 0,
@@ -289,6 +290,7 @@ class Outputs:
         shape = {0: (rows, n, 7, 7, 3), 1: (rows, n, 7, 7)}.get(obs_mode, (rows, row_bytes))
         return Outputs(np.zeros(shape, dtype=np.uint8) if with_obs else None,
                        np.zeros((rows, n), dtype=np.float32),
+                       np.zeros((rows, n), dtype=np.uint8),
                        np.zeros((rows, n), dtype=np.uint8),
                        np.zeros((rows, n), dtype=np.uint8))
 
@@ -299,7 +301,7 @@ def reset(batch: Batch, state: State, out: Outputs | None = None, nthreads: int 
     cb = _cbatch(batch, keep)
     cs = _cstate(state)
     rc = lib().ox_reset(ctypes.byref(cb), ctypes.byref(cs), _ptr(out.obs), _ptr(out.reward),
-                        _ptr(out.flags), _ptr(out.action), nthreads)
+                        _ptr(out.flags), _ptr(out.action), _ptr(out.mission), nthreads)
     if rc != 0:
         raise ValueError(f"oracle reset failed ({rc})")
     return out
@@ -319,7 +321,7 @@ def rollout(batch: Batch, state: State, n_steps: int, actions: np.ndarray | None
     cs = _cstate(state)
     rc = lib().ox_rollout(ctypes.byref(cb), ctypes.byref(cs), n_steps, _ptr(actions), rows,
                           _ptr(out.obs), _ptr(out.reward), _ptr(out.flags), _ptr(out.action),
-                          nthreads)
+                          _ptr(out.mission), nthreads)
     if rc != 0:
         raise ValueError(f"oracle rollout failed ({rc})")
     return out

@@ -60,7 +60,7 @@ enum { D_OPEN = 0, D_CLOSED = 1, D_LOCKED = 2 };
 enum { A_LEFT = 0, A_RIGHT = 1, A_FORWARD = 2, A_PICKUP = 3, A_DROP = 4,
        A_TOGGLE = 5, A_DONE = 6 };
 enum { FAM_EMPTY = 0, FAM_TWOROOM = 1, FAM_FOURROOMS = 2, FAM_LAVAGAP = 3,
-       FAM_CROSSINGS = 4, FAM_DISTSHIFT = 5, FAM_DYNOBS = 6 };
+       FAM_CROSSINGS = 4, FAM_DISTSHIFT = 5, FAM_DYNOBS = 6, FAM_GOTODOOR = 7 };
 #define OX_MAX_OBST 8
 
 #define OX_FLAG_TERMINATED 1u
@@ -186,6 +186,7 @@ int ox_side_ok(int family, int side, int param) {
     case FAM_DYNOBS:
       return side >= 5 && param >= 1 && param <= OX_MAX_OBST &&
              param <= (side - 2) * (side - 2) - 2;
+    case FAM_GOTODOOR: return side >= 5;
   }
   return 0;
 }
@@ -230,6 +231,16 @@ int ox_side_ok(int family, int side, int param) {
 /*   the k-th empty interior cell other than the agent's, k uniform,    */
 /*   placed in order b = 0..n-1; their positions are listed in obst     */
 /*   (x, y per ball, 0xFF for unused slots and other families).         */
+/* GoToDoor(S): a room of width w = 5 + u(S-4) and height             */
+/*   h = 5 + u(S-4) in the top-left corner, walled; every cell outside  */
+/*   the room is wall too.  One closed door on each room wall, at a     */
+/*   uniform non-corner position, drawn in the order top (x), right     */
+/*   (y), bottom (x), left (y); the four doors take four distinct       */
+/*   colours by a partial Fisher-Yates shuffle of the six (step k swaps */
+/*   colour k with colour k + u(6-k)), door i getting colour i of the   */
+/*   shuffle; the mission is the colour of door u(4) (kept in obst[0]); */
+/*   agent uniform over the room's interior; direction uniform.  No     */
+/*   goal.                                                              */
 /* Pinned by: structural invariants, uniformity tests and the hand     */
 /* layouts in tests; agreement with MiniGrid's own generators: parity  */
 /* unpinned (MiniGrid is not available).                               */
@@ -289,6 +300,28 @@ int ox_layout(int family, int S, int param, uint64_t seed, uint32_t rng_id,
     put(grid, S, gx, gy, O_GOAL, C_GREEN, 0);
     n = count_empty(grid, S, 1, S - 2, 1, S - 2);
     if (kth_empty(grid, S, 1, S - 2, 1, S - 2, DRAW(n), ax, ay)) return -2;
+    *adir = (int)DRAW(4);
+  } else if (family == FAM_GOTODOOR) {
+    int rw = 5 + (int)DRAW(S - 4);
+    int rh = 5 + (int)DRAW(S - 4);
+    for (int y = 0; y < S; ++y)
+      for (int x = 0; x < S; ++x)
+        if (x >= rw - 1 || y >= rh - 1) put(grid, S, x, y, O_WALL, C_GREY, 0);
+    int dx[4], dy[4];
+    dx[0] = 1 + (int)DRAW(rw - 2); dy[0] = 0;        /* top */
+    dx[1] = rw - 1; dy[1] = 1 + (int)DRAW(rh - 2);   /* right */
+    dx[2] = 1 + (int)DRAW(rw - 2); dy[2] = rh - 1;   /* bottom */
+    dx[3] = 0; dy[3] = 1 + (int)DRAW(rh - 2);        /* left */
+    int col[6] = {0, 1, 2, 3, 4, 5};
+    for (int k = 0; k < 4; ++k) {
+      int r = k + (int)DRAW(6 - k);
+      int tmp = col[k]; col[k] = col[r]; col[r] = tmp;
+    }
+    for (int i = 0; i < 4; ++i) put(grid, S, dx[i], dy[i], O_DOOR, col[i], D_CLOSED);
+    int target = (int)DRAW(4);
+    if (obst) obst[0] = (uint8_t)col[target];
+    uint32_t n = count_empty(grid, S, 1, rw - 2, 1, rh - 2);
+    if (kth_empty(grid, S, 1, rw - 2, 1, rh - 2, DRAW(n), ax, ay)) return -2;
     *adir = (int)DRAW(4);
   } else {
     *ax = 1; *ay = 1; *adir = 0;
@@ -580,6 +613,11 @@ static void move_obstacles(uint8_t *grid, int S, int n, int ax, int ay,
 /* move (the transition system), then the action applies; moving       */
 /* forward when that cell held a ball or a wall ends the episode with  */
 /* reward -1, as MiniGrid's version does.                              */
+/* GoToDoor (on_door_done of Tables "rewards" and "terminations"): the */
+/* done action (any action >= 6) with the cell ahead a door of the     */
+/* mission's colour ends the episode with the goal reward; toggling    */
+/* (the door opens or closes as usual) ends it with reward 0, as       */
+/* MiniGrid's version does.                                            */
 /* ------------------------------------------------------------------ */
 static void step_one(int family, int S, int param, int32_t T, uint64_t seed,
                      uint32_t rng_id, int reward_mode, int obs_mode, ox_env_ref e,
@@ -602,6 +640,7 @@ static void step_one(int family, int S, int param, int32_t T, uint64_t seed,
   int fx = *e.x + DIR_X[dir], fy = *e.y + DIR_Y[dir];
   uint8_t *front = cell(e.grid, S, fx, fy);
   int terminated = 0, lava = 0, blocked = 0;
+  int goal = 0;   /* the task is achieved: the goal reached, or the mission's door done */
   if (family == FAM_DYNOBS) {
     if (action > A_FORWARD) action = A_LEFT;   /* three actions only */
     blocked = front[0] != O_EMPTY && front[0] != O_GOAL;
@@ -615,7 +654,7 @@ static void step_one(int family, int S, int param, int32_t T, uint64_t seed,
       int walkable = type == O_EMPTY || type == O_GOAL || type == O_LAVA ||
                      (type == O_DOOR && front[2] == D_OPEN);
       if (walkable) { *e.x = fx; *e.y = fy; }
-      if (type == O_GOAL) terminated = 1;
+      if (type == O_GOAL) terminated = goal = 1;
       if (type == O_LAVA) terminated = lava = 1;
       break;
     }
@@ -642,15 +681,18 @@ static void step_one(int family, int S, int param, int32_t T, uint64_t seed,
           front[2] = front[2] == D_OPEN ? D_CLOSED : D_OPEN;
         }
       }
+      if (family == FAM_GOTODOOR) terminated = 1;   /* toggling ends GoToDoor, reward 0 */
       break;
-    default: /* done, and any out-of-range action: no-op */
+    default: /* done, and any out-of-range action: no effect on the grid */
+      if (family == FAM_GOTODOOR && front[0] == O_DOOR && front[1] == e.obst[0])
+        terminated = goal = 1;                      /* on_door_done */
       break;
   }
   *e.t += 1;
   int truncated = *e.t >= T;
   if (blocked && action == A_FORWARD) terminated = lava = 1;
   if (lava) *reward = -1.0f;
-  else *reward = terminated ? ox_goal_reward(*e.t, T, reward_mode) : 0.0f;
+  else *reward = goal ? ox_goal_reward(*e.t, T, reward_mode) : 0.0f;
   *flags = (uint8_t)((terminated ? OX_FLAG_TERMINATED : 0) |
                      (truncated ? OX_FLAG_TRUNCATED : 0));
   *rec_action = (uint8_t)action;
@@ -663,8 +705,8 @@ static void step_one(int family, int S, int param, int32_t T, uint64_t seed,
 /*   family[i], side[i], param[i], max_steps[i], seed[i], rng_id[i],  */
 /*   grid + grid_off[i] ([side][side][3]),                             */
 /*   x, y, dir, t, carry, episode, done_prev.                          */
-/* Outputs are [N] rows; obs records as emit_obs describes; obs may be */
-/* NULL.                                                               */
+/* Outputs are [N] rows; obs records as emit_obs describes; obs and    */
+/* mission may be NULL.                                                */
 /* nthreads > 0 runs envs in parallel with OpenMP (timing mode).       */
 /* ------------------------------------------------------------------ */
 typedef struct {
@@ -729,9 +771,16 @@ static void set_threads(int nthreads) {
 #endif
 }
 
+/* The mission of an env's current episode (the state component of   */
+/* Sec. 3.2.1): GoToDoor's target door colour, 0xFF for the families   */
+/* without one.                                                        */
+static uint8_t mission_of(int family, const uint8_t *obst) {
+  return family == FAM_GOTODOOR ? obst[0] : (uint8_t)0xFF;
+}
+
 /* Reset every env to episode 0 (reset(key) of Sec. 3.2.2). */
 int ox_reset(const ox_batch *b, const ox_state *s, uint8_t *obs, float *reward,
-             uint8_t *flags, uint8_t *action, int nthreads) {
+             uint8_t *flags, uint8_t *action, uint8_t *mission, int nthreads) {
   for (int i = 0; i < b->n; ++i)
     if (!ox_side_ok(b->family[i], b->side[i], PARAM(b, i))) return -1;
   set_threads(nthreads);
@@ -752,6 +801,7 @@ int ox_reset(const ox_batch *b, const ox_state *s, uint8_t *obs, float *reward,
     if (reward) reward[i] = 0.0f;
     if (flags) flags[i] = OX_FLAG_FIRST;
     if (action) action[i] = OX_ACTION_NONE;
+    if (mission) mission[i] = mission_of(b->family[i], e.obst);
   }
   return 0;
 }
@@ -761,7 +811,8 @@ int ox_reset(const ox_batch *b, const ox_state *s, uint8_t *obs, float *reward,
  * k % rows. */
 int ox_rollout(const ox_batch *b, const ox_state *s, int32_t n_steps,
                const uint8_t *actions, int32_t rows, uint8_t *obs,
-               float *reward, uint8_t *flags, uint8_t *action, int nthreads) {
+               float *reward, uint8_t *flags, uint8_t *action, uint8_t *mission,
+               int nthreads) {
   if (rows <= 0) return -1;
   set_threads(nthreads);
   const size_t N = (size_t)b->n;
@@ -779,6 +830,7 @@ int ox_rollout(const ox_batch *b, const ox_state *s, int32_t n_steps,
                obs ? obs_at(b, obs, row_bytes, row, i) : NULL,
                reward + row * N + i,
                flags + row * N + i, action + row * N + i);
+      if (mission) mission[row * N + i] = mission_of(b->family[i], e.obst);
       *e.calls += 1u;
     }
   }

@@ -19,9 +19,11 @@ import numpy as np
 
 FAMILY_EMPTY, FAMILY_TWOROOM, FAMILY_FOURROOMS = 0, 1, 2
 FAMILY_LAVAGAP, FAMILY_CROSSINGS, FAMILY_DISTSHIFT, FAMILY_DYNOBS = 3, 4, 5, 6
+FAMILY_GOTODOOR = 7
 FAMILY_NAMES = {FAMILY_EMPTY: "Empty", FAMILY_TWOROOM: "TwoRoom", FAMILY_FOURROOMS: "FourRooms",
                 FAMILY_LAVAGAP: "LavaGap", FAMILY_CROSSINGS: "Crossings",
-                FAMILY_DISTSHIFT: "DistShift", FAMILY_DYNOBS: "Dynamic-Obstacles"}
+                FAMILY_DISTSHIFT: "DistShift", FAMILY_DYNOBS: "Dynamic-Obstacles",
+                FAMILY_GOTODOOR: "GoToDoor"}
 N_ACTIONS = 7
 
 
