@@ -41,6 +41,8 @@ WORKLOADS = {
             "S11N5, DistShift1 (6x6), DistShift2 (8x8), random policy on device, trajectory ring in HBM",
     "dynobs": "Dynamic-Obstacles tasks: 262144 envs in equal shares of 5x5 (2 balls), 6x6 (3), 8x8 (4), "
               "16x16 (8), random policy on device, trajectory ring in HBM",
+    "gotodoor": "GoToDoor tasks: 262144 envs in equal shares of 5x5, 6x6, 8x8, random policy on device, "
+                "trajectory ring in HBM",
 }
 
 
@@ -169,9 +171,10 @@ def main():
             "empty8": lambda: wl.workload_empty8(seed=0),
             "empty5": lambda: wl.workload_empty5(seed=0),
             "lava": lambda: wl.workload_lava(seed=0, n=args.envs or 262144),
-            "dynobs": lambda: wl.workload_dynobs(seed=0, n=args.envs or 262144)}[args.workload]
+            "dynobs": lambda: wl.workload_dynobs(seed=0, n=args.envs or 262144),
+            "gotodoor": lambda: wl.workload_gotodoor(seed=0, n=args.envs or 262144)}[args.workload]
     table = make()
-    if args.envs and args.workload not in ("mixed", "lava", "dynobs"):
+    if args.envs and args.workload not in ("mixed", "lava", "dynobs", "gotodoor"):
         table = table.subset(np.arange(args.envs) % table.n)
     obs_mode = OBS_MODES[args.obs]
     env = ge.GridEnv(table, obs_mode=obs_mode)
@@ -244,8 +247,7 @@ def main():
     plain_rate = None
     plain_lat = None
     if args.plain_steps > 0:
-        rows = [ge.Traj(traj.obs[r:r + 1], traj.reward[r:r + 1], traj.flags[r:r + 1], traj.action[r:r + 1])
-                for r in range(traj.rows)]
+        rows = [traj.row(r) for r in range(traj.rows)]
         acts = None
         if args.plain_actions:
             acts = torch.from_numpy(wl.random_actions(args.plain_steps, table.n, seed=1)).to(dev)

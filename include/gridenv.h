@@ -13,11 +13,12 @@
  * transition (identity for these families), observation, reward,
  * termination.  The families are those of Table "envs": Empty, DoorKey,
  * FourRooms (reward R1), the lava families LavaGap, Crossings, DistShift
- * (reward R2) and Dynamic-Obstacles (reward R3), whose balls move every
- * step (its transition system).  An episode terminates on reaching the
- * goal or walking into lava (Tables "rewards" and "terminations":
- * on_goal_reached, on_lava_fall), or, in Dynamic-Obstacles, on stepping
- * forward at a ball or wall.
+ * (reward R2), Dynamic-Obstacles (reward R3), whose balls move every
+ * step (its transition system), and GoToDoor, whose state holds a mission.
+ * An episode terminates on reaching the goal or walking into lava (Tables
+ * "rewards" and "terminations": on_goal_reached, on_lava_fall), in
+ * Dynamic-Obstacles on stepping forward at a ball or wall, and in GoToDoor
+ * on the done action at the mission's door (on_door_done) or on a toggle.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -58,14 +59,16 @@
  * State of env i (caller-owned device buffers, struct gx_state)
  *   grid: bytes [S_i][S_i][3] (row y, column x, channel) at byte offset
  *     grid_off(i) = sum_{j<i} 3 * S_j^2 of one buffer of env_sizes()
- *     bytes; the outermost ring of every grid must be walls and types
- *     must be among those listed above (every generated layout is);
+ *     bytes; the outermost ring of every grid must be walls (GoToDoor:
+ *     walls and closed doors) and types must be among those listed above
+ *     (every generated layout is);
  *   x, y, dir, t (int32): position, heading, steps since the last reset;
  *   carry (int32), episode (uint32: resets so far), done_prev (uint8:
  *   the last step ended the episode, so the next call resets), calls
  *   (uint32: step calls since env_reset, the random policy's counter),
- *   obst (bytes [16] per env: the Dynamic-Obstacles balls' x, y in their
- *   move order, 0xFF for unused slots and for the other families).
+ *   obst (bytes [16] per env of family state: the Dynamic-Obstacles balls'
+ *   x, y in their move order; GoToDoor's mission colour in byte 0; 0xFF in
+ *   every unused byte and for the other families).
  *
  * Outputs (struct gx_traj): row r of each buffer holds n_envs entries:
  *   obs: row r is env_info's obs_row_bytes bytes; may be NULL to skip
@@ -80,7 +83,10 @@
  *       the carried object is not shown);
  *     3 categorical: the type channel of 2, [S_i][S_i] at grid_off(i) / 3;
  *   reward: float [rows][n_envs]; flags, action: bytes [rows][n_envs]
- *     (action is the action applied, 0xFF on reset steps).
+ *     (action is the action applied, 0xFF on reset steps);
+ *   mission: bytes [rows][n_envs] or NULL: the mission of the step's
+ *     episode (the state's mission component, Sec. 3.2.1): GoToDoor's target
+ *     door colour, 0xFF for the families without a mission.
  */
 #ifndef GRIDENV_H
 #define GRIDENV_H
@@ -113,6 +119,13 @@ extern "C" {
                                   (S-2)^2 - 2), side 5..32; three actions (any
                                   other acts as 0); every step the balls move at
                                   random first; forward at a ball or wall: -1, end */
+#define GX_FAMILY_GOTODOOR 7   /* GoToDoor: a walled room of random size in the
+                                  grid's top-left corner (the rest is wall), four
+                                  closed doors of distinct colours, one per room
+                                  wall; the mission names one colour.  done (any
+                                  action >= 6) with that door directly ahead: the
+                                  goal reward, end; toggle: reward 0, end.  Side
+                                  5..32; no goal square */
 
 #define GX_OBS_BYTES 147      /* symbolic first-person record */
 #define GX_OBS_CAT_BYTES 49   /* categorical first-person record */
@@ -159,6 +172,7 @@ typedef struct {
   uint8_t* flags;
   uint8_t* action;
   int32_t rows;      /* >= 1 */
+  uint8_t* mission;  /* may be NULL */
 } gx_traj;
 
 /* Launch and tiling facts of a context (for tools and benchmarks). */

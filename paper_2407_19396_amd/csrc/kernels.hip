@@ -54,7 +54,7 @@ constexpr uint32_t kActionNone = 0xFF;
 enum : uint32_t { kLeft = 0, kRight = 1, kForward = 2, kPickup = 3, kDrop = 4, kToggle = 5 };
 enum : uint32_t {
   kFamEmpty = 0, kFamTwoRoom = 1, kFamFourRooms = 2,
-  kFamLavaGap = 3, kFamCrossings = 4, kFamDistShift = 5, kFamDynObs = 6
+  kFamLavaGap = 3, kFamCrossings = 4, kFamDistShift = 5, kFamDynObs = 6, kFamGoToDoor = 7
 };
 constexpr int kMaxObst = 8;
 constexpr uint32_t kBlue = 2;
@@ -114,9 +114,10 @@ __device__ __forceinline__ uint4 policy_block(uint2 seed, uint32_t rng_id, uint3
 struct Layout {
   int fam, S;
   int a, b, c, d;      // TwoRoom: a = wall column, b = door row; FourRooms: the 4 openings;
-                       // LavaGap: a = lava column, b = gap row; DistShift: a = second lava row
-  int colour;          // TwoRoom door / key colour
-  int kx, ky;          // TwoRoom key
+                       // LavaGap: a = lava column, b = gap row; DistShift: a = second lava row;
+                       // GoToDoor: the doors' positions along the top, right, bottom, left walls
+  int colour;          // TwoRoom door / key colour; GoToDoor: door i's colour at bits 4i..4i+3
+  int kx, ky;          // TwoRoom key; GoToDoor: the room's width and height
   int gx, gy;          // goal
   int ax, ay, dir;     // agent
   uint32_t vmask, hmask;   // Crossings: river columns / rows (bit = coordinate)
@@ -323,6 +324,42 @@ __device__ Layout make_layout(uint32_t meta, uint2 seed, uint32_t rng_id, uint32
     }
     return L;
   }
+  if (fam == kFamGoToDoor) {
+    // room w x h in the top-left corner, one closed door per wall (top x,
+    // right y, bottom x, left y), four distinct colours by a partial
+    // Fisher-Yates shuffle of the six, the mission the colour of door u(4),
+    // the agent uniform over the room's interior; 13 words in draw order
+    const uint4 w0 = philox10(make_uint4(rng_id, episode, 0u, 0u), seed);
+    const uint4 w1 = philox10(make_uint4(rng_id, episode, 1u, 0u), seed);
+    const uint4 w2 = philox10(make_uint4(rng_id, episode, 2u, 0u), seed);
+    const uint4 w3 = philox10(make_uint4(rng_id, episode, 3u, 0u), seed);
+    const int rw = 5 + (int)bounded(w0.x, (uint32_t)(S - 4));
+    const int rh = 5 + (int)bounded(w0.y, (uint32_t)(S - 4));
+    L.kx = rw;
+    L.ky = rh;
+    L.gx = L.gy = -1;   // no goal square
+    L.a = 1 + (int)bounded(w0.z, (uint32_t)(rw - 2));
+    L.b = 1 + (int)bounded(w0.w, (uint32_t)(rh - 2));
+    L.c = 1 + (int)bounded(w1.x, (uint32_t)(rw - 2));
+    L.d = 1 + (int)bounded(w1.y, (uint32_t)(rh - 2));
+    uint32_t col = 0x543210u;   // colour k at bits 4k..4k+3
+    const uint32_t sw[4] = {w1.z, w1.w, w2.x, w2.y};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t r = (uint32_t)k + bounded(sw[k], (uint32_t)(6 - k));
+      const uint32_t ck = (col >> (4 * k)) & 15u, cr = (col >> (4 * r)) & 15u;
+      col = (col & ~((15u << (4 * k)) | (15u << (4 * r)))) | (cr << (4 * k)) | (ck << (4 * r));
+    }
+    L.colour = (int)(col & 0xFFFFu);
+    const uint32_t target = bounded(w2.z, 4u);
+    L.ob[0] = 0xFFFFFF00u | ((col >> (4 * target)) & 15u);
+    uint32_t q, r;
+    small_divmod(bounded(w2.w, (uint32_t)((rw - 2) * (rh - 2))), (uint32_t)(rw - 2), q, r);
+    L.ax = 1 + (int)r;
+    L.ay = 1 + (int)q;
+    L.dir = (int)bounded(w3.x, 4u);
+    return L;
+  }
   if (fam >= kFamLavaGap) {
     L.ax = L.ay = 1;
     L.dir = 0;
@@ -386,8 +423,23 @@ __device__ Layout make_layout(uint32_t meta, uint2 seed, uint32_t rng_id, uint32
 }
 
 // content of cell (x, y) of a freshly generated layout (triple, no see bit)
+// GoToDoor door i's colour, or -1 when (x, y) holds no door
+__device__ __forceinline__ int gotodoor_door(const Layout& L, int x, int y) {
+  int i = -1;
+  i = (y == 0 && x == L.a) ? 0 : i;
+  i = (x == L.kx - 1 && y == L.b) ? 1 : i;
+  i = (y == L.ky - 1 && x == L.c) ? 2 : i;
+  i = (x == 0 && y == L.d) ? 3 : i;
+  return i < 0 ? -1 : (int)(((uint32_t)L.colour >> (4 * i)) & 15u);
+}
+
 __device__ __forceinline__ uint32_t layout_cell(const Layout& L, int x, int y) {
   const int S = L.S;
+  if (L.fam == kFamGoToDoor) {
+    const int dc = gotodoor_door(L, x, y);
+    if (dc >= 0) return kDoor | ((uint32_t)dc << 8) | (kClosed << 16);
+    return (x == 0 || y == 0 || x >= L.kx - 1 || y >= L.ky - 1) ? kCellWall : kCellEmpty;
+  }
   if (x == 0 || y == 0 || x == S - 1 || y == S - 1) return kCellWall;
   if (x == L.gx && y == L.gy) return kCellGoal;
   if (L.fam == kFamTwoRoom) {
@@ -438,6 +490,7 @@ struct ActResult {
   uint32_t new_front;
   bool front_changed;
   bool terminated;
+  bool goal;      // the task achieved: the goal reached, or (GoToDoor) done at the mission's door
   bool penalty;   // ended with reward -1: walked into lava, or (Dynamic-Obstacles)
                   // stepped forward at a ball or wall
 };
@@ -464,7 +517,8 @@ __device__ __forceinline__ ActResult intervene(uint32_t act, int& x, int& y, int
   r.new_front = pick ? kCellEmpty : (drop ? carry : (unlock ? door_open : (flip ? door_flipped : front24)));
   r.front_changed = pick || drop || unlock || flip;
   r.penalty = act == kForward && type == kLava;
-  r.terminated = (act == kForward && type == kGoal) || r.penalty;
+  r.goal = act == kForward && type == kGoal;
+  r.terminated = r.goal || r.penalty;
   carry = pick ? front24 : (drop ? kCellEmpty : carry);
   return r;
 }
@@ -525,7 +579,22 @@ __device__ __forceinline__ float goal_reward(int32_t t, int32_t T, int32_t mode)
 // Dynamic-Obstacles, for stepping forward at a ball or wall (R3), in both
 // modes; the goal reward on reaching the goal; else 0.
 __device__ __forceinline__ float step_reward(const ActResult& r, int32_t t, int32_t T, int32_t mode) {
-  return r.penalty ? -1.0f : (r.terminated ? goal_reward(t, T, mode) : 0.0f);
+  return r.penalty ? -1.0f : (r.goal ? goal_reward(t, T, mode) : 0.0f);
+}
+
+// GoToDoor's rules on top of the intervention (on_door_done of Tables
+// "rewards" and "terminations"): the done action (any value >= 6) with the
+// mission's door directly ahead achieves the task; toggling ends the
+// episode with reward 0.  mission = the target door's colour.
+__device__ __forceinline__ void gotodoor_rules(ActResult& r, uint32_t act, uint32_t front, uint32_t mission) {
+  const bool done_at = act >= 6u && (front & 0xFF) == kDoor && ((front >> 8) & 0xFF) == mission;
+  r.goal = r.goal || done_at;
+  r.terminated = r.terminated || done_at || act == kToggle;
+}
+
+// the mission reported with every record: GoToDoor's target colour, else 0xFF
+__device__ __forceinline__ uint32_t mission_of(uint32_t fam, uint32_t ob0) {
+  return fam == kFamGoToDoor ? (ob0 & 0xFFu) : 0xFFu;
 }
 
 // ---------------------------------------------------------------------------
@@ -848,7 +917,7 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
       episode = a.st.episode[e];
       done_prev = a.st.done_prev[e] != 0;
       calls = a.st.calls[e];
-      if (fam == kFamDynObs) {
+      if (fam == kFamDynObs || fam == kFamGoToDoor) {   // the balls, or the mission
         const uint4 o4 = *reinterpret_cast<const uint4*>(a.st.obst + 16 * (size_t)e);
         ob[0] = o4.x; ob[1] = o4.y; ob[2] = o4.z; ob[3] = o4.w;
       }
@@ -906,6 +975,7 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
     ActResult r = intervene(act, x, y, dir, carry, front, fx, fy);
     r.penalty = r.penalty || (blocked && act == kForward);
     r.terminated = r.terminated || r.penalty;
+    if (fam == kFamGoToDoor) gotodoor_rules(r, act, front, ob[0] & 0xFFu);
     if (r.front_changed) store_triple(g + 3 * (fy * S + fx), r.new_front);
     t += 1;
     const bool trunc = t >= T;
@@ -956,6 +1026,7 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
     a.out.reward[rowN + e] = reward;
     a.out.flags[rowN + e] = (uint8_t)flags;
     a.out.action[rowN + e] = (uint8_t)act_rec;
+    if (a.out.mission) a.out.mission[rowN + e] = (uint8_t)mission_of(fam, ob[0]);
   }
   if (active) {
     a.st.x[e] = x;
@@ -1038,6 +1109,10 @@ __device__ __forceinline__ uint32_t layout_code(const Layout& L, int x, int y) {
     code = ((y == 1 || y == L.a) && x >= 3 && x <= S - 3) ? kLavaCode : code;
   } else if (L.fam == kFamDynObs) {
     code = is_ball(L, x, y) ? 4u * (19u + kBlue) : code;
+  } else if (L.fam == kFamGoToDoor) {
+    const int dc = gotodoor_door(L, x, y);
+    const bool wall = x == 0 || y == 0 || x >= L.kx - 1 || y >= L.ky - 1;
+    return dc >= 0 ? 4u * (31u + 6u * kClosed + (uint32_t)dc) : (wall ? kWallCode : 0u);
   }
   code = (x == L.gx && y == L.gy) ? kGoalCode : code;
   const bool border = x == 0 || y == 0 || x == S - 1 || y == S - 1;
@@ -1064,11 +1139,30 @@ __device__ __forceinline__ uint32_t table_at(const uint32_t* table, uint32_t cod
 // +-1 or +-S in the row-major grid, so each cell is one add away.  All 49
 // codes are read before any table lookup, so the lookups wait on the code
 // reads in bulk rather than one dependent pair at a time.
+// With `checked` (wave-uniform) every cell is bounds-checked and cells
+// outside the grid read as walls instead: needed only on the rare step whose
+// view can leave the grid, through a door on the outer ring that the step
+// itself opened (GoToDoor rooms use the grid's border as walls).
 struct LdsRows {
   const uint32_t* table;
   const uint8_t* center;   // the agent's cell
   int R, F;                // linear steps to the agent's right and ahead
+  bool checked;
+  int S, x, y, dir;
   __device__ __forceinline__ void load_all(uint32_t (&c)[kView][kView]) const {
+    if (checked) {
+      const int fx = dir_dx(dir), fy = dir_dy(dir), rx = -fy, ry = fx;
+      const uint8_t* g = center - (y * S + x);
+#pragma unroll
+      for (int j = kView - 1; j >= 0; --j)
+#pragma unroll
+        for (int i = 0; i < kView; ++i) {
+          const int wx = x + (i - 3) * rx + (6 - j) * fx, wy = y + (i - 3) * ry + (6 - j) * fy;
+          const bool in = (unsigned)wx < (unsigned)S && (unsigned)wy < (unsigned)S;
+          c[j][i] = in ? table_at(table + kKinds * i, g[in ? wy * S + wx : 0]) : kCellWall;
+        }
+      return;
+    }
     uint32_t code[kView][kView];
 #pragma unroll
     for (int j = kView - 1; j >= 0; --j) {
@@ -1087,11 +1181,11 @@ struct LdsRows {
 };
 
 __device__ __forceinline__ LdsRows lds_rows(const uint32_t* table, const uint8_t* codes, int S, int x,
-                                            int y, int dir) {
+                                            int y, int dir, bool checked) {
   // heading 0: ahead +1, right +S; 1: ahead +S, right -1; 2: -1, -S; 3: -S, +1
   const int F = (dir & 1) ? ((dir == 1) ? S : -S) : ((dir == 0) ? 1 : -1);
   const int R = (dir & 1) ? ((dir == 1) ? -1 : 1) : ((dir == 0) ? S : -S);
-  return LdsRows{table, codes + y * S + x, R, F};
+  return LdsRows{table, codes + y * S + x, R, F, checked, S, x, y, dir};
 }
 
 struct LdsGrid {
@@ -1264,7 +1358,7 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
     const int e0 = tile * kWave;
     int n_here, steps;
     uint64_t g0 = 0;
-    uint8_t *o_obs, *o_flags, *o_action;
+    uint8_t *o_obs, *o_flags, *o_action, *o_mission = nullptr;
     float* o_reward;
     uint32_t step0 = 0;
     size_t rec_stride;
@@ -1292,6 +1386,7 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
       o_reward = a.out.reward + e0;
       o_flags = a.out.flags + e0;
       o_action = a.out.action + e0;
+      o_mission = a.out.mission ? a.out.mission + e0 : nullptr;
       rec_stride = (size_t)N;
     }
     const int e = e0 + lane;
@@ -1397,6 +1492,7 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
 
       float reward = 0.0f;
       uint32_t flags = 0, act_rec = kActionNone;
+      bool edge_view = false;
       if (active && !do_reset) {
         uint32_t act = kActions ? act_now : bounded(pick4(pol, call & 3u), 7u);
         const int fx = x + dir_dx(dir), fy = y + dir_dy(dir);
@@ -1412,6 +1508,10 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
         ActResult r = intervene(act, x, y, dir, carry, front, fx, fy);
         r.penalty = r.penalty || (blocked && act == kForward);
         r.terminated = r.terminated || r.penalty;
+        if (fam == kFamGoToDoor) {
+          gotodoor_rules(r, act, front, ob[0] & 0xFFu);
+          edge_view = r.front_changed;   // a door toggled, possibly on the outer ring
+        }
         if (r.front_changed) my_codes[fy * S + fx] = (uint8_t)code_of(r.new_front);
         t += 1;
         const bool trunc = t >= T;
@@ -1444,7 +1544,8 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
       } else if (o_obs && !kServe && a.env.obs_mode == 1) {
         // categorical records (49 bytes): the stage holds all 64 at once
         uint32_t u[kObsWords + 1];
-        observe_words<true>(lds_rows(table, my_codes, S, x, y, dir), carry, active, lane, u);
+        observe_words<true>(lds_rows(table, my_codes, S, x, y, dir, __ballot(edge_view) != 0), carry, active,
+                            lane, u);
         store_words<true>(stage, lane, u);
         wave_sync();
         copy_out<kWave, kCatBytes>(stage, o_obs + rec * kCatBytes, n_here, lane);
@@ -1452,7 +1553,8 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
       } else if (o_obs) {
         // inactive lanes (S = 0, pose (1, 1)) read inside the guard margin
         uint32_t u[kObsWords + 1];
-        observe_words<false>(lds_rows(table, my_codes, S, x, y, dir), carry, active, lane & 31, u);
+        observe_words<false>(lds_rows(table, my_codes, S, x, y, dir, __ballot(edge_view) != 0), carry, active,
+                             lane & 31, u);
         // the stage holds 32 records: lanes 0-31, then lanes 32-63 (each half
         // starts and ends on a word boundary, so the halves are independent)
         uint8_t* dst = o_obs + rec * kObsBytes;
@@ -1470,6 +1572,7 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
         o_reward[rec + lane] = reward;
         o_flags[rec + lane] = (uint8_t)flags;
         o_action[rec + lane] = (uint8_t)act_rec;
+        if (o_mission) o_mission[rec + lane] = (uint8_t)mission_of(fam, ob[0]);
       }
       wave_sync();
     }

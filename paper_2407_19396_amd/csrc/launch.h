@@ -36,7 +36,8 @@ struct TrajBufs {
   uint8_t* flags;   // [rows][N]
   uint8_t* action;  // [rows][N]
   int32_t rows;
-  uint64_t obs_row = 0;   // bytes of one whole-grid observation row (sum 3 S^2 or sum S^2)
+  uint64_t obs_row = 0;        // bytes of one whole-grid observation row (sum 3 S^2 or sum S^2)
+  uint8_t* mission = nullptr;  // [rows][N] the episode's mission (GoToDoor colour, else 0xFF), or nullptr
 };
 
 // Fused rollout tiling: tile i covers envs [i*64, i*64+64) (the last is
@@ -91,6 +92,7 @@ inline bool family_ok(int family, int side, int param, int max_side) {
     case 5: return side >= 6 && (param == 1 || param == 2);    // DistShift
     case 6: return side >= 5 && param >= 1 && param <= 8 &&
                    param <= (side - 2) * (side - 2) - 2;       // Dynamic-Obstacles
+    case 7: return side >= 5;                                  // GoToDoor
     default: return false;
   }
 }

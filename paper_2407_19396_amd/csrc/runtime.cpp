@@ -95,7 +95,7 @@ gx::StateBufs state_of(const gx_state* st) {
 }
 
 gx::TrajBufs traj_of(const gx_ctx* c, const gx_traj* tr) {
-  return gx::TrajBufs{tr->obs, tr->reward, tr->flags, tr->action, tr->rows, obs_row_bytes(c)};
+  return gx::TrajBufs{tr->obs, tr->reward, tr->flags, tr->action, tr->rows, obs_row_bytes(c), tr->mission};
 }
 
 int check_device(const gx_ctx* c) {

@@ -43,7 +43,7 @@ class GxState(ctypes.Structure):
 class GxTraj(ctypes.Structure):
     _fields_ = [("obs", ctypes.c_void_p), ("reward", ctypes.c_void_p),
                 ("flags", ctypes.c_void_p), ("action", ctypes.c_void_p),
-                ("rows", ctypes.c_int32)]
+                ("rows", ctypes.c_int32), ("mission", ctypes.c_void_p)]
 
 
 class GxInfo(ctypes.Structure):
@@ -205,6 +205,7 @@ class Traj:
     reward: object
     flags: object
     action: object
+    mission: object = None   # u8 [rows][N]: the episode's mission (GoToDoor colour, else 0xFF)
 
     @staticmethod
     def alloc(rows: int, n: int, device="cuda", with_obs: bool = True, obs_mode: int = 0,
@@ -214,15 +215,22 @@ class Traj:
         return Traj(torch.zeros(shape, dtype=torch.uint8, device=device) if with_obs else None,
                     torch.zeros((rows, n), dtype=torch.float32, device=device),
                     torch.zeros((rows, n), dtype=torch.uint8, device=device),
+                    torch.zeros((rows, n), dtype=torch.uint8, device=device),
                     torch.zeros((rows, n), dtype=torch.uint8, device=device))
 
     @property
     def rows(self) -> int:
         return int(self.reward.shape[0])
 
+    def row(self, k: int) -> "Traj":
+        """Row k alone, as a one-row Traj (e.g. the output of one env_step)."""
+        sl = lambda t: None if t is None else t[k:k + 1]   # noqa: E731
+        return Traj(sl(self.obs), sl(self.reward), sl(self.flags), sl(self.action), sl(self.mission))
+
     def c(self) -> GxTraj:
         return GxTraj(self.obs.data_ptr() if self.obs is not None else None, self.reward.data_ptr(),
-                      self.flags.data_ptr(), self.action.data_ptr(), self.rows)
+                      self.flags.data_ptr(), self.action.data_ptr(), self.rows,
+                      self.mission.data_ptr() if self.mission is not None else None)
 
 
 class GridEnv:

@@ -153,8 +153,37 @@ def workload_lava(seed: int = 0, n: int = 262144) -> EnvTable:
     return lava_table(n, seed)
 
 
+# the GoToDoor tasks of the paper's environment table: sides
+GOTODOOR_SIDES = [5, 6, 8]
+
+
+def gotodoor_table(n: int, seed: int = 0, mix_seed: int = 999) -> EnvTable:
+    """The GoToDoor tasks in equal shares, i.i.d. per env."""
+    rng = np.random.default_rng(mix_seed)
+    side = np.array(GOTODOOR_SIDES)[rng.integers(0, len(GOTODOOR_SIDES), n)]
+    return _table(np.full(n, FAMILY_GOTODOOR), side, seed, f"gotodoor x{n}")
+
+
+def workload_gotodoor(seed: int = 0, n: int = 262144) -> EnvTable:
+    """262144 envs of the GoToDoor tasks (fused, 4096 steps)."""
+    return gotodoor_table(n, seed)
+
+
+def families_table(n: int, seed: int = 0, mix_seed: int = 4242) -> EnvTable:
+    """Every family in one batch: each env draws a task uniformly from the
+    paper's tasks of every family (the uneven mix, the lava, obstacle and
+    door tasks)."""
+    rng = np.random.default_rng(mix_seed)
+    tasks = ([(FAMILY_EMPTY, s, 0) for s in (5, 6, 8, 16)] +
+             [(FAMILY_TWOROOM, s, 0) for s in (5, 6, 8, 16)] + [(FAMILY_FOURROOMS, 19, 0)] +
+             LAVA_TASKS + [(FAMILY_DYNOBS, s, k) for s, k in DYNOBS_TASKS] +
+             [(FAMILY_GOTODOOR, s, 0) for s in GOTODOOR_SIDES])
+    pick = np.array(tasks)[rng.integers(0, len(tasks), n)]
+    return _table(pick[:, 0], pick[:, 1], seed, f"all families x{n}", None, pick[:, 2])
+
+
 WORKLOAD_STEPS = {"empty5": 100, "empty8": 1000, "tworoom8": 2048, "mixed": 4096, "lava": 4096,
-                  "dynobs": 4096}
+                  "dynobs": 4096, "gotodoor": 4096}
 
 
 def random_actions(n_steps: int, n_envs: int, seed: int) -> np.ndarray:

@@ -28,6 +28,8 @@ def assert_rows_equal(gpu, ref: ox.Outputs, rows=None, what=""):
     np.testing.assert_array_equal(to_np(gpu.action)[rows], ref.action[rows], err_msg=f"action {what}")
     np.testing.assert_array_equal(g_rew.view(np.uint32), ref.reward[rows].view(np.uint32),
                                   err_msg=f"reward bits {what}")
+    if getattr(gpu, "mission", None) is not None and ref.mission is not None:
+        np.testing.assert_array_equal(to_np(gpu.mission)[rows], ref.mission[rows], err_msg=f"mission {what}")
     if gpu.obs is not None and ref.obs is not None:
         g_obs = to_np(gpu.obs)[rows]
         r_obs = ref.obs[rows]

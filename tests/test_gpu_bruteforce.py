@@ -36,8 +36,7 @@ def test_bruteforce_parity(case, kernel):
             env.rollout(L, traj, dacts, K=L)
         else:
             for k in range(L):
-                env.step(ge.Traj(traj.obs[k:k + 1], traj.reward[k:k + 1], traj.flags[k:k + 1],
-                                 traj.action[k:k + 1]), dacts[k])
+                env.step(traj.row(k), dacts[k])
         torch.cuda.synchronize()
         P.assert_rows_equal(traj, ref, what=f"{case} {kernel} starts {c0}..")
         P.assert_state_equal(env, s, f"{case} {kernel}")

@@ -33,7 +33,7 @@ def test_empty5_plain_whole(seed):
     traj = ge.Traj.alloc(100, table.n)
     d = torch.from_numpy(acts).cuda()
     for k in range(100):
-        env.step(ge.Traj(traj.obs[k:k + 1], traj.reward[k:k + 1], traj.flags[k:k + 1], traj.action[k:k + 1]), d[k])
+        env.step(traj.row(k), d[k])
     torch.cuda.synchronize()
     P.assert_rows_equal(traj, ref, what=f"empty5 seed {seed}")
     P.assert_state_equal(env, s)
@@ -52,7 +52,7 @@ def test_empty8_plain_whole():
     traj = ge.Traj.alloc(1000, table.n)
     d = torch.from_numpy(acts).cuda()
     for k in range(1000):
-        env.step(ge.Traj(traj.obs[k:k + 1], traj.reward[k:k + 1], traj.flags[k:k + 1], traj.action[k:k + 1]), d[k])
+        env.step(traj.row(k), d[k])
     torch.cuda.synchronize()
     P.assert_rows_equal(traj, ref, what="empty8")
     P.assert_state_equal(env, s)

@@ -67,8 +67,7 @@ def test_injected_state_parity(seed, kernel):
         env.rollout(steps, traj, dacts, K=13)
     else:
         for k in range(steps):
-            env.step(ge.Traj(traj.obs[k:k + 1], traj.reward[k:k + 1], traj.flags[k:k + 1],
-                             traj.action[k:k + 1]), dacts[k])
+            env.step(traj.row(k), dacts[k])
     torch.cuda.synchronize()
     P.assert_rows_equal(traj, ref, what=f"injected seed {seed} {kernel}")
     P.assert_state_equal(env, s, f"injected seed {seed} {kernel}")
@@ -135,8 +134,7 @@ def test_injected_dynobs_parity(seed, kernel):
         env.rollout(steps, traj, dacts, K=11)
     else:
         for k in range(steps):
-            env.step(ge.Traj(traj.obs[k:k + 1], traj.reward[k:k + 1], traj.flags[k:k + 1],
-                             traj.action[k:k + 1]), dacts[k])
+            env.step(traj.row(k), dacts[k])
     torch.cuda.synchronize()
     P.assert_rows_equal(traj, ref, what=f"injected dynobs seed {seed} {kernel}")
     P.assert_state_equal(env, s, f"injected dynobs seed {seed} {kernel}")
@@ -182,8 +180,7 @@ def test_malformed_obstacle_lists(kernel):
         env.rollout(20, traj, dacts, K=7)
     else:
         for k in range(20):
-            env.step(ge.Traj(traj.obs[k:k + 1], traj.reward[k:k + 1], traj.flags[k:k + 1],
-                             traj.action[k:k + 1]), dacts[k])
+            env.step(traj.row(k), dacts[k])
     torch.cuda.synchronize()
     P.assert_rows_equal(traj, ref, what=f"malformed lists {kernel}")
     P.assert_state_equal(env, s, f"malformed lists {kernel}")

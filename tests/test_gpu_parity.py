@@ -39,7 +39,20 @@ def tables():
         "lava_all": lava_all_table(),
         "dynobs": wl.dynobs_table(3000, seed=41, mix_seed=42),
         "dynobs_all": dynobs_all_table(),
+        "gotodoor": wl.gotodoor_table(3000, seed=61, mix_seed=62),
+        "gotodoor_all": gotodoor_all_table(),
+        "families": wl.families_table(3000, seed=71, mix_seed=72),
     }
+
+
+def gotodoor_all_table():
+    """Every side 5..32 of GoToDoor, three envs each."""
+    side = np.repeat(np.arange(5, 33), 3)
+    n = len(side)
+    fam = np.full(n, wl.FAMILY_GOTODOOR)
+    ms = np.array([wl.default_max_steps(int(f), int(s)) for f, s in zip(fam, side)]) // 8 + 1
+    return wl.EnvTable(fam.astype(np.uint8), side.astype(np.uint8), ms.astype(np.int32),
+                       np.full(n, 78, np.uint64), np.arange(n, dtype=np.uint32), "gotodoor all sides")
 
 
 def all_sides_table():
@@ -99,7 +112,8 @@ def test_reset_parity(ge, name):
 @pytest.mark.parametrize("name,steps", [("empty5", 100), ("empty8", 300), ("tworoom8", 300),
                                         ("fourrooms19", 250), ("mixed", 300), ("all_sides", 200),
                                         ("lava", 300), ("lava_all", 200), ("dynobs", 300),
-                                        ("dynobs_all", 150)])
+                                        ("dynobs_all", 150), ("gotodoor", 300),
+                                        ("gotodoor_all", 200), ("families", 300)])
 @pytest.mark.parametrize("policy", [False, True])
 def test_plain_step_parity(ge, name, steps, policy):
     import torch
@@ -111,7 +125,7 @@ def test_plain_step_parity(ge, name, steps, policy):
     traj = ge.Traj.alloc(steps, table.n)
     dacts = torch.from_numpy(acts).cuda() if acts is not None else None
     for k in range(steps):
-        row = ge.Traj(traj.obs[k:k + 1], traj.reward[k:k + 1], traj.flags[k:k + 1], traj.action[k:k + 1])
+        row = traj.row(k)
         env.step(row, dacts[k] if dacts is not None else None)
     torch.cuda.synchronize()
     P.assert_rows_equal(traj, ref, what=f"plain {name}")
@@ -121,7 +135,8 @@ def test_plain_step_parity(ge, name, steps, policy):
 @pytest.mark.parametrize("name,steps", [("empty5", 100), ("empty8", 300), ("tworoom8", 300),
                                         ("fourrooms19", 250), ("mixed", 300), ("all_sides", 200),
                                         ("lava", 300), ("lava_all", 200), ("dynobs", 300),
-                                        ("dynobs_all", 150)])
+                                        ("dynobs_all", 150), ("gotodoor", 300),
+                                        ("gotodoor_all", 200), ("families", 300)])
 @pytest.mark.parametrize("K", [1, 7, 64])
 @pytest.mark.parametrize("policy", [False, True])
 def test_fused_rollout_parity(ge, name, steps, K, policy):
@@ -213,9 +228,9 @@ def test_observations_skipped_when_null(ge):
     ref = ox.rollout(b, s, 50, None, nthreads=8)
     traj = ge.Traj.alloc(50, table.n, with_obs=False)
     env.rollout(30, traj, K=8)
-    row = ge.Traj(None, traj.reward[30:31], traj.flags[30:31], traj.action[30:31])
+    row = ge.Traj(None, traj.reward[30:31], traj.flags[30:31], traj.action[30:31], traj.mission[30:31])
     env.step(row)
-    env.rollout(19, ge.Traj(None, traj.reward[31:], traj.flags[31:], traj.action[31:]), K=8)
+    env.rollout(19, ge.Traj(None, traj.reward[31:], traj.flags[31:], traj.action[31:], traj.mission[31:]), K=8)
     torch.cuda.synchronize()
     P.assert_rows_equal(traj, ref, what="no obs")
     P.assert_state_equal(env, s, "no obs")
@@ -296,8 +311,7 @@ def test_categorical_observation_parity(ge, name, kernel):
         env.rollout(steps, traj, K=32)
     else:
         for k in range(steps):
-            env.step(ge.Traj(traj.obs[k:k + 1], traj.reward[k:k + 1], traj.flags[k:k + 1],
-                             traj.action[k:k + 1]))
+            env.step(traj.row(k))
     torch.cuda.synchronize()
     P.assert_rows_equal(traj, ref, what=f"categorical {kernel} {name}")
     P.assert_state_equal(env, s, f"categorical {kernel} {name}")
@@ -339,8 +353,7 @@ def test_whole_grid_observation_parity(ge, name, kernel, mode):
         env.rollout(steps, traj, K=16)
     else:
         for k in range(steps):
-            env.step(ge.Traj(traj.obs[k:k + 1], traj.reward[k:k + 1], traj.flags[k:k + 1],
-                             traj.action[k:k + 1]))
+            env.step(traj.row(k))
     torch.cuda.synchronize()
     P.assert_rows_equal(traj, ref, what=f"grid mode {mode} {kernel} {name}")
     P.assert_state_equal(env, s, f"grid mode {mode} {kernel} {name}")
@@ -361,3 +374,29 @@ def test_whole_grid_ragged_and_ring(ge, n, mode):
     env.rollout(30, traj, K=8)
     torch.cuda.synchronize()
     P.assert_rows_equal(traj, ref, what=f"grid mode {mode} n={n}")
+
+
+@pytest.mark.parametrize("kernel", ["plain", "fused"])
+def test_gotodoor_done_and_out_of_range_actions(ge, kernel):
+    """External actions biased to done, toggle and values >= 7, so that
+    on_door_done, toggles of doors on the grid's outer ring (whose view the
+    fused kernel reads bounds-checked) and out-of-range actions all occur."""
+    import torch
+    table = tables()["gotodoor"]
+    env, first = make(ge, table)
+    b, s, ref0 = P.oracle_reset(table)
+    rng = np.random.default_rng(5)
+    steps = 200
+    acts = rng.choice(np.array([0, 1, 2, 2, 5, 6, 6, 7, 200], np.uint8), size=(steps, table.n))
+    ref = ox.rollout(b, s, steps, acts, nthreads=8)
+    assert (ref.flags & 1).sum() > 1000 and (ref.reward > 0).sum() > 100
+    traj = ge.Traj.alloc(steps, table.n)
+    dacts = torch.from_numpy(acts).cuda()
+    if kernel == "fused":
+        env.rollout(steps, traj, dacts, K=32)
+    else:
+        for k in range(steps):
+            env.step(traj.row(k), dacts[k])
+    torch.cuda.synchronize()
+    P.assert_rows_equal(traj, ref, what=f"gotodoor {kernel}")
+    P.assert_state_equal(env, s, f"gotodoor {kernel}")
