@@ -60,7 +60,8 @@ enum { D_OPEN = 0, D_CLOSED = 1, D_LOCKED = 2 };
 enum { A_LEFT = 0, A_RIGHT = 1, A_FORWARD = 2, A_PICKUP = 3, A_DROP = 4,
        A_TOGGLE = 5, A_DONE = 6 };
 enum { FAM_EMPTY = 0, FAM_TWOROOM = 1, FAM_FOURROOMS = 2, FAM_LAVAGAP = 3,
-       FAM_CROSSINGS = 4, FAM_DISTSHIFT = 5, FAM_DYNOBS = 6, FAM_GOTODOOR = 7 };
+       FAM_CROSSINGS = 4, FAM_DISTSHIFT = 5, FAM_DYNOBS = 6, FAM_GOTODOOR = 7,
+       FAM_KEYCORRIDOR = 8 };
 #define OX_MAX_OBST 8
 
 #define OX_FLAG_TERMINATED 1u
@@ -187,6 +188,8 @@ int ox_side_ok(int family, int side, int param) {
       return side >= 5 && param >= 1 && param <= OX_MAX_OBST &&
              param <= (side - 2) * (side - 2) - 2;
     case FAM_GOTODOOR: return side >= 5;
+    case FAM_KEYCORRIDOR:   /* side = 3 s - 2 for rooms of size s >= 3; param = rows 1..3 */
+      return side >= 7 && (side + 2) % 3 == 0 && param >= 1 && param <= 3;
   }
   return 0;
 }
@@ -241,6 +244,26 @@ int ox_side_ok(int family, int side, int param) {
 /*   shuffle; the mission is the colour of door u(4) (kept in obst[0]); */
 /*   agent uniform over the room's interior; direction uniform.  No     */
 /*   goal.                                                              */
+/* KeyCorridor(S = 3s-2, R rows): a lattice of 3 x R rooms of size s    */
+/*   (walls shared, stride s-1) in the top rows of the grid, H = R(s-1) */
+/*   + 1; the rows below H are wall.  The middle column is a hallway:   */
+/*   the walls between its rooms are open.  Every wall between two     */
+/*   rooms has a door position, drawn in the order rows j, columns i:   */
+/*   the right wall of room (i, j) (i < 2), then its lower wall (j <    */
+/*   R-1), each uniform over the wall's s-2 inner cells.  Then: the     */
+/*   locked room's row u(R) and the colour u(6) of its locked door, on  */
+/*   the wall between the hallway and the right-column room of that     */
+/*   row; the goal uniform in that room; the key (the door's colour) in */
+/*   the left-column room of row u(R), uniform; the agent uniform in    */
+/*   the hallway room of row R/2, heading uniform.  Last, every room is */
+/*   connected as MiniGrid's connect_all does: while some room is not   */
+/*   reachable from the agent's room through openings and doors, draw a */
+/*   room (u(3), u(R)) and a side u(4); if a neighbour lies there, the  */
+/*   wall between has no door or opening yet and neither room is the   */
+/*   locked one, add a closed door of colour u(6) at the wall's         */
+/*   position (at most 1024 draws of a room).  The paper lists R1 (the  */
+/*   goal square) for this family, so the goal sits behind the locked   */
+/*   door where MiniGrid puts a ball to pick up.                        */
 /* Pinned by: structural invariants, uniformity tests and the hand     */
 /* layouts in tests; agreement with MiniGrid's own generators: parity  */
 /* unpinned (MiniGrid is not available).                               */
@@ -301,6 +324,76 @@ int ox_layout(int family, int S, int param, uint64_t seed, uint32_t rng_id,
     n = count_empty(grid, S, 1, S - 2, 1, S - 2);
     if (kth_empty(grid, S, 1, S - 2, 1, S - 2, DRAW(n), ax, ay)) return -2;
     *adir = (int)DRAW(4);
+  } else if (family == FAM_KEYCORRIDOR) {
+    const int rs = (S + 2) / 3, st = rs - 1, R = param, H = R * st + 1;
+    for (int y = 0; y < S; ++y)
+      for (int x = 0; x < S; ++x)
+        if (y >= H || x % st == 0 || y % st == 0) put(grid, S, x, y, O_WALL, C_GREY, 0);
+    /* door positions of the walls between rooms: pv[i][j] between (i, j)
+     * and (i+1, j), ph[i][j] between (i, j) and (i, j+1) */
+    int pv[2][3], ph[3][2];
+    for (int j = 0; j < R; ++j)
+      for (int i = 0; i < 3; ++i) {
+        if (i < 2) pv[i][j] = (int)DRAW(rs - 2);
+        if (j < R - 1) ph[i][j] = (int)DRAW(rs - 2);
+      }
+    /* openings: ov[i][j] / oh[i][j] = 1 where the wall is open or has a door */
+    int ov[2][3] = {{0}}, oh[3][2] = {{0}};
+    for (int j = 0; j + 1 < R; ++j) {           /* the hallway */
+      oh[1][j] = 1;
+      for (int x = st + 1; x < 2 * st; ++x) put(grid, S, x, (j + 1) * st, O_EMPTY, 0, 0);
+    }
+    int rl = (int)DRAW(R);
+    int colour = (int)DRAW(6);
+    put(grid, S, 2 * st, rl * st + 1 + pv[1][rl], O_DOOR, colour, D_LOCKED);
+    ov[1][rl] = 1;
+    int gx, gy, kx, ky;
+    uint32_t n = count_empty(grid, S, 2 * st + 1, 3 * st - 1, rl * st + 1, (rl + 1) * st - 1);
+    if (kth_empty(grid, S, 2 * st + 1, 3 * st - 1, rl * st + 1, (rl + 1) * st - 1, DRAW(n), &gx, &gy))
+      return -2;
+    put(grid, S, gx, gy, O_GOAL, C_GREEN, 0);
+    int rk = (int)DRAW(R);
+    n = count_empty(grid, S, 1, st - 1, rk * st + 1, (rk + 1) * st - 1);
+    if (kth_empty(grid, S, 1, st - 1, rk * st + 1, (rk + 1) * st - 1, DRAW(n), &kx, &ky)) return -2;
+    put(grid, S, kx, ky, O_KEY, colour, 0);
+    int ra = R / 2;
+    n = count_empty(grid, S, st + 1, 2 * st - 1, ra * st + 1, (ra + 1) * st - 1);
+    if (kth_empty(grid, S, st + 1, 2 * st - 1, ra * st + 1, (ra + 1) * st - 1, DRAW(n), ax, ay))
+      return -2;
+    *adir = (int)DRAW(4);
+    for (int it = 0; it < 1024; ++it) {
+      /* rooms reachable from the agent's: repeated relaxation over the walls */
+      int reach[3][3] = {{0}}, grew = 1, count = 0;
+      reach[1][ra] = 1;
+      while (grew) {
+        grew = 0;
+        for (int j = 0; j < R; ++j)
+          for (int i = 0; i < 3; ++i) {
+            if (reach[i][j]) continue;
+            int nb = (i > 0 && ov[i - 1][j] && reach[i - 1][j]) || (i < 2 && ov[i][j] && reach[i + 1][j]) ||
+                     (j > 0 && oh[i][j - 1] && reach[i][j - 1]) || (j < R - 1 && oh[i][j] && reach[i][j + 1]);
+            if (nb) { reach[i][j] = 1; grew = 1; }
+          }
+      }
+      for (int j = 0; j < R; ++j)
+        for (int i = 0; i < 3; ++i) count += reach[i][j];
+      if (count == 3 * R) break;
+      int i = (int)DRAW(3), j = (int)DRAW(R), k = (int)DRAW(4);
+      int i2 = i + (k == 0) - (k == 2), j2 = j + (k == 1) - (k == 3);
+      if (i2 < 0 || i2 > 2 || j2 < 0 || j2 >= R) continue;
+      int *open = (j2 == j) ? &ov[i < i2 ? i : i2][j] : &oh[i][j < j2 ? j : j2];
+      if (*open) continue;
+      if ((i == 2 && j == rl) || (i2 == 2 && j2 == rl)) continue;
+      int c = (int)DRAW(6);
+      *open = 1;
+      if (j2 == j) {
+        int iw = i < i2 ? i : i2;
+        put(grid, S, (iw + 1) * st, j * st + 1 + pv[iw][j], O_DOOR, c, D_CLOSED);
+      } else {
+        int jw = j < j2 ? j : j2;
+        put(grid, S, i * st + 1 + ph[i][jw], (jw + 1) * st, O_DOOR, c, D_CLOSED);
+      }
+    }
   } else if (family == FAM_GOTODOOR) {
     int rw = 5 + (int)DRAW(S - 4);
     int rh = 5 + (int)DRAW(S - 4);

@@ -19,21 +19,24 @@ import numpy as np
 
 FAMILY_EMPTY, FAMILY_TWOROOM, FAMILY_FOURROOMS = 0, 1, 2
 FAMILY_LAVAGAP, FAMILY_CROSSINGS, FAMILY_DISTSHIFT, FAMILY_DYNOBS = 3, 4, 5, 6
-FAMILY_GOTODOOR = 7
+FAMILY_GOTODOOR, FAMILY_KEYCORRIDOR = 7, 8
 FAMILY_NAMES = {FAMILY_EMPTY: "Empty", FAMILY_TWOROOM: "TwoRoom", FAMILY_FOURROOMS: "FourRooms",
                 FAMILY_LAVAGAP: "LavaGap", FAMILY_CROSSINGS: "Crossings",
                 FAMILY_DISTSHIFT: "DistShift", FAMILY_DYNOBS: "Dynamic-Obstacles",
-                FAMILY_GOTODOOR: "GoToDoor"}
+                FAMILY_GOTODOOR: "GoToDoor", FAMILY_KEYCORRIDOR: "KeyCorridor"}
 N_ACTIONS = 7
 
 
 def default_max_steps(family: int, side: int) -> int:
     """MiniGrid's default step limits for each family: 4*S^2 (Empty, the
-    lava families and Dynamic-Obstacles), 10*S^2 (DoorKey), 100 (FourRooms)."""
+    lava families, Dynamic-Obstacles, GoToDoor), 10*S^2 (DoorKey), 100
+    (FourRooms), 30*s^2 for KeyCorridor's rooms of size s = (S + 2) / 3."""
     if family == FAMILY_TWOROOM:
         return 10 * side * side
     if family == FAMILY_FOURROOMS:
         return 100
+    if family == FAMILY_KEYCORRIDOR:
+        return 30 * ((side + 2) // 3) ** 2
     return 4 * side * side
 
 
@@ -169,6 +172,24 @@ def workload_gotodoor(seed: int = 0, n: int = 262144) -> EnvTable:
     return gotodoor_table(n, seed)
 
 
+# the KeyCorridor tasks of the paper's environment table: (side, rows) for
+# S3R1, S3R2, S3R3, S4R3, S5R3, S6R3 (side = 3 * room size - 2)
+KEYCORRIDOR_TASKS = [(7, 1), (7, 2), (7, 3), (10, 3), (13, 3), (16, 3)]
+
+
+def keycorridor_table(n: int, seed: int = 0, mix_seed: int = 1001) -> EnvTable:
+    """The KeyCorridor tasks in equal shares, i.i.d. per env."""
+    rng = np.random.default_rng(mix_seed)
+    pick = np.array(KEYCORRIDOR_TASKS)[rng.integers(0, len(KEYCORRIDOR_TASKS), n)]
+    return _table(np.full(n, FAMILY_KEYCORRIDOR), pick[:, 0], seed, f"keycorridor x{n}", None,
+                  pick[:, 1])
+
+
+def workload_keycorridor(seed: int = 0, n: int = 262144) -> EnvTable:
+    """262144 envs of the KeyCorridor tasks (fused, 4096 steps)."""
+    return keycorridor_table(n, seed)
+
+
 def families_table(n: int, seed: int = 0, mix_seed: int = 4242) -> EnvTable:
     """Every family in one batch: each env draws a task uniformly from the
     paper's tasks of every family (the uneven mix, the lava, obstacle and
@@ -177,13 +198,14 @@ def families_table(n: int, seed: int = 0, mix_seed: int = 4242) -> EnvTable:
     tasks = ([(FAMILY_EMPTY, s, 0) for s in (5, 6, 8, 16)] +
              [(FAMILY_TWOROOM, s, 0) for s in (5, 6, 8, 16)] + [(FAMILY_FOURROOMS, 19, 0)] +
              LAVA_TASKS + [(FAMILY_DYNOBS, s, k) for s, k in DYNOBS_TASKS] +
-             [(FAMILY_GOTODOOR, s, 0) for s in GOTODOOR_SIDES])
+             [(FAMILY_GOTODOOR, s, 0) for s in GOTODOOR_SIDES] +
+             [(FAMILY_KEYCORRIDOR, s, r) for s, r in KEYCORRIDOR_TASKS])
     pick = np.array(tasks)[rng.integers(0, len(tasks), n)]
     return _table(pick[:, 0], pick[:, 1], seed, f"all families x{n}", None, pick[:, 2])
 
 
 WORKLOAD_STEPS = {"empty5": 100, "empty8": 1000, "tworoom8": 2048, "mixed": 4096, "lava": 4096,
-                  "dynobs": 4096, "gotodoor": 4096}
+                  "dynobs": 4096, "gotodoor": 4096, "keycorridor": 4096}
 
 
 def random_actions(n_steps: int, n_envs: int, seed: int) -> np.ndarray:
