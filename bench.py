@@ -43,6 +43,8 @@ WORKLOADS = {
               "16x16 (8), random policy on device, trajectory ring in HBM",
     "gotodoor": "GoToDoor tasks: 262144 envs in equal shares of 5x5, 6x6, 8x8, random policy on device, "
                 "trajectory ring in HBM",
+    "keycorridor": "KeyCorridor tasks: 262144 envs in equal shares of S3R1, S3R2, S3R3, S4R3, S5R3, S6R3, "
+                   "random policy on device, trajectory ring in HBM",
 }
 
 
@@ -172,9 +174,10 @@ def main():
             "empty5": lambda: wl.workload_empty5(seed=0),
             "lava": lambda: wl.workload_lava(seed=0, n=args.envs or 262144),
             "dynobs": lambda: wl.workload_dynobs(seed=0, n=args.envs or 262144),
-            "gotodoor": lambda: wl.workload_gotodoor(seed=0, n=args.envs or 262144)}[args.workload]
+            "gotodoor": lambda: wl.workload_gotodoor(seed=0, n=args.envs or 262144),
+            "keycorridor": lambda: wl.workload_keycorridor(seed=0, n=args.envs or 262144)}[args.workload]
     table = make()
-    if args.envs and args.workload not in ("mixed", "lava", "dynobs", "gotodoor"):
+    if args.envs and args.workload not in ("mixed", "lava", "dynobs", "gotodoor", "keycorridor"):
         table = table.subset(np.arange(args.envs) % table.n)
     obs_mode = OBS_MODES[args.obs]
     env = ge.GridEnv(table, obs_mode=obs_mode)

@@ -14,7 +14,8 @@
  * termination.  The families are those of Table "envs": Empty, DoorKey,
  * FourRooms (reward R1), the lava families LavaGap, Crossings, DistShift
  * (reward R2), Dynamic-Obstacles (reward R3), whose balls move every
- * step (its transition system), and GoToDoor, whose state holds a mission.
+ * step (its transition system), GoToDoor, whose state holds a mission, and
+ * KeyCorridor (reward R1).
  * An episode terminates on reaching the goal or walking into lava (Tables
  * "rewards" and "terminations": on_goal_reached, on_lava_fall), in
  * Dynamic-Obstacles on stepping forward at a ball or wall, and in GoToDoor
@@ -126,6 +127,12 @@ extern "C" {
                                   action >= 6) with that door directly ahead: the
                                   goal reward, end; toggle: reward 0, end.  Side
                                   5..32; no goal square */
+#define GX_FAMILY_KEYCORRIDOR 8 /* KeyCorridor: param = R rows (1..3) of three
+                                  rooms of size s, side = 3s - 2 (7, 10, .., 31);
+                                  the middle column an open hallway, the goal
+                                  behind a locked door, its key in a left room,
+                                  closed doors connecting every room; the rows
+                                  below the rooms are wall */
 
 #define GX_OBS_BYTES 147      /* symbolic first-person record */
 #define GX_OBS_CAT_BYTES 49   /* categorical first-person record */

@@ -54,7 +54,8 @@ constexpr uint32_t kActionNone = 0xFF;
 enum : uint32_t { kLeft = 0, kRight = 1, kForward = 2, kPickup = 3, kDrop = 4, kToggle = 5 };
 enum : uint32_t {
   kFamEmpty = 0, kFamTwoRoom = 1, kFamFourRooms = 2,
-  kFamLavaGap = 3, kFamCrossings = 4, kFamDistShift = 5, kFamDynObs = 6, kFamGoToDoor = 7
+  kFamLavaGap = 3, kFamCrossings = 4, kFamDistShift = 5, kFamDynObs = 6, kFamGoToDoor = 7,
+  kFamKeyCorridor = 8
 };
 constexpr int kMaxObst = 8;
 constexpr uint32_t kBlue = 2;
@@ -116,14 +117,16 @@ struct Layout {
   int a, b, c, d;      // TwoRoom: a = wall column, b = door row; FourRooms: the 4 openings;
                        // LavaGap: a = lava column, b = gap row; DistShift: a = second lava row;
                        // GoToDoor: the doors' positions along the top, right, bottom, left walls
-  int colour;          // TwoRoom door / key colour; GoToDoor: door i's colour at bits 4i..4i+3
-  int kx, ky;          // TwoRoom key; GoToDoor: the room's width and height
+  int colour;          // TwoRoom, KeyCorridor: locked door / key colour; GoToDoor: door i's
+                       // colour at bits 4i..4i+3
+  int kx, ky;          // TwoRoom, KeyCorridor: key; GoToDoor: the room's width and height
   int gx, gy;          // goal
   int ax, ay, dir;     // agent
   uint32_t vmask, hmask;   // Crossings: river columns / rows (bit = coordinate)
   uint64_t vopen, hopen;   // Crossings: opening row of each river column, opening column
                            // of each river row, 5 bits each in ascending river order
   uint32_t ob[4];          // Dynamic-Obstacles: ball b at bytes 2b (x), 2b + 1 (y); 0xFF unused
+  uint32_t kd[3];          // KeyCorridor: the doors between rooms, one byte each (see below)
 };
 
 // (x, y) of ball b from a packed obstacle list
@@ -245,6 +248,94 @@ __device__ __forceinline__ void small_divmod(uint32_t k, uint32_t w, uint32_t& q
   r -= under ? w : 0u;
 }
 
+// KeyCorridor(S = 3s - 2, R rows of rooms): walls between two rooms, one
+// byte each in L.kd (byte e of word e / 4): bit 7 set when the wall has a
+// door, bits 4-6 its colour, bits 0-3 its position along the wall.  Walls
+// between columns i and i + 1 in row j: e = 2j + i; walls between rows jw
+// and jw + 1 in column 0 or 2: e = 6 + 2 jw + i / 2 (column 1 is the open
+// hallway).  The locked door is the wall e = 2 rl + 1 of the locked row rl.
+__device__ __forceinline__ uint32_t kc_byte(const uint32_t (&kd)[3], int e) {
+  const uint64_t lo = (uint64_t)kd[0] | ((uint64_t)kd[1] << 32);
+  return e < 8 ? (uint32_t)(lo >> (8 * e)) & 0xFFu : (kd[2] >> (8 * (e - 8))) & 0xFFu;
+}
+
+// rooms reachable from room `from` (bit j * 3 + i) through the open walls:
+// right[r] / down[r] bits say room r connects to r + 1 / r + 3
+__device__ __forceinline__ uint32_t kc_reach(uint32_t from, uint32_t right, uint32_t down) {
+  uint32_t r = from;
+#pragma unroll
+  for (int it = 0; it < 8; ++it)
+    r |= ((r & right) << 1) | ((r >> 1) & right) | ((r & down) << 3) | ((r >> 3) & down);
+  return r;
+}
+
+struct KcLayout {
+  int rl, colour, gx, gy, kx, ky, ax, ay, dir;
+  uint32_t kd[3];
+};
+
+__device__ __noinline__ KcLayout keycorridor_layout(int S, int R, uint2 seed, uint32_t rng_id,
+                                                    uint32_t episode) {
+  DrawStream ds{seed, rng_id, episode, 0u, make_uint4(0, 0, 0, 0)};
+  const int st = (S - 1) / 3, inner = st - 1;
+  // door positions of walls e = 0..9 (the table's numbering), 4 bits each
+  uint64_t pos = 0;
+  for (int j = 0; j < R; ++j)
+    for (int i = 0; i < 3; ++i) {
+      if (i < 2) pos |= (uint64_t)ds.next((uint32_t)inner) << (4 * (2 * j + i));
+      if (j < R - 1) {
+        const uint64_t p = ds.next((uint32_t)inner);   // the hallway's wall draws one too
+        if (i != 1) pos |= p << (4 * (6 + 2 * j + (i >> 1)));
+      }
+    }
+  KcLayout K;
+  K.rl = (int)ds.next((uint32_t)R);
+  K.colour = (int)ds.next(6u);
+  // the door table: bytes 0-7 in lo, 8-9 in hi
+  uint64_t lo = 0;
+  uint32_t hi = 0;
+  const int el = 2 * K.rl + 1;   // < 8
+  lo |= (uint64_t)(0x80u | ((uint32_t)K.colour << 4) | (uint32_t)((pos >> (4 * el)) & 15u)) << (8 * el);
+  uint32_t q, r;
+  small_divmod(ds.next((uint32_t)(inner * inner)), (uint32_t)inner, q, r);
+  K.gx = 2 * st + 1 + (int)r;
+  K.gy = K.rl * st + 1 + (int)q;
+  const int rk = (int)ds.next((uint32_t)R);
+  small_divmod(ds.next((uint32_t)(inner * inner)), (uint32_t)inner, q, r);
+  K.kx = 1 + (int)r;
+  K.ky = rk * st + 1 + (int)q;
+  const int ra = R / 2;
+  small_divmod(ds.next((uint32_t)(inner * inner)), (uint32_t)inner, q, r);
+  K.ax = st + 1 + (int)r;
+  K.ay = ra * st + 1 + (int)q;
+  K.dir = (int)ds.next(4u);
+  // connect every room (MiniGrid's connect_all), the locked room excepted
+  const uint32_t all = (1u << (3 * R)) - 1u;
+  uint32_t right = 1u << (3 * K.rl + 1), down = 0u;   // the locked door
+  for (int j = 0; j + 1 < R; ++j) down |= 1u << (3 * j + 1);   // the hallway
+  for (int it = 0; it < 1024; ++it) {
+    if (kc_reach(1u << (3 * ra + 1), right, down) == all) break;
+    const int i = (int)ds.next(3u), j = (int)ds.next((uint32_t)R), k = (int)ds.next(4u);
+    const int i2 = i + (k == 0) - (k == 2), j2 = j + (k == 1) - (k == 3);
+    if (i2 < 0 || i2 > 2 || j2 < 0 || j2 >= R) continue;
+    const bool horiz = j2 == j;
+    const int room = horiz ? 3 * j + min(i, i2) : 3 * min(j, j2) + i;
+    if (((horiz ? right : down) >> room) & 1u) continue;
+    if ((i == 2 && j == K.rl) || (i2 == 2 && j2 == K.rl)) continue;
+    const uint32_t c = ds.next(6u);
+    const int e = horiz ? 2 * j + min(i, i2) : 6 + 2 * min(j, j2) + (i >> 1);
+    if (horiz) right |= 1u << room;
+    else down |= 1u << room;
+    const uint32_t v = 0x80u | (c << 4) | (uint32_t)((pos >> (4 * e)) & 15u);
+    if (e < 8) lo |= (uint64_t)v << (8 * e);
+    else hi |= v << (8 * (e - 8));
+  }
+  K.kd[0] = (uint32_t)lo;
+  K.kd[1] = (uint32_t)(lo >> 32);
+  K.kd[2] = hi;
+  return K;
+}
+
 // idx-th free cell, row-major, of a four-room grid of side S = 2m + 1 with
 // openings (m, g1), (m, g2) in the vertical wall (g1 < m < g2) and
 // (g3, m), (g4, m) in the horizontal one.  Rows other than m hold S - 3 free
@@ -291,6 +382,24 @@ __device__ Layout make_layout(uint32_t meta, uint2 seed, uint32_t rng_id, uint32
   L.vmask = L.hmask = 0;
   L.vopen = L.hopen = 0;
   L.ob[0] = L.ob[1] = L.ob[2] = L.ob[3] = 0xFFFFFFFFu;
+  L.kd[0] = L.kd[1] = L.kd[2] = 0u;
+  if (fam == kFamKeyCorridor) {
+    const KcLayout K = keycorridor_layout(S, param, seed, rng_id, episode);
+    L.a = K.rl;
+    L.b = param;   // rows of rooms
+    L.colour = K.colour;
+    L.gx = K.gx;
+    L.gy = K.gy;
+    L.kx = K.kx;
+    L.ky = K.ky;
+    L.ax = K.ax;
+    L.ay = K.ay;
+    L.dir = K.dir;
+    L.kd[0] = K.kd[0];
+    L.kd[1] = K.kd[1];
+    L.kd[2] = K.kd[2];
+    return L;
+  }
   if (fam == kFamDynObs) {
     // balls in order, ball b at the draw-b-th free interior cell other than
     // the agent's (1, 1): linear interior index c with c - #{earlier balls
@@ -433,8 +542,41 @@ __device__ __forceinline__ int gotodoor_door(const Layout& L, int x, int y) {
   return i < 0 ? -1 : (int)(((uint32_t)L.colour >> (4 * i)) & 15u);
 }
 
+// content of KeyCorridor cell (x, y): rooms of stride st = (S - 1) / 3 in
+// the top R * st + 1 rows, wall below; doors from the wall table
+__device__ __forceinline__ uint32_t keycorridor_cell(const Layout& L, int x, int y) {
+  const int st = (L.S - 1) / 3, R = L.b;
+  if (y > R * st) return kCellWall;
+  uint32_t qx, mx, qy, my;
+  small_divmod((uint32_t)x, (uint32_t)st, qx, mx);
+  small_divmod((uint32_t)y, (uint32_t)st, qy, my);
+  if (mx != 0 && my != 0) {
+    if (x == L.gx && y == L.gy) return kCellGoal;
+    if (x == L.kx && y == L.ky) return kKey | ((uint32_t)L.colour << 8);
+    return kCellEmpty;
+  }
+  if (mx == 0 && my == 0) return kCellWall;
+  int e;
+  uint32_t p;
+  if (mx == 0) {   // a wall between columns qx - 1 and qx, in row qy
+    if (qx == 0 || qx == 3) return kCellWall;
+    e = 2 * (int)qy + (int)qx - 1;
+    p = my - 1;
+  } else {         // a wall between rows qy - 1 and qy, in column qx
+    if (qy == 0 || (int)qy == R) return kCellWall;
+    if (qx == 1) return kCellEmpty;   // the hallway
+    e = 6 + 2 * ((int)qy - 1) + (int)(qx >> 1);
+    p = mx - 1;
+  }
+  const uint32_t d = kc_byte(L.kd, e);
+  if (!(d & 0x80u) || (d & 15u) != p) return kCellWall;
+  const uint32_t state = e == 2 * L.a + 1 ? kLocked : kClosed;
+  return kDoor | (((d >> 4) & 7u) << 8) | (state << 16);
+}
+
 __device__ __forceinline__ uint32_t layout_cell(const Layout& L, int x, int y) {
   const int S = L.S;
+  if (L.fam == kFamKeyCorridor) return keycorridor_cell(L, x, y);
   if (L.fam == kFamGoToDoor) {
     const int dc = gotodoor_door(L, x, y);
     if (dc >= 0) return kDoor | ((uint32_t)dc << 8) | (kClosed << 16);
@@ -479,6 +621,8 @@ __device__ __forceinline__ Layout bcast_layout(const Layout& L, int r) {
             ((uint64_t)(uint32_t)bcast((int)(L.hopen >> 32), r) << 32);
 #pragma unroll
   for (int i = 0; i < 4; ++i) o.ob[i] = (uint32_t)bcast((int)L.ob[i], r);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) o.kd[i] = (uint32_t)bcast((int)L.kd[i], r);
   return o;
 }
 
@@ -1093,6 +1237,7 @@ constexpr int kKinds = 64;
 __device__ __forceinline__ uint32_t layout_code(const Layout& L, int x, int y) {
   constexpr uint32_t kWallCode = 4 * (1 + kGrey), kGoalCode = 4 * (7 + kGreen), kLavaCode = 4 * 49;
   const int S = L.S;
+  if (L.fam == kFamKeyCorridor) return code_of(keycorridor_cell(L, x, y));
   uint32_t code = 0;
   if (L.fam == kFamTwoRoom) {   // the family is uniform across the wave here
     code = (x == L.kx && y == L.ky) ? 4u * (13u + (uint32_t)L.colour) : code;

@@ -93,6 +93,8 @@ inline bool family_ok(int family, int side, int param, int max_side) {
     case 6: return side >= 5 && param >= 1 && param <= 8 &&
                    param <= (side - 2) * (side - 2) - 2;       // Dynamic-Obstacles
     case 7: return side >= 5;                                  // GoToDoor
+    case 8: return side >= 7 && (side + 2) % 3 == 0 && param >= 1 &&
+                   param <= 3;                                 // KeyCorridor: side 3s - 2, R rows
     default: return false;
   }
 }

@@ -42,7 +42,24 @@ def tables():
         "gotodoor": wl.gotodoor_table(3000, seed=61, mix_seed=62),
         "gotodoor_all": gotodoor_all_table(),
         "families": wl.families_table(3000, seed=71, mix_seed=72),
+        "keycorridor": wl.keycorridor_table(3000, seed=81, mix_seed=82),
+        "keycorridor_all": keycorridor_all_table(),
     }
+
+
+def keycorridor_all_table():
+    """Every side 7..31 of KeyCorridor with 1..3 rows of rooms, two envs each."""
+    side, rows = [], []
+    for S in range(7, 32, 3):
+        for R in (1, 2, 3):
+            side += [S, S]
+            rows += [R, R]
+    n = len(side)
+    fam = np.full(n, wl.FAMILY_KEYCORRIDOR)
+    ms = np.array([wl.default_max_steps(int(f), int(s)) for f, s in zip(fam, side)]) // 8 + 1
+    return wl.EnvTable(fam.astype(np.uint8), np.array(side, np.uint8), ms.astype(np.int32),
+                       np.full(n, 79, np.uint64), np.arange(n, dtype=np.uint32), "keycorridor all sides",
+                       np.array(rows, np.uint8))
 
 
 def gotodoor_all_table():
@@ -113,7 +130,8 @@ def test_reset_parity(ge, name):
                                         ("fourrooms19", 250), ("mixed", 300), ("all_sides", 200),
                                         ("lava", 300), ("lava_all", 200), ("dynobs", 300),
                                         ("dynobs_all", 150), ("gotodoor", 300),
-                                        ("gotodoor_all", 200), ("families", 300)])
+                                        ("gotodoor_all", 200), ("families", 300),
+                                        ("keycorridor", 300), ("keycorridor_all", 200)])
 @pytest.mark.parametrize("policy", [False, True])
 def test_plain_step_parity(ge, name, steps, policy):
     import torch
@@ -136,7 +154,8 @@ def test_plain_step_parity(ge, name, steps, policy):
                                         ("fourrooms19", 250), ("mixed", 300), ("all_sides", 200),
                                         ("lava", 300), ("lava_all", 200), ("dynobs", 300),
                                         ("dynobs_all", 150), ("gotodoor", 300),
-                                        ("gotodoor_all", 200), ("families", 300)])
+                                        ("gotodoor_all", 200), ("families", 300),
+                                        ("keycorridor", 300), ("keycorridor_all", 200)])
 @pytest.mark.parametrize("K", [1, 7, 64])
 @pytest.mark.parametrize("policy", [False, True])
 def test_fused_rollout_parity(ge, name, steps, K, policy):
