@@ -160,3 +160,20 @@ def test_lava_and_obstacle_requests_equal_oracle():
     assert info["live_requests"] == 0
     for i, r in enumerate(reqs):
         P.assert_rows_equal(crop(outs[i], r.n_envs), oracle_of(r), what=f"lava request {i}")
+
+
+def test_requests_of_every_family_equal_oracle():
+    """Requests mixing every family (GoToDoor and KeyCorridor included) through
+    the server equal the oracle's reset + rollout."""
+    from paper_2407_19396_amd import gridenv as ge
+    rng = np.random.default_rng(4)
+    reqs = []
+    for i in range(8):
+        n = int(rng.integers(1, 300))
+        make = [wl.families_table, wl.gotodoor_table, wl.keycorridor_table][i % 3]
+        t = make(n, seed=int(rng.integers(0, 2 ** 62)), mix_seed=100 + i)
+        reqs.append(wl.Request(i, 0.0, n, int(rng.integers(20, 120)), int(t.seed[0]), t))
+    outs, _, info = run_mix(ge, reqs, 32, max_tiles=10)
+    assert info["live_requests"] == 0
+    for i, r in enumerate(reqs):
+        P.assert_rows_equal(crop(outs[i], r.n_envs), oracle_of(r), what=f"family request {i}")
