@@ -77,9 +77,20 @@ def cpu_baseline(table, n_envs: int, n_steps: int) -> dict:
     t0 = time.perf_counter()
     ox.rollout(b, s, n_steps, None, rows=16, nthreads=threads)
     dt = time.perf_counter() - t0
+    # the same oracle on one thread, over 1 / threads of the envs
+    n1 = max(1, n_envs // threads)
+    sub1 = table.subset(np.arange(n1))
+    b1 = ox.Batch(sub1.family, sub1.side, sub1.max_steps, sub1.seed, sub1.rng_id, 0, sub1.param)
+    s1 = ox.State.empty(b1)
+    ox.reset(b1, s1)
+    t1 = time.perf_counter()
+    ox.rollout(b1, s1, n_steps, None, rows=16)
+    dt1 = time.perf_counter() - t1
     return {"value": n_envs * n_steps / dt, "unit": "env-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n_envs} envs of the same mix, {n_steps} steps, random policy, "
-                      f"observations on, {dt:.1f} s"}
+                      f"observations on, {dt:.1f} s",
+            "single_thread": {"value": n1 * n_steps / dt1, "cores": 1,
+                              "sample": f"first {n1} envs, {n_steps} steps, {dt1:.1f} s"}}
 
 
 def run_serving(capacity: float, n_requests: int, loads, K: int, budget_gib: int,
@@ -123,6 +134,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4096, help="timed environment steps of the batch")
     ap.add_argument("--warmup", type=int, default=256)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="further timed runs of the same rollout, reported as median / min / max")
     ap.add_argument("--workload", default="mixed", choices=sorted(WORKLOADS))
     ap.add_argument("--envs", type=int, default=0, help="override the workload's env count")
     ap.add_argument("--K", type=int, default=0, help="steps fused per launch (0: autotune)")
@@ -235,6 +248,18 @@ def main():
     log(f"[bench] fused: {args.steps} steps in {ms:.1f} ms ({wall * 1e3:.1f} ms wall), "
         f"{value / 1e9:.2f} G env-steps/s")
 
+    # the same timed rollout repeated, for its spread
+    reps = []
+    for _ in range(args.repeats):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        if graph is not None:
+            graph.replay()
+        else:
+            env.rollout(args.steps, traj, K=K)
+        b.record(stream)
+        b.synchronize()
+        reps.append(env_steps / (a.elapsed_time(b) / 1e3))
     # per-launch latency of the fused kernel
     lat = []
     for _ in range(min(64, max(8, launches))):
@@ -317,6 +342,8 @@ def main():
                    "autotuned": tuned is not None, "hip_graph": graph is not None,
                    "observation": args.obs},
         "fused_launch_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "repeats": None if not reps else {"n": len(reps), "median": float(np.median(reps)),
+                                          "min": float(np.min(reps)), "max": float(np.max(reps))},
         "plain": None if plain_rate is None else {
             "value": plain_rate, "unit": "env-steps/s", "steps": args.plain_steps,
             "launch_ms": {"p50": float(np.percentile(plain_lat, 50)),

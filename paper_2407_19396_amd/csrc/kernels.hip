@@ -4,8 +4,8 @@
 // step(timestep, action) with autoreset; reset pads action -1, reward 0)
 // applied to MiniGrid's dynamics, which the paper reproduces exactly
 // (Sec. 3.2.1): the intervention / transition / observation / reward /
-// termination systems of Table "systems" and App. A over the Wall, Key,
-// Door and Goal entities of Table "entities".
+// termination systems of Table "systems" and App. A over the entities of
+// Table "entities", for every family of Table "envs".
 //
 // Two kernels share the device functions below:
 //   k_plain  -- one launch per step; one env per lane; state, grid and
@@ -14,8 +14,10 @@
 //               mix of sizes, stages their grids in LDS as one byte per
 //               cell, runs K steps with the pose in registers, writes one
 //               trajectory record per env-step, then writes the state back.
-// Both stage the 147-byte observations of a wave through LDS so that the
-// wave's 64 records leave as one contiguous, 16-byte-vectorised block.
+//               Its serving variant also admits and resets new requests.
+// Both stage the first-person observations of a wave through LDS so that
+// the wave's records leave as one contiguous, 16-byte-vectorised block;
+// whole-grid observations leave the same way, packed like the grids.
 //
 // All arithmetic is integer except the reward, which is three separately
 // rounded fp32 operations (built with -ffp-contract=off).
