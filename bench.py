@@ -53,6 +53,7 @@ def log(msg):
 
 
 OBS_MODES = {"symbolic": 0, "categorical": 1, "symbolic_grid": 2, "categorical_grid": 3}
+RING_BUDGET = 64 << 30   # bytes of HBM the trajectory ring of one launch may take
 
 
 def fused_bytes(n_envs: int, grid_bytes: int, k: int, obs_bytes: int = OBS) -> float:
@@ -203,9 +204,12 @@ def main():
         env.set_launch(args.K or env.info()["k_default"], args.blocks)
     else:
         from paper_2407_19396_amd import autotune
-        probe = env.traj(512)
+        # K up to 1024, as long as a ring of K rows stays within RING_BUDGET
+        row_bytes = table.n * (obs_bytes + 6)
+        Ks = [k for k in (128, 256, 512, 1024) if k * row_bytes <= RING_BUDGET] or [128]
+        probe = env.traj(max(Ks))
         env.reset(first)
-        tuned = autotune.tune(env, probe, log=log)
+        tuned = autotune.tune(env, probe, Ks=tuple(Ks), log=log)
         del probe
         log(f"[bench] autotuned K={tuned['K']} blocks={tuned['blocks']}")
     info = env.info()
