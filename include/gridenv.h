@@ -10,7 +10,7 @@
  * action), which resets automatically once the episode is done; reset pads
  * the action with -1 and the reward with 0.  Inside a step the systems of
  * Table "systems" (App. A) apply in order: intervention (the action),
- * transition (identity for these families), observation, reward,
+ * transition (the identity except in Dynamic-Obstacles), observation, reward,
  * termination.  The families are those of Table "envs": Empty, DoorKey,
  * FourRooms (reward R1), the lava families LavaGap, Crossings, DistShift
  * (reward R2), Dynamic-Obstacles (reward R3), whose balls move every

@@ -32,7 +32,10 @@
  *     Tables "rewards" and "terminations", on_lava_fall);
  *   - Dynamic-Obstacles (Table "envs", reward R3; Fig. 1): balls that move
  *     at random every step, the first family whose transition system is
- *     not the identity (Table "systems").
+ *     not the identity (Table "systems");
+ *   - GoToDoor (on_door_done of Tables "rewards" and "terminations"; its
+ *     mission is part of the state) and KeyCorridor (reward R1), the last
+ *     families of Table "envs".
  *
  * Every point the paper leaves open is fixed by a documented reading; the
  * readings are listed next to each function.  Parity status of each
@@ -171,9 +174,9 @@ static uint32_t count_empty(const uint8_t *g, int S, int x0, int x1, int y0,
 
 /* Side (and parameter) limits of each family.  The parameter is the
  * number of lava rivers of Crossings (at most 8 and at most S - 3), the
- * variant (1 or 2) of DistShift and the number of obstacles (1 to 8, leaving
- * two free interior cells) of Dynamic-Obstacles; the other families ignore
- * it. */
+ * variant (1 or 2) of DistShift, the number of obstacles (1 to 8, leaving
+ * two free interior cells) of Dynamic-Obstacles and the rows of rooms (1 to
+ * 3) of KeyCorridor; the other families ignore it. */
 int ox_side_ok(int family, int side, int param) {
   if (side > 32) return 0;
   switch (family) {
@@ -695,8 +698,9 @@ static void move_obstacles(uint8_t *grid, int S, int n, int ax, int ay,
 /* episode (reset pads: action -1 recorded as 0xFF, reward 0).        */
 /* Otherwise: intervention I(s, a) (turn, forward with collision,     */
 /* pickup, drop, toggle with colour-matched keys; App. A), transition */
-/* (identity for these families), observation O(s'), reward R, and    */
-/* termination (goal reached or lava entered) plus truncation at t = T.*/
+/* (identity except in Dynamic-Obstacles), observation O(s'), reward  */
+/* R, and termination (goal reached or lava entered) plus truncation   */
+/* at t = T.                                                           */
 /* Lava (Table "entities") is walked onto like an empty cell and ends  */
 /* the episode with reward -1 (R2 of Table "envs"; on_lava_fall of     */
 /* Tables "rewards" and "terminations"), in both reward modes: the     */

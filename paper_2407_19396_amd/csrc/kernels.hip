@@ -369,7 +369,8 @@ __device__ __forceinline__ void fourrooms_cell(int S, int m, int g1, int g2, int
 }
 
 // meta = family | side << 8 | parameter << 16 (Crossings: rivers; DistShift:
-// variant).  The lava families start at (1, 1) facing east.
+// variant; Dynamic-Obstacles: balls; KeyCorridor: rows of rooms).  The lava
+// families and Dynamic-Obstacles start at (1, 1) facing east.
 __device__ Layout make_layout(uint32_t meta, uint2 seed, uint32_t rng_id, uint32_t episode) {
   const uint32_t fam = meta & 0xFF;
   const int S = (int)((meta >> 8) & 0xFF), param = (int)((meta >> 16) & 0xFF);

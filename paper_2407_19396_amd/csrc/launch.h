@@ -79,7 +79,8 @@ struct SlotConfig {
 
 
 // Whether (family, side, param) describes a valid env with side <= max_side
-// (the families of Table "envs"; param: Crossings rivers, DistShift variant).
+// (the families of Table "envs"; param: Crossings rivers, DistShift variant,
+// Dynamic-Obstacles balls, KeyCorridor rows of rooms).
 inline bool family_ok(int family, int side, int param, int max_side) {
   if (side > max_side || side > 32) return false;
   switch (family) {
