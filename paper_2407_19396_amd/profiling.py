@@ -6,7 +6,8 @@ WRITE_SIZE (and optional SQ) counter runs into a short text summary for
 device-to-device copy of known size recorded in the same runs (the copy
 reads and writes exactly that many bytes).  The summary ends with one
 machine-readable line that ``traffic_bytes`` reads back for the benchmark;
-it is ignored once the kernel source has changed.
+it is ignored once the kernel's code has changed (comments and layout
+aside).
 
     python -m paper_2407_19396_amd.profiling --trace DIR --fetch DIR --write DIR
         [--sq DIR] --copy-bytes N --K K --envs N --command "..." -o profiles/x.txt
@@ -19,17 +20,31 @@ import csv
 import glob
 import hashlib
 import os
+import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCE = os.path.join(HERE, "csrc", "kernels.hip")
+KERNEL_SOURCES = (KERNEL_SOURCE, os.path.join(HERE, "csrc", "launch.h"))
 COPY_KERNEL = "copyBuffer"
 FUSED = "k_fused"
 PLAIN = "k_plain"
 
 
-def kernel_source_hash(path: str = KERNEL_SOURCE) -> str:
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def _code_only(text: str) -> str:
+    """The source without its comments and with blank space collapsed: a
+    change to either leaves the compiled kernel as it was."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def kernel_source_hash(paths=KERNEL_SOURCES) -> str:
+    """Hash of the kernel's code: the kernel source and the launch header."""
+    h = hashlib.sha256()
+    for p in ([paths] if isinstance(paths, str) else paths):
+        with open(p) as f:
+            h.update(_code_only(f.read()).encode())
+    return h.hexdigest()[:16]
 
 
 def _one(pattern: str) -> str:
@@ -83,7 +98,7 @@ def summarize(trace: str, fetch: str, write: str, sq, copy_bytes: int, K: int,
         "# k_fused on the mixed 262144-env workload (rocprofv3)",
         "",
         f"command: {command}",
-        f"kernel source sha256[:16]: {kernel}",
+        f"kernel code sha256[:16] (kernels.hip + launch.h, comments aside): {kernel}",
         f"steps per launch K = {K}, envs = {envs}",
         "",
         "## kernel trace (--kernel-trace --stats)",
@@ -132,7 +147,8 @@ def main():
     ap.add_argument("--fetch", required=True)
     ap.add_argument("--write", required=True)
     ap.add_argument("--sq", action="append", help="SQ counter run directory (repeatable)")
-    ap.add_argument("--source", default=KERNEL_SOURCE, help="kernel source the profiled build used")
+    ap.add_argument("--source", nargs="+", default=list(KERNEL_SOURCES),
+                    help="kernel source and launch header the profiled build used")
     ap.add_argument("--copy-bytes", type=int, required=True)
     ap.add_argument("--K", type=int, required=True)
     ap.add_argument("--envs", type=int, required=True)

@@ -50,3 +50,17 @@ def test_serving_requests_shape():
     assert (np.diff(arr) > 0).all() and 2.5 < arr[-1] < 3.5            # Poisson at 1000/s
     assert all(r.table.n == r.n_envs and (r.table.seed == r.seed).all() for r in reqs[:50])
     assert len({r.seed for r in reqs}) == len(reqs)
+
+
+def test_kernel_hash_ignores_comments_but_not_code(tmp_path):
+    a, b = tmp_path / "a.hip", tmp_path / "b.h"
+    a.write_text("int f(int x) { return x + 1; }  // one\n/* block */\n")
+    b.write_text("struct S { int y; };\n")
+    h = profiling.kernel_source_hash((str(a), str(b)))
+    a.write_text("// a new comment\nint f(int x)   {\n  return x + 1;  /* two */ }\n")
+    assert profiling.kernel_source_hash((str(a), str(b))) == h
+    a.write_text("int f(int x) { return x + 2; }\n")
+    assert profiling.kernel_source_hash((str(a), str(b))) != h
+    a.write_text("int f(int x) { return x + 1; }\n")
+    b.write_text("struct S { long y; };\n")
+    assert profiling.kernel_source_hash((str(a), str(b))) != h
