@@ -679,6 +679,22 @@ __device__ __forceinline__ ActResult intervene(uint32_t act, int& x, int& y, int
 // grid accessor reads "is empty" and writes a ball or an empty cell.  List
 // entries off the interior (only a malformed state has them) do not move.
 // ---------------------------------------------------------------------------
+// position of the k-th (0-based) set bit of an 8-bit m, k < popcount(m):
+// halve the search range three times instead of clearing k bits one by one
+__device__ __forceinline__ uint32_t kth_bit8(uint32_t m, uint32_t k) {
+  uint32_t base = 0, p = (uint32_t)__builtin_popcount(m & 15u);
+  const bool hi4 = k >= p;
+  k -= hi4 ? p : 0u;
+  m = hi4 ? m >> 4 : m;
+  base += hi4 ? 4u : 0u;
+  p = (uint32_t)__builtin_popcount(m & 3u);
+  const bool hi2 = k >= p;
+  k -= hi2 ? p : 0u;
+  m = hi2 ? m >> 2 : m;
+  base += hi2 ? 2u : 0u;
+  return base + ((k >= (m & 1u)) ? 1u : 0u);
+}
+
 template <class Grid>
 __device__ __forceinline__ void move_obstacles(const Grid& g, int n, int ax, int ay, uint32_t (&ob)[4],
                                                uint2 seed, uint32_t rng_id, uint32_t call) {
@@ -693,18 +709,16 @@ __device__ __forceinline__ void move_obstacles(const Grid& g, int n, int ax, int
       // an entry off the interior (a malformed state) is left alone, so no
       // access ever leaves the env's grid
       const bool inside = bx >= 1 && by >= 1 && bx <= g.S - 2 && by <= g.S - 2;
-      uint32_t mask = 0;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int dx = (i < 3) ? i - 1 : (i < 5 ? (i == 3 ? -1 : 1) : i - 6);
-        const int dy = (i < 3) ? -1 : (i < 5 ? 0 : 1);
-        const bool free = inside && g.empty(bx + dx, by + dy) && !(bx + dx == ax && by + dy == ay);
-        mask |= free ? (1u << i) : 0u;
-      }
+      uint32_t mask = 0;   // bit i: neighbour i (row-major, the ball's own cell skipped) is empty
+      if (inside) mask = g.free8(bx, by);
+      // the agent's cell is never a destination
+      const uint32_t ac = (uint32_t)(3 * (ay - by + 1) + (ax - bx + 1));
+      if ((unsigned)(ax - bx + 1) < 3u && (unsigned)(ay - by + 1) < 3u && ac != 4u)
+        mask &= ~(1u << (ac - (ac > 4u)));
       if (mask) {
-        const int i = kth_bit(mask, (int)bounded(word, (uint32_t)__builtin_popcount(mask)));
-        const int dx = (i < 3) ? i - 1 : (i < 5 ? (i == 3 ? -1 : 1) : i - 6);
-        const int dy = (i < 3) ? -1 : (i < 5 ? 0 : 1);
+        const uint32_t i = kth_bit8(mask, bounded(word, (uint32_t)__builtin_popcount(mask)));
+        const uint32_t cell = i + (i >= 4u);   // 0..8 without the centre
+        const int dx = (int)(cell % 3u) - 1, dy = (int)(cell / 3u) - 1;
         g.put_empty(bx, by);
         g.put_ball(bx + dx, by + dy);
         obst_set(ob, b, (uint32_t)(bx + dx), (uint32_t)(by + dy));
@@ -1015,7 +1029,15 @@ __device__ __forceinline__ void store_triple(uint8_t* p, uint32_t tri) {
 struct HbmGrid {
   uint8_t* g;
   int S;
-  __device__ __forceinline__ bool empty(int x, int y) const { return g[3 * (y * S + x)] == kEmpty; }
+  // the 8 cells around interior cell (x, y), row-major, as bits: set = empty
+  __device__ __forceinline__ uint32_t free8(int x, int y) const {
+    const uint8_t* p = g + 3 * ((y - 1) * S + (x - 1));
+    const uint8_t* q = p + 3 * S;
+    const uint8_t* r = q + 3 * S;
+    return (p[0] == kEmpty ? 1u : 0u) | (p[3] == kEmpty ? 2u : 0u) | (p[6] == kEmpty ? 4u : 0u) |
+           (q[0] == kEmpty ? 8u : 0u) | (q[6] == kEmpty ? 16u : 0u) | (r[0] == kEmpty ? 32u : 0u) |
+           (r[3] == kEmpty ? 64u : 0u) | (r[6] == kEmpty ? 128u : 0u);
+  }
   __device__ __forceinline__ void put_empty(int x, int y) const { store_triple(g + 3 * (y * S + x), kCellEmpty); }
   __device__ __forceinline__ void put_ball(int x, int y) const { store_triple(g + 3 * (y * S + x), kCellBall); }
 };
@@ -1339,7 +1361,14 @@ __device__ __forceinline__ LdsRows lds_rows(const uint32_t* table, const uint8_t
 struct LdsGrid {
   uint8_t* g;
   int S;
-  __device__ __forceinline__ bool empty(int x, int y) const { return g[y * S + x] == 0; }
+  // the 8 cells around interior cell (x, y), row-major, as bits: set = empty
+  __device__ __forceinline__ uint32_t free8(int x, int y) const {
+    const uint8_t* p = g + (y - 1) * S + (x - 1);
+    const uint8_t* q = p + S;
+    const uint8_t* r = q + S;
+    return (p[0] == 0 ? 1u : 0u) | (p[1] == 0 ? 2u : 0u) | (p[2] == 0 ? 4u : 0u) | (q[0] == 0 ? 8u : 0u) |
+           (q[2] == 0 ? 16u : 0u) | (r[0] == 0 ? 32u : 0u) | (r[1] == 0 ? 64u : 0u) | (r[2] == 0 ? 128u : 0u);
+  }
   __device__ __forceinline__ void put_empty(int x, int y) const { g[y * S + x] = 0; }
   __device__ __forceinline__ void put_ball(int x, int y) const { g[y * S + x] = (uint8_t)(4u * (19u + kBlue)); }
 };
