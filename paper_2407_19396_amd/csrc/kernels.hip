@@ -1309,30 +1309,11 @@ __device__ __forceinline__ uint32_t table_at(const uint32_t* table, uint32_t cod
 // +-1 or +-S in the row-major grid, so each cell is one add away.  All 49
 // codes are read before any table lookup, so the lookups wait on the code
 // reads in bulk rather than one dependent pair at a time.
-// With `checked` (wave-uniform) every cell is bounds-checked and cells
-// outside the grid read as walls instead: needed only on the rare step whose
-// view can leave the grid, through a door on the outer ring that the step
-// itself opened (GoToDoor rooms use the grid's border as walls).
 struct LdsRows {
   const uint32_t* table;
   const uint8_t* center;   // the agent's cell
   int R, F;                // linear steps to the agent's right and ahead
-  bool checked;
-  int S, x, y, dir;
   __device__ __forceinline__ void load_all(uint32_t (&c)[kView][kView]) const {
-    if (checked) {
-      const int fx = dir_dx(dir), fy = dir_dy(dir), rx = -fy, ry = fx;
-      const uint8_t* g = center - (y * S + x);
-#pragma unroll
-      for (int j = kView - 1; j >= 0; --j)
-#pragma unroll
-        for (int i = 0; i < kView; ++i) {
-          const int wx = x + (i - 3) * rx + (6 - j) * fx, wy = y + (i - 3) * ry + (6 - j) * fy;
-          const bool in = (unsigned)wx < (unsigned)S && (unsigned)wy < (unsigned)S;
-          c[j][i] = in ? table_at(table + kKinds * i, g[in ? wy * S + wx : 0]) : kCellWall;
-        }
-      return;
-    }
     uint32_t code[kView][kView];
 #pragma unroll
     for (int j = kView - 1; j >= 0; --j) {
@@ -1351,12 +1332,34 @@ struct LdsRows {
 };
 
 __device__ __forceinline__ LdsRows lds_rows(const uint32_t* table, const uint8_t* codes, int S, int x,
-                                            int y, int dir, bool checked) {
+                                            int y, int dir) {
   // heading 0: ahead +1, right +S; 1: ahead +S, right -1; 2: -1, -S; 3: -S, +1
   const int F = (dir & 1) ? ((dir == 1) ? S : -S) : ((dir == 0) ? 1 : -1);
   const int R = (dir & 1) ? ((dir == 1) ? -1 : 1) : ((dir == 0) ? S : -S);
-  return LdsRows{table, codes + y * S + x, R, F, checked, S, x, y, dir};
+  return LdsRows{table, codes + y * S + x, R, F};
 }
+
+// View rows from the LDS codes with every cell bounds-checked, cells outside
+// the grid read as walls: for the rare step whose view can leave the grid,
+// through a door on the outer ring that the step itself opened (GoToDoor
+// rooms use the grid's border as walls).  The views of such a step are
+// computed a second time with these rows.
+struct LdsCheckedRows {
+  const uint32_t* table;
+  const uint8_t* g;   // the env's codes
+  int S, x, y, dir;
+  __device__ __forceinline__ void load_all(uint32_t (&c)[kView][kView]) const {
+    const int fx = dir_dx(dir), fy = dir_dy(dir), rx = -fy, ry = fx;
+#pragma unroll
+    for (int j = kView - 1; j >= 0; --j)
+#pragma unroll
+      for (int i = 0; i < kView; ++i) {
+        const int wx = x + (i - 3) * rx + (6 - j) * fx, wy = y + (i - 3) * ry + (6 - j) * fy;
+        const bool in = (unsigned)wx < (unsigned)S && (unsigned)wy < (unsigned)S;
+        c[j][i] = in ? table_at(table + kKinds * i, g[in ? wy * S + wx : 0]) : kCellWall;
+      }
+  }
+};
 
 struct LdsGrid {
   uint8_t* g;
@@ -1492,11 +1495,14 @@ __device__ __forceinline__ int wave_excl_scan(int v, int lane, int& total) {
 // kServe: tiles belong to requests described by a.serve (serving): each runs
 // min(K, steps it has left) steps from its own counter step0, writes to its
 // own output rows and advances step0.
+// kObs: the observation records written, 0 symbolic first person, 1
+// categorical first person, 2 whole grid (a.env.obs_mode 2 or 3); each
+// variant carries only its own record code.
 // On this GPU one counter tracks both outstanding loads and stores, so a
 // load consumed in the same step would also wait for every earlier record
 // store: the action of step s + 1 is therefore fetched during step s, and
 // the policy variant has no loads in its step loop at all.
-template <bool kActions, bool kServe>
+template <bool kActions, bool kServe, int kObs>
 __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
   // static LDS (table and record stage) sits at fixed addresses, so table
   // reads take their base as an immediate; the tile grids are dynamic
@@ -1559,7 +1565,7 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
     } else {
       n_here = min(kWave, N - e0);
       steps = a.k_steps;
-      o_obs = a.out.obs ? a.out.obs + (size_t)e0 * (a.env.obs_mode == 1 ? kCatBytes : kObsBytes) : nullptr;
+      o_obs = a.out.obs ? a.out.obs + (size_t)e0 * (kObs == 1 ? kCatBytes : kObsBytes) : nullptr;
       o_reward = a.out.reward + e0;
       o_flags = a.out.flags + e0;
       o_action = a.out.action + e0;
@@ -1703,7 +1709,7 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
 
       const size_t row = kServe ? (size_t)(step0 + s) : (size_t)((a.row0 + s) % a.out.rows);
       const size_t rec = row * rec_stride;   // index of lane 0's record
-      if (o_obs && !kServe && a.env.obs_mode >= 2) {
+      if (kObs == 2 && o_obs && !kServe) {
         // whole-grid records, packed like the tile's grids (from g0): the
         // agents are drawn into the codes for the copy and then removed
         uint8_t* at = my_codes + y * S + x;
@@ -1718,20 +1724,22 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
         else emit_tile_grids<false>(dst + g0, tile_cells, table, codes, lane);
         wave_sync();
         if (active) *at = under;
-      } else if (o_obs && !kServe && a.env.obs_mode == 1) {
+      } else if (kObs == 1 && o_obs && !kServe) {
         // categorical records (49 bytes): the stage holds all 64 at once
         uint32_t u[kObsWords + 1];
-        observe_words<true>(lds_rows(table, my_codes, S, x, y, dir, __ballot(edge_view) != 0), carry, active,
-                            lane, u);
+        observe_words<true>(lds_rows(table, my_codes, S, x, y, dir), carry, active, lane, u);
+        if (__ballot(edge_view))
+          observe_words<true>(LdsCheckedRows{table, my_codes, S, x, y, dir}, carry, active, lane, u);
         store_words<true>(stage, lane, u);
         wave_sync();
         copy_out<kWave, kCatBytes>(stage, o_obs + rec * kCatBytes, n_here, lane);
         wave_sync();
-      } else if (o_obs) {
+      } else if (kObs == 0 && o_obs) {
         // inactive lanes (S = 0, pose (1, 1)) read inside the guard margin
         uint32_t u[kObsWords + 1];
-        observe_words<false>(lds_rows(table, my_codes, S, x, y, dir, __ballot(edge_view) != 0), carry, active,
-                             lane & 31, u);
+        observe_words<false>(lds_rows(table, my_codes, S, x, y, dir), carry, active, lane & 31, u);
+        if (__ballot(edge_view))
+          observe_words<false>(LdsCheckedRows{table, my_codes, S, x, y, dir}, carry, active, lane & 31, u);
         // the stage holds 32 records: lanes 0-31, then lanes 32-63 (each half
         // starts and ends on a word boundary, so the halves are independent)
         uint8_t* dst = o_obs + rec * kObsBytes;
@@ -1803,20 +1811,19 @@ hipError_t launch_fused(const EnvTables& env, const TileTables& tiles, const Sta
                         const SlotConfig* host_slots) {
   FusedArgs a{env, tiles, st, actions, k_steps, out, row0, serve, host_tiles, host_slots};
   const size_t lds = fused_dynamic_lds_bytes(tiles.max_tile_cells);
-  const void* fn = serve ? reinterpret_cast<const void*>(&k_fused<false, true>)
-                 : actions ? reinterpret_cast<const void*>(&k_fused<true, false>)
-                           : reinterpret_cast<const void*>(&k_fused<false, false>);
+  // serving requests record symbolic first-person observations
+  const int obs = serve ? 0 : (env.obs_mode >= 2 ? 2 : env.obs_mode);
+  using Kernel = void (*)(FusedArgs);
+  static const Kernel kernels[2][3] = {
+      {&k_fused<false, false, 0>, &k_fused<false, false, 1>, &k_fused<false, false, 2>},
+      {&k_fused<true, false, 0>, &k_fused<true, false, 1>, &k_fused<true, false, 2>}};
+  const Kernel fn = serve ? &k_fused<false, true, 0> : kernels[actions ? 1 : 0][obs];
   if (lds > 65536) {
-    const hipError_t e =
-        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  if (serve)
-    hipLaunchKernelGGL((k_fused<false, true>), dim3(grid_blocks), dim3(kWave), lds, stream, a);
-  else if (actions)
-    hipLaunchKernelGGL((k_fused<true, false>), dim3(grid_blocks), dim3(kWave), lds, stream, a);
-  else
-    hipLaunchKernelGGL((k_fused<false, false>), dim3(grid_blocks), dim3(kWave), lds, stream, a);
+  hipLaunchKernelGGL(fn, dim3(grid_blocks), dim3(kWave), lds, stream, a);
   return hipGetLastError();
 }
 
