@@ -156,7 +156,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=0, help="CPU oracle sample steps (0: --steps)")
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests per serving load level (0: skip serving)")
-    ap.add_argument("--serve-K", type=int, default=128)
+    ap.add_argument("--serve-K", type=int, default=256)
     ap.add_argument("--serve-inflight", type=int, default=2, help="launches enqueued ahead of the device")
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95")
     ap.add_argument("--serve-budget-gib", type=int, default=64)
