@@ -83,9 +83,9 @@ def sampled_run(table, n_steps, K, sample, blocks=0):
     return cat(obs), cat(rew), cat(flg), cat(act), st
 
 
-def check_sample(table, n_steps, K, stride):
+def check_sample(table, n_steps, K, stride, blocks=0):
     sample = np.arange(0, table.n, stride)
-    obs, rew, flg, act, st = sampled_run(table, n_steps, K, sample)
+    obs, rew, flg, act, st = sampled_run(table, n_steps, K, sample, blocks)
     sub = table.subset(sample)
     b, s, _ = P.oracle_reset(sub)
     ref = ox.rollout(b, s, n_steps, None, nthreads=16)
@@ -108,11 +108,17 @@ def check_sample(table, n_steps, K, stride):
     assert (st["episode"] > 0).any()
 
 
-def test_tworoom8_fused_sampled():
-    """65536 two-room 8x8 layouts, 2048 steps, fused, random policy."""
-    check_sample(wl.workload_tworoom8(0), 2048, 64, stride=257)
+@pytest.mark.parametrize("K,blocks", [(1024, 1024), (64, 0)])
+def test_tworoom8_fused_sampled(K, blocks):
+    """65536 two-room 8x8 layouts, 2048 steps, fused, random policy, in the
+    shape the benchmark's tuner picks (K = 1024, one workgroup per tile) and
+    in short launches."""
+    check_sample(wl.workload_tworoom8(0), 2048, K, stride=257, blocks=blocks)
 
 
-def test_mixed_fused_sampled():
-    """262144 mixed-size envs, 4096 steps, fused persistent launches."""
-    check_sample(wl.workload_mixed(0), 4096, 64, stride=683)
+@pytest.mark.parametrize("K,blocks", [(1024, 2048), (64, 0)])
+def test_mixed_fused_sampled(K, blocks):
+    """262144 mixed-size envs, 4096 steps, fused persistent launches, in the
+    benchmark's shape (K = 1024, 2048 workgroups: two tiles each) and in
+    short launches."""
+    check_sample(wl.workload_mixed(0), 4096, K, stride=683, blocks=blocks)
