@@ -245,7 +245,7 @@ int env_rollout(gx_ctx* c, const gx_state* st, int32_t n_steps, const uint8_t* a
   if (rc != GX_OK) return rc;
   if ((rc = device_status()) != GX_OK) return rc;
   const int32_t k = K > 0 ? K : c->k_default;
-  const gx::TileTables tiles{c->n_tiles, c->max_tile_cells};
+  const gx::TileTables tiles{c->n_tiles, c->max_tile_cells, nullptr};   // every tile, in order
   for (int32_t s0 = 0; s0 < n_steps; s0 += k) {
     const int32_t ks = std::min(k, n_steps - s0);
     const uint8_t* act = actions ? actions + (size_t)s0 * (size_t)c->n : nullptr;
