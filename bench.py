@@ -9,8 +9,12 @@ an HBM trajectory ring.  One benchmark "step" is one environment step of
 the whole batch; the fused persistent kernel runs K of them per launch.
 
 Reported beside it on the same input: the plain one-launch-per-step
-kernel, per-launch latency percentiles, the dominant kernel's roofline
-position and the CPU oracle's rate on a bounded sample.
+kernel, per-launch latency percentiles, five repeats of the timed rollout,
+the dominant kernel's roofline position (with the HBM traffic of the
+committed rocprofv3 summary when it was taken of this kernel's code), the
+native serving loop at three offered loads, and the CPU oracle's rate on
+its whole job and on one thread.  --workload and --obs select the other
+task mixes and observation functions.
 """
 from __future__ import annotations
 
