@@ -54,7 +54,13 @@ def _cfg(family, side, max_steps, n=None, reward_mode=0, param=None, obs_mode=0)
     ([2], [8], [10], None, 0, None),          # FourRooms needs an odd side
     ([2], [5], [10], None, 0, None),          # FourRooms needs side >= 7
     ([0], [33], [10], None, 0, None),         # side <= 32
-    ([6], [8], [10], None, 0, None),          # unknown family
+    ([9], [8], [10], None, 0, None),          # unknown family
+    ([6], [8], [10], None, 0, None),          # Dynamic-Obstacles needs 1..8 balls
+    ([6], [5], [10], None, 0, [8]),           # ... and two free interior cells
+    ([7], [4], [10], None, 0, None),          # GoToDoor needs side >= 5
+    ([8], [8], [10], None, 0, [1]),           # KeyCorridor side is 3 s - 2
+    ([8], [10], [10], None, 0, [0]),          # KeyCorridor needs 1..3 rows
+    ([8], [10], [10], None, 0, [4]),
     ([3], [4], [10], None, 0, None),          # LavaGap needs side >= 5
     ([4], [9], [10], None, 0, None),          # Crossings needs N >= 1 (NULL param: 0)
     ([4], [10], [10], None, 0, [2]),          # Crossings needs an odd side
