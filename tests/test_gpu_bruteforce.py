@@ -1,7 +1,8 @@
 """Brute force on the GPU: every action sequence of length 6 from every
 5x5 start (single room and two-room key/door, with and without early
-truncation), each sequence one env, compared with the oracle step by step
-(plain kernel and fused kernel)."""
+truncation; and of length 5 or 6 from the 5x5 GoToDoor and one-ball
+Dynamic-Obstacles starts), each sequence one env, compared with the oracle
+step by step (plain kernel and fused kernel)."""
 import numpy as np
 import pytest
 
@@ -13,18 +14,23 @@ from paper_2407_19396_amd import workloads as wl
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("case", list(es.CASES))
+CASES = {k: v + (0,) for k, v in es.CASES.items()} | es.PARITY_CASES
+
+
+@pytest.mark.parametrize("case", list(CASES))
 @pytest.mark.parametrize("kernel", ["plain", "fused"])
 def test_bruteforce_parity(case, kernel):
     import torch
     from paper_2407_19396_amd import gridenv as ge
-    make, L, family, T = es.CASES[case]
+    make, L, family, T, param = CASES[case]
     starts = make()
     per_chunk = 16
     for c0 in range(0, len(starts), per_chunk):
-        cfg, st, actions = es.batch_arrays(starts[c0:c0 + per_chunk], L, family, T)
-        table = wl.EnvTable(cfg["family"], cfg["side"], cfg["max_steps"], cfg["seed"], cfg["rng_id"])
-        b = ox.Batch(cfg["family"], cfg["side"], cfg["max_steps"], cfg["seed"], cfg["rng_id"])
+        cfg, st, actions = es.batch_arrays(starts[c0:c0 + per_chunk], L, family, T, param=param)
+        table = wl.EnvTable(cfg["family"], cfg["side"], cfg["max_steps"], cfg["seed"], cfg["rng_id"], "",
+                            cfg.get("param"))
+        b = ox.Batch(cfg["family"], cfg["side"], cfg["max_steps"], cfg["seed"], cfg["rng_id"], 0,
+                     cfg.get("param"))
         s = ox.State(**{k: v.copy() for k, v in st.items()})
         ref = ox.rollout(b, s, L, actions, nthreads=16)
         env = ge.GridEnv(table)
