@@ -11,6 +11,12 @@ aside).
 
     python -m paper_2407_19396_amd.profiling --trace DIR --fetch DIR --write DIR
         [--sq DIR] --copy-bytes N --K K --envs N --command "..." -o profiles/x.txt
+
+``serving_summary`` reads the kernel trace of a serving run instead: how
+busy the device was between the first and the last serving launch, and the
+launches' durations and gaps.
+
+    python -m paper_2407_19396_amd.profiling --serving-trace DIR --command "..." -o profiles/y.txt
 """
 from __future__ import annotations
 
@@ -141,21 +147,64 @@ def traffic_bytes(profile_path: str, K: int, envs: int) -> float | None:
     return None
 
 
+def _is_serving_launch(name: str) -> bool:
+    # the serving variant of the fused kernel: template arguments <false, true, ...>
+    return FUSED in name and ("<false, true" in name or "ILb0ELb1E" in name)
+
+
+def serving_summary(trace: str, command: str) -> str:
+    """Device occupancy of a serving run from its --kernel-trace CSV."""
+    rows = list(csv.DictReader(open(_one(os.path.join(trace, "*kernel_trace.csv")))))
+    spans = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]) for r in rows)
+    serve = [(a, b) for a, b, n in spans if _is_serving_launch(n)]
+    if not serve:
+        raise ValueError("no serving launches in the trace")
+    t0, t1 = serve[0][0], max(b for _, b in serve)
+    dur = sorted((b - a) / 1e6 for a, b in serve)
+    gaps = sorted((serve[i + 1][0] - serve[i][1]) / 1e3 for i in range(len(serve) - 1)) or [0.0]
+    others = collections.defaultdict(float)
+    for a, b, n in spans:
+        if a >= t0 and b <= t1 and not _is_serving_launch(n):
+            others[n.split("(")[0][:60]] += (b - a) / 1e6
+    busy = sum(dur)
+    pct = lambda xs, q: xs[min(len(xs) - 1, int(q * (len(xs) - 1) + 0.5))]  # noqa: E731
+    lines = [
+        "# serving launches of k_fused (rocprofv3 --kernel-trace)",
+        "",
+        f"command: {command}",
+        f"kernel code sha256[:16] (kernels.hip + launch.h, comments aside): {kernel_source_hash()}",
+        "",
+        f"serving launches: {len(serve)}; span {(t1 - t0) / 1e6:.1f} ms; busy {busy:.1f} ms "
+        f"({100.0 * busy / ((t1 - t0) / 1e6):.1f} % of the span)",
+        f"launch duration ms: p50 {pct(dur, 0.5):.3f}, p99 {pct(dur, 0.99):.3f}, max {dur[-1]:.3f}",
+        f"gap between launches us: p50 {pct(gaps, 0.5):.1f}, max {gaps[-1]:.1f}",
+        "other kernels inside the span (ms): " +
+        (", ".join(f"{k} {v:.2f}" for k, v in sorted(others.items(), key=lambda kv: -kv[1])) or "none"),
+    ]
+    return "\n".join(lines) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--trace", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
+    ap.add_argument("--serving-trace", help="kernel trace directory of a serving run")
+    ap.add_argument("--trace")
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
     ap.add_argument("--sq", action="append", help="SQ counter run directory (repeatable)")
     ap.add_argument("--source", nargs="+", default=list(KERNEL_SOURCES),
                     help="kernel source and launch header the profiled build used")
-    ap.add_argument("--copy-bytes", type=int, required=True)
-    ap.add_argument("--K", type=int, required=True)
-    ap.add_argument("--envs", type=int, required=True)
+    ap.add_argument("--copy-bytes", type=int)
+    ap.add_argument("--K", type=int)
+    ap.add_argument("--envs", type=int)
     ap.add_argument("--command", required=True)
     ap.add_argument("-o", "--out", required=True)
     a = ap.parse_args()
-    text = summarize(a.trace, a.fetch, a.write, a.sq, a.copy_bytes, a.K, a.envs, a.command, a.source)
+    if a.serving_trace:
+        text = serving_summary(a.serving_trace, a.command)
+    else:
+        if not (a.trace and a.fetch and a.write and a.copy_bytes and a.K and a.envs):
+            ap.error("--trace, --fetch, --write, --copy-bytes, --K and --envs are needed")
+        text = summarize(a.trace, a.fetch, a.write, a.sq, a.copy_bytes, a.K, a.envs, a.command, a.source)
     with open(a.out, "w") as f:
         f.write(text)
     print(text)
