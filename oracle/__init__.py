@@ -29,6 +29,9 @@ FAMILY_LAVAGAP, FAMILY_CROSSINGS, FAMILY_DISTSHIFT, FAMILY_DYNOBS = 3, 4, 5, 6
 BALL, LAVA = 6, 9
 MAX_OBST = 8
 OBS_BYTES = 147
+SPRITE = 32                        # pixels per cell side in the rgb observations
+N_SPRITES = 11 * 6 * 4             # atlas entries: (type * 6 + colour) * 4 + state
+RGB_FP = (7 * SPRITE, 7 * SPRITE, 3)
 
 
 def build(force: bool = True) -> str:
@@ -51,7 +54,7 @@ class _Batch(ctypes.Structure):
                 ("max_steps", ctypes.c_void_p), ("seed", ctypes.c_void_p),
                 ("rng_id", ctypes.c_void_p), ("grid_off", ctypes.c_void_p),
                 ("reward_mode", ctypes.c_int32), ("param", ctypes.c_void_p),
-                ("obs_mode", ctypes.c_int32)]
+                ("obs_mode", ctypes.c_int32), ("sprites", ctypes.c_void_p)]
 
 
 STATE_FIELDS = ("grid", "x", "y", "dir", "t", "carry", "episode", "done_prev", "calls", "obst")
@@ -85,6 +88,10 @@ def lib():
         L.ox_observe_full.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P]
         L.ox_observe_full_categorical.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                   ctypes.c_int, P]
+        L.ox_render.argtypes = [P, ctypes.c_int, P, P]
+        L.ox_observe_rgb.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P]
+        L.ox_observe_rgb_full.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          P, P]
         L.ox_goal_reward.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int]
         L.ox_goal_reward.restype = ctypes.c_float
         L.ox_reset.argtypes = [ctypes.POINTER(_Batch), ctypes.POINTER(_State), P, P, P, P, P,
@@ -170,6 +177,43 @@ def observe_full_categorical(grid: np.ndarray, x: int, y: int, d: int) -> np.nda
     return obs
 
 
+def _atlas(sprites: np.ndarray) -> np.ndarray:
+    a = np.ascontiguousarray(sprites, dtype=np.uint8)
+    assert a.shape == (N_SPRITES, SPRITE, SPRITE, 3), a.shape
+    return a
+
+
+def render(cells: np.ndarray, sprites: np.ndarray) -> np.ndarray:
+    """Image [32W][32W][3] of W x W symbolic cells [W][W][3] drawn with the
+    atlas sprites [264][32][32][3]."""
+    c = np.ascontiguousarray(cells, dtype=np.uint8)
+    W = c.shape[0]
+    assert c.shape == (W, W, 3)
+    a = _atlas(sprites)
+    img = np.zeros((SPRITE * W, SPRITE * W, 3), dtype=np.uint8)
+    lib().ox_render(_ptr(c), W, _ptr(a), _ptr(img))
+    return img
+
+
+def observe_rgb(grid: np.ndarray, x: int, y: int, d: int, sprites: np.ndarray) -> np.ndarray:
+    """rgb_first_person image [224][224][3] of one env."""
+    g = np.ascontiguousarray(grid, dtype=np.uint8)
+    a = _atlas(sprites)
+    img = np.zeros(RGB_FP, dtype=np.uint8)
+    lib().ox_observe_rgb(_ptr(g), g.shape[0], x, y, d, _ptr(a), _ptr(img))
+    return img
+
+
+def observe_rgb_full(grid: np.ndarray, x: int, y: int, d: int, sprites: np.ndarray) -> np.ndarray:
+    """rgb image [32S][32S][3] of one env's whole grid."""
+    g = np.ascontiguousarray(grid, dtype=np.uint8)
+    S = g.shape[0]
+    a = _atlas(sprites)
+    img = np.zeros((SPRITE * S, SPRITE * S, 3), dtype=np.uint8)
+    lib().ox_observe_rgb_full(_ptr(g), S, x, y, d, _ptr(a), _ptr(img))
+    return img
+
+
 def goal_reward(t: int, T: int, reward_mode: int = 0) -> float:
     return float(np.float32(lib().ox_goal_reward(t, T, reward_mode)))
 
@@ -189,7 +233,9 @@ class Batch:
     reward_mode: int = 0
     param: np.ndarray | None = None   # u8[N] family parameter (Crossings N, DistShift k)
     obs_mode: int = 0                 # 0 symbolic_first_person [7][7][3], 1 categorical_first_person
-                                      # [7][7], 2 symbolic [S][S][3], 3 categorical [S][S]
+                                      # [7][7], 2 symbolic [S][S][3], 3 categorical [S][S],
+                                      # 4 rgb_first_person [224][224][3], 5 rgb [32S][32S][3]
+    sprites: np.ndarray | None = None  # modes 4 and 5: the atlas u8[264][32][32][3]
 
     @property
     def n(self) -> int:
@@ -211,15 +257,20 @@ class Batch:
 
 
 def obs_row_bytes(obs_mode: int, n: int, grid_bytes: int) -> int:
-    """First-person rows hold n records of 147 or 49 bytes; whole-grid rows
-    are packed like the grids: sum 3 S^2 (symbolic) or sum S^2 bytes."""
-    return {0: 147 * n, 1: 49 * n, 2: grid_bytes, 3: grid_bytes // 3}[obs_mode]
+    """First-person rows hold n records of 147, 49 or 150528 bytes; whole-grid
+    rows are packed like the grids: sum 3 S^2 (symbolic), sum S^2
+    (categorical) or sum 3072 S^2 bytes (rgb)."""
+    return {0: 147 * n, 1: 49 * n, 2: grid_bytes, 3: grid_bytes // 3, 4: 147 * 1024 * n,
+            5: 1024 * grid_bytes}[obs_mode]
 
 
 def full_record(row: np.ndarray, obs_mode: int, grid_off: int, S: int) -> np.ndarray:
-    """One env's whole-grid record inside an output row (modes 2 and 3)."""
+    """One env's whole-grid record inside an output row (modes 2, 3 and 5)."""
     if obs_mode == 2:
         return row[grid_off:grid_off + 3 * S * S].reshape(S, S, 3)
+    if obs_mode == 5:
+        o = 1024 * grid_off
+        return row[o:o + 3072 * S * S].reshape(SPRITE * S, SPRITE * S, 3)
     o = grid_off // 3
     return row[o:o + S * S].reshape(S, S)
 
@@ -263,9 +314,11 @@ def _cbatch(b: Batch, keep: list):
             np.ascontiguousarray(b.rng_id, dtype=np.uint32),
             b.grid_offsets()]
     param = None if b.param is None else np.ascontiguousarray(b.param, dtype=np.uint8)
-    keep.extend(arrs + [param])
+    sprites = None if b.sprites is None else _atlas(b.sprites)
+    keep.extend(arrs + [param, sprites])
     return _Batch(b.n, *[a.ctypes.data for a in arrs], b.reward_mode,
-                  None if param is None else param.ctypes.data, b.obs_mode)
+                  None if param is None else param.ctypes.data, b.obs_mode,
+                  None if sprites is None else sprites.ctypes.data)
 
 
 def _cstate(s: State):
@@ -277,7 +330,8 @@ def _cstate(s: State):
 
 @dataclass
 class Outputs:
-    obs: np.ndarray | None   # u8[rows][N][7][7][3], [rows][N][7][7] or [rows][row bytes]
+    obs: np.ndarray | None   # u8[rows][N][7][7][3], [rows][N][7][7], [rows][N][224][224][3]
+                             # or [rows][row bytes] (whole-grid modes)
     reward: np.ndarray       # f32[rows][N]
     flags: np.ndarray        # u8[rows][N]
     action: np.ndarray       # u8[rows][N]
@@ -287,7 +341,8 @@ class Outputs:
     def empty(rows: int, n: int, with_obs: bool = True, obs_mode: int = 0,
               row_bytes: int = 0) -> "Outputs":
         """row_bytes: bytes of one observation row in the whole-grid modes."""
-        shape = {0: (rows, n, 7, 7, 3), 1: (rows, n, 7, 7)}.get(obs_mode, (rows, row_bytes))
+        shape = {0: (rows, n, 7, 7, 3), 1: (rows, n, 7, 7),
+                 4: (rows, n) + RGB_FP}.get(obs_mode, (rows, row_bytes))
         return Outputs(np.zeros(shape, dtype=np.uint8) if with_obs else None,
                        np.zeros((rows, n), dtype=np.float32),
                        np.zeros((rows, n), dtype=np.uint8),

@@ -612,16 +612,79 @@ void ox_observe_full_categorical(const uint8_t *grid, int S, int ax, int ay, int
       obs[y * S + x] = (x == ax && y == ay) ? (uint8_t)O_AGENT : grid[3 * (y * S + x)];
 }
 
+/* ------------------------------------------------------------------ */
+/* rgb and rgb_first_person (Table "observations": images of 32 pixels */
+/* per cell side, [32H][32W][3] of the whole grid and [32R][32R][3] of */
+/* the first-person view).  Every entity carries a sprite, a          */
+/* u8[32][32][3] image (Table "components": HasSprite); the sprites are */
+/* data, an atlas of 264 images indexed (type * 6 + colour) * 4 +      */
+/* state for type 0..10, colour 0..5, state 0..3 (a door's state, the  */
+/* agent's heading).  A cell is drawn as the sprite of its symbolic     */
+/* triple; a triple outside those ranges draws sprite 0, the unseen     */
+/* cell's.  The image of W x W cells is [32W][32W][3]: pixel row        */
+/* 32 j + py, column 32 i + px holds pixel (py, px) of cell (i, j)'s    */
+/* sprite.  rgb draws the symbolic whole grid (the agent over its cell */
+/* with its heading); rgb_first_person draws the first-person view      */
+/* with the agent's own cell as the agent facing the top of the image  */
+/* (heading 3, north), the carried object not drawn.                   */
+/* Pinned by decoding: under an atlas whose pixels spell out their      */
+/* sprite index and position, every pixel names its cell's triple in   */
+/* the independently pinned symbolic views.  Agreement with NAVIX's or  */
+/* MiniGrid's drawings: parity unpinned (their sprites are not here).   */
+/* ------------------------------------------------------------------ */
+#define OX_SPRITE 32
+#define OX_SPRITE_BYTES (OX_SPRITE * OX_SPRITE * 3)
+
+static int sprite_index(const uint8_t *triple) {
+  if (triple[0] > O_AGENT || triple[1] > C_GREY || triple[2] > 3) return 0;
+  return (triple[0] * 6 + triple[1]) * 4 + triple[2];
+}
+
+/* Draw W x W cells (symbolic triples, [W][W][3]) into img [32W][32W][3]. */
+void ox_render(const uint8_t *cells, int W, const uint8_t *sprites, uint8_t *img) {
+  const size_t row_pixels = (size_t)OX_SPRITE * (size_t)W;
+  for (int j = 0; j < W; ++j)
+    for (int i = 0; i < W; ++i) {
+      const uint8_t *sp = sprites + (size_t)sprite_index(cells + 3 * (j * W + i)) * OX_SPRITE_BYTES;
+      for (int py = 0; py < OX_SPRITE; ++py)
+        for (int px = 0; px < OX_SPRITE; ++px)
+          for (int ch = 0; ch < 3; ++ch) {
+            size_t row = (size_t)(OX_SPRITE * j + py), col = (size_t)(OX_SPRITE * i + px);
+            img[(row * row_pixels + col) * 3 + ch] = sp[(py * OX_SPRITE + px) * 3 + ch];
+          }
+    }
+}
+
+void ox_observe_rgb(const uint8_t *grid, int S, int ax, int ay, int dir,
+                    const uint8_t *sprites, uint8_t *img /* [224][224][3] */) {
+  uint8_t view[OX_VIEW * OX_VIEW * 3];
+  ox_observe(grid, S, ax, ay, dir, O_EMPTY, view);
+  uint8_t *agent = view + 3 * ((OX_VIEW - 1) * OX_VIEW + 3);
+  agent[0] = O_AGENT; agent[1] = C_RED; agent[2] = 3;
+  ox_render(view, OX_VIEW, sprites, img);
+}
+
+void ox_observe_rgb_full(const uint8_t *grid, int S, int ax, int ay, int dir,
+                         const uint8_t *sprites, uint8_t *img /* [32S][32S][3] */) {
+  uint8_t whole[32 * 32 * 3];
+  if (S > 32) return;
+  ox_observe_full(grid, S, ax, ay, dir, whole);
+  ox_render(whole, S, sprites, img);
+}
+
 /* Observation modes: 0 symbolic_first_person, 1 categorical_first_person, */
-/* 2 symbolic, 3 categorical.  The first-person records of one output row  */
-/* are [N][147] or [N][49]; the whole-grid records are packed like the     */
-/* grids, env i's at grid_off(i) (symbolic) or grid_off(i) / 3             */
-/* (categorical) of a row of sum 3 S^2 or sum S^2 bytes.                   */
-static void emit_obs(int mode, const uint8_t *grid, int S, int ax, int ay, int dir,
-                     int32_t carry, uint8_t *obs) {
+/* 2 symbolic, 3 categorical, 4 rgb_first_person, 5 rgb.  The first-person */
+/* records of one output row are [N][147], [N][49] or [N][224][224][3];    */
+/* the whole-grid records are packed like the grids, env i's at            */
+/* grid_off(i) (symbolic), grid_off(i) / 3 (categorical) or 1024           */
+/* grid_off(i) (rgb) of a row of sum 3 S^2, sum S^2 or sum 3072 S^2 bytes. */
+static void emit_obs(int mode, const uint8_t *sprites, const uint8_t *grid, int S, int ax,
+                     int ay, int dir, int32_t carry, uint8_t *obs) {
   if (mode == 1) ox_observe_categorical(grid, S, ax, ay, dir, carry, obs);
   else if (mode == 2) ox_observe_full(grid, S, ax, ay, dir, obs);
   else if (mode == 3) ox_observe_full_categorical(grid, S, ax, ay, dir, obs);
+  else if (mode == 4) ox_observe_rgb(grid, S, ax, ay, dir, sprites, obs);
+  else if (mode == 5) ox_observe_rgb_full(grid, S, ax, ay, dir, sprites, obs);
   else ox_observe(grid, S, ax, ay, dir, carry, obs);
 }
 
@@ -717,7 +780,8 @@ static void move_obstacles(uint8_t *grid, int S, int n, int ax, int ay,
 /* MiniGrid's version does.                                            */
 /* ------------------------------------------------------------------ */
 static void step_one(int family, int S, int param, int32_t T, uint64_t seed,
-                     uint32_t rng_id, int reward_mode, int obs_mode, ox_env_ref e,
+                     uint32_t rng_id, int reward_mode, int obs_mode,
+                     const uint8_t *sprites, ox_env_ref e,
                      uint32_t action, uint8_t *obs, float *reward,
                      uint8_t *flags, uint8_t *rec_action) {
   if (*e.done_prev) {
@@ -727,7 +791,7 @@ static void step_one(int family, int S, int param, int32_t T, uint64_t seed,
     *e.t = 0;
     *e.carry = O_EMPTY;
     *e.done_prev = 0;
-    if (obs) emit_obs(obs_mode, e.grid, S, *e.x, *e.y, *e.dir, *e.carry, obs);
+    if (obs) emit_obs(obs_mode, sprites, e.grid, S, *e.x, *e.y, *e.dir, *e.carry, obs);
     *reward = 0.0f;
     *flags = OX_FLAG_FIRST;
     *rec_action = OX_ACTION_NONE;
@@ -794,7 +858,7 @@ static void step_one(int family, int S, int param, int32_t T, uint64_t seed,
                      (truncated ? OX_FLAG_TRUNCATED : 0));
   *rec_action = (uint8_t)action;
   *e.done_prev = (uint8_t)(terminated || truncated);
-  if (obs) emit_obs(obs_mode, e.grid, S, *e.x, *e.y, *e.dir, *e.carry, obs);
+  if (obs) emit_obs(obs_mode, sprites, e.grid, S, *e.x, *e.y, *e.dir, *e.carry, obs);
 }
 
 /* ------------------------------------------------------------------ */
@@ -816,7 +880,8 @@ typedef struct {
   int32_t reward_mode;
   const uint8_t *param;   /* per env family parameter, or NULL (all 0) */
   int32_t obs_mode;       /* 0 symbolic_first_person, 1 categorical_first_person,
-                             2 symbolic, 3 categorical */
+                             2 symbolic, 3 categorical, 4 rgb_first_person, 5 rgb */
+  const uint8_t *sprites; /* modes 4 and 5: the atlas [264][32][32][3] */
 } ox_batch;
 
 typedef struct {
@@ -833,9 +898,10 @@ typedef struct {
 /* bytes of one output row of observations */
 static size_t obs_row_bytes(const ox_batch *b) {
   if (b->obs_mode == 0 || b->obs_mode == 1) return (size_t)b->n * (b->obs_mode == 1 ? 49 : 147);
+  if (b->obs_mode == 4) return (size_t)b->n * 147 * 1024;
   size_t cells = 0;
   for (int i = 0; i < b->n; ++i) cells += (size_t)b->side[i] * b->side[i];
-  return b->obs_mode == 2 ? 3 * cells : cells;
+  return b->obs_mode == 2 ? 3 * cells : b->obs_mode == 5 ? 3072 * cells : cells;
 }
 
 /* env i's record in output row `row` */
@@ -845,6 +911,8 @@ static uint8_t *obs_at(const ox_batch *b, uint8_t *obs, size_t row_bytes, size_t
     case 1: return r + (size_t)49 * i;
     case 2: return r + b->grid_off[i];
     case 3: return r + b->grid_off[i] / 3;
+    case 4: return r + (size_t)147 * 1024 * i;
+    case 5: return r + (size_t)1024 * b->grid_off[i];
     default: return r + (size_t)147 * i;
   }
 }
@@ -880,6 +948,7 @@ int ox_reset(const ox_batch *b, const ox_state *s, uint8_t *obs, float *reward,
              uint8_t *flags, uint8_t *action, uint8_t *mission, int nthreads) {
   for (int i = 0; i < b->n; ++i)
     if (!ox_side_ok(b->family[i], b->side[i], PARAM(b, i))) return -1;
+  if (obs && b->obs_mode >= 4 && !b->sprites) return -1;
   set_threads(nthreads);
   const size_t row_bytes = obs_row_bytes(b);
 #pragma omp parallel for schedule(dynamic, 64) if (nthreads > 0)
@@ -893,7 +962,7 @@ int ox_reset(const ox_batch *b, const ox_state *s, uint8_t *obs, float *reward,
     *e.done_prev = 0;
     *e.calls = 0;
     if (obs)
-      emit_obs(b->obs_mode, e.grid, b->side[i], *e.x, *e.y, *e.dir, *e.carry,
+      emit_obs(b->obs_mode, b->sprites, e.grid, b->side[i], *e.x, *e.y, *e.dir, *e.carry,
                obs_at(b, obs, row_bytes, 0, i));
     if (reward) reward[i] = 0.0f;
     if (flags) flags[i] = OX_FLAG_FIRST;
@@ -910,7 +979,7 @@ int ox_rollout(const ox_batch *b, const ox_state *s, int32_t n_steps,
                const uint8_t *actions, int32_t rows, uint8_t *obs,
                float *reward, uint8_t *flags, uint8_t *action, uint8_t *mission,
                int nthreads) {
-  if (rows <= 0) return -1;
+  if (rows <= 0 || (obs && b->obs_mode >= 4 && !b->sprites)) return -1;
   set_threads(nthreads);
   const size_t N = (size_t)b->n;
   const size_t row_bytes = obs_row_bytes(b);
@@ -923,7 +992,7 @@ int ox_rollout(const ox_batch *b, const ox_state *s, int32_t n_steps,
       if (actions) a = actions[(size_t)k * N + i];
       else a = ox_policy_action(b->seed[i], b->rng_id[i], *e.calls);
       step_one(b->family[i], b->side[i], PARAM(b, i), b->max_steps[i],
-               b->seed[i], b->rng_id[i], b->reward_mode, b->obs_mode, e, a,
+               b->seed[i], b->rng_id[i], b->reward_mode, b->obs_mode, b->sprites, e, a,
                obs ? obs_at(b, obs, row_bytes, row, i) : NULL,
                reward + row * N + i,
                flags + row * N + i, action + row * N + i);
