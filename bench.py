@@ -36,18 +36,18 @@ STATE_BYTES_PER_ENV = 4 * 5 + 4 + 1 + 4 + 16  # x, y, dir, t, carry + episode + 
 
 
 WORKLOADS = {
-    "mixed": "mixed uneven sizes: 262144 envs (40% Empty S in {5,6,8,16}, 40% TwoRoom key/door "
+    "mixed": "mixed uneven sizes: {n} envs (40% Empty S in {5,6,8,16}, 40% TwoRoom key/door "
              "S in {5,6,8,16}, 20% FourRooms 19x19), random policy on device, trajectory ring in HBM",
     "tworoom8": "65536 TwoRoom key/door 8x8, T=640, random policy on device, trajectory ring in HBM",
     "empty8": "4096 Empty 8x8, T=256, random policy on device, trajectory ring in HBM",
     "empty5": "16 Empty 5x5, T=100, random policy on device, trajectory ring in HBM",
-    "lava": "lava tasks: 262144 envs in equal shares of LavaGap S5/S6/S7, Crossings S9N1/S9N2/S9N3/"
+    "lava": "lava tasks: {n} envs in equal shares of LavaGap S5/S6/S7, Crossings S9N1/S9N2/S9N3/"
             "S11N5, DistShift1 (6x6), DistShift2 (8x8), random policy on device, trajectory ring in HBM",
-    "dynobs": "Dynamic-Obstacles tasks: 262144 envs in equal shares of 5x5 (2 balls), 6x6 (3), 8x8 (4), "
+    "dynobs": "Dynamic-Obstacles tasks: {n} envs in equal shares of 5x5 (2 balls), 6x6 (3), 8x8 (4), "
               "16x16 (8), random policy on device, trajectory ring in HBM",
-    "gotodoor": "GoToDoor tasks: 262144 envs in equal shares of 5x5, 6x6, 8x8, random policy on device, "
+    "gotodoor": "GoToDoor tasks: {n} envs in equal shares of 5x5, 6x6, 8x8, random policy on device, "
                 "trajectory ring in HBM",
-    "keycorridor": "KeyCorridor tasks: 262144 envs in equal shares of S3R1, S3R2, S3R3, S4R3, S5R3, S6R3, "
+    "keycorridor": "KeyCorridor tasks: {n} envs in equal shares of S3R1, S3R2, S3R3, S4R3, S5R3, S6R3, "
                    "random policy on device, trajectory ring in HBM",
 }
 
@@ -56,7 +56,9 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-OBS_MODES = {"symbolic": 0, "categorical": 1, "symbolic_grid": 2, "categorical_grid": 3}
+OBS_MODES = {"symbolic": 0, "categorical": 1, "symbolic_grid": 2, "categorical_grid": 3,
+             "rgb_first_person": 4, "rgb": 5}
+RGB_SCALE = 1024   # rgb bytes per symbolic byte (32 x 32 pixels per cell)
 RING_BUDGET = 64 << 30   # bytes of HBM the trajectory ring of one launch may take
 
 
@@ -67,29 +69,39 @@ def fused_bytes(n_envs: int, grid_bytes: int, k: int, obs_bytes: int = OBS) -> f
     return n_envs * k * record + 2.0 * (grid_bytes + STATE_BYTES_PER_ENV * n_envs)
 
 
-def cpu_baseline(table, n_envs: int, n_steps: int) -> dict:
+def rgb_path_bytes(n_envs: int, grid_bytes: int, k: int, sym_bytes: float) -> float:
+    """Algorithmic HBM bytes of one chunk of the rgb path: the fused launch
+    with its symbolic records staged, then the renderer reading them (with
+    the 7 scalar bytes) and writing the images (and the scalars)."""
+    render = n_envs * k * (sym_bytes + 7 + RGB_SCALE * sym_bytes + 7)
+    return fused_bytes(n_envs, grid_bytes, k, sym_bytes) + render
+
+
+def cpu_baseline(table, n_envs: int, n_steps: int, obs_mode: int = 0, sprites=None) -> dict:
     import oracle as ox
-    from paper_2407_19396_amd import workloads as wl
     sub = table.subset(np.arange(n_envs))
-    b = ox.Batch(sub.family, sub.side, sub.max_steps, sub.seed, sub.rng_id, 0, sub.param)
+    b = ox.Batch(sub.family, sub.side, sub.max_steps, sub.seed, sub.rng_id, 0, sub.param, obs_mode,
+                 sprites)
     s = ox.State.empty(b)
     threads = os.cpu_count() or 1
     try:
         threads = len(os.sched_getaffinity(0))
     except AttributeError:
         pass
+    rows = 1 if obs_mode >= 4 else 16   # rgb records are 1024 times larger
     ox.reset(b, s, nthreads=threads)
     t0 = time.perf_counter()
-    ox.rollout(b, s, n_steps, None, rows=16, nthreads=threads)
+    ox.rollout(b, s, n_steps, None, rows=rows, nthreads=threads)
     dt = time.perf_counter() - t0
     # the same oracle on one thread, over 1 / threads of the envs
     n1 = max(1, n_envs // threads)
     sub1 = table.subset(np.arange(n1))
-    b1 = ox.Batch(sub1.family, sub1.side, sub1.max_steps, sub1.seed, sub1.rng_id, 0, sub1.param)
+    b1 = ox.Batch(sub1.family, sub1.side, sub1.max_steps, sub1.seed, sub1.rng_id, 0, sub1.param, obs_mode,
+                  sprites)
     s1 = ox.State.empty(b1)
     ox.reset(b1, s1)
     t1 = time.perf_counter()
-    ox.rollout(b1, s1, n_steps, None, rows=16)
+    ox.rollout(b1, s1, n_steps, None, rows=rows)
     dt1 = time.perf_counter() - t1
     return {"value": n_envs * n_steps / dt, "unit": "env-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n_envs} envs of the same mix, {n_steps} steps, random policy, "
@@ -150,7 +162,9 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=512)
     ap.add_argument("--obs", default="symbolic", choices=list(OBS_MODES),
                     help="observation function: symbolic (147 B) or categorical (49 B) first person, "
-                         "or the whole grid: symbolic_grid (3 S^2 B) or categorical_grid (S^2 B)")
+                         "the whole grid: symbolic_grid (3 S^2 B) or categorical_grid (S^2 B), or "
+                         "images drawn with the default sprites: rgb_first_person (150528 B) or rgb "
+                         "(3072 S^2 B); the rgb modes default to 16384 envs and K = 16")
     ap.add_argument("--graph", action="store_true",
                     help="capture the timed rollout in a HIP graph and time its replay")
     ap.add_argument("--plain-actions", action="store_true",
@@ -194,17 +208,27 @@ def main():
             "dynobs": lambda: wl.workload_dynobs(seed=0, n=args.envs or 262144),
             "gotodoor": lambda: wl.workload_gotodoor(seed=0, n=args.envs or 262144),
             "keycorridor": lambda: wl.workload_keycorridor(seed=0, n=args.envs or 262144)}[args.workload]
+    obs_mode = OBS_MODES[args.obs]
+    rgb = obs_mode >= 4
+    if rgb and not args.envs:
+        args.envs = 16384          # a step writes 2.5 GB of first-person images at this size
     table = make()
     if args.envs and args.workload not in ("mixed", "lava", "dynobs", "gotodoor", "keycorridor"):
         table = table.subset(np.arange(args.envs) % table.n)
-    obs_mode = OBS_MODES[args.obs]
-    env = ge.GridEnv(table, obs_mode=obs_mode)
+    sprites = None
+    if rgb:
+        from paper_2407_19396_amd.sprites import default_atlas
+        sprites = default_atlas()
+    env = ge.GridEnv(table, obs_mode=obs_mode, sprites=sprites)
     # observation bytes per env-step (the mean record size in the whole-grid modes)
     obs_bytes = env.info()["obs_row_bytes"] / table.n
     first = env.traj(1)
     stream = torch.cuda.current_stream()
     tuned = None
-    if args.K or args.blocks or args.no_tune:
+    if rgb:
+        # launches of K steps, each drawn by the renderer right after
+        env.set_launch(args.K or 16, args.blocks)
+    elif args.K or args.blocks or args.no_tune:
         env.set_launch(args.K or env.info()["k_default"], args.blocks)
     else:
         from paper_2407_19396_amd import autotune
@@ -311,7 +335,10 @@ def main():
             f"{np.percentile(plain_lat, 50) * 1e3:.1f} us")
 
     per_launch_ms = ms / launches
-    bytes_launch = fused_bytes(table.n, info["grid_bytes"], K, obs_bytes)
+    if rgb:
+        bytes_launch = rgb_path_bytes(table.n, info["grid_bytes"], K, obs_bytes / RGB_SCALE)
+    else:
+        bytes_launch = fused_bytes(table.n, info["grid_bytes"], K, obs_bytes)
     achieved = bytes_launch / (per_launch_ms / 1e3) / 1e9
     from paper_2407_19396_amd import profiling
     traffic = None
@@ -328,7 +355,11 @@ def main():
     cpu = None
     if not args.no_cpu:
         log("[bench] timing the CPU oracle on a sample")
-        cpu = cpu_baseline(table, min(args.cpu_envs or table.n, table.n), args.cpu_steps or args.steps)
+        if rgb:   # the oracle draws every pixel: a smaller sample
+            cpu = cpu_baseline(table, min(args.cpu_envs or 1024, table.n), args.cpu_steps or 128,
+                               obs_mode, sprites)
+        else:
+            cpu = cpu_baseline(table, min(args.cpu_envs or table.n, table.n), args.cpu_steps or args.steps)
         log(f"[bench] cpu oracle: {cpu['value'] / 1e6:.2f} M env-steps/s on {cpu['cores']} threads")
 
     out = {
@@ -344,7 +375,7 @@ def main():
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload],
+        "config": {"workload": WORKLOADS[args.workload].format(n=table.n),
                    "n_envs": table.n, "K": K, "ring_rows": ring, "blocks": info["blocks"],
                    "lds_bytes_per_wg": info["lds_bytes"], "global_batch": table.n,
                    "autotuned": tuned is not None, "hip_graph": graph is not None,
@@ -359,7 +390,7 @@ def main():
             "fused_over_plain": value / plain_rate},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_fused", "bytes_per_launch": bytes_launch,
+                     "kernel": "k_fused + k_render" if rgb else "k_fused", "bytes_per_launch": bytes_launch,
                      "launch_ms": per_launch_ms},
         "serving": serving,
         "cpu_baseline": cpu,

@@ -83,6 +83,14 @@
  *       its cell as (10, 0, heading) (MiniGrid's fully observed encoding;
  *       the carried object is not shown);
  *     3 categorical: the type channel of 2, [S_i][S_i] at grid_off(i) / 3;
+ *     4 rgb_first_person: [n_envs][224][224][3], the view of mode 0 drawn
+ *       with 32 x 32 sprites: pixel row 32 j + py, column 32 i + px is
+ *       pixel (py, px) of view cell (i, j)'s sprite; the agent's own cell
+ *       (3, 6) is drawn as the agent facing the image's top, the sprite of
+ *       (10, 0, 3) (the carried object is not drawn);
+ *     5 rgb: env i's whole grid of mode 2 drawn the same way,
+ *       [32 S_i][32 S_i][3] at byte 1024 * grid_off(i) of the row;
+ *     rows of modes 4 and 5 must start 16-byte aligned;
  *   reward: float [rows][n_envs]; flags, action: bytes [rows][n_envs]
  *     (action is the action applied, 0xFF on reset steps);
  *   mission: bytes [rows][n_envs] or NULL: the mission of the step's
@@ -136,6 +144,9 @@ extern "C" {
 
 #define GX_OBS_BYTES 147      /* symbolic first-person record */
 #define GX_OBS_CAT_BYTES 49   /* categorical first-person record */
+#define GX_OBS_RGB_BYTES 150528 /* rgb first-person record, 224 * 224 * 3 */
+#define GX_SPRITES 264          /* sprites in the atlas of the rgb modes */
+#define GX_SPRITE_BYTES 3072    /* one sprite, [32][32][3] */
 
 typedef struct gx_ctx gx_ctx;
 
@@ -152,7 +163,9 @@ typedef struct {
                                   records [7][7] of type ids (49 bytes), the
                                   same view and occlusion; 2 symbolic, the
                                   whole grid [S][S][3]; 3 categorical, the
-                                  whole grid's type ids [S][S] */
+                                  whole grid's type ids [S][S]; 4
+                                  rgb_first_person, records [224][224][3];
+                                  5 rgb, the whole grid [32S][32S][3] */
   const uint8_t* family;       /* [n_envs] GX_FAMILY_* */
   const uint8_t* side;         /* [n_envs] grid side S (height = width) */
   const uint8_t* param;        /* [n_envs] family parameter, or NULL: all 0 */
@@ -160,6 +173,16 @@ typedef struct {
   const uint64_t* seed;        /* [n_envs] RNG key per env, or NULL: seed_all */
   uint64_t seed_all;
   const uint32_t* rng_id;      /* [n_envs] RNG stream id per env, or NULL: i */
+  const uint8_t* sprites;      /* obs_mode 4 and 5 (required there, else
+                                  ignored): the sprite atlas, host bytes
+                                  [264][32][32][3] copied during env_create.
+                                  Every entity is drawn with the sprite of its
+                                  symbolic triple (Table "components":
+                                  HasSprite), sprite (type * 6 + colour) * 4 +
+                                  state for type 0..10, colour 0..5, state
+                                  0..3 (a door's state, the agent's heading);
+                                  any other triple draws sprite 0, the unseen
+                                  cell's */
 } gx_config;
 
 /* Caller-owned device state (layout above). */
@@ -196,8 +219,12 @@ typedef struct {
 
 /* Validate a batch description (families and sides of Table "envs"),
  * build the per-env tables (grid offsets, RNG keys) and the tiling of the
- * fused kernel, and upload them to the current device.  *out receives the
- * context, or NULL on failure. */
+ * fused kernel, and upload them to the current device.  In the rgb modes
+ * the context also holds the sprite atlas and a staging ring of at most 64
+ * rows of symbolic records (within 256 MiB, at least one row) that the
+ * step kernels fill and the renderer draws; env_rollout then launches the
+ * fused kernel for at most that many steps at a time, each launch followed
+ * by the renderer's.  *out receives the context, or NULL on failure. */
 int env_create(const gx_config* cfg, gx_ctx** out);
 
 /* Bytes of the grid buffer and number of envs of a context. */

@@ -12,6 +12,7 @@
 
 #include "../../include/gridenv.h"
 #include "launch.h"
+#include "render.h"
 
 struct gx_ctx {
   int device = 0;
@@ -31,6 +32,13 @@ struct gx_ctx {
   int32_t max_tile_cells = 0;
   int32_t blocks = 0;
   int32_t k_default = 64;
+  // rgb modes: the sprite atlas, and the staging ring of symbolic records
+  // (obs [stage_rows][sym_row], then reward, flags, action, mission
+  // [stage_rows][n]) that the step kernels fill and the renderer expands
+  uint8_t* d_sprites = nullptr;
+  uint8_t* d_stage = nullptr;
+  int32_t stage_rows = 0;
+  int32_t render_blocks = 0;
 };
 
 namespace {
@@ -57,6 +65,10 @@ void free_tables(gx_ctx* c) {
   (void)hipFree(c->d_seed);
   (void)hipFree(c->d_rng_id);
   (void)hipFree(c->d_grid_off);
+  (void)hipFree(c->d_sprites);
+  (void)hipFree(c->d_stage);
+  c->d_sprites = nullptr;
+  c->d_stage = nullptr;
   c->d_meta = nullptr;
   c->d_max_steps = nullptr;
   c->d_seed = nullptr;
@@ -70,9 +82,17 @@ bool state_ok(const gx_state* st) {
          (reinterpret_cast<uintptr_t>(st->obst) & 15) == 0;
 }
 
-// bytes of one output row of observations
-uint64_t obs_row_bytes(const gx_ctx* c) {
-  switch (c->obs_mode) {
+bool rgb_mode(const gx_ctx* c) { return c->obs_mode >= 4; }
+
+// the observation function the step kernels compute: the rgb modes draw
+// the symbolic records of the same view (4: first person, 5: whole grid)
+int32_t step_obs_mode(const gx_ctx* c) {
+  return c->obs_mode == 4 ? 0 : c->obs_mode == 5 ? 2 : c->obs_mode;
+}
+
+// bytes of one row of the step kernels' observation records
+uint64_t sym_row_bytes(const gx_ctx* c) {
+  switch (step_obs_mode(c)) {
     case 1: return (uint64_t)c->n * GX_OBS_CAT_BYTES;
     case 2: return c->grid_bytes;
     case 3: return c->grid_bytes / 3;
@@ -80,13 +100,28 @@ uint64_t obs_row_bytes(const gx_ctx* c) {
   }
 }
 
-bool traj_ok(const gx_traj* tr) {
-  return tr && tr->reward && tr->flags && tr->action && tr->rows >= 1;
+// bytes of one output row of observations
+uint64_t obs_row_bytes(const gx_ctx* c) {
+  return rgb_mode(c) ? sym_row_bytes(c) * (uint64_t)gx::kRgbScale : sym_row_bytes(c);
+}
+
+uint64_t align256(uint64_t v) { return (v + 255) & ~(uint64_t)255; }
+
+// staging ring layout: obs rows, then reward, flags, action, mission rows
+uint64_t stage_bytes(const gx_ctx* c, int32_t rows) {
+  const uint64_t n = (uint64_t)c->n;
+  return align256(rows * sym_row_bytes(c)) + align256(rows * n * 4) + 3 * align256(rows * n);
+}
+
+bool traj_ok(const gx_ctx* c, const gx_traj* tr) {
+  if (!tr || !tr->reward || !tr->flags || !tr->action || tr->rows < 1) return false;
+  // rgb records are written with 16-byte stores
+  return !(rgb_mode(c) && tr->obs && (reinterpret_cast<uintptr_t>(tr->obs) & 15) != 0);
 }
 
 gx::EnvTables tables_of(const gx_ctx* c) {
   return gx::EnvTables{c->n, c->d_meta, c->d_max_steps, c->d_seed, c->d_rng_id, c->d_grid_off,
-                       c->reward_mode, c->obs_mode};
+                       c->reward_mode, step_obs_mode(c)};
 }
 
 gx::StateBufs state_of(const gx_state* st) {
@@ -95,7 +130,41 @@ gx::StateBufs state_of(const gx_state* st) {
 }
 
 gx::TrajBufs traj_of(const gx_ctx* c, const gx_traj* tr) {
-  return gx::TrajBufs{tr->obs, tr->reward, tr->flags, tr->action, tr->rows, obs_row_bytes(c), tr->mission};
+  return gx::TrajBufs{tr->obs, tr->reward, tr->flags, tr->action, tr->rows, sym_row_bytes(c), tr->mission};
+}
+
+// Whether the call's observations go through the staging ring (rgb modes
+// with observations requested).
+bool staged(const gx_ctx* c, const gx_traj* tr) { return rgb_mode(c) && tr && tr->obs; }
+
+gx::TrajBufs stage_traj(const gx_ctx* c) {
+  const uint64_t n = (uint64_t)c->n, R = (uint64_t)c->stage_rows;
+  uint8_t* p = c->d_stage;
+  uint8_t* obs = p;
+  p += align256(R * sym_row_bytes(c));
+  float* reward = reinterpret_cast<float*>(p);
+  p += align256(R * n * 4);
+  uint8_t* flags = p;
+  p += align256(R * n);
+  uint8_t* action = p;
+  p += align256(R * n);
+  return gx::TrajBufs{obs, reward, flags, action, c->stage_rows, sym_row_bytes(c), p};
+}
+
+// Draw staging rows [0, n_rows) into the caller's rows from dst_row0 on.
+// When the chunk has more steps than the caller's ring has rows, its first
+// n_rows - rows steps would be overwritten by later ones in the same ring
+// row, so only the last tr->rows are drawn (drawing both would race).
+hipError_t render_rows(const gx_ctx* c, int32_t n_rows, const gx_traj* tr, int32_t dst_row0,
+                       hipStream_t stream) {
+  const gx::TrajBufs s = stage_traj(c);
+  const int32_t skip = std::max(0, n_rows - tr->rows);
+  const uint64_t k = (uint64_t)skip, n = (uint64_t)c->n;
+  const gx::RenderSrc src{s.obs + k * s.obs_row, s.reward + k * n, s.flags + k * n, s.action + k * n,
+                          s.mission + k * n, s.obs_row};
+  const gx::RenderDst dst{tr->obs, tr->reward, tr->flags, tr->action, tr->mission, tr->rows};
+  return gx::launch_render(src, n_rows - skip, c->n, c->obs_mode == 5, c->d_meta, c->d_grid_off,
+                           c->d_sprites, dst, (dst_row0 + skip) % tr->rows, c->render_blocks, stream);
 }
 
 int check_device(const gx_ctx* c) {
@@ -125,7 +194,8 @@ int env_create(const gx_config* cfg, gx_ctx** out) {
   *out = nullptr;
   if (!cfg || cfg->n_envs < 1 || !cfg->family || !cfg->side || !cfg->max_steps) return GX_EINVAL;
   if (cfg->reward_mode != 0 && cfg->reward_mode != 1) return GX_EINVAL;
-  if (cfg->obs_mode < 0 || cfg->obs_mode > 3) return GX_EINVAL;
+  if (cfg->obs_mode < 0 || cfg->obs_mode > 5) return GX_EINVAL;
+  if (cfg->obs_mode >= 4 && !cfg->sprites) return GX_EINVAL;
   const int32_t n = cfg->n_envs;
   // the grid of a tile must fit the LDS of one workgroup; side <= 32 and
   // 64 envs per tile bound it at 64 KiB of cells
@@ -168,6 +238,18 @@ int env_create(const gx_config* cfg, gx_ctx** out) {
   if (rc == GX_OK) rc = upload(&c->d_seed, seed);
   if (rc == GX_OK) rc = upload(&c->d_rng_id, rng_id);
   if (rc == GX_OK) rc = upload(&c->d_grid_off, grid_off);
+  if (rc == GX_OK && rgb_mode(c)) {
+    // the atlas, and a staging ring of up to 64 rows within 256 MiB
+    const uint64_t per_row = stage_bytes(c, 1);
+    c->stage_rows = (int32_t)std::max<uint64_t>(1, std::min<uint64_t>(64, (256ull << 20) / per_row));
+    // the renderer numbers its records with 32-bit ints
+    while (c->stage_rows > 1 && (int64_t)c->stage_rows * n > INT32_MAX) --c->stage_rows;
+    std::vector<uint8_t> atlas(cfg->sprites, cfg->sprites + (size_t)gx::kSprites * gx::kSpriteBytes);
+    rc = upload(&c->d_sprites, atlas);
+    if (rc == GX_OK && hipMalloc(reinterpret_cast<void**>(&c->d_stage), stage_bytes(c, c->stage_rows)) !=
+                           hipSuccess)
+      rc = GX_ENOMEM;
+  }
   if (rc != GX_OK) {
     free_tables(c);
     delete c;
@@ -185,6 +267,7 @@ int env_create(const gx_config* cfg, gx_ctx** out) {
   const size_t lds = gx::fused_lds_bytes(c->max_tile_cells);
   const int per_cu = std::max<int>(1, std::min<int>(16, (int)(lds_per_cu / lds)));
   c->blocks = std::min<int32_t>(c->n_tiles, cus * per_cu);
+  c->render_blocks = cus * 8;   // eight 256-thread workgroups per compute unit
   *out = c;
   return GX_OK;
 }
@@ -211,48 +294,56 @@ int env_info(const gx_ctx* c, gx_info* info) {
 
 int env_reset(gx_ctx* c, const gx_state* st, const gx_traj* first, void* stream) {
   if (!c || !state_ok(st)) return GX_EINVAL;
-  if (first && !traj_ok(first)) return GX_EINVAL;
+  if (first && !traj_ok(c, first)) return GX_EINVAL;
   int rc = check_device(c);
   if (rc != GX_OK) return rc;
   if ((rc = device_status()) != GX_OK) return rc;
+  const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   gx::TrajBufs tb{nullptr, nullptr, nullptr, nullptr, 1};
-  if (first) tb = traj_of(c, first);
-  if (gx::launch_plain(tables_of(c), state_of(st), nullptr, 1, tb, 0,
-                       reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
+  if (first) tb = staged(c, first) ? stage_traj(c) : traj_of(c, first);
+  if (gx::launch_plain(tables_of(c), state_of(st), nullptr, 1, tb, 0, s) != hipSuccess)
     return GX_EDEVICE;
+  if (staged(c, first) && render_rows(c, 1, first, 0, s) != hipSuccess) return GX_EDEVICE;
   c->has_reset = true;
   return GX_OK;
 }
 
 int env_step(gx_ctx* c, const gx_state* st, const uint8_t* actions, const gx_traj* out,
              void* stream) {
-  if (!c || !state_ok(st) || !traj_ok(out)) return GX_EINVAL;
+  if (!c || !state_ok(st) || !traj_ok(c, out)) return GX_EINVAL;
   if (!c->has_reset) return GX_ESTATE;
   int rc = check_device(c);
   if (rc != GX_OK) return rc;
   if ((rc = device_status()) != GX_OK) return rc;
-  if (gx::launch_plain(tables_of(c), state_of(st), actions, 0, traj_of(c, out), 0,
-                       reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
+  const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const bool stg = staged(c, out);
+  if (gx::launch_plain(tables_of(c), state_of(st), actions, 0, stg ? stage_traj(c) : traj_of(c, out), 0,
+                       s) != hipSuccess)
     return GX_EDEVICE;
+  if (stg && render_rows(c, 1, out, 0, s) != hipSuccess) return GX_EDEVICE;
   return GX_OK;
 }
 
 int env_rollout(gx_ctx* c, const gx_state* st, int32_t n_steps, const uint8_t* actions,
                 const gx_traj* traj, int32_t K, void* stream) {
-  if (!c || !state_ok(st) || !traj_ok(traj) || n_steps < 0 || K < 0) return GX_EINVAL;
+  if (!c || !state_ok(st) || !traj_ok(c, traj) || n_steps < 0 || K < 0) return GX_EINVAL;
   if (!c->has_reset) return GX_ESTATE;
   int rc = check_device(c);
   if (rc != GX_OK) return rc;
   if ((rc = device_status()) != GX_OK) return rc;
-  const int32_t k = K > 0 ? K : c->k_default;
+  const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const bool stg = staged(c, traj);
+  // rgb: each fused launch fills the staging ring from row 0, then the
+  // renderer draws those rows into the caller's ring
+  const int32_t k = std::min(K > 0 ? K : c->k_default, stg ? c->stage_rows : INT32_MAX);
   const gx::TileTables tiles{c->n_tiles, c->max_tile_cells, nullptr};   // every tile, in order
   for (int32_t s0 = 0; s0 < n_steps; s0 += k) {
     const int32_t ks = std::min(k, n_steps - s0);
     const uint8_t* act = actions ? actions + (size_t)s0 * (size_t)c->n : nullptr;
-    if (gx::launch_fused(tables_of(c), tiles, state_of(st), act, ks, traj_of(c, traj),
-                         s0 % traj->rows, c->blocks, reinterpret_cast<hipStream_t>(stream)) !=
-        hipSuccess)
+    if (gx::launch_fused(tables_of(c), tiles, state_of(st), act, ks, stg ? stage_traj(c) : traj_of(c, traj),
+                         stg ? 0 : s0 % traj->rows, c->blocks, s) != hipSuccess)
       return GX_EDEVICE;
+    if (stg && render_rows(c, ks, traj, s0 % traj->rows, s) != hipSuccess) return GX_EDEVICE;
   }
   return GX_OK;
 }

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libgridenv.so")
 
 GX_OK, GX_EINVAL, GX_ENOMEM, GX_EDEVICE, GX_ESTATE, GX_EBUSY = 0, -1, -2, -3, -4, -5
 OBS_BYTES = 147
+RGB_FIRST_PERSON = (224, 224, 3)
 EXPORTS = ("env_create", "env_sizes", "env_info", "env_reset", "env_step", "env_rollout",
            "env_set_launch", "env_destroy", "env_strerror",
            "env_server_create", "env_server_admit", "env_server_step", "env_server_release",
@@ -30,7 +31,8 @@ class GxConfig(ctypes.Structure):
     _fields_ = [("n_envs", ctypes.c_int32), ("reward_mode", ctypes.c_int32), ("obs_mode", ctypes.c_int32),
                 ("family", ctypes.c_void_p), ("side", ctypes.c_void_p), ("param", ctypes.c_void_p),
                 ("max_steps", ctypes.c_void_p), ("seed", ctypes.c_void_p),
-                ("seed_all", ctypes.c_uint64), ("rng_id", ctypes.c_void_p)]
+                ("seed_all", ctypes.c_uint64), ("rng_id", ctypes.c_void_p),
+                ("sprites", ctypes.c_void_p)]
 
 
 STATE_FIELDS = ("grid", "x", "y", "dir", "t", "carry", "episode", "done_prev", "calls", "obst")
@@ -144,15 +146,23 @@ def _stream_ptr(stream) -> int | None:
 
 
 # --------------------------------------------------------------- C names
-def env_create(table: workloads.EnvTable, reward_mode: int = 0, obs_mode: int = 0) -> int:
+def env_create(table: workloads.EnvTable, reward_mode: int = 0, obs_mode: int = 0,
+               sprites: np.ndarray | None = None) -> int:
+    """sprites: the atlas u8[264][32][32][3] of the rgb modes (4, 5)."""
     fam = np.ascontiguousarray(table.family, np.uint8)
     side = np.ascontiguousarray(table.side, np.uint8)
     ms = np.ascontiguousarray(table.max_steps, np.int32)
     seed = np.ascontiguousarray(table.seed, np.uint64)
     rid = np.ascontiguousarray(table.rng_id, np.uint32)
     par = np.ascontiguousarray(table.param, np.uint8)
+    atlas = None
+    if sprites is not None:
+        atlas = np.ascontiguousarray(sprites, np.uint8)
+        if atlas.shape != (264, 32, 32, 3):
+            raise ValueError(f"sprite atlas must be [264][32][32][3], got {atlas.shape}")
     cfg = GxConfig(table.n, reward_mode, obs_mode, fam.ctypes.data, side.ctypes.data, par.ctypes.data,
-                   ms.ctypes.data, seed.ctypes.data, 0, rid.ctypes.data)
+                   ms.ctypes.data, seed.ctypes.data, 0, rid.ctypes.data,
+                   atlas.ctypes.data if atlas is not None else None)
     ctx = ctypes.c_void_p()
     _check("env_create", load().env_create(ctypes.byref(cfg), ctypes.byref(ctx)))
     return ctx.value
@@ -199,8 +209,9 @@ def env_destroy(ctx: int):
 @dataclass
 class Traj:
     """Device output rows: obs u8 [rows][N][7][7][3] (mode 0), [rows][N][7][7]
-    (mode 1) or [rows][row_bytes] (whole-grid modes 2 and 3, records packed
-    like the grids), or None; reward f32, flags u8, action u8 [rows][N]."""
+    (mode 1), [rows][N][224][224][3] (mode 4) or [rows][row_bytes]
+    (whole-grid modes 2, 3 and 5, records packed like the grids), or None;
+    reward f32, flags u8, action u8 [rows][N]."""
     obs: object
     reward: object
     flags: object
@@ -211,7 +222,8 @@ class Traj:
     def alloc(rows: int, n: int, device="cuda", with_obs: bool = True, obs_mode: int = 0,
               row_bytes: int = 0) -> "Traj":
         import torch
-        shape = {0: (rows, n, 7, 7, 3), 1: (rows, n, 7, 7)}.get(obs_mode, (rows, row_bytes))
+        shape = {0: (rows, n, 7, 7, 3), 1: (rows, n, 7, 7),
+                 4: (rows, n) + RGB_FIRST_PERSON}.get(obs_mode, (rows, row_bytes))
         return Traj(torch.zeros(shape, dtype=torch.uint8, device=device) if with_obs else None,
                     torch.zeros((rows, n), dtype=torch.float32, device=device),
                     torch.zeros((rows, n), dtype=torch.uint8, device=device),
@@ -238,12 +250,18 @@ class GridEnv:
 
     FIELDS = STATE_FIELDS
 
-    def __init__(self, table: workloads.EnvTable, reward_mode: int = 0, device="cuda", obs_mode: int = 0):
+    def __init__(self, table: workloads.EnvTable, reward_mode: int = 0, device="cuda", obs_mode: int = 0,
+                 sprites: np.ndarray | None = None):
+        """obs_mode 4 (rgb_first_person) and 5 (rgb) draw with `sprites`, an
+        atlas u8[264][32][32][3]; None takes sprites.default_atlas()."""
         import torch
         self.table = table
         self.obs_mode = obs_mode
         self.device = torch.device(device)
-        self.ctx = env_create(table, reward_mode, obs_mode)
+        if obs_mode >= 4 and sprites is None:
+            from .sprites import default_atlas
+            sprites = default_atlas()
+        self.ctx = env_create(table, reward_mode, obs_mode, sprites)
         grid_bytes, n = env_sizes(self.ctx)
         self.n = n
         dev = self.device

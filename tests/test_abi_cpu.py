@@ -80,8 +80,9 @@ def test_create_rejects_bad_configs(family, side, T, n, mode, param):
     assert ctx.value is None
 
 
-@pytest.mark.parametrize("obs_mode", [-1, 4, 99])
+@pytest.mark.parametrize("obs_mode", [-1, 6, 99, 4, 5])
 def test_create_rejects_bad_observation_modes(obs_mode):
+    """Unknown modes, and the rgb modes (4, 5) without a sprite atlas."""
     lib = ge.load()
     cfg, keep = _cfg([0], [8], [10], obs_mode=obs_mode)
     ctx = ctypes.c_void_p(1)

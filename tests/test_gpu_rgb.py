@@ -1,0 +1,181 @@
+"""GPU parity of the rgb observation functions (rgb_first_person, obs_mode
+4; rgb, obs_mode 5): the step kernels' symbolic records drawn by the
+renderer, through the C-ABI, against the CPU oracle on the same seeded
+inputs, byte for byte.  The atlas is random bytes, so any wrong sprite,
+row, column or channel shows; the scalar outputs and the final state
+must match as in every other mode."""
+import numpy as np
+import pytest
+
+import oracle as ox
+import parity as P
+from paper_2407_19396_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ge():
+    import torch
+    from paper_2407_19396_amd import gridenv
+    assert torch.cuda.is_available()
+    gridenv.load()
+    return gridenv
+
+
+def atlas(seed=0):
+    return np.random.default_rng(seed).integers(0, 256, (264, 32, 32, 3), dtype=np.uint8)
+
+
+def oracle_reset(table, mode, sprites):
+    b = ox.Batch(table.family, table.side, table.max_steps, table.seed, table.rng_id, 0, table.param,
+                 mode, sprites)
+    s = ox.State.empty(b)
+    return b, s, ox.reset(b, s, nthreads=8)
+
+
+def tables():
+    return {"mixed": wl.mixed_table(96, seed=7, mix_seed=8),
+            "families": wl.families_table(96, seed=71, mix_seed=72),
+            "large_sides": wl.uniform_table(20, wl.FAMILY_EMPTY, 32, seed=9)}
+
+
+@pytest.mark.parametrize("name", ["mixed", "families", "large_sides"])
+@pytest.mark.parametrize("kernel", ["plain", "fused"])
+@pytest.mark.parametrize("mode", [4, 5])
+def test_rgb_parity(ge, name, kernel, mode):
+    import torch
+    table = tables()[name]
+    sprites = atlas(mode)
+    env = ge.GridEnv(table, obs_mode=mode, sprites=sprites)
+    first = env.traj(1)
+    env.reset(first)
+    b, s, ref0 = oracle_reset(table, mode, sprites)
+    assert env.info()["obs_row_bytes"] == b.obs_row_bytes()
+    torch.cuda.synchronize()
+    P.assert_rows_equal(first, ref0, what=f"rgb mode {mode} reset {name}")
+    steps = 20
+    ref = ox.rollout(b, s, steps, None, nthreads=8)
+    traj = env.traj(steps)
+    if kernel == "fused":
+        env.rollout(steps, traj, K=8)       # three launches, the last one short
+    else:
+        for k in range(steps):
+            env.step(traj.row(k))
+    torch.cuda.synchronize()
+    P.assert_rows_equal(traj, ref, what=f"rgb mode {mode} {kernel} {name}")
+    P.assert_state_equal(env, s, f"rgb mode {mode} {kernel} {name}")
+
+
+@pytest.mark.parametrize("n", [1, 65])
+@pytest.mark.parametrize("mode", [4, 5])
+def test_rgb_ragged_and_ring(ge, n, mode):
+    """Ragged batches, and a ring of 7 rows that 30 steps in launches of
+    K = 8 wrap around (the renderer writes rows from mid-ring)."""
+    import torch
+    table = wl.mixed_table(n, seed=n + 19, mix_seed=n + 20)
+    sprites = atlas(n)
+    env = ge.GridEnv(table, obs_mode=mode, sprites=sprites)
+    env.reset(env.traj(1))
+    b, s, _ = oracle_reset(table, mode, sprites)
+    ref = ox.rollout(b, s, 30, None, rows=7, nthreads=8)
+    traj = env.traj(7)
+    env.rollout(30, traj, K=8)
+    torch.cuda.synchronize()
+    P.assert_rows_equal(traj, ref, what=f"rgb mode {mode} n={n}")
+
+
+@pytest.mark.parametrize("mode", [4, 5])
+def test_rgb_without_observations(ge, mode):
+    """obs = NULL skips the drawing; the other outputs still match."""
+    import torch
+    table = wl.families_table(130, seed=3, mix_seed=4)
+    env = ge.GridEnv(table, obs_mode=mode, sprites=atlas())
+    env.reset()
+    b, s, _ = oracle_reset(table, mode, atlas())
+    ref = ox.rollout(b, s, 12, None, with_obs=False, nthreads=8)
+    traj = env.traj(12, with_obs=False)
+    env.rollout(12, traj, K=5)
+    torch.cuda.synchronize()
+    P.assert_rows_equal(traj, ref, what=f"rgb mode {mode} without obs")
+    P.assert_state_equal(env, s)
+
+
+def test_default_atlas_draws_the_same_records(ge):
+    """GridEnv's default atlas, checked like any other."""
+    import torch
+    from paper_2407_19396_amd.sprites import default_atlas
+    table = wl.mixed_table(40, seed=5, mix_seed=6)
+    env = ge.GridEnv(table, obs_mode=4)
+    env.reset()
+    b, s, _ = oracle_reset(table, 4, default_atlas())
+    ref = ox.rollout(b, s, 6, None)
+    traj = env.traj(6)
+    env.rollout(6, traj)
+    torch.cuda.synchronize()
+    P.assert_rows_equal(traj, ref, what="default atlas")
+
+
+def test_rgb_rejects_unaligned_rows(ge):
+    import torch
+    table = wl.mixed_table(8, seed=1, mix_seed=2)
+    env = ge.GridEnv(table, obs_mode=4, sprites=atlas())
+    env.reset()
+    traj = env.traj(2)
+    raw = torch.zeros(2 * 8 * 150528 + 16, dtype=torch.uint8, device="cuda")
+    traj.obs = raw[1:1 + 2 * 8 * 150528]
+    with pytest.raises(ge.GridEnvError) as e:
+        env.rollout(2, traj)
+    assert e.value.status == ge.GX_EINVAL
+
+
+def test_rgb_first_person_full_size_sample(ge):
+    """The benchmark's rgb configuration (16384 mixed envs, launches of
+    16 steps, a ring of 16 rows) on a strided sample of envs, each
+    recomputed by the oracle on its own."""
+    import torch
+    table = wl.workload_mixed(seed=0, n=16384)
+    sprites = atlas(11)
+    env = ge.GridEnv(table, obs_mode=4, sprites=sprites)
+    env.reset()
+    sample = np.arange(5, table.n, 509)
+    idx = torch.from_numpy(sample).cuda()
+    traj = env.traj(16)
+    got = []
+    for _ in range(2):
+        env.rollout(16, traj, K=16)
+        got.append((traj.obs[:, idx].cpu().numpy(), traj.reward[:, idx].cpu().numpy(),
+                    traj.flags[:, idx].cpu().numpy()))
+    torch.cuda.synchronize()
+    sub = table.subset(sample)
+    b, s, _ = oracle_reset(sub, 4, sprites)
+    for c in range(2):
+        ref = ox.rollout(b, s, 16, None, nthreads=8)
+        np.testing.assert_array_equal(got[c][2], ref.flags)
+        np.testing.assert_array_equal(got[c][1].view(np.uint32), ref.reward.view(np.uint32))
+        assert np.array_equal(got[c][0], ref.obs), f"rgb records differ in chunk {c}"
+
+
+def test_rgb_whole_grid_full_size_sample(ge):
+    """4096 mixed envs drawn whole (records of 75 KB to 1.1 MB at offsets
+    1024 grid_off), launches of 8 steps, on a strided sample."""
+    import torch
+    table = wl.workload_mixed(seed=1, n=4096)
+    sprites = atlas(12)
+    env = ge.GridEnv(table, obs_mode=5, sprites=sprites)
+    env.reset()
+    traj = env.traj(8)
+    env.rollout(8, traj, K=8)
+    torch.cuda.synchronize()
+    sample = np.arange(3, table.n, 197)
+    off = ox.Batch(table.family, table.side, table.max_steps, table.seed, table.rng_id).grid_offsets()
+    got = [traj.obs[:, 1024 * int(off[e]):1024 * int(off[e]) + 3072 * int(table.side[e]) ** 2].cpu().numpy()
+           for e in sample]
+    sub = table.subset(sample)
+    b, s, _ = oracle_reset(sub, 5, sprites)
+    ref = ox.rollout(b, s, 8, None, nthreads=8)
+    sub_off = b.grid_offsets()
+    for k, e in enumerate(sample):
+        S = int(table.side[e])
+        want = ref.obs[:, 1024 * int(sub_off[k]):1024 * int(sub_off[k]) + 3072 * S * S]
+        assert np.array_equal(got[k], want), f"env {e} (side {S})"
