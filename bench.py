@@ -375,7 +375,7 @@ def main():
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload].format(n=table.n),
+        "config": {"workload": WORKLOADS[args.workload].replace("{n}", str(table.n)),
                    "n_envs": table.n, "K": K, "ring_rows": ring, "blocks": info["blocks"],
                    "lds_bytes_per_wg": info["lds_bytes"], "global_batch": table.n,
                    "autotuned": tuned is not None, "hip_graph": graph is not None,

@@ -9,14 +9,17 @@
 // kernel expands them, so it is a pure stream: per env-step it reads 147
 // bytes (first person) and writes 150 528.
 //
-// One workgroup of 256 threads draws one record at a time (persistent
-// over the (row, env) records of a launch).  It first turns the record's
-// W x W triples into sprite ids in LDS; then thread t owns the 16-byte
-// chunk t of a block of P whole image rows (an image row is 96 W bytes =
-// 6 W chunks, P = floor(256 / 6W)), so each pass of the workgroup writes
-// P * 96 W contiguous bytes with non-temporal 16-byte stores.  A chunk lies
-// inside one sprite row of one cell, so it is one 16-byte load of the atlas
-// (which stays in L2: 811 KB, the same few sprites in most cells).
+// Work split: one 64-lane wave per piece of 8 image rows of one cell row
+// (8 * 96 W contiguous bytes; 5.25 KB for a first-person view), pieces
+// numbered in address order, a non-persistent grid.  HBM write bandwidth
+// depends on the order the chip's stores arrive in: small pieces handed
+// out in address order keep every compute unit's stores inside one narrow
+// window sweeping the output, which measures about 20 % faster than
+// workgroups that each stream a whole 150 KB image (the same bytes, more
+// scattered).  Lanes 0..W-1 turn the cell row's triples into sprite ids;
+// each 16-byte chunk of the piece lies inside one sprite row of one cell,
+// so it is one 16-byte atlas load (the atlas, 811 KB, stays in L2) and one
+// non-temporal 16-byte store, four chunks per lane in flight.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -29,18 +32,25 @@ namespace {
 
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 64;                                // one wave per piece
 constexpr int kMaxSide = 32;
 constexpr int kView = 7;
 constexpr int kViewBytes = kView * kView * 3;
 constexpr int kChunk = 16;
 constexpr int kChunksPerSpriteRow = kSprite * 3 / kChunk;   // 6
+constexpr int kPieceRows = 8;                               // image rows per piece
+constexpr int kPiecesPerCellRow = kSprite / kPieceRows;     // 4
+constexpr int kInFlight = 4;                                // chunks per lane per round
 constexpr uint32_t kAgentType = 10, kNorth = 3;
 
 struct RenderArgs {
   RenderSrc src;
   RenderDst dst;
-  int32_t n_rows, n, dst_row0;
+  int32_t n;                 // envs
+  int32_t row0;              // first staging row of this launch
+  int32_t dst_row0;          // caller row of staging row 0
+  uint32_t pieces_per_row;   // first person: 28 n; whole grids: 4 * sum of sides
+  const uint32_t* crow;      // whole grids: env << 5 | cell row, per cell row of a staging row
   const uint32_t* meta;
   const uint64_t* grid_off;
   const uint8_t* sprites;
@@ -52,84 +62,102 @@ __device__ __forceinline__ uint32_t sprite_id(uint32_t type, uint32_t colour, ui
   return (type > kAgentType || colour > 5u || state > 3u) ? 0u : (type * 6u + colour) * 4u + state;
 }
 
-__device__ __forceinline__ v4u sprite_chunk(const uint8_t* base, const uint16_t* ids, int W, int x, int y) {
-  const uint32_t id = ids[(y >> 5) * W + x];
-  return *reinterpret_cast<const v4u*>(base + id * (uint32_t)kSpriteBytes + (uint32_t)(y & 31) * (kSprite * 3));
-}
-
 template <bool kWhole>
 __global__ __launch_bounds__(kThreads) void k_render(RenderArgs a) {
-  __shared__ uint16_t ids[kMaxSide * kMaxSide];
-  const int tid = threadIdx.x;
-  const int items = a.n_rows * a.n;   // < 2^31, checked by the host
-  for (int it = blockIdx.x; it < items; it += gridDim.x) {
-    const int r = it / a.n;
-    const int e = it - r * a.n;
-    const int W = kWhole ? (int)((a.meta[e] >> 8) & 0xFFu) : kView;
-    const uint64_t off = kWhole ? a.grid_off[e] : (uint64_t)e * kViewBytes;
-    const uint8_t* cells = a.src.obs + (uint64_t)r * a.src.sym_row + off;
-    const int drow = (a.dst_row0 + r) % a.dst.rows;
-    uint8_t* img = a.dst.obs + ((uint64_t)drow * a.src.sym_row + off) * kRgbScale;
-    for (int c = tid; c < W * W; c += kThreads) {
-      uint32_t type = cells[3 * c], colour = cells[3 * c + 1], state = cells[3 * c + 2];
-      if (!kWhole && c == (kView - 1) * kView + 3) {   // the agent's own cell
-        type = kAgentType;
-        colour = 0;
-        state = kNorth;
+  __shared__ uint16_t ids[kMaxSide];
+  const int lane = threadIdx.x;
+  const uint32_t b = blockIdx.x;
+  const uint32_t rr = b / a.pieces_per_row;
+  const uint32_t pc = b - rr * a.pieces_per_row;
+  const int r = a.row0 + (int)rr;
+  const int quarter = (int)(pc & (kPiecesPerCellRow - 1));
+  int e, cy, W;
+  if (kWhole) {
+    const uint32_t cr = a.crow[pc / kPiecesPerCellRow];
+    e = (int)(cr >> 5);
+    cy = (int)(cr & 31u);
+    W = (int)((a.meta[e] >> 8) & 0xFFu);
+  } else {
+    e = (int)(pc / (kView * kPiecesPerCellRow));
+    cy = (int)(pc - (uint32_t)e * (kView * kPiecesPerCellRow)) / kPiecesPerCellRow;
+    W = kView;
+  }
+  const uint64_t off = kWhole ? a.grid_off[e] : (uint64_t)e * kViewBytes;
+  const uint8_t* cells = a.src.obs + (uint64_t)r * a.src.sym_row + off + 3u * (uint32_t)(cy * W);
+  if (lane < W) {
+    uint32_t type = cells[3 * lane], colour = cells[3 * lane + 1], state = cells[3 * lane + 2];
+    if (!kWhole && cy == kView - 1 && lane == 3) {   // the agent's own cell
+      type = kAgentType;
+      colour = 0;
+      state = kNorth;
+    }
+    ids[lane] = (uint16_t)sprite_id(type, colour, state);
+  }
+  const int drow = (a.dst_row0 + r) % a.dst.rows;
+  if (cy == 0 && quarter == 0 && lane == 0) {   // one wave per record copies its scalars
+    const uint64_t si = (uint64_t)r * (uint64_t)a.n + (uint64_t)e;
+    const uint64_t di = (uint64_t)drow * (uint64_t)a.n + (uint64_t)e;
+    a.dst.reward[di] = a.src.reward[si];
+    a.dst.flags[di] = a.src.flags[si];
+    a.dst.action[di] = a.src.action[si];
+    if (a.dst.mission) a.dst.mission[di] = a.src.mission[si];
+  }
+  __syncthreads();
+  const int row_chunks = kChunksPerSpriteRow * W;   // 16-byte chunks per image row
+  const int chunks = kPieceRows * row_chunks;
+  const int py0 = quarter * kPieceRows;             // first sprite row of the piece
+  // q / row_chunks for q < 48 W, row_chunks = 6 W in [24, 192]: exact by
+  // multiplication with floor(2^20 / row_chunks) + 1 (checked for every W)
+  const uint32_t inv = (1u << 20) / (uint32_t)row_chunks + 1u;
+  v4u* out = reinterpret_cast<v4u*>(a.dst.obs + ((uint64_t)drow * a.src.sym_row + off) * kRgbScale +
+                                    (uint64_t)(cy * kSprite + py0) * (uint64_t)(row_chunks * kChunk));
+  const v4u* atlas = reinterpret_cast<const v4u*>(a.sprites);
+  for (int q0 = 0; q0 < chunks; q0 += kInFlight * kThreads) {
+    v4u v[kInFlight];
+#pragma unroll
+    for (int k = 0; k < kInFlight; ++k) {
+      const int q = q0 + lane + k * kThreads;
+      if (q < chunks) {
+        const int row = (int)(((uint32_t)q * inv) >> 20);
+        const int cc = q - row * row_chunks;
+        const int x = cc / kChunksPerSpriteRow;
+        const int part = cc - x * kChunksPerSpriteRow;
+        v[k] = atlas[(uint32_t)ids[x] * (kSpriteBytes / kChunk) +
+                     (uint32_t)((py0 + row) * kChunksPerSpriteRow + part)];
       }
-      ids[c] = (uint16_t)sprite_id(type, colour, state);
     }
-    if (tid == kThreads - 1) {
-      const uint64_t si = (uint64_t)r * a.n + e, di = (uint64_t)drow * a.n + e;
-      a.dst.reward[di] = a.src.reward[si];
-      a.dst.flags[di] = a.src.flags[si];
-      a.dst.action[di] = a.src.action[si];
-      if (a.dst.mission) a.dst.mission[di] = a.src.mission[si];
+#pragma unroll
+    for (int k = 0; k < kInFlight; ++k) {
+      const int q = q0 + lane + k * kThreads;
+      if (q < chunks) __builtin_nontemporal_store(v[k], out + q);
     }
-    __syncthreads();
-    const int chunks = kChunksPerSpriteRow * W;   // per image row
-    const int P = kThreads / chunks;              // image rows per pass (W <= 32: P >= 1)
-    const int H = kSprite * W;
-    if (tid < P * chunks) {
-      const int rp = tid / chunks, cc = tid - rp * chunks;
-      const int x = cc / kChunksPerSpriteRow;
-      const uint8_t* base = a.sprites + (cc - kChunksPerSpriteRow * x) * kChunk;
-      const uint64_t step = (uint64_t)P * (uint64_t)(chunks * kChunk);
-      uint8_t* o = img + (uint64_t)rp * (uint64_t)(chunks * kChunk) + (uint64_t)cc * kChunk;
-      int y = rp;
-      // four rows in flight per thread: loads first, then the stores
-      for (; y + 3 * P < H; y += 4 * P, o += 4 * step) {
-        const v4u v0 = sprite_chunk(base, ids, W, x, y);
-        const v4u v1 = sprite_chunk(base, ids, W, x, y + P);
-        const v4u v2 = sprite_chunk(base, ids, W, x, y + 2 * P);
-        const v4u v3 = sprite_chunk(base, ids, W, x, y + 3 * P);
-        __builtin_nontemporal_store(v0, reinterpret_cast<v4u*>(o));
-        __builtin_nontemporal_store(v1, reinterpret_cast<v4u*>(o + step));
-        __builtin_nontemporal_store(v2, reinterpret_cast<v4u*>(o + 2 * step));
-        __builtin_nontemporal_store(v3, reinterpret_cast<v4u*>(o + 3 * step));
-      }
-      for (; y < H; y += P, o += step)
-        __builtin_nontemporal_store(sprite_chunk(base, ids, W, x, y), reinterpret_cast<v4u*>(o));
-    }
-    __syncthreads();   // ids are rewritten by the next record
   }
 }
 
 }  // namespace
 
 hipError_t launch_render(const RenderSrc& src, int32_t n_rows, int32_t n_envs, bool whole,
-                         const uint32_t* meta, const uint64_t* grid_off, const uint8_t* sprites,
-                         const RenderDst& dst, int32_t dst_row0, int32_t blocks, hipStream_t stream) {
+                         const uint32_t* meta, const uint64_t* grid_off, const uint32_t* cell_rows,
+                         uint32_t n_cell_rows, const uint8_t* sprites, const RenderDst& dst,
+                         int32_t dst_row0, hipStream_t stream) {
   if (n_rows <= 0 || n_envs <= 0) return hipSuccess;
-  const int64_t items = (int64_t)n_rows * n_envs;
-  if (items > INT32_MAX || blocks < 1) return hipErrorInvalidValue;
-  RenderArgs a{src, dst, n_rows, n_envs, dst_row0, meta, grid_off, sprites};
-  const int grid = (int)std::min<int64_t>(items, blocks);
-  if (whole)
-    hipLaunchKernelGGL(k_render<true>, dim3(grid), dim3(kThreads), 0, stream, a);
-  else
-    hipLaunchKernelGGL(k_render<false>, dim3(grid), dim3(kThreads), 0, stream, a);
-  return hipGetLastError();
+  const uint64_t per_row = whole ? (uint64_t)kPiecesPerCellRow * n_cell_rows
+                                 : (uint64_t)kView * kPiecesPerCellRow * (uint64_t)n_envs;
+  if (per_row == 0 || per_row > (uint64_t)INT32_MAX) return hipErrorInvalidValue;
+  // launches of as many whole rows as one grid's x dimension holds
+  const int32_t rows_per_launch = (int32_t)std::max<uint64_t>(1, (uint64_t)INT32_MAX / per_row);
+  for (int32_t r0 = 0; r0 < n_rows; r0 += rows_per_launch) {
+    const int32_t nr = std::min(rows_per_launch, n_rows - r0);
+    RenderArgs a{src, dst, n_envs, r0, dst_row0, (uint32_t)per_row, cell_rows, meta, grid_off, sprites};
+    const dim3 grid((uint32_t)(per_row * (uint64_t)nr));
+    if (whole)
+      hipLaunchKernelGGL(k_render<true>, grid, dim3(kThreads), 0, stream, a);
+    else
+      hipLaunchKernelGGL(k_render<false>, grid, dim3(kThreads), 0, stream, a);
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  return hipSuccess;
 }
 
 }  // namespace gx

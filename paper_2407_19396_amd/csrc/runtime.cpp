@@ -38,7 +38,8 @@ struct gx_ctx {
   uint8_t* d_sprites = nullptr;
   uint8_t* d_stage = nullptr;
   int32_t stage_rows = 0;
-  int32_t render_blocks = 0;
+  uint32_t* d_cell_rows = nullptr;   // rgb: env << 5 | row for every cell row of the grids
+  uint32_t n_cell_rows = 0;
 };
 
 namespace {
@@ -67,8 +68,10 @@ void free_tables(gx_ctx* c) {
   (void)hipFree(c->d_grid_off);
   (void)hipFree(c->d_sprites);
   (void)hipFree(c->d_stage);
+  (void)hipFree(c->d_cell_rows);
   c->d_sprites = nullptr;
   c->d_stage = nullptr;
+  c->d_cell_rows = nullptr;
   c->d_meta = nullptr;
   c->d_max_steps = nullptr;
   c->d_seed = nullptr;
@@ -164,7 +167,8 @@ hipError_t render_rows(const gx_ctx* c, int32_t n_rows, const gx_traj* tr, int32
                           s.mission + k * n, s.obs_row};
   const gx::RenderDst dst{tr->obs, tr->reward, tr->flags, tr->action, tr->mission, tr->rows};
   return gx::launch_render(src, n_rows - skip, c->n, c->obs_mode == 5, c->d_meta, c->d_grid_off,
-                           c->d_sprites, dst, (dst_row0 + skip) % tr->rows, c->render_blocks, stream);
+                           c->d_cell_rows, c->n_cell_rows, c->d_sprites, dst, (dst_row0 + skip) % tr->rows,
+                           stream);
 }
 
 int check_device(const gx_ctx* c) {
@@ -242,10 +246,15 @@ int env_create(const gx_config* cfg, gx_ctx** out) {
     // the atlas, and a staging ring of up to 64 rows within 256 MiB
     const uint64_t per_row = stage_bytes(c, 1);
     c->stage_rows = (int32_t)std::max<uint64_t>(1, std::min<uint64_t>(64, (256ull << 20) / per_row));
-    // the renderer numbers its records with 32-bit ints
-    while (c->stage_rows > 1 && (int64_t)c->stage_rows * n > INT32_MAX) --c->stage_rows;
     std::vector<uint8_t> atlas(cfg->sprites, cfg->sprites + (size_t)gx::kSprites * gx::kSpriteBytes);
     rc = upload(&c->d_sprites, atlas);
+    if (rc == GX_OK && c->obs_mode == 5) {
+      std::vector<uint32_t> cell_rows;
+      for (int32_t i = 0; i < n; ++i)
+        for (uint32_t y = 0; y < cfg->side[i]; ++y) cell_rows.push_back(((uint32_t)i << 5) | y);
+      c->n_cell_rows = (uint32_t)cell_rows.size();
+      rc = upload(&c->d_cell_rows, cell_rows);
+    }
     if (rc == GX_OK && hipMalloc(reinterpret_cast<void**>(&c->d_stage), stage_bytes(c, c->stage_rows)) !=
                            hipSuccess)
       rc = GX_ENOMEM;
@@ -267,7 +276,6 @@ int env_create(const gx_config* cfg, gx_ctx** out) {
   const size_t lds = gx::fused_lds_bytes(c->max_tile_cells);
   const int per_cu = std::max<int>(1, std::min<int>(16, (int)(lds_per_cu / lds)));
   c->blocks = std::min<int32_t>(c->n_tiles, cus * per_cu);
-  c->render_blocks = cus * 8;   // eight 256-thread workgroups per compute unit
   *out = c;
   return GX_OK;
 }
