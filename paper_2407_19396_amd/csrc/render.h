@@ -15,7 +15,8 @@ constexpr int kRgbScale = kSpriteBytes / 3;            // rgb bytes per symbolic
 
 // Symbolic rows written by a step kernel: obs [rows][sym_row] (first person
 // [N][7][7][3], or whole grids packed like the grid buffer), and the
-// scalar outputs [rows][N].
+// scalar outputs [rows][N]; ids [rows][sym_row / 3] receives the sprite
+// index of every cell (the renderer's first pass).
 struct RenderSrc {
   const uint8_t* obs;
   const float* reward;
@@ -23,6 +24,7 @@ struct RenderSrc {
   const uint8_t* action;
   const uint8_t* mission;
   uint64_t sym_row;
+  uint16_t* ids;
 };
 
 // The caller's rows: obs [rows][kRgbScale * sym_row], 16-byte aligned; the
@@ -38,7 +40,8 @@ struct RenderDst {
 };
 
 // Draw rows [0, n_rows) of src into rows (dst_row0 + r) % dst.rows of dst and
-// copy their scalar outputs.  whole: records are whole grids, env e's side
+// copy their scalar outputs (two launches: sprite indices and scalars, then
+// the images).  whole: records are whole grids, env e's side
 // in bits 8..15 of meta[e] and its offset grid_off[e], and cell_rows lists
 // the n_cell_rows (= sum of sides) cell rows of one staging row as
 // e << 5 | row, in address order; otherwise 7 x 7 views at 147 e, the

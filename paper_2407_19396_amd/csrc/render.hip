@@ -9,15 +9,22 @@
 // kernel expands them, so it is a pure stream: per env-step it reads 147
 // bytes (first person) and writes 150 528.
 //
-// Work split: one 64-lane wave per piece of 8 image rows of one cell row
+// Two passes per launch of rows.  The first streams the staged records
+// once: every cell's sprite index goes to a 2-byte index row (ordinary
+// stores, so it stays in the caches) and the scalar outputs move to the
+// caller's rows.  The staged records were just written by the step kernel's
+// non-temporal stores; reading them from the draw pass, one dependent load
+// at the start of every short-lived wave, cost 15 % of the draw's time.
+//
+// Draw pass: one 64-lane wave per piece of 8 image rows of one cell row
 // (8 * 96 W contiguous bytes; 5.25 KB for a first-person view), pieces
 // numbered in address order, a non-persistent grid.  HBM write bandwidth
 // depends on the order the chip's stores arrive in: small pieces handed
 // out in address order keep every compute unit's stores inside one narrow
 // window sweeping the output, which measures about 20 % faster than
 // workgroups that each stream a whole 150 KB image (the same bytes, more
-// scattered).  Lanes 0..W-1 turn the cell row's triples into sprite ids;
-// each 16-byte chunk of the piece lies inside one sprite row of one cell,
+// scattered).  Lanes 0..W-1 read the cell row's sprite indices; each
+// 16-byte chunk of the piece lies inside one sprite row of one cell,
 // so it is one 16-byte atlas load (the atlas, 811 KB, stays in L2) and one
 // non-temporal 16-byte store, four chunks per lane in flight.
 #include <hip/hip_runtime.h>
@@ -41,7 +48,17 @@ constexpr int kChunksPerSpriteRow = kSprite * 3 / kChunk;   // 6
 constexpr int kPieceRows = 8;                               // image rows per piece
 constexpr int kPiecesPerCellRow = kSprite / kPieceRows;     // 4
 constexpr int kInFlight = 4;                                // chunks per lane per round
+constexpr int kIdThreads = 256;
+constexpr uint32_t kAgentCell = (kView - 1) * kView + 3;    // the agent's own cell in a view
 constexpr uint32_t kAgentType = 10, kNorth = 3;
+
+struct IdArgs {
+  RenderSrc src;
+  RenderDst dst;
+  int32_t n;                 // envs
+  int32_t dst_row0;          // caller row of staging row 0
+  uint32_t cells_per_row;    // sym_row / 3
+};
 
 struct RenderArgs {
   RenderSrc src;
@@ -62,6 +79,33 @@ __device__ __forceinline__ uint32_t sprite_id(uint32_t type, uint32_t colour, ui
   return (type > kAgentType || colour > 5u || state > 3u) ? 0u : (type * 6u + colour) * 4u + state;
 }
 
+// Pass 1: grid (cells of a row / 256, rows).  Thread c of row r: the sprite
+// index of cell c (first person: cell c % 49 of env c / 49, the agent's own
+// cell drawn as the north-facing agent), and for c < n env c's scalars.
+template <bool kWhole>
+__global__ __launch_bounds__(kIdThreads) void k_sprite_ids(IdArgs a) {
+  const uint32_t c = blockIdx.x * kIdThreads + threadIdx.x;
+  const int r = (int)blockIdx.y;
+  if (c >= a.cells_per_row) return;
+  const uint8_t* t = a.src.obs + (uint64_t)r * a.src.sym_row + 3u * (uint64_t)c;
+  uint32_t type = t[0], colour = t[1], state = t[2];
+  if (!kWhole && c % (kView * kView) == kAgentCell) {
+    type = kAgentType;
+    colour = 0;
+    state = kNorth;
+  }
+  a.src.ids[(uint64_t)r * a.cells_per_row + c] = (uint16_t)sprite_id(type, colour, state);
+  if (c < (uint32_t)a.n) {
+    const int drow = (a.dst_row0 + r) % a.dst.rows;
+    const uint64_t si = (uint64_t)r * (uint64_t)a.n + c, di = (uint64_t)drow * (uint64_t)a.n + c;
+    a.dst.reward[di] = a.src.reward[si];
+    a.dst.flags[di] = a.src.flags[si];
+    a.dst.action[di] = a.src.action[si];
+    if (a.dst.mission) a.dst.mission[di] = a.src.mission[si];
+  }
+}
+
+// Pass 2: the images (see the top of the file).
 template <bool kWhole>
 __global__ __launch_bounds__(kThreads) void k_render(RenderArgs a) {
   __shared__ uint16_t ids[kMaxSide];
@@ -83,25 +127,9 @@ __global__ __launch_bounds__(kThreads) void k_render(RenderArgs a) {
     W = kView;
   }
   const uint64_t off = kWhole ? a.grid_off[e] : (uint64_t)e * kViewBytes;
-  const uint8_t* cells = a.src.obs + (uint64_t)r * a.src.sym_row + off + 3u * (uint32_t)(cy * W);
-  if (lane < W) {
-    uint32_t type = cells[3 * lane], colour = cells[3 * lane + 1], state = cells[3 * lane + 2];
-    if (!kWhole && cy == kView - 1 && lane == 3) {   // the agent's own cell
-      type = kAgentType;
-      colour = 0;
-      state = kNorth;
-    }
-    ids[lane] = (uint16_t)sprite_id(type, colour, state);
-  }
+  if (lane < W)
+    ids[lane] = a.src.ids[((uint64_t)r * a.src.sym_row + off) / 3u + (uint32_t)(cy * W + lane)];
   const int drow = (a.dst_row0 + r) % a.dst.rows;
-  if (cy == 0 && quarter == 0 && lane == 0) {   // one wave per record copies its scalars
-    const uint64_t si = (uint64_t)r * (uint64_t)a.n + (uint64_t)e;
-    const uint64_t di = (uint64_t)drow * (uint64_t)a.n + (uint64_t)e;
-    a.dst.reward[di] = a.src.reward[si];
-    a.dst.flags[di] = a.src.flags[si];
-    a.dst.action[di] = a.src.action[si];
-    if (a.dst.mission) a.dst.mission[di] = a.src.mission[si];
-  }
   __syncthreads();
   const int row_chunks = kChunksPerSpriteRow * W;   // 16-byte chunks per image row
   const int chunks = kPieceRows * row_chunks;
@@ -145,6 +173,18 @@ hipError_t launch_render(const RenderSrc& src, int32_t n_rows, int32_t n_envs, b
                                  : (uint64_t)kView * kPiecesPerCellRow * (uint64_t)n_envs;
   if (per_row == 0 || per_row > (uint64_t)INT32_MAX) return hipErrorInvalidValue;
   // launches of as many whole rows as one grid's x dimension holds
+  const uint64_t cells_per_row = src.sym_row / 3;
+  if (cells_per_row > (uint64_t)UINT32_MAX - kIdThreads || n_rows > 65535) return hipErrorInvalidValue;
+  {
+    IdArgs ia{src, dst, n_envs, dst_row0, (uint32_t)cells_per_row};
+    const dim3 grid((uint32_t)((cells_per_row + kIdThreads - 1) / kIdThreads), (uint32_t)n_rows);
+    if (whole)
+      hipLaunchKernelGGL(k_sprite_ids<true>, grid, dim3(kIdThreads), 0, stream, ia);
+    else
+      hipLaunchKernelGGL(k_sprite_ids<false>, grid, dim3(kIdThreads), 0, stream, ia);
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
   const int32_t rows_per_launch = (int32_t)std::max<uint64_t>(1, (uint64_t)INT32_MAX / per_row);
   for (int32_t r0 = 0; r0 < n_rows; r0 += rows_per_launch) {
     const int32_t nr = std::min(rows_per_launch, n_rows - r0);

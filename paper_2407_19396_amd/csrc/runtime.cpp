@@ -110,10 +110,12 @@ uint64_t obs_row_bytes(const gx_ctx* c) {
 
 uint64_t align256(uint64_t v) { return (v + 255) & ~(uint64_t)255; }
 
-// staging ring layout: obs rows, then reward, flags, action, mission rows
+// staging ring layout: obs rows, then reward, flags, action, mission rows,
+// then the renderer's sprite indices (2 bytes per cell)
 uint64_t stage_bytes(const gx_ctx* c, int32_t rows) {
   const uint64_t n = (uint64_t)c->n;
-  return align256(rows * sym_row_bytes(c)) + align256(rows * n * 4) + 3 * align256(rows * n);
+  return align256(rows * sym_row_bytes(c)) + align256(rows * n * 4) + 3 * align256(rows * n) +
+         align256(rows * (sym_row_bytes(c) / 3) * 2);
 }
 
 bool traj_ok(const gx_ctx* c, const gx_traj* tr) {
@@ -154,6 +156,12 @@ gx::TrajBufs stage_traj(const gx_ctx* c) {
   return gx::TrajBufs{obs, reward, flags, action, c->stage_rows, sym_row_bytes(c), p};
 }
 
+uint16_t* stage_ids(const gx_ctx* c) {
+  const uint64_t n = (uint64_t)c->n, R = (uint64_t)c->stage_rows;
+  return reinterpret_cast<uint16_t*>(c->d_stage + align256(R * sym_row_bytes(c)) + align256(R * n * 4) +
+                                     3 * align256(R * n));
+}
+
 // Draw staging rows [0, n_rows) into the caller's rows from dst_row0 on.
 // When the chunk has more steps than the caller's ring has rows, its first
 // n_rows - rows steps would be overwritten by later ones in the same ring
@@ -164,7 +172,7 @@ hipError_t render_rows(const gx_ctx* c, int32_t n_rows, const gx_traj* tr, int32
   const int32_t skip = std::max(0, n_rows - tr->rows);
   const uint64_t k = (uint64_t)skip, n = (uint64_t)c->n;
   const gx::RenderSrc src{s.obs + k * s.obs_row, s.reward + k * n, s.flags + k * n, s.action + k * n,
-                          s.mission + k * n, s.obs_row};
+                          s.mission + k * n, s.obs_row, stage_ids(c) + k * (s.obs_row / 3)};
   const gx::RenderDst dst{tr->obs, tr->reward, tr->flags, tr->action, tr->mission, tr->rows};
   return gx::launch_render(src, n_rows - skip, c->n, c->obs_mode == 5, c->d_meta, c->d_grid_off,
                            c->d_cell_rows, c->n_cell_rows, c->d_sprites, dst, (dst_row0 + skip) % tr->rows,

@@ -12,6 +12,13 @@ aside).
     python -m paper_2407_19396_amd.profiling --trace DIR --fetch DIR --write DIR
         [--sq DIR] --copy-bytes N --K K --envs N --command "..." -o profiles/x.txt
 
+``render_summary`` covers the rgb path: the renderer's launches of K rows
+(the one-row launch after a reset left out) against their algorithmic bytes,
+with its calibrated HBM traffic, and the fused launches beside them.
+
+    python -m paper_2407_19396_amd.profiling --render-trace DIR --fetch DIR --write DIR
+        --copy-bytes N --K K --envs N --command "..." -o profiles/z.txt
+
 ``serving_summary`` reads the kernel trace of a serving run instead: how
 busy the device was between the first and the last serving launch, and the
 launches' durations and gaps.
@@ -34,6 +41,9 @@ KERNEL_SOURCES = (KERNEL_SOURCE, os.path.join(HERE, "csrc", "launch.h"))
 COPY_KERNEL = "copyBuffer"
 FUSED = "k_fused"
 PLAIN = "k_plain"
+RENDER = "k_render"
+RGB_FIRST_PERSON_BYTES = 224 * 224 * 3
+RENDER_SOURCES = (os.path.join(HERE, "csrc", "render.hip"), os.path.join(HERE, "csrc", "render.h"))
 
 
 def _code_only(text: str) -> str:
@@ -147,6 +157,58 @@ def traffic_bytes(profile_path: str, K: int, envs: int) -> float | None:
     return None
 
 
+def _dispatches(directory: str, pattern: str, key: str, column: str) -> list:
+    """Per-dispatch values of one kernel, in dispatch order."""
+    path = _one(os.path.join(directory, pattern))
+    rows = [r for r in csv.DictReader(open(path)) if key in r["Kernel_Name"]]
+    if "Dispatch_Id" in (rows[0] if rows else {}):
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    return rows if column is None else [float(r[column]) for r in rows]
+
+
+def render_summary(trace: str, fetch: str, write: str, copy_bytes: int, K: int, envs: int,
+                   command: str) -> str:
+    """The rgb first-person path: renderer launches of K rows each."""
+    tr = _dispatches(trace, "*kernel_trace.csv", RENDER, None)
+    dur = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) for r in tr]
+    full = [d for d in dur if d > 0.5 * max(dur)]          # the one-row reset launch left out
+    fused = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+             for r in _dispatches(trace, "*kernel_trace.csv", FUSED, None)]
+    fc, wc = _counters(fetch), _counters(write)
+    f_scale = copy_bytes / (_mean(fc[(COPY_KERNEL, "FETCH_SIZE")]) * 1024)
+    w_scale = copy_bytes / (_mean(wc[(COPY_KERNEL, "WRITE_SIZE")]) * 1024)
+    rf = _dispatches(fetch, "*counter_collection.csv", RENDER, "Counter_Value")
+    rw = _dispatches(write, "*counter_collection.csv", RENDER, "Counter_Value")
+    big_f = [v for v, w in zip(rf, rw) if w > 0.5 * max(rw)]
+    big_w = [w for w in rw if w > 0.5 * max(rw)]
+    r_fetch = _mean(big_f) * 1024 * f_scale
+    r_write = _mean(big_w) * 1024 * w_scale
+    algo = K * envs * (147 + 7 + RGB_FIRST_PERSON_BYTES + 7)
+    avg = _mean(full)
+    h = hashlib.sha256()
+    for p in RENDER_SOURCES:
+        h.update(_code_only(open(p).read()).encode())
+    lines = [
+        f"# k_render, rgb_first_person, {envs} mixed envs, launches of K = {K} rows (rocprofv3)",
+        "",
+        f"command: {command}",
+        f"renderer code sha256[:16] (render.hip + render.h, comments aside): {h.hexdigest()[:16]}",
+        "",
+        "## kernel trace (--kernel-trace)",
+        f"k_render, {K}-row launches: {len(full)}, average {avg / 1e3:.1f} us "
+        f"(min {min(full) / 1e3:.1f}, max {max(full) / 1e3:.1f})",
+        f"k_fused (fills the staging ring): {len(fused)} launches, average {_mean(fused) / 1e3:.1f} us",
+        f"algorithmic bytes per k_render launch: {algo} (K x envs x (147 + 7 read, 150528 + 7 written))",
+        f"achieved: {algo / avg:.1f} GB/s = {algo / avg / 8000.0:.3f} of 8000 GB/s",
+        "",
+        "## HBM traffic per K-row launch (--pmc FETCH_SIZE, then --pmc WRITE_SIZE)",
+        f"copy probe of {copy_bytes} bytes -> scale fetch x{f_scale:.3f}, write x{w_scale:.3f}",
+        f"k_render: fetch {r_fetch / 1e6:.1f} MB, write {r_write / 1e6:.1f} MB (scaled); "
+        f"traffic / algorithmic bytes = {(r_fetch + r_write) / algo:.3f}",
+    ]
+    return "\n".join(lines) + "\n"
+
+
 def _is_serving_launch(name: str) -> bool:
     # the serving variant of the fused kernel: template arguments <false, true, ...>
     return FUSED in name and ("<false, true" in name or "ILb0ELb1E" in name)
@@ -187,6 +249,7 @@ def serving_summary(trace: str, command: str) -> str:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--serving-trace", help="kernel trace directory of a serving run")
+    ap.add_argument("--render-trace", help="kernel trace directory of an rgb_first_person run")
     ap.add_argument("--trace")
     ap.add_argument("--fetch")
     ap.add_argument("--write")
@@ -201,6 +264,10 @@ def main():
     a = ap.parse_args()
     if a.serving_trace:
         text = serving_summary(a.serving_trace, a.command)
+    elif a.render_trace:
+        if not (a.fetch and a.write and a.copy_bytes and a.K and a.envs):
+            ap.error("--fetch, --write, --copy-bytes, --K and --envs are needed")
+        text = render_summary(a.render_trace, a.fetch, a.write, a.copy_bytes, a.K, a.envs, a.command)
     else:
         if not (a.trace and a.fetch and a.write and a.copy_bytes and a.K and a.envs):
             ap.error("--trace, --fetch, --write, --copy-bytes, --K and --envs are needed")
