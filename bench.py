@@ -356,7 +356,7 @@ def main():
     if not args.no_cpu:
         log("[bench] timing the CPU oracle on a sample")
         if rgb:   # the oracle draws every pixel: a smaller sample
-            cpu = cpu_baseline(table, min(args.cpu_envs or 1024, table.n), args.cpu_steps or 128,
+            cpu = cpu_baseline(table, min(args.cpu_envs or 4096, table.n), args.cpu_steps or 1024,
                                obs_mode, sprites)
         else:
             cpu = cpu_baseline(table, min(args.cpu_envs or table.n, table.n), args.cpu_steps or args.steps)
@@ -390,7 +390,8 @@ def main():
             "fused_over_plain": value / plain_rate},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_fused + k_render" if rgb else "k_fused", "bytes_per_launch": bytes_launch,
+                     "kernel": "k_fused + k_sprite_ids + k_render" if rgb else "k_fused",
+                     "bytes_per_launch": bytes_launch,
                      "launch_ms": per_launch_ms},
         "serving": serving,
         "cpu_baseline": cpu,

@@ -174,6 +174,8 @@ def render_summary(trace: str, fetch: str, write: str, copy_bytes: int, K: int, 
     full = [d for d in dur if d > 0.5 * max(dur)]          # the one-row reset launch left out
     fused = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
              for r in _dispatches(trace, "*kernel_trace.csv", FUSED, None)]
+    ids = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+           for r in _dispatches(trace, "*kernel_trace.csv", "k_sprite_ids", None)]
     fc, wc = _counters(fetch), _counters(write)
     f_scale = copy_bytes / (_mean(fc[(COPY_KERNEL, "FETCH_SIZE")]) * 1024)
     w_scale = copy_bytes / (_mean(wc[(COPY_KERNEL, "WRITE_SIZE")]) * 1024)
@@ -198,6 +200,7 @@ def render_summary(trace: str, fetch: str, write: str, copy_bytes: int, K: int, 
         f"k_render, {K}-row launches: {len(full)}, average {avg / 1e3:.1f} us "
         f"(min {min(full) / 1e3:.1f}, max {max(full) / 1e3:.1f})",
         f"k_fused (fills the staging ring): {len(fused)} launches, average {_mean(fused) / 1e3:.1f} us",
+        f"k_sprite_ids (the renderer's index pass, K rows): average {_mean(sorted(ids)[1:] or ids) / 1e3:.1f} us",
         f"algorithmic bytes per k_render launch: {algo} (K x envs x (147 + 7 read, 150528 + 7 written))",
         f"achieved: {algo / avg:.1f} GB/s = {algo / avg / 8000.0:.3f} of 8000 GB/s",
         "",
