@@ -64,3 +64,39 @@ def test_kernel_hash_ignores_comments_but_not_code(tmp_path):
     a.write_text("int f(int x) { return x + 1; }\n")
     b.write_text("struct S { long y; };\n")
     assert profiling.kernel_source_hash((str(a), str(b))) != h
+
+
+def _write_csv(path, header, rows):
+    import csv
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def test_render_summary_leaves_out_the_reset_launch(tmp_path):
+    """Synthetic rocprofv3 CSVs: two 16-row renderer launches and a one-row
+    launch (after a reset) that must not count; the copy probe calibrates."""
+    K, envs = 16, 1024
+    algo = K * envs * (147 + 7 + 224 * 224 * 3 + 7)
+    tr = tmp_path / "trace"
+    tr.mkdir()
+    _write_csv(tr / "t_kernel_trace.csv", ["Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"],
+               [[1, "k_render<false>", 0, 100_000], [2, "k_fused<false>", 100_000, 110_000],
+                [3, "k_sprite_ids<false>", 110_000, 111_000], [4, "k_render<false>", 111_000, 2_111_000],
+                [5, "k_render<false>", 2_200_000, 4_200_000]])
+    for kind, counter, copy_kib, render_kib in (("fetch", "FETCH_SIZE", 512, 100.0),
+                                                 ("write", "WRITE_SIZE", 1024, algo / 1024)):
+        d = tmp_path / kind
+        d.mkdir()
+        _write_csv(d / "c_counter_collection.csv", ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"],
+                   [[1, "__amd_rocclr_copyBuffer", counter, copy_kib],
+                    [2, "k_render<false>", counter, render_kib / 16],
+                    [3, "k_render<false>", counter, render_kib],
+                    [4, "k_render<false>", counter, render_kib]])
+    text = profiling.render_summary(str(tr), str(tmp_path / "fetch"), str(tmp_path / "write"), 1 << 20,
+                                    K, envs, "cmd")
+    assert "16-row launches: 2, average 2000.0 us" in text
+    assert f"achieved: {algo / 2_000_000:.1f} GB/s" in text
+    # fetch is scaled x2 by the copy probe (512 KiB for 1 MiB), write x1
+    assert f"fetch {2 * 100.0 * 1024 / 1e6:.1f} MB" in text
