@@ -41,15 +41,14 @@ struct RenderDst {
 
 // Draw rows [0, n_rows) of src into rows (dst_row0 + r) % dst.rows of dst and
 // copy their scalar outputs (two launches: sprite indices and scalars, then
-// the images).  whole: records are whole grids, env e's side
-// in bits 8..15 of meta[e] and its offset grid_off[e], and cell_rows lists
-// the n_cell_rows (= sum of sides) cell rows of one staging row as
-// e << 5 | row, in address order; otherwise 7 x 7 views at 147 e, the
-// agent's own cell drawn as the north-facing agent (meta, grid_off and
-// cell_rows unused).  sprites: the device atlas [kSprites][32][32][3].
+// the images).  whole: records are whole grids and cell_rows lists the
+// n_cell_rows (= sum of sides) cell rows of one staging row in address
+// order as (index of the row's first cell among the staging row's cells,
+// grid side); otherwise 7 x 7 views at 147 e, the agent's own cell drawn as
+// the north-facing agent (cell_rows unused).  sprites: the device atlas
+// [kSprites][32][32][3].
 hipError_t launch_render(const RenderSrc& src, int32_t n_rows, int32_t n_envs, bool whole,
-                         const uint32_t* meta, const uint64_t* grid_off, const uint32_t* cell_rows,
-                         uint32_t n_cell_rows, const uint8_t* sprites, const RenderDst& dst,
-                         int32_t dst_row0, hipStream_t stream);
+                         const uint2* cell_rows, uint32_t n_cell_rows, const uint8_t* sprites,
+                         const RenderDst& dst, int32_t dst_row0, hipStream_t stream);
 
 }  // namespace gx

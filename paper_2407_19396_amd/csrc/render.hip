@@ -42,7 +42,6 @@ typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 constexpr int kThreads = 64;                                // one wave per piece
 constexpr int kMaxSide = 32;
 constexpr int kView = 7;
-constexpr int kViewBytes = kView * kView * 3;
 constexpr int kChunk = 16;
 constexpr int kChunksPerSpriteRow = kSprite * 3 / kChunk;   // 6
 constexpr int kPieceRows = 8;                               // image rows per piece
@@ -67,9 +66,8 @@ struct RenderArgs {
   int32_t row0;              // first staging row of this launch
   int32_t dst_row0;          // caller row of staging row 0
   uint32_t pieces_per_row;   // first person: 28 n; whole grids: 4 * sum of sides
-  const uint32_t* crow;      // whole grids: env << 5 | cell row, per cell row of a staging row
-  const uint32_t* meta;
-  const uint64_t* grid_off;
+  uint32_t cells_per_row;    // sym_row / 3
+  const uint2* crow;         // whole grids, per cell row: (index of its first cell, width)
   const uint8_t* sprites;
 };
 
@@ -115,20 +113,19 @@ __global__ __launch_bounds__(kThreads) void k_render(RenderArgs a) {
   const uint32_t pc = b - rr * a.pieces_per_row;
   const int r = a.row0 + (int)rr;
   const int quarter = (int)(pc & (kPiecesPerCellRow - 1));
-  int e, cy, W;
+  // the cell row's first cell (its index among the row's cells) and width;
+  // its image starts at kSpriteBytes times that index in the record row
+  uint32_t start;
+  int W;
   if (kWhole) {
-    const uint32_t cr = a.crow[pc / kPiecesPerCellRow];
-    e = (int)(cr >> 5);
-    cy = (int)(cr & 31u);
-    W = (int)((a.meta[e] >> 8) & 0xFFu);
+    const uint2 cr = a.crow[pc / kPiecesPerCellRow];
+    start = cr.x;
+    W = (int)cr.y;
   } else {
-    e = (int)(pc / (kView * kPiecesPerCellRow));
-    cy = (int)(pc - (uint32_t)e * (kView * kPiecesPerCellRow)) / kPiecesPerCellRow;
+    start = (pc / kPiecesPerCellRow) * kView;   // env pc / 28, cell row (pc % 28) / 4
     W = kView;
   }
-  const uint64_t off = kWhole ? a.grid_off[e] : (uint64_t)e * kViewBytes;
-  if (lane < W)
-    ids[lane] = a.src.ids[((uint64_t)r * a.src.sym_row + off) / 3u + (uint32_t)(cy * W + lane)];
+  if (lane < W) ids[lane] = a.src.ids[(uint64_t)r * a.cells_per_row + start + (uint32_t)lane];
   const int drow = (a.dst_row0 + r) % a.dst.rows;
   __syncthreads();
   const int row_chunks = kChunksPerSpriteRow * W;   // 16-byte chunks per image row
@@ -137,8 +134,8 @@ __global__ __launch_bounds__(kThreads) void k_render(RenderArgs a) {
   // q / row_chunks for q < 48 W, row_chunks = 6 W in [24, 192]: exact by
   // multiplication with floor(2^20 / row_chunks) + 1 (checked for every W)
   const uint32_t inv = (1u << 20) / (uint32_t)row_chunks + 1u;
-  v4u* out = reinterpret_cast<v4u*>(a.dst.obs + ((uint64_t)drow * a.src.sym_row + off) * kRgbScale +
-                                    (uint64_t)(cy * kSprite + py0) * (uint64_t)(row_chunks * kChunk));
+  v4u* out = reinterpret_cast<v4u*>(a.dst.obs + (uint64_t)drow * a.src.sym_row * kRgbScale +
+                                    (uint64_t)start * kSpriteBytes + (uint64_t)py0 * (uint64_t)(row_chunks * kChunk));
   const v4u* atlas = reinterpret_cast<const v4u*>(a.sprites);
   for (int q0 = 0; q0 < chunks; q0 += kInFlight * kThreads) {
     v4u v[kInFlight];
@@ -165,9 +162,8 @@ __global__ __launch_bounds__(kThreads) void k_render(RenderArgs a) {
 }  // namespace
 
 hipError_t launch_render(const RenderSrc& src, int32_t n_rows, int32_t n_envs, bool whole,
-                         const uint32_t* meta, const uint64_t* grid_off, const uint32_t* cell_rows,
-                         uint32_t n_cell_rows, const uint8_t* sprites, const RenderDst& dst,
-                         int32_t dst_row0, hipStream_t stream) {
+                         const uint2* cell_rows, uint32_t n_cell_rows, const uint8_t* sprites,
+                         const RenderDst& dst, int32_t dst_row0, hipStream_t stream) {
   if (n_rows <= 0 || n_envs <= 0) return hipSuccess;
   const uint64_t per_row = whole ? (uint64_t)kPiecesPerCellRow * n_cell_rows
                                  : (uint64_t)kView * kPiecesPerCellRow * (uint64_t)n_envs;
@@ -188,7 +184,7 @@ hipError_t launch_render(const RenderSrc& src, int32_t n_rows, int32_t n_envs, b
   const int32_t rows_per_launch = (int32_t)std::max<uint64_t>(1, (uint64_t)INT32_MAX / per_row);
   for (int32_t r0 = 0; r0 < n_rows; r0 += rows_per_launch) {
     const int32_t nr = std::min(rows_per_launch, n_rows - r0);
-    RenderArgs a{src, dst, n_envs, r0, dst_row0, (uint32_t)per_row, cell_rows, meta, grid_off, sprites};
+    RenderArgs a{src, dst, n_envs, r0, dst_row0, (uint32_t)per_row, (uint32_t)cells_per_row, cell_rows, sprites};
     const dim3 grid((uint32_t)(per_row * (uint64_t)nr));
     if (whole)
       hipLaunchKernelGGL(k_render<true>, grid, dim3(kThreads), 0, stream, a);

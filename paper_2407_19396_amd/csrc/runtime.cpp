@@ -38,7 +38,7 @@ struct gx_ctx {
   uint8_t* d_sprites = nullptr;
   uint8_t* d_stage = nullptr;
   int32_t stage_rows = 0;
-  uint32_t* d_cell_rows = nullptr;   // rgb: env << 5 | row for every cell row of the grids
+  uint2* d_cell_rows = nullptr;      // rgb whole grids: (first cell index, side) per cell row
   uint32_t n_cell_rows = 0;
 };
 
@@ -174,9 +174,8 @@ hipError_t render_rows(const gx_ctx* c, int32_t n_rows, const gx_traj* tr, int32
   const gx::RenderSrc src{s.obs + k * s.obs_row, s.reward + k * n, s.flags + k * n, s.action + k * n,
                           s.mission + k * n, s.obs_row, stage_ids(c) + k * (s.obs_row / 3)};
   const gx::RenderDst dst{tr->obs, tr->reward, tr->flags, tr->action, tr->mission, tr->rows};
-  return gx::launch_render(src, n_rows - skip, c->n, c->obs_mode == 5, c->d_meta, c->d_grid_off,
-                           c->d_cell_rows, c->n_cell_rows, c->d_sprites, dst, (dst_row0 + skip) % tr->rows,
-                           stream);
+  return gx::launch_render(src, n_rows - skip, c->n, c->obs_mode == 5, c->d_cell_rows, c->n_cell_rows,
+                           c->d_sprites, dst, (dst_row0 + skip) % tr->rows, stream);
 }
 
 int check_device(const gx_ctx* c) {
@@ -257,9 +256,10 @@ int env_create(const gx_config* cfg, gx_ctx** out) {
     std::vector<uint8_t> atlas(cfg->sprites, cfg->sprites + (size_t)gx::kSprites * gx::kSpriteBytes);
     rc = upload(&c->d_sprites, atlas);
     if (rc == GX_OK && c->obs_mode == 5) {
-      std::vector<uint32_t> cell_rows;
+      std::vector<uint2> cell_rows;
       for (int32_t i = 0; i < n; ++i)
-        for (uint32_t y = 0; y < cfg->side[i]; ++y) cell_rows.push_back(((uint32_t)i << 5) | y);
+        for (uint32_t y = 0; y < cfg->side[i]; ++y)
+          cell_rows.push_back(make_uint2((uint32_t)(grid_off[i] / 3 + (uint64_t)y * cfg->side[i]), cfg->side[i]));
       c->n_cell_rows = (uint32_t)cell_rows.size();
       rc = upload(&c->d_cell_rows, cell_rows);
     }
