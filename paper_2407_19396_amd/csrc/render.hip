@@ -16,17 +16,20 @@
 // non-temporal stores; reading them from the draw pass, one dependent load
 // at the start of every short-lived wave, cost 15 % of the draw's time.
 //
-// Draw pass: one 64-lane wave per piece of 8 image rows of one cell row
-// (8 * 96 W contiguous bytes; 5.25 KB for a first-person view), pieces
+// Draw pass: one 64-lane wave per piece of 2 image rows of one cell row
+// (2 * 96 W contiguous bytes; 1344 B for a first-person view), pieces
 // numbered in address order, a non-persistent grid.  HBM write bandwidth
 // depends on the order the chip's stores arrive in: small pieces handed
 // out in address order keep every compute unit's stores inside one narrow
-// window sweeping the output, which measures about 20 % faster than
+// window sweeping the output, which measures about 25 % faster than
 // workgroups that each stream a whole 150 KB image (the same bytes, more
-// scattered).  Lanes 0..W-1 read the cell row's sprite indices; each
-// 16-byte chunk of the piece lies inside one sprite row of one cell,
-// so it is one 16-byte atlas load (the atlas, 811 KB, stays in L2) and one
-// non-temporal 16-byte store, four chunks per lane in flight.
+// scattered).  Measured on 16 rows of 16 384 first-person images: pieces
+// of 16, 8, 4 and 2 rows take 6.87, 6.86, 6.67 and 6.42 ms; pieces of one
+// row leave 22 of 64 lanes idle and take 12.4 ms.  Lanes 0..W-1 read the
+// cell row's sprite indices; each 16-byte chunk of the piece lies inside
+// one sprite row of one cell, so it is one 16-byte atlas load (the atlas,
+// 811 KB, stays in L2) and one non-temporal 16-byte store, two chunks per
+// lane in flight.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -44,9 +47,9 @@ constexpr int kMaxSide = 32;
 constexpr int kView = 7;
 constexpr int kChunk = 16;
 constexpr int kChunksPerSpriteRow = kSprite * 3 / kChunk;   // 6
-constexpr int kPieceRows = 8;                               // image rows per piece
-constexpr int kPiecesPerCellRow = kSprite / kPieceRows;     // 4
-constexpr int kInFlight = 4;                                // chunks per lane per round
+constexpr int kPieceRows = 2;                               // image rows per piece
+constexpr int kPiecesPerCellRow = kSprite / kPieceRows;     // 16
+constexpr int kInFlight = 2;                                // chunks per lane per round
 constexpr int kIdThreads = 256;
 constexpr uint32_t kAgentCell = (kView - 1) * kView + 3;    // the agent's own cell in a view
 constexpr uint32_t kAgentType = 10, kNorth = 3;
@@ -65,7 +68,7 @@ struct RenderArgs {
   int32_t n;                 // envs
   int32_t row0;              // first staging row of this launch
   int32_t dst_row0;          // caller row of staging row 0
-  uint32_t pieces_per_row;   // first person: 28 n; whole grids: 4 * sum of sides
+  uint32_t pieces_per_row;   // first person: 7 * 16 n; whole grids: 16 * sum of sides
   uint32_t cells_per_row;    // sym_row / 3
   const uint2* crow;         // whole grids, per cell row: (index of its first cell, width)
   const uint8_t* sprites;
@@ -112,7 +115,7 @@ __global__ __launch_bounds__(kThreads) void k_render(RenderArgs a) {
   const uint32_t rr = b / a.pieces_per_row;
   const uint32_t pc = b - rr * a.pieces_per_row;
   const int r = a.row0 + (int)rr;
-  const int quarter = (int)(pc & (kPiecesPerCellRow - 1));
+  const int piece = (int)(pc & (kPiecesPerCellRow - 1));   // within the cell row
   // the cell row's first cell (its index among the row's cells) and width;
   // its image starts at kSpriteBytes times that index in the record row
   uint32_t start;
@@ -122,7 +125,7 @@ __global__ __launch_bounds__(kThreads) void k_render(RenderArgs a) {
     start = cr.x;
     W = (int)cr.y;
   } else {
-    start = (pc / kPiecesPerCellRow) * kView;   // env pc / 28, cell row (pc % 28) / 4
+    start = (pc / kPiecesPerCellRow) * kView;   // env pc / 112, cell row (pc % 112) / 16
     W = kView;
   }
   if (lane < W) ids[lane] = a.src.ids[(uint64_t)r * a.cells_per_row + start + (uint32_t)lane];
@@ -130,8 +133,8 @@ __global__ __launch_bounds__(kThreads) void k_render(RenderArgs a) {
   __syncthreads();
   const int row_chunks = kChunksPerSpriteRow * W;   // 16-byte chunks per image row
   const int chunks = kPieceRows * row_chunks;
-  const int py0 = quarter * kPieceRows;             // first sprite row of the piece
-  // q / row_chunks for q < 48 W, row_chunks = 6 W in [24, 192]: exact by
+  const int py0 = piece * kPieceRows;               // first sprite row of the piece
+  // q / row_chunks for q < 12 W, row_chunks = 6 W in [24, 192]: exact by
   // multiplication with floor(2^20 / row_chunks) + 1 (checked for every W)
   const uint32_t inv = (1u << 20) / (uint32_t)row_chunks + 1u;
   v4u* out = reinterpret_cast<v4u*>(a.dst.obs + (uint64_t)drow * a.src.sym_row * kRgbScale +
