@@ -38,3 +38,35 @@ def test_graph_replays_match_eager(K):
         for f in P.FIELDS:
             np.testing.assert_array_equal(sg[f], se[f], err_msg=f"replay {replay}: state {f}")
     assert (eager.state_numpy()["calls"] == 4 * K).all()
+
+
+@pytest.mark.parametrize("mode", [4, 5])
+def test_rgb_graph_replays_match_eager(mode):
+    """The rgb path (fused launches, index passes and draws, no allocation)
+    captured whole: every replay equals the eager rollout."""
+    import torch
+    from paper_2407_19396_amd import gridenv as ge
+    table = wl.mixed_table(200, seed=5, mix_seed=6)
+    sprites = np.random.default_rng(mode).integers(0, 256, (264, 32, 32, 3), dtype=np.uint8)
+    eager = ge.GridEnv(table, obs_mode=mode, sprites=sprites)
+    eager.reset()
+    tr_e = eager.traj(6)
+    graph = ge.GridEnv(table, obs_mode=mode, sprites=sprites)
+    graph.reset()
+    tr_g = graph.traj(6)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        graph.rollout(10, tr_g, K=4)         # three fused launches, the ring wrapped
+    noise = torch.zeros(1 << 20, device="cuda")
+    for replay in range(3):
+        eager.rollout(10, tr_e, K=4)
+        g.replay()
+        noise.add_(1.0)
+        torch.cuda.synchronize()
+        for f in ("obs", "reward", "flags", "action", "mission"):
+            np.testing.assert_array_equal(P.to_np(getattr(tr_g, f)), P.to_np(getattr(tr_e, f)),
+                                          err_msg=f"replay {replay}: {f}")
+        se, sg = eager.state_numpy(), graph.state_numpy()
+        for f in P.FIELDS:
+            np.testing.assert_array_equal(sg[f], se[f], err_msg=f"replay {replay}: state {f}")
