@@ -17,7 +17,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gridworld_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+_LIB = os.environ.get("OX_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
+_SAN_LIB = os.path.join(_HERE, "liboracle_san.so")
 
 # encoding of the oracle (MiniGrid's canonical indices)
 EMPTY, WALL, DOOR, KEY, GOAL = 1, 2, 4, 5, 8
@@ -34,15 +35,22 @@ N_SPRITES = 11 * 6 * 4             # atlas entries: (type * 6 + colour) * 4 + st
 RGB_FP = (7 * SPRITE, 7 * SPRITE, 3)
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no FMA contraction, no fast math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
+
+
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (no FMA contraction, no fast math).
+    sanitize: an AddressSanitizer + UndefinedBehaviorSanitizer build at
+    liboracle_san.so instead (load it by setting OX_ORACLE_LIB to its path
+    in a process that preloads libasan)."""
+    out = _SAN_LIB if sanitize else _LIB
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
         cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
                "-fopenmp", "-shared", "-fPIC", "-Wall", "-Wextra",
-               "-o", _LIB + ".tmp", _SRC]
+               *(SAN_FLAGS if sanitize else []), "-o", out + ".tmp", _SRC]
         subprocess.run(cmd, check=True)
-        os.replace(_LIB + ".tmp", _LIB)
-    return _LIB
+        os.replace(out + ".tmp", out)
+    return out
 
 
 _lib = None
@@ -67,7 +75,8 @@ class _State(ctypes.Structure):
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not os.environ.get("OX_ORACLE_LIB") and (
+                not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
             build(force=True)
         L = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p

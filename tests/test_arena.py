@@ -6,14 +6,14 @@ import subprocess
 
 import pytest
 
-CSRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
-                    "paper_2407_19396_amd", "csrc")
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(os.path.dirname(HERE), "paper_2407_19396_amd", "csrc")
 
 
 @pytest.fixture(scope="module")
 def binary(tmp_path_factory):
     out = str(tmp_path_factory.mktemp("arena") / "arena_check")
-    subprocess.run(["g++", "-O2", "-std=c++17", "-I", CSRC, os.path.join(CSRC, "arena_check.cpp"),
+    subprocess.run(["g++", "-O2", "-std=c++17", "-I", CSRC, os.path.join(HERE, "arena_check.cpp"),
                     "-o", out], check=True)
     return out
 
