@@ -4,21 +4,34 @@
 Workload: 262144 envs of uneven sizes (40 % single rooms and 40 % two-room
 key/door layouts with side in {5, 6, 8, 16}, 20 % 19x19 four-room
 layouts), uniform random actions drawn on the device, every env-step
-writing its record (147-byte observation, fp32 reward, flags, action) to
-an HBM trajectory ring.  One benchmark "step" is one environment step of
-the whole batch; the fused persistent kernel runs K of them per launch.
+writing its record (147-byte symbolic first-person observation, fp32
+reward, flags, action) to an HBM trajectory ring.  One benchmark "step" is
+one environment step of the whole batch; the fused persistent kernel runs
+K of them per launch.
 
-Reported beside it on the same input: the plain one-launch-per-step
-kernel, per-launch latency percentiles, five repeats of the timed rollout,
-the dominant kernel's roofline position (with the HBM traffic of the
-committed rocprofv3 summary when it was taken of this kernel's code), the
-native serving loop at three offered loads, and the CPU oracle's rate on
-its whole job and on one thread.  --workload and --obs select the other
-task mixes and observation functions.
+Reported beside it:
+  * roofline: the fused launches of the timed region (algorithmic bytes of
+    the steps they ran over their HIP-event time) and, under steady_state,
+    launches of K steps; each with the calibrated HBM traffic of the
+    committed rocprofv3 summary taken of that launch shape and kernel code;
+  * the plain one-launch-per-step kernel on the same input, per-launch
+    latency percentiles, five repeats of the timed rollout;
+  * configs: the smaller workloads as their own legs -- 16 Empty 5x5 and
+    4096 Empty 8x8 through the plain kernel with external uniform actions
+    (per-launch latency), 65536 TwoRoom 8x8 through the fused kernel with
+    the rollout captured in a HIP graph and its replay timed;
+  * serving: the native Poisson loop -- its capacity from a saturated run,
+    then 0.5 / 0.8 / 0.95 of it, with results left in HBM (device-ready
+    latency) and with each request's scalar outputs delivered to pinned host
+    memory (host-ready latency, anchored on the delivering loop's own
+    saturated capacity);
+  * cpu_baseline: the oracle on the host's cores on a bounded sample.
+--workload and --obs select the other task mixes and observation functions.
 """
 from __future__ import annotations
 
 import argparse
+import glob
 import json
 import os
 import sys
@@ -33,6 +46,10 @@ HBM_PEAK_GBS = 8000.0
 OBS = 147
 RECORD_BYTES = OBS + 4 + 1 + 1          # obs + reward + flags + action per env-step
 STATE_BYTES_PER_ENV = 4 * 5 + 4 + 1 + 4 + 16  # x, y, dir, t, carry + episode + done_prev + calls + obstacles
+# plain kernel per env-step: state and tables read (x, y, dir, t, carry, episode, done_prev, calls,
+# meta, max_steps, seed, rng_id, grid_off), the view's cells, the state written, the record
+PLAIN_READ = 4 * 5 + 4 + 1 + 4 + 4 + 4 + 8 + 4 + 8
+PLAIN_WRITE = 4 * 5 + 4 + 1 + 4
 
 
 WORKLOADS = {
@@ -56,13 +73,14 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-OBS_MODES = {"symbolic": 0, "categorical": 1, "symbolic_grid": 2, "categorical_grid": 3,
+# observation functions by the names of the paper's table of observations
+OBS_MODES = {"symbolic_first_person": 0, "categorical_first_person": 1, "symbolic": 2, "categorical": 3,
              "rgb_first_person": 4, "rgb": 5}
 RGB_SCALE = 1024   # rgb bytes per symbolic byte (32 x 32 pixels per cell)
 RING_BUDGET = 64 << 30   # bytes of HBM the trajectory ring of one launch may take
 
 
-def fused_bytes(n_envs: int, grid_bytes: int, k: int, obs_bytes: int = OBS) -> float:
+def fused_bytes(n_envs: int, grid_bytes: int, k: int, obs_bytes: float = OBS) -> float:
     """Algorithmic HBM bytes of one fused launch of k steps: every record
     written once, the state (grids + scalars) read and written once."""
     record = obs_bytes + 4 + 1 + 1
@@ -77,17 +95,46 @@ def rgb_path_bytes(n_envs: int, grid_bytes: int, k: int, sym_bytes: float) -> fl
     return fused_bytes(n_envs, grid_bytes, k, sym_bytes) + render
 
 
+def chunks(steps: int, K: int) -> list:
+    """Steps run by each fused launch of a rollout of `steps` steps."""
+    return [K] * (steps // K) + ([steps % K] if steps % K else [])
+
+
+def profile_traffic(workload: str, k: int, n_envs: int):
+    """Calibrated HBM bytes of one k-step launch from the committed
+    rocprofv3 summaries of this workload, or None."""
+    from paper_2407_19396_amd import profiling
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"k_fused_{workload}{n_envs}_*.txt"))):
+        t = profiling.traffic_bytes(path, k, n_envs)
+        if t is not None:
+            return t
+    return None
+
+
+def roofline_entry(bytes_per_launch: float, launch_ms: float, traffic=None, **extra) -> dict:
+    achieved = bytes_per_launch / (launch_ms / 1e3) / 1e9
+    frac = achieved / HBM_PEAK_GBS
+    if not frac <= 1.0:
+        raise SystemExit(f"bench.py: roofline fraction {frac:.3f} > 1 ({bytes_per_launch:.4g} B in "
+                         f"{launch_ms:.4g} ms): the byte or time accounting is wrong")
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": frac,
+            "traffic": traffic, "bytes_per_launch": bytes_per_launch, "launch_ms": launch_ms, **extra}
+
+
+def host_threads() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
 def cpu_baseline(table, n_envs: int, n_steps: int, obs_mode: int = 0, sprites=None) -> dict:
     import oracle as ox
     sub = table.subset(np.arange(n_envs))
     b = ox.Batch(sub.family, sub.side, sub.max_steps, sub.seed, sub.rng_id, 0, sub.param, obs_mode,
                  sprites)
     s = ox.State.empty(b)
-    threads = os.cpu_count() or 1
-    try:
-        threads = len(os.sched_getaffinity(0))
-    except AttributeError:
-        pass
+    threads = host_threads()
     rows = 1 if obs_mode >= 4 else 16   # rgb records are 1024 times larger
     ox.reset(b, s, nthreads=threads)
     t0 = time.perf_counter()
@@ -110,9 +157,31 @@ def cpu_baseline(table, n_envs: int, n_steps: int, obs_mode: int = 0, sprites=No
                               "sample": f"first {n1} envs, {n_steps} steps, {dt1:.1f} s"}}
 
 
-def run_serving(capacity: float, n_requests: int, loads, K: int, budget_gib: int,
-                inflight: int = 2) -> list:
-    """Poisson serving at fractions of the measured fused capacity."""
+def pct(xs, q):
+    return float(np.percentile(np.asarray(xs), q))
+
+
+def serving_run(ge, wl, srv, n_requests, rate, K, budget, arena, inflight, host=None, seed=0) -> dict:
+    reqs = wl.serving_requests(n_requests, rate, master_seed=seed)
+    res = ge.serve_run(srv, reqs, K, budget, arena, max_inflight=inflight, host_arena=host)
+    lat = res["latency_s"] * 1e3
+    wait = (res["admit_s"] - res["arrival_s"]) * 1e3
+    rec = {"requests": n_requests, "completed": res["completed"], "rate_req_per_s": rate,
+           "env_steps_per_s": res["env_steps"] / res["wall_s"], "wall_s": res["wall_s"],
+           "launches": res["launches"],
+           "host_s": {"admit": res["host_admit_s"], "step": res["host_step_s"], "wait": res["host_wait_s"]},
+           "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
+           "admission_wait_ms": {"p50": pct(wait, 50), "p99": pct(wait, 99)}}
+    if host is not None:
+        hl = res["host_latency_s"] * 1e3
+        rec["host_latency_ms"] = {"p50": pct(hl, 50), "p99": pct(hl, 99)}
+    return rec
+
+
+def run_serving(n_requests: int, loads, K: int, budget_gib: int, inflight: int = 2) -> dict:
+    """Poisson serving: capacity from a saturated run (every request arrives
+    at once), then fractions of it; once with results left in HBM, once
+    with every request's scalar outputs delivered to pinned host memory."""
     import torch
     from paper_2407_19396_amd import gridenv as ge
     from paper_2407_19396_amd import workloads as wl
@@ -122,27 +191,133 @@ def run_serving(capacity: float, n_requests: int, loads, K: int, budget_gib: int
     srv = ge.Server(max_tiles=16384, max_side=19)
     budget = budget_gib << 30
     arena = torch.empty(budget - srv.info()["device_bytes"], dtype=torch.uint8, device="cuda")
-    out = []
-    for load in loads:
-        rate = load * capacity / ework
-        reqs = wl.serving_requests(n_requests, rate, master_seed=int(load * 1000))
-        res = ge.serve_run(srv, reqs, K, budget, arena, max_inflight=inflight)
-        lat = res["latency_s"] * 1e3
-        wait = (res["admit_s"] - res["arrival_s"]) * 1e3
-        rec = {"load": load, "requests": n_requests, "completed": res["completed"],
-               "rate_req_per_s": rate, "mean_env_steps_per_request": ework,
-               "env_steps_per_s": res["env_steps"] / res["wall_s"], "wall_s": res["wall_s"],
-               "launches": res["launches"],
-               "host_s": {"admit": res["host_admit_s"], "step": res["host_step_s"],
-                          "wait": res["host_wait_s"]},
-               "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-               "admission_wait_ms": {"p50": float(np.percentile(wait, 50)),
-                                     "p99": float(np.percentile(wait, 99))}}
-        log(f"[bench] serving load {load}: {rec['env_steps_per_s'] / 1e9:.2f} G env-steps/s, "
-            f"latency p50 {rec['latency_ms']['p50']:.1f} ms p99 {rec['latency_ms']['p99']:.1f} ms")
-        out.append(rec)
+    host = torch.empty(4 << 30, dtype=torch.uint8, pin_memory=True)
+    out = {"K": K, "budget_gib": budget_gib, "mean_env_steps_per_request": ework,
+           "request_mix": "log-uniform 1..8192 envs of the mixed workload, n_steps uniform 64..1024"}
+    for name, h in (("device", None), ("host", host)):
+        sat = serving_run(ge, wl, srv, n_requests, 1e9, K, budget, arena, inflight, h, seed=4321)
+        cap = sat["env_steps_per_s"]
+        log(f"[bench] serving ({name}-ready results) capacity: {cap / 1e9:.2f} G env-steps/s")
+        levels = []
+        for load in loads:
+            rec = serving_run(ge, wl, srv, n_requests, load * cap / ework, K, budget, arena, inflight, h,
+                              seed=int(load * 1000))
+            rec["load"] = load
+            key = "host_latency_ms" if h is not None else "latency_ms"
+            log(f"[bench] serving load {load} ({name}): {rec['env_steps_per_s'] / 1e9:.2f} G env-steps/s, "
+                f"latency p50 {rec[key]['p50']:.1f} ms p99 {rec[key]['p99']:.1f} ms")
+            levels.append(rec)
+        out[name] = {"capacity_env_steps_per_s": cap, "saturated": sat, "loads": levels}
+    out["host"]["delivered"] = "reward, flags and action of every env-step (6 B) to pinned host memory; " \
+                               "observations stay in HBM"
     srv.close()
-    del arena
+    del arena, host
+    return out
+
+
+def plain_leg(ge, wl, table, n_steps: int, seed: int) -> dict:
+    """A workload through the plain kernel, one launch per step, external
+    uniform actions: rate over all launches and per-launch latency."""
+    import torch
+    env = ge.GridEnv(table)
+    traj = env.traj(n_steps)
+    acts = torch.from_numpy(wl.random_actions(n_steps, table.n, seed=seed)).to("cuda")
+    stream = torch.cuda.current_stream()
+    env.reset()
+    for k in range(min(8, n_steps)):
+        env.step(traj.row(k), acts[k])
+    env.reset()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for k in range(n_steps):
+        env.step(traj.row(k), acts[k])
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    lat = []
+    env.reset()
+    for k in range(n_steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        env.step(traj.row(k), acts[k])
+        e1.record(stream)
+        e1.synchronize()
+        lat.append(e0.elapsed_time(e1))
+    env.close()
+    return {"value": table.n * n_steps / (ms / 1e3), "unit": "env-steps/s", "steps": n_steps,
+            "kernel": "k_plain", "ms": ms, "launch_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)}}
+
+
+def graph_leg(ge, wl, table, n_steps: int, warmup: int) -> dict:
+    """A workload through the fused kernel with the on-device policy, K
+    autotuned, the whole rollout captured in a HIP graph and its replay
+    timed; per-chunk latency from eager launches of K steps."""
+    import torch
+    from paper_2407_19396_amd import autotune
+    env = ge.GridEnv(table)
+    Ks = tuple(k for k in (64, 128, 256, 512, 1024, 2048) if k <= n_steps)
+    probe = env.traj(max(Ks))
+    env.reset()
+    tuned = autotune.tune(env, probe, Ks=Ks, steps=max(Ks), log=None)
+    del probe
+    K = env.info()["k_default"]
+    traj = env.traj(K)
+    env.reset()
+    env.rollout(warmup, traj, K=K)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        env.rollout(n_steps, traj, K=K)
+    graph.replay()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    reps = []
+    for _ in range(5):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        graph.replay()
+        b.record(stream)
+        b.synchronize()
+        reps.append(a.elapsed_time(b))
+    ms = float(np.median(reps))
+    lat = []
+    for _ in range(16):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        env.rollout(K, traj, K=K)
+        b.record(stream)
+        b.synchronize()
+        lat.append(a.elapsed_time(b))
+    info = env.info()
+    cs = chunks(n_steps, K)
+    total = sum(fused_bytes(table.n, info["grid_bytes"], k) for k in cs)
+    roof = roofline_entry(total / len(cs), ms / len(cs), None, kernel="k_fused", launches=len(cs),
+                          steps_per_launch=K, timing="median of 5 graph replays")
+    env.close()
+    del graph
+    return {"value": table.n * n_steps / (ms / 1e3), "unit": "env-steps/s", "steps": n_steps, "K": K,
+            "blocks": info["blocks"], "autotuned": True, "cached_tuning": bool(tuned.get("cached")),
+            "hip_graph": True, "replay_ms": ms, "replay_ms_range": [min(reps), max(reps)],
+            "chunk_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)}, "roofline": roof}
+
+
+def run_configs(steps_c3: int) -> dict:
+    from paper_2407_19396_amd import gridenv as ge
+    from paper_2407_19396_amd import workloads as wl
+    out = {}
+    t = wl.workload_empty5(seed=0)
+    out["empty5_plain"] = {"workload": "16 Empty 5x5, T=100, 100 steps of external uniform actions, "
+                                       "plain kernel (one launch per step)", **plain_leg(ge, wl, t, 100, 1)}
+    t = wl.workload_empty8(seed=0)
+    out["empty8_plain"] = {"workload": "4096 Empty 8x8, T=256, 1000 steps of external uniform actions, "
+                                       "plain kernel (one launch per step)", **plain_leg(ge, wl, t, 1000, 2)}
+    t = wl.workload_tworoom8(seed=0)
+    out["tworoom8_graph"] = {"workload": f"65536 TwoRoom key/door 8x8, T=640, {steps_c3} steps, random "
+                                         "policy on device, fused kernel, rollout captured in a HIP graph",
+                             **graph_leg(ge, wl, t, steps_c3, 256)}
+    for k, v in out.items():
+        log(f"[bench] {k}: {v['value'] / 1e9:.3f} G env-steps/s")
     return out
 
 
@@ -160,20 +335,25 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner, use library defaults")
     ap.add_argument("--ring", type=int, default=0, help="trajectory ring rows (0: K)")
     ap.add_argument("--plain-steps", type=int, default=512)
-    ap.add_argument("--obs", default="symbolic", choices=list(OBS_MODES),
-                    help="observation function: symbolic (147 B) or categorical (49 B) first person, "
-                         "the whole grid: symbolic_grid (3 S^2 B) or categorical_grid (S^2 B), or "
-                         "images drawn with the default sprites: rgb_first_person (150528 B) or rgb "
-                         "(3072 S^2 B); the rgb modes default to 16384 envs and K = 16")
+    ap.add_argument("--obs", default="symbolic_first_person", choices=list(OBS_MODES),
+                    help="observation function (the paper's names): symbolic_first_person (147 B) or "
+                         "categorical_first_person (49 B), the whole grid: symbolic (3 S^2 B) or "
+                         "categorical (S^2 B), or images drawn with the default sprites: "
+                         "rgb_first_person (150528 B) or rgb (3072 S^2 B); the rgb modes default to "
+                         "16384 envs and K = 16")
     ap.add_argument("--graph", action="store_true",
                     help="capture the timed rollout in a HIP graph and time its replay")
     ap.add_argument("--plain-actions", action="store_true",
                     help="plain steps take an external action buffer instead of the device policy")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the small-workload legs (Empty 5x5 and 8x8 plain, TwoRoom 8x8 graph)")
+    ap.add_argument("--c3-steps", type=int, default=2048, help="steps of the TwoRoom 8x8 graph leg")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-envs", type=int, default=0, help="CPU oracle sample envs (0: all)")
-    ap.add_argument("--cpu-steps", type=int, default=0, help="CPU oracle sample steps (0: --steps)")
+    ap.add_argument("--cpu-steps", type=int, default=2048,
+                    help="CPU oracle sample steps (about 10 s on 16 host threads for the mixed batch)")
     ap.add_argument("--serve-requests", type=int, default=10000,
-                    help="requests per serving load level (0: skip serving)")
+                    help="requests per serving run (0: skip serving)")
     ap.add_argument("--serve-K", type=int, default=256)
     ap.add_argument("--serve-inflight", type=int, default=2, help="launches enqueued ahead of the device")
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95")
@@ -274,10 +454,10 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = start.elapsed_time(stop)
-    launches = -(-args.steps // K)
+    timed_chunks = chunks(args.steps, K)
     env_steps = table.n * args.steps
     value = env_steps / (ms / 1e3)
-    log(f"[bench] fused: {args.steps} steps in {ms:.1f} ms ({wall * 1e3:.1f} ms wall), "
+    log(f"[bench] fused: {args.steps} steps in {ms:.3f} ms ({wall * 1e3:.1f} ms wall), "
         f"{value / 1e9:.2f} G env-steps/s")
 
     # the same timed rollout repeated, for its spread
@@ -292,9 +472,9 @@ def main():
         b.record(stream)
         b.synchronize()
         reps.append(env_steps / (a.elapsed_time(b) / 1e3))
-    # per-launch latency of the fused kernel
+    # per-launch latency of the fused kernel at K steps per launch
     lat = []
-    for _ in range(min(64, max(8, launches))):
+    for _ in range(min(64, max(8, len(timed_chunks)))):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
         env.rollout(K, traj, K=K)
@@ -304,8 +484,7 @@ def main():
     lat = np.array(lat)
 
     # plain kernel on the same input, writing a ring of the same size
-    plain_rate = None
-    plain_lat = None
+    plain = None
     if args.plain_steps > 0:
         rows = [traj.row(r) for r in range(traj.rows)]
         acts = None
@@ -330,36 +509,58 @@ def main():
             b.record(stream)
             b.synchronize()
             pl.append(a.elapsed_time(b))
-        plain_lat = np.array(pl)
+        plain = {"value": plain_rate, "unit": "env-steps/s", "steps": args.plain_steps,
+                 "launch_ms": {"p50": pct(pl, 50), "p99": pct(pl, 99)},
+                 "fused_over_plain": value / plain_rate}
+        if obs_mode == 0:
+            # algorithmic bytes of a plain step: state, view cells (at most 49 in the grid), record
+            cells = float(np.mean(np.minimum(49, table.side.astype(np.int64) ** 2)))
+            per_step = table.n * (PLAIN_READ + 3 * cells + PLAIN_WRITE + RECORD_BYTES)
+            plain["roofline"] = roofline_entry(per_step, pms / args.plain_steps, None, kernel="k_plain",
+                                               bytes_per_env_step=per_step / table.n)
         log(f"[bench] plain: {plain_rate / 1e9:.2f} G env-steps/s, launch p50 "
-            f"{np.percentile(plain_lat, 50) * 1e3:.1f} us")
+            f"{plain['launch_ms']['p50'] * 1e3:.1f} us")
 
-    per_launch_ms = ms / launches
-    if rgb:
-        bytes_launch = rgb_path_bytes(table.n, info["grid_bytes"], K, obs_bytes / RGB_SCALE)
-    else:
-        bytes_launch = fused_bytes(table.n, info["grid_bytes"], K, obs_bytes)
-    achieved = bytes_launch / (per_launch_ms / 1e3) / 1e9
-    from paper_2407_19396_amd import profiling
-    traffic = None
-    if args.workload == "mixed" and args.steps % K == 0 and obs_mode == 0:
-        traffic = profiling.traffic_bytes(os.path.join(ROOT, "profiles", "k_fused_mixed262144.txt"),
-                                          K, table.n)
+    # roofline of the dominant kernel over the timed region: the algorithmic
+    # bytes of the steps each launch ran (the state term once per launch)
+    def launch_bytes(k):
+        if rgb:
+            return rgb_path_bytes(table.n, info["grid_bytes"], k, obs_bytes / RGB_SCALE)
+        return fused_bytes(table.n, info["grid_bytes"], k, obs_bytes)
+
+    def traffic_of(ks):
+        if rgb or obs_mode != 0:
+            return None
+        ts = [profile_traffic(args.workload, k, table.n) for k in ks]
+        return None if any(t is None for t in ts) else sum(ts) / len(ts)
+
+    kernel = "k_fused + k_sprite_ids + k_render" if rgb else "k_fused"
+    roof = roofline_entry(sum(launch_bytes(k) for k in timed_chunks) / len(timed_chunks),
+                          ms / len(timed_chunks), traffic_of(timed_chunks), kernel=kernel,
+                          launches=len(timed_chunks), steps_per_launch=sorted(set(timed_chunks)),
+                          timing="HIP events around the timed rollout")
+    roof["steady_state"] = roofline_entry(launch_bytes(K), float(np.mean(lat)), traffic_of([K]),
+                                          steps_per_launch=K, launches=len(lat),
+                                          timing="HIP events around each launch of K steps, mean")
+
+    del traj, env, first
+    torch.cuda.empty_cache()
+    configs = None
+    if not args.no_configs and args.workload == "mixed" and obs_mode == 0:
+        configs = run_configs(args.c3_steps)
     serving = None
     if args.serve_requests > 0 and args.workload == "mixed" and obs_mode == 0:
-        del traj, env
-        torch.cuda.empty_cache()
         loads = tuple(float(x) for x in args.serve_loads.split(","))
-        serving = run_serving(value, args.serve_requests, loads, args.serve_K,
-                              args.serve_budget_gib, args.serve_inflight)
+        serving = run_serving(args.serve_requests, loads, args.serve_K, args.serve_budget_gib,
+                              args.serve_inflight)
     cpu = None
     if not args.no_cpu:
         log("[bench] timing the CPU oracle on a sample")
         if rgb:   # the oracle draws every pixel: a smaller sample
-            cpu = cpu_baseline(table, min(args.cpu_envs or 4096, table.n), args.cpu_steps or 1024,
+            cpu = cpu_baseline(table, min(args.cpu_envs or 4096, table.n), min(args.cpu_steps, 1024),
                                obs_mode, sprites)
         else:
-            cpu = cpu_baseline(table, min(args.cpu_envs or table.n, table.n), args.cpu_steps or args.steps)
+            cpu = cpu_baseline(table, min(args.cpu_envs or table.n, table.n), args.cpu_steps, obs_mode)
         log(f"[bench] cpu oracle: {cpu['value'] / 1e6:.2f} M env-steps/s on {cpu['cores']} threads")
 
     out = {
@@ -377,22 +578,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload].replace("{n}", str(table.n)),
                    "n_envs": table.n, "K": K, "ring_rows": ring, "blocks": info["blocks"],
-                   "lds_bytes_per_wg": info["lds_bytes"], "global_batch": table.n,
-                   "autotuned": tuned is not None, "hip_graph": graph is not None,
-                   "observation": args.obs},
-        "fused_launch_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+                   "lds_bytes_per_wg": info["lds_bytes"], "max_tile_cells": info["max_tile_cells"],
+                   "global_batch": table.n, "autotuned": tuned is not None,
+                   "hip_graph": graph is not None, "observation": args.obs},
+        "fused_launch_ms": {"K": K, "p50": pct(lat, 50), "p99": pct(lat, 99)},
         "repeats": None if not reps else {"n": len(reps), "median": float(np.median(reps)),
                                           "min": float(np.min(reps)), "max": float(np.max(reps))},
-        "plain": None if plain_rate is None else {
-            "value": plain_rate, "unit": "env-steps/s", "steps": args.plain_steps,
-            "launch_ms": {"p50": float(np.percentile(plain_lat, 50)),
-                          "p99": float(np.percentile(plain_lat, 99))},
-            "fused_over_plain": value / plain_rate},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_fused + k_sprite_ids + k_render" if rgb else "k_fused",
-                     "bytes_per_launch": bytes_launch,
-                     "launch_ms": per_launch_ms},
+        "plain": plain,
+        "roofline": roof,
+        "configs": configs,
         "serving": serving,
         "cpu_baseline": cpu,
     }

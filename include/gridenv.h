@@ -348,6 +348,11 @@ typedef struct {
   uint64_t budget_bytes;       /* HBM budget: the server's pool plus request outputs */
   uint8_t* arena;              /* device memory for request outputs */
   uint64_t arena_bytes;
+  uint8_t* host_arena;         /* pinned host memory (hipHostMalloc) to deliver each request's
+                                  scalar outputs to, or NULL: results stay in HBM */
+  uint64_t host_arena_bytes;
+  double* host_done_s;         /* [n_items] out, or NULL: when a request's scalar outputs
+                                  were in host_arena (seconds from the start; -1 if not) */
 } gx_serve_opts;
 
 typedef struct {
@@ -362,11 +367,19 @@ typedef struct {
 /* Serve items in real time on an idle server: admit each request when it
  * has arrived, in arrival order, once tiles free up and its outputs fit the
  * budget (outputs are carved from the arena, row stride rounded up to 16
- * envs); step every live request K steps per launch with up to
- * max_inflight launches ahead of the device; a request completes when the
- * host sees its last launch finish, and its tiles and outputs are then
- * reused.  admit_s / done_s [n_items] receive admission and completion
- * times (seconds from the start); latency = done_s - arrival_s. */
+ * envs: reward, flags and action first, then the observations); step every
+ * live request K steps per launch with up to max_inflight launches ahead of
+ * the device (a launch only while some request has steps left); a request
+ * completes on the device when the host sees its last launch finish, and
+ * its tiles are then reused.  With a host arena its scalar outputs (reward,
+ * flags, action: 6 bytes per env-step plus padding) are then copied there
+ * on a stream of the library's own, and its device outputs are reused once
+ * that copy has finished; the observations stay in HBM for an on-device
+ * consumer.  The host arena's contents are overwritten by later requests.
+ * admit_s / done_s [n_items] receive admission and device-completion times
+ * (seconds from the start); latency = done_s - arrival_s, or
+ * host_done_s - arrival_s to the host.  EINVAL when a request alone would
+ * not fit the arenas. */
 int env_serve_run(gx_server* srv, const gx_serve_item* items, int32_t n_items,
                   const uint8_t* family, const uint8_t* side, const uint8_t* param,
                   const int32_t* max_steps, const gx_serve_opts* opts, void* stream,

@@ -22,11 +22,18 @@ import numpy as np
 CACHE = os.path.join(os.path.expanduser("~"), ".cache", "gridenv", "autotune.json")
 
 
-def batch_key(table, device_name: str) -> str:
+def batch_key(table, device_name: str, obs_mode: int = 0, reward_mode: int = 0, Ks=()) -> str:
+    """Cache key of a tuning: the device, the batch's composition (families,
+    sides, parameters, limits), the observation and reward modes (each
+    observation mode runs its own kernel variant), the K candidates and the
+    kernel's code, so that an edited kernel is tuned afresh."""
+    from .profiling import kernel_source_hash
     h = hashlib.sha256()
-    for a in (table.family, table.side, table.max_steps):
+    for a in (table.family, table.side, table.param, table.max_steps):
         h.update(np.ascontiguousarray(a).tobytes())
-    return f"{device_name}|{table.n}|{h.hexdigest()[:16]}"
+    ks = ",".join(str(k) for k in Ks)
+    return (f"{device_name}|{table.n}|{h.hexdigest()[:16]}|obs{obs_mode}|rew{reward_mode}|K{ks}|"
+            f"code{kernel_source_hash()}")
 
 
 def block_candidates(n_tiles: int, lds_bytes: int, cus: int, lds_per_cu: int = 160 * 1024) -> list[int]:
@@ -50,20 +57,20 @@ def tune(env, traj, Ks=(128, 256, 512), steps: int = 1024, use_cache: bool = Tru
 
     dev = torch.cuda.current_device()
     props = torch.cuda.get_device_properties(dev)
-    key = batch_key(env.table, props.name)
+    Ks = [k for k in Ks if k <= traj.rows]
+    key = batch_key(env.table, props.name, env.obs_mode, env.reward_mode, Ks)
     cache = {}
     if use_cache and os.path.exists(CACHE):
         try:
             cache = json.load(open(CACHE))
         except (OSError, ValueError):
             cache = {}
-    if use_cache and key in cache:
+    if use_cache and key in cache and cache[key].get("K") in Ks:
         best = cache[key]
         env.set_launch(best["K"], best["blocks"])
         return best | {"cached": True}
 
     info = env.info()
-    Ks = [k for k in Ks if k <= traj.rows]
     blocks = block_candidates(info["n_tiles"], info["lds_bytes"], props.multi_processor_count)
     results = []
     stream = torch.cuda.current_stream()

@@ -1003,6 +1003,77 @@ struct HbmCells {
   }
 };
 
+// The 7x7 view straight from the HBM grid, cells outside it read as walls.
+// Whatever the heading, the view covers a 7x7 square of the world: 7 grid
+// rows of 7 consecutive cells, i.e. 21 contiguous bytes each.  A row is
+// read as the 24 bytes from its dword-aligned start (one 16-byte and one
+// 8-byte load) instead of 21 byte loads; near the grid's first and last
+// bytes the row falls back to single dwords, each read only if it holds a
+// byte of the env's grid.  The square is then turned to the view's
+// orientation by selects on the heading.
+struct HbmWindow {
+  const uint8_t* g;
+  int S;   // 0: every cell reads as a wall
+  int ax, ay, dir;
+  __device__ __forceinline__ void load_all(uint32_t (&c)[kView][kView]) const {
+    // top-left world cell of the square
+    const int x0 = dir == 0 ? ax : (dir == 2 ? ax - 6 : ax - 3);
+    const int y0 = dir == 3 ? ay - 6 : (dir == 1 ? ay : ay - 3);
+    const uintptr_t gb = reinterpret_cast<uintptr_t>(g);
+    const uintptr_t lo = gb & ~(uintptr_t)3, hi = (gb + 3 * (uintptr_t)(S * S) + 3) & ~(uintptr_t)3;
+    uint32_t w[kView][6];
+#pragma unroll
+    for (int r = 0; r < kView; ++r) {
+      const int yy = y0 + r;
+#pragma unroll
+      for (int d = 0; d < 6; ++d) w[r][d] = 0u;
+      if ((unsigned)yy < (unsigned)S) {
+        const uintptr_t a = (uintptr_t)((intptr_t)gb + 3 * (intptr_t)(yy * S + x0)) & ~(uintptr_t)3;
+        if (a >= lo && a + 24 <= hi) {
+          const uint32_t* q = reinterpret_cast<const uint32_t*>(a);
+          const u32x4 v4 = *reinterpret_cast<const u32x4*>(q);
+          const uint2 v2 = *reinterpret_cast<const uint2*>(q + 4);
+          w[r][0] = v4.x; w[r][1] = v4.y; w[r][2] = v4.z; w[r][3] = v4.w;
+          w[r][4] = v2.x; w[r][5] = v2.y;
+        } else {
+#pragma unroll
+          for (int d = 0; d < 6; ++d)
+            if (a + 4 * d >= lo && a + 4 * d < hi) w[r][d] = reinterpret_cast<const uint32_t*>(a)[d];
+        }
+      }
+    }
+    // world cell (x0 + k, y0 + r), with its see-through flag at bit 31
+    uint32_t W[kView][kView];
+#pragma unroll
+    for (int r = 0; r < kView; ++r) {
+      const int yy = y0 + r;
+      const uint32_t rb = (uint32_t)((uintptr_t)((intptr_t)gb + 3 * (intptr_t)(yy * S + x0)) & 3);
+      uint32_t b[6];
+#pragma unroll
+      for (int d = 0; d < 5; ++d) b[d] = __builtin_amdgcn_alignbyte(w[r][d + 1], w[r][d], rb);
+      b[5] = w[r][5] >> (8 * rb);
+#pragma unroll
+      for (int k = 0; k < kView; ++k) {
+        const int o = 3 * k, d = o >> 2, off = o & 3;
+        const uint32_t tri = (__builtin_amdgcn_alignbyte(b[d + 1], b[d], (uint32_t)off)) & 0xFFFFFFu;
+        const bool in = (unsigned)yy < (unsigned)S && (unsigned)(x0 + k) < (unsigned)S;
+        W[r][k] = in ? tri | see_through(tri) : kCellWall;
+      }
+    }
+    // view cell (i, j) = world a + (i - 3) right + (6 - j) ahead
+#pragma unroll
+    for (int j = 0; j < kView; ++j)
+#pragma unroll
+      for (int i = 0; i < kView; ++i) {
+        uint32_t v = W[j][i];                              // north
+        v = dir == 0 ? W[i][6 - j] : v;                    // east
+        v = dir == 1 ? W[6 - j][6 - i] : v;                // south
+        v = dir == 2 ? W[6 - i][j] : v;                    // west
+        c[j][i] = (v & ~kSeeBit) | ((v & kSeeBit) >> i);
+      }
+  }
+};
+
 // View rows straight from the HBM grid, cells outside it read as walls.
 struct HbmRows {
   HbmCells cells;
@@ -1178,7 +1249,7 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
   } else if (a.out.obs) {
     // inactive lanes get an empty grid: every read is out of bounds (a wall)
     uint32_t u[kObsWords + 1];
-    const HbmRows rows{HbmCells{g, active ? S : 0}, x, y, dir_dx(dir), dir_dy(dir)};
+    const HbmWindow rows{g, active ? S : 0, x, y, dir};
     if (a.env.obs_mode == 1) {
       observe_words<true>(rows, carry, active, lane, u);
       store_words<true>(stage, lane, u);
@@ -1387,7 +1458,9 @@ struct LdsGrid {
 // two ends store only their bytes inside [0, n) (the rest belong to the
 // neighbouring tiles' records); their reads reach at most 15 cells before
 // or after the tile, inside the cleared margins.
-template <bool kCat>
+// kNT: non-temporal stores (trajectory records); the state write-back uses
+// ordinary ones, since the next launch reads it again.
+template <bool kCat, bool kNT = true>
 __device__ __forceinline__ void emit_tile_grids(uint8_t* dst, int n_cells, const uint32_t* table,
                                                 const uint8_t* codes, int lane) {
   constexpr int kUnit = kCat ? 4 : 16;
@@ -1411,7 +1484,8 @@ __device__ __forceinline__ void emit_tile_grids(uint8_t* dst, int n_cells, const
       const uint32_t w = __builtin_amdgcn_perm(__builtin_amdgcn_perm(ty[3], ty[2], 0x0c0c0400u),
                                                __builtin_amdgcn_perm(ty[1], ty[0], 0x0c0c0400u), 0x05040100u);
       if (a >= d0 && a + 4 <= d1) {
-        __builtin_nontemporal_store(w, reinterpret_cast<uint32_t*>(a));
+        if (kNT) __builtin_nontemporal_store(w, reinterpret_cast<uint32_t*>(a));
+        else *reinterpret_cast<uint32_t*>(a) = w;
       } else {
 #pragma unroll
         for (int b = 0; b < 4; ++b)
@@ -1432,13 +1506,79 @@ __device__ __forceinline__ void emit_tile_grids(uint8_t* dst, int n_cells, const
       w.z = __builtin_amdgcn_alignbyte(s3, s2, r);
       w.w = __builtin_amdgcn_alignbyte(s4, s3, r);
       if (a >= d0 && a + 16 <= d1) {
-        __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(a));
+        if (kNT) __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(a));
+        else *reinterpret_cast<u32x4*>(a) = w;
       } else {
 #pragma unroll
         for (int b = 0; b < 16; ++b)
           if (a + b >= d0 && a + b < d1) reinterpret_cast<uint8_t*>(a)[b] = (uint8_t)(w[b >> 2] >> (8 * (b & 3)));
       }
     }
+  }
+}
+
+// Stages a tile's grids, the 3 * n_cells bytes at src (any alignment), into
+// LDS as codes.  Lane u converts cells [16u, 16u + 16), i.e. the 48 bytes
+// at src + 48u; 48 being a multiple of 16, every such run starts at the
+// same offset r = src mod 16 in its first aligned 16-byte chunk, so a run is
+// at most four aligned chunk loads and one wave-uniform realignment.  A
+// chunk is loaded only if it holds a byte of the block (so it lies in the
+// block's own memory pages); the codes of the at most 15 cells past n_cells
+// (decoded from bytes after the block, or zeros) land in the trailing LDS
+// margin, which needs nothing but valid codes.  Two runs per lane are in
+// flight together.
+struct GridRun {
+  u32x4 q[4];
+};
+
+__device__ __forceinline__ GridRun load_run(uintptr_t a, uintptr_t end, uint32_t r) {
+  GridRun g;
+  g.q[0] = *reinterpret_cast<const u32x4*>(a);
+  g.q[1] = g.q[2] = g.q[3] = u32x4{0u, 0u, 0u, 0u};
+  if (a + 16 < end) g.q[1] = *reinterpret_cast<const u32x4*>(a + 16);
+  if (a + 32 < end) g.q[2] = *reinterpret_cast<const u32x4*>(a + 32);
+  if (r != 0 && a + 48 < end) g.q[3] = *reinterpret_cast<const u32x4*>(a + 48);
+  return g;
+}
+
+__device__ __forceinline__ void store_run_codes(const GridRun& g, uint32_t r, uint8_t* dst) {
+  uint32_t w[16];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) w[4 * k + c] = g.q[k][c];
+  // bytes r .. r + 47 of the chunks as 12 words
+  const uint32_t rw = r >> 2, rb = r & 3u;
+  uint32_t v[13];
+#pragma unroll
+  for (int i = 0; i < 13; ++i) v[i] = rw == 0 ? w[i] : rw == 1 ? w[i + 1] : rw == 2 ? w[i + 2] : w[i + 3];
+  uint32_t b[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) b[i] = __builtin_amdgcn_alignbyte(v[i + 1], v[i], rb);
+  uint32_t out[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int d = (3 * k) >> 2, off = (3 * k) & 3;
+    const uint32_t tri = (d + 1 < 12 ? __builtin_amdgcn_alignbyte(b[d + 1], b[d], (uint32_t)off)
+                                     : b[d] >> (8 * off)) & 0xFFFFFFu;
+    out[k >> 2] |= code_of(tri) << (8 * (k & 3));
+  }
+  *reinterpret_cast<u32x4*>(dst) = u32x4{out[0], out[1], out[2], out[3]};
+}
+
+__device__ __forceinline__ void stage_in_codes(const uint8_t* src, int n_cells, uint8_t* codes, int lane) {
+  const uintptr_t s0 = reinterpret_cast<uintptr_t>(src);
+  const uint32_t r = (uint32_t)__builtin_amdgcn_readfirstlane((int)(s0 & 15u));
+  const uintptr_t end = s0 + 3 * (uintptr_t)(uint32_t)n_cells;
+  const uintptr_t a0 = s0 - r;
+  const int units = (n_cells + 15) >> 4;
+  for (int u = lane; u < units; u += 2 * kWave) {
+    const bool two = u + kWave < units;
+    const GridRun g0 = load_run(a0 + 48 * (uintptr_t)u, end, r);
+    GridRun g1;
+    if (two) g1 = load_run(a0 + 48 * (uintptr_t)(u + kWave), end, r);
+    store_run_codes(g0, r, codes + 16 * u);
+    if (two) store_run_codes(g1, r, codes + 16 * (u + kWave));
   }
 }
 
@@ -1524,8 +1664,9 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
   // the tables off an entry boundary and could set another column's
   // see-through flag, which the row's combined flags would then pick up.
   {
-    const uint32_t words = (uint32_t)(tile_lds_bytes(a.tiles.max_tile_cells) >> 2);
-    for (uint32_t w = (uint32_t)lane; w < words; w += kWave) reinterpret_cast<uint32_t*>(grids)[w] = 0u;
+    const uint32_t quads = (uint32_t)(tile_lds_bytes(a.tiles.max_tile_cells) >> 4);
+    for (uint32_t w = (uint32_t)lane; w < quads; w += kWave)
+      reinterpret_cast<u32x4*>(grids)[w] = u32x4{0u, 0u, 0u, 0u};
   }
   wave_sync();
 
@@ -1630,12 +1771,7 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
     if (fresh) {
       fill_layouts(__ballot(active), L0, codes, my_off, lane);
     } else {
-      const uint8_t* src = a.st.grid + g0;
-      for (int c = lane; c < tile_cells; c += kWave) {
-        const uint32_t tri = (uint32_t)src[3 * c] | ((uint32_t)src[3 * c + 1] << 8) |
-                             ((uint32_t)src[3 * c + 2] << 16);
-        codes[c] = (uint8_t)code_of(tri);
-      }
+      stage_in_codes(a.st.grid + g0, tile_cells, codes, lane);
     }
     wave_sync();
 
@@ -1762,16 +1898,10 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
       wave_sync();
     }
 
-    // write the chunk's final state back
-    {
-      uint8_t* dst = a.st.grid + g0;
-      for (int c = lane; c < tile_cells; c += kWave) {
-        const uint32_t tri = table_at(table, codes[c]);
-        dst[3 * c] = (uint8_t)tri;
-        dst[3 * c + 1] = (uint8_t)(tri >> 8);
-        dst[3 * c + 2] = (uint8_t)(tri >> 16);
-      }
-    }
+    // write the chunk's final state back: the grids as aligned 16-byte
+    // units (the two at the block's ends byte by byte, since neighbouring
+    // tiles own the rest of those units)
+    emit_tile_grids<false, false>(a.st.grid + g0, tile_cells, table, codes, lane);
     if (active) {
       a.st.x[e] = x;
       a.st.y[e] = y;

@@ -326,8 +326,10 @@ int env_server_info(const gx_server* s, gx_server_info* info) {
 
 namespace {
 
+// A request's outputs in the arena: the scalar outputs first (one range,
+// what a host delivery copies), then the observations.
 struct Layout {
-  uint64_t reward = 0, obs = 0, flags = 0, action = 0, total = 0;
+  uint64_t reward = 0, flags = 0, action = 0, scalars = 0, obs = 0, total = 0;
 };
 
 Layout output_layout(int32_t stride, int32_t n_steps, bool keep_obs) {
@@ -335,10 +337,11 @@ Layout output_layout(int32_t stride, int32_t n_steps, bool keep_obs) {
   auto up = [](uint64_t x) { return (x + 255) & ~255ull; };
   Layout l;
   l.reward = 0;
-  l.obs = up(4 * recs);
-  l.flags = l.obs + (keep_obs ? up((uint64_t)GX_OBS_BYTES * recs) : 0);
+  l.flags = up(4 * recs);
   l.action = l.flags + up(recs);
-  l.total = l.action + up(recs);
+  l.scalars = l.action + up(recs);
+  l.obs = l.scalars;
+  l.total = l.obs + (keep_obs ? up((uint64_t)GX_OBS_BYTES * recs) : 0);
   return l;
 }
 
@@ -353,7 +356,9 @@ int env_serve_run(gx_server* s, const gx_serve_item* items, int32_t n_items, con
   if (!s || !items || n_items < 0 || !family || !side || !max_steps || !o || !admit_s || !done_s ||
       !stats || o->K < 1 || o->max_inflight < 1 || !o->arena)
     return GX_EINVAL;
+  if (o->host_arena && o->host_arena_bytes < 256) return GX_EINVAL;
   if (s->live != 0) return GX_ESTATE;
+  const bool deliver = o->host_arena != nullptr;
   const uint64_t budget = o->budget_bytes > s->device_bytes ? o->budget_bytes - s->device_bytes : 0;
   const uint64_t capacity = std::min<uint64_t>(o->arena_bytes, budget) & ~255ull;
   // every item must fit an idle server on its own, or the loop could wait forever
@@ -363,30 +368,101 @@ int env_serve_run(gx_server* s, const gx_serve_item* items, int32_t n_items, con
         (i > 0 && it.arrival_s < items[i - 1].arrival_s))
       return GX_EINVAL;
     if ((it.n_envs + kTileEnvs - 1) / kTileEnvs > s->max_tiles) return GX_EINVAL;
-    if (output_layout((it.n_envs + 15) / 16 * 16, it.n_steps, o->keep_obs != 0).total > capacity)
-      return GX_EINVAL;
+    const Layout lay = output_layout((it.n_envs + 15) / 16 * 16, it.n_steps, o->keep_obs != 0);
+    if (lay.total > capacity || (deliver && lay.scalars > (o->host_arena_bytes & ~255ull))) return GX_EINVAL;
   }
   using clock = std::chrono::steady_clock;
   const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   gx::Arena arena(capacity);
+  gx::Arena host_arena(deliver ? o->host_arena_bytes : 0);
   struct Live {
     int32_t item;
-    uint64_t off, bytes;
+    uint64_t off, bytes;     // the request's block of the device arena
+    uint64_t scalars;        // bytes of its scalar outputs (the head of the block)
   };
   std::vector<Live> by_handle;
   std::vector<hipEvent_t> events(o->max_inflight + 1);
-  for (auto& e : events)
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return GX_EDEVICE;
+  for (auto& e : events) e = nullptr;
+  // host delivery: once the host has seen a launch complete, the scalar
+  // outputs of the requests it finished are copied to the host arena on a
+  // stream of their own (overlapping later launches); a batch's event
+  // recycles through a free list once the host has seen the copy complete
+  hipStream_t copy_stream = nullptr;
+  struct Copy {
+    hipEvent_t ev;
+    std::vector<Live> reqs;
+    std::vector<uint64_t> host_off;
+  };
+  std::deque<Copy> copies;                       // issued, in stream order
+  std::deque<std::vector<Live>> to_copy;         // waiting for host arena space
+  std::vector<hipEvent_t> spare_events;
   std::deque<std::pair<int32_t, std::vector<int32_t>>> inflight;   // (event index, finished handles)
   int32_t next_event = 0;
   std::deque<int32_t> queue;
-  int32_t next = 0, completed = 0, launches = 0;
+  int32_t next = 0, completed = 0, delivered = 0, launches = 0;
   uint64_t env_steps = 0;
   std::vector<int32_t> fin(4096);
   int rc = GX_OK;
   double t_admit = 0, t_step = 0, t_wait = 0;
   const auto t0 = clock::now();
   auto now_s = [&]() { return std::chrono::duration<double>(clock::now() - t0).count(); };
+  auto take_event = [&](hipEvent_t* e) -> bool {
+    if (!spare_events.empty()) {
+      *e = spare_events.back();
+      spare_events.pop_back();
+      return true;
+    }
+    return hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
+  };
+  // issues the copies of waiting batches, in order, while host space lasts
+  auto issue_copies = [&]() -> int {
+    while (!to_copy.empty()) {
+      std::vector<Live>& reqs = to_copy.front();
+      std::vector<uint64_t> offs;
+      for (const Live& l : reqs) {
+        uint64_t off;
+        if (!host_arena.alloc(l.scalars, &off)) {
+          for (size_t k = 0; k < offs.size(); ++k) host_arena.release(offs[k], reqs[k].scalars);
+          return GX_OK;   // retried when earlier copies have freed space
+        }
+        offs.push_back(off);
+      }
+      Copy c;
+      if (!take_event(&c.ev)) return GX_EDEVICE;
+      for (size_t k = 0; k < reqs.size(); ++k)
+        if (hipMemcpyAsync(o->host_arena + offs[k], o->arena + reqs[k].off, reqs[k].scalars,
+                           hipMemcpyDeviceToHost, copy_stream) != hipSuccess)
+          return GX_EDEVICE;
+      if (hipEventRecord(c.ev, copy_stream) != hipSuccess) return GX_EDEVICE;
+      c.reqs = std::move(reqs);
+      c.host_off = std::move(offs);
+      copies.push_back(std::move(c));
+      to_copy.pop_front();
+    }
+    return GX_OK;
+  };
+  // host side of finished copies: the results are in host memory
+  auto retire_copies = [&](bool wait) -> int {
+    while (!copies.empty()) {
+      Copy& c = copies.front();
+      const double w0 = wait ? now_s() : 0.0;
+      const hipError_t q = wait ? hipEventSynchronize(c.ev) : hipEventQuery(c.ev);
+      if (wait) t_wait += now_s() - w0;
+      if (q == hipErrorNotReady) return GX_OK;
+      if (q != hipSuccess) return GX_EDEVICE;
+      const double t = now_s();
+      for (size_t k = 0; k < c.reqs.size(); ++k) {
+        if (o->host_done_s) o->host_done_s[c.reqs[k].item] = t;
+        host_arena.release(c.host_off[k], c.reqs[k].scalars);
+        arena.release(c.reqs[k].off, c.reqs[k].bytes);
+        ++delivered;
+      }
+      spare_events.push_back(c.ev);
+      copies.pop_front();
+      wait = false;
+    }
+    return issue_copies();
+  };
   auto retire = [&](bool wait) -> int {
     while (!inflight.empty()) {
       hipEvent_t ev = events[inflight.front().first];
@@ -396,21 +472,36 @@ int env_serve_run(gx_server* s, const gx_serve_item* items, int32_t n_items, con
       if (q == hipErrorNotReady) return GX_OK;
       if (q != hipSuccess) return GX_EDEVICE;
       const double t = now_s();
+      std::vector<Live> fin_reqs;
       for (int32_t h : inflight.front().second) {
         const Live& l = by_handle[h];
         done_s[l.item] = t;
         env_steps += (uint64_t)items[l.item].n_envs * (uint64_t)items[l.item].n_steps;
-        arena.release(l.off, l.bytes);
+        if (deliver) fin_reqs.push_back(l);
+        else arena.release(l.off, l.bytes);
         if (env_server_release(s, h) != GX_OK) return GX_EDEVICE;
         ++completed;
       }
       inflight.pop_front();
       wait = false;
+      if (deliver && !fin_reqs.empty()) {
+        to_copy.push_back(std::move(fin_reqs));
+        const int r = issue_copies();
+        if (r != GX_OK) return r;
+      }
     }
-    return GX_OK;
+    return deliver ? retire_copies(false) : GX_OK;
   };
-  for (int32_t i = 0; i < n_items; ++i) admit_s[i] = done_s[i] = -1.0;
-  while (completed < n_items) {
+  for (auto& e : events)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) rc = GX_EDEVICE;
+  if (rc == GX_OK && deliver && hipStreamCreateWithFlags(&copy_stream, hipStreamNonBlocking) != hipSuccess)
+    rc = GX_EDEVICE;
+  for (int32_t i = 0; i < n_items; ++i) {
+    admit_s[i] = done_s[i] = -1.0;
+    if (o->host_done_s) o->host_done_s[i] = -1.0;
+  }
+  if (rc != GX_OK) goto out;
+  while (completed < n_items || (deliver && delivered < n_items)) {
     const double t = now_s();
     while (next < n_items && items[next].arrival_s <= t) queue.push_back(next++);
     // admission in arrival order while tiles and budget allow
@@ -447,12 +538,14 @@ int env_serve_run(gx_server* s, const gx_serve_item* items, int32_t n_items, con
         goto out;
       }
       if ((int32_t)by_handle.size() <= h) by_handle.resize(h + 1);
-      by_handle[h] = Live{queue.front(), off, lay.total};
+      by_handle[h] = Live{queue.front(), off, lay.total, lay.scalars};
       admit_s[queue.front()] = t;
       queue.pop_front();
     }
     t_admit += now_s() - a0;
-    if (s->live > 0 && (int32_t)inflight.size() < o->max_inflight) {
+    // a launch only when some request still has steps to run (a request
+    // whose last steps are enqueued is finished as far as launches go)
+    if (!s->running.empty() && (int32_t)inflight.size() < o->max_inflight) {
       int32_t n = 0;
       const double s0 = now_s();
       rc = env_server_step(s, o->K, stream, fin.data(), (int32_t)fin.size(), &n);
@@ -466,16 +559,30 @@ int env_serve_run(gx_server* s, const gx_serve_item* items, int32_t n_items, con
       next_event = (next_event + 1) % (int32_t)events.size();
       ++launches;
     }
-    // wait for the oldest launch when the pipeline is full; otherwise poll
-    if ((rc = retire((int32_t)inflight.size() >= o->max_inflight)) != GX_OK) goto out;
-    if (s->live == 0 && queue.empty() && next < n_items) {
+    // wait for the oldest launch when the pipeline is full, or for the
+    // oldest copy when nothing else can progress; otherwise poll
+    {
+      const bool full = (int32_t)inflight.size() >= o->max_inflight;
+      const bool stalled = !full && inflight.empty() && s->running.empty() && !copies.empty();
+      if ((rc = retire(full)) != GX_OK) goto out;
+      if (stalled && (rc = retire_copies(true)) != GX_OK) goto out;
+    }
+    if (s->live == 0 && queue.empty() && next < n_items && copies.empty() && to_copy.empty()) {
       const double wait = items[next].arrival_s - now_s();
       if (wait > 2e-4) std::this_thread::sleep_for(std::chrono::duration<double>(wait - 1e-4));
     }
   }
 out:
   if (rc == GX_OK) rc = retire(true);
-  for (auto& e : events) (void)hipEventDestroy(e);
+  if (rc == GX_OK && deliver) {
+    while (rc == GX_OK && (!copies.empty() || !to_copy.empty())) rc = retire_copies(true);
+  }
+  if (copy_stream) (void)hipStreamSynchronize(copy_stream);
+  for (auto& e : events)
+    if (e) (void)hipEventDestroy(e);
+  for (Copy& c : copies) (void)hipEventDestroy(c.ev);
+  for (hipEvent_t e : spare_events) (void)hipEventDestroy(e);
+  if (copy_stream) (void)hipStreamDestroy(copy_stream);
   stats->wall_s = now_s();
   stats->env_steps = env_steps;
   stats->completed = completed;

@@ -77,7 +77,8 @@ class GxServeItem(ctypes.Structure):
 class GxServeOpts(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("max_inflight", ctypes.c_int32), ("keep_obs", ctypes.c_int32),
                 ("budget_bytes", ctypes.c_uint64), ("arena", ctypes.c_void_p),
-                ("arena_bytes", ctypes.c_uint64)]
+                ("arena_bytes", ctypes.c_uint64), ("host_arena", ctypes.c_void_p),
+                ("host_arena_bytes", ctypes.c_uint64), ("host_done_s", ctypes.c_void_p)]
 
 
 class GxServeStats(ctypes.Structure):
@@ -257,6 +258,7 @@ class GridEnv:
         import torch
         self.table = table
         self.obs_mode = obs_mode
+        self.reward_mode = reward_mode
         self.device = torch.device(device)
         if obs_mode >= 4 and sprites is None:
             from .sprites import default_atlas
@@ -395,9 +397,11 @@ class Server:
 
 
 def serve_run(server: Server, requests: list, K: int, budget_bytes: int, arena, keep_obs: bool = True,
-              max_inflight: int = 2, stream=None) -> dict:
+              max_inflight: int = 2, stream=None, host_arena=None) -> dict:
     """Run a Poisson serving workload (workloads.serving_requests) through
-    the native serving loop; returns throughput and per-request latencies."""
+    the native serving loop; returns throughput and per-request latencies.
+    host_arena: a pinned host uint8 tensor to deliver each request's scalar
+    outputs to (latency then also to the host), or None."""
     n = len(requests)
     items = (GxServeItem * max(n, 1))()
     fam, side, par, ms = [], [], [], []
@@ -415,8 +419,14 @@ def serve_run(server: Server, requests: list, K: int, budget_bytes: int, arena, 
     ms = np.ascontiguousarray(np.concatenate(ms), np.int32)
     admit = np.zeros(n, np.float64)
     done = np.zeros(n, np.float64)
+    host_done = np.full(n, -1.0, np.float64)
+    if host_arena is not None and not host_arena.is_pinned():
+        raise ValueError("host_arena must be pinned host memory")
     opts = GxServeOpts(K, max_inflight, 1 if keep_obs else 0, budget_bytes, arena.data_ptr(),
-                       arena.numel() * arena.element_size())
+                       arena.numel() * arena.element_size(),
+                       host_arena.data_ptr() if host_arena is not None else None,
+                       host_arena.numel() * host_arena.element_size() if host_arena is not None else 0,
+                       host_done.ctypes.data if host_arena is not None else None)
     st = GxServeStats()
     _check("env_serve_run", load().env_serve_run(server.ptr, items, n, fam.ctypes.data, side.ctypes.data,
                                                  par.ctypes.data, ms.ctypes.data, ctypes.byref(opts),
@@ -426,4 +436,6 @@ def serve_run(server: Server, requests: list, K: int, budget_bytes: int, arena, 
     return {"wall_s": st.wall_s, "env_steps": st.env_steps, "completed": st.completed,
             "launches": st.launches, "host_admit_s": st.admit_s, "host_step_s": st.step_s,
             "host_wait_s": st.wait_s, "arrival_s": arrival, "admit_s": admit, "done_s": done,
-            "latency_s": done - arrival}
+            "latency_s": done - arrival,
+            "host_done_s": host_done if host_arena is not None else None,
+            "host_latency_s": host_done - arrival if host_arena is not None else None}

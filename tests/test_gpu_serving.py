@@ -138,8 +138,50 @@ def test_native_serving_loop_completes_everything():
     assert res["env_steps"] == sum(r.n_envs * r.n_steps for r in reqs)
     assert (res["admit_s"] >= res["arrival_s"] - 1e-9).all()
     assert (res["done_s"] > res["admit_s"]).all()
+    # every launch advances some request: no more launches than request chunks
+    assert 0 < res["launches"] <= sum(-(-r.n_steps // 32) for r in reqs)
+    assert res["host_latency_s"] is None
     info = srv.info()
     assert info["live_requests"] == 0 and info["free_tiles"] == 256
+    srv.close()
+
+
+def test_host_delivery_of_scalar_outputs():
+    """With a host arena every request's reward, flags and action reach
+    pinned host memory after its device completion; a lone request's copy
+    sits at the arena's start (reward, then flags and action at 256-byte
+    aligned offsets) and equals the oracle's rollout."""
+    import torch
+    from paper_2407_19396_amd import gridenv as ge
+    srv = ge.Server(max_tiles=64)
+    budget = 1 << 30
+    arena = torch.empty(budget - srv.info()["device_bytes"], dtype=torch.uint8, device="cuda")
+    host = torch.empty(64 << 20, dtype=torch.uint8, pin_memory=True)
+    # one request alone: its delivered outputs are checked against the oracle
+    t = wl.mixed_table(100, seed=11, mix_seed=12)
+    r = wl.Request(0, 0.0, 100, 70, int(t.seed[0]), t)
+    res = ge.serve_run(srv, [r], 16, budget, arena, keep_obs=False, host_arena=host)
+    assert res["completed"] == 1
+    assert res["host_done_s"][0] >= res["done_s"][0] > 0
+    stride = ge.padded_stride(r.n_envs)
+    recs = stride * r.n_steps
+    up = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    h = host.numpy()
+    reward = h[:4 * recs].view(np.float32).reshape(r.n_steps, stride)[:, :r.n_envs]
+    flags = h[up(4 * recs):up(4 * recs) + recs].reshape(r.n_steps, stride)[:, :r.n_envs]
+    action = h[up(4 * recs) + up(recs):up(4 * recs) + up(recs) + recs].reshape(r.n_steps, stride)[:, :r.n_envs]
+    ref = oracle_of(r)
+    np.testing.assert_array_equal(reward.view(np.uint32), ref.reward.view(np.uint32))
+    np.testing.assert_array_equal(flags, ref.flags)
+    np.testing.assert_array_equal(action, ref.action)
+    # a Poisson mix through a small host arena: everything is delivered
+    reqs = wl.serving_requests(200, rate_per_s=3000.0, master_seed=9, max_envs=1024)
+    res = ge.serve_run(srv, reqs, 32, budget, arena, keep_obs=True, host_arena=host)
+    assert res["completed"] == len(reqs)
+    assert (res["host_done_s"] >= res["done_s"]).all() and (res["done_s"] > res["admit_s"]).all()
+    assert (res["host_latency_s"] > 0).all()
+    info = srv.info()
+    assert info["live_requests"] == 0 and info["free_tiles"] == 64
     srv.close()
 
 
