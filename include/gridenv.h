@@ -32,8 +32,9 @@
  *   The library owns only its contexts (host memory plus small device
  *   tables allocated in env_create and freed in env_destroy) and servers
  *   (slot pools allocated in env_server_create, freed in
- *   env_server_destroy), never frees caller memory, and allocates nothing
- *   in env_reset / env_step / env_rollout / env_server_admit /
+ *   env_server_destroy) and the fixed device array of env_rollout_static,
+ *   never frees caller memory, and allocates nothing in env_reset /
+ *   env_step / env_rollout / env_rollout_static / env_server_admit /
  *   env_server_step.
  * Streams: stream is a hipStream_t passed as void* (NULL = the default
  *   stream).  Calls enqueue work and return; results are valid once the
@@ -113,6 +114,7 @@ extern "C" {
 #define GX_EDEVICE -3  /* a HIP call failed, or earlier GPU work faulted */
 #define GX_ESTATE -4   /* call order violated (e.g. a step before any reset) */
 #define GX_EBUSY -5    /* a server has no free tiles for the request right now */
+#define GX_ESIZE -6    /* env_rollout_static: more envs than its static tables hold */
 
 /* Families (Table "envs").  The lava families and Dynamic-Obstacles start
  * the agent at (1, 1) facing east; walking into lava gives reward -1 in
@@ -385,6 +387,32 @@ int env_serve_run(gx_server* srv, const gx_serve_item* items, int32_t n_items,
                   const int32_t* max_steps, const gx_serve_opts* opts, void* stream,
                   double* admit_s, double* done_s,
                   gx_serve_stats* stats);
+
+/* ------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).
+ *
+ * env_rollout_static runs what env_create(cfg), then env_reset(st, first)
+ * when reset != 0, then env_rollout(st, n_steps, actions, traj, K) and
+ * env_destroy would run, with bit-identical results, but allocates nothing:
+ * the per-env tables (28 bytes per env) live in a fixed array of the
+ * library's device code, GX_STATIC_MAX_ENVS envs' worth (7 MiB), which
+ * each device the library runs on holds until the process ends.  Launch
+ * shape: env_create's workgroup count; K = 0 means 64 steps per launch.
+ * Observation modes 0..3 only (EINVAL for the rgb modes, whose staging ring
+ * would not be modest); GX_ESIZE when cfg->n_envs > GX_STATIC_MAX_ENVS.
+ * With reset == 0 the state must come from an earlier reset of the same
+ * batch description (by either entry point); first may be NULL.
+ * The call uploads the tables on `stream` and waits for that upload (and so
+ * for the stream's earlier work) before it enqueues the kernels: it cannot
+ * be captured in a graph, and it returns with the kernels still running.
+ * Every call on one device shares that device's tables: calls that overlap
+ * on one device (other streams or host threads whose kernels are still
+ * running) race; host threads are serialised only while they upload. */
+#define GX_STATIC_MAX_ENVS 262144
+int env_rollout_static(const gx_config* cfg, const gx_state* st, int32_t reset, const gx_traj* first,
+                       int32_t n_steps, const uint8_t* actions, const gx_traj* traj, int32_t K,
+                       void* stream);
 
 /* Static text for a status code. */
 const char* env_strerror(int status);

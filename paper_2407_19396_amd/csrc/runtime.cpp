@@ -196,6 +196,7 @@ const char* env_strerror(int status) {
     case GX_EDEVICE: return "HIP device error";
     case GX_ESTATE: return "call order violated (reset the envs first)";
     case GX_EBUSY: return "no free server tiles for the request now";
+    case GX_ESIZE: return "batch larger than env_rollout_static's tables (GX_STATIC_MAX_ENVS envs)";
     default: return "unknown status";
   }
 }

@@ -18,13 +18,14 @@ from . import workloads
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgridenv.so")
 
-GX_OK, GX_EINVAL, GX_ENOMEM, GX_EDEVICE, GX_ESTATE, GX_EBUSY = 0, -1, -2, -3, -4, -5
+GX_OK, GX_EINVAL, GX_ENOMEM, GX_EDEVICE, GX_ESTATE, GX_EBUSY, GX_ESIZE = 0, -1, -2, -3, -4, -5, -6
+GX_STATIC_MAX_ENVS = 262144
 OBS_BYTES = 147
 RGB_FIRST_PERSON = (224, 224, 3)
 EXPORTS = ("env_create", "env_sizes", "env_info", "env_reset", "env_step", "env_rollout",
            "env_set_launch", "env_destroy", "env_strerror",
            "env_server_create", "env_server_admit", "env_server_step", "env_server_release",
-           "env_server_info", "env_server_destroy", "env_serve_run")
+           "env_server_info", "env_server_destroy", "env_serve_run", "env_rollout_static")
 
 
 class GxConfig(ctypes.Structure):
@@ -122,6 +123,8 @@ def load(path: str = LIB_PATH):
     L.env_server_destroy.argtypes = [P]
     L.env_serve_run.argtypes = [P, ctypes.POINTER(GxServeItem), I32, P, P, P, P,
                                 ctypes.POINTER(GxServeOpts), P, P, P, ctypes.POINTER(GxServeStats)]
+    L.env_rollout_static.argtypes = [ctypes.POINTER(GxConfig), ctypes.POINTER(GxState), I32,
+                                     ctypes.POINTER(GxTraj), I32, P, ctypes.POINTER(GxTraj), I32, P]
     L.env_strerror.argtypes = [ctypes.c_int]
     L.env_strerror.restype = ctypes.c_char_p
     for f in EXPORTS:
@@ -150,6 +153,15 @@ def _stream_ptr(stream) -> int | None:
 def env_create(table: workloads.EnvTable, reward_mode: int = 0, obs_mode: int = 0,
                sprites: np.ndarray | None = None) -> int:
     """sprites: the atlas u8[264][32][32][3] of the rgb modes (4, 5)."""
+    cfg, keep = _config(table, reward_mode, obs_mode, sprites)
+    ctx = ctypes.c_void_p()
+    _check("env_create", load().env_create(ctypes.byref(cfg), ctypes.byref(ctx)))
+    del keep
+    return ctx.value
+
+
+def _config(table: workloads.EnvTable, reward_mode: int, obs_mode: int, sprites=None):
+    """The gx_config of a table, and the host arrays it points into."""
     fam = np.ascontiguousarray(table.family, np.uint8)
     side = np.ascontiguousarray(table.side, np.uint8)
     ms = np.ascontiguousarray(table.max_steps, np.int32)
@@ -164,9 +176,21 @@ def env_create(table: workloads.EnvTable, reward_mode: int = 0, obs_mode: int = 
     cfg = GxConfig(table.n, reward_mode, obs_mode, fam.ctypes.data, side.ctypes.data, par.ctypes.data,
                    ms.ctypes.data, seed.ctypes.data, 0, rid.ctypes.data,
                    atlas.ctypes.data if atlas is not None else None)
-    ctx = ctypes.c_void_p()
-    _check("env_create", load().env_create(ctypes.byref(cfg), ctypes.byref(ctx)))
-    return ctx.value
+    return cfg, (fam, side, ms, seed, rid, par, atlas)
+
+
+def env_rollout_static(table: workloads.EnvTable, state: GxState, reset: bool, first: GxTraj | None,
+                       n_steps: int, actions_ptr: int | None, traj: GxTraj | None, K: int = 0,
+                       reward_mode: int = 0, obs_mode: int = 0, stream=None):
+    """env_create + (env_reset) + env_rollout of `table` without any
+    allocation: the library's fixed tables hold up to GX_STATIC_MAX_ENVS envs."""
+    cfg, keep = _config(table, reward_mode, obs_mode)
+    _check("env_rollout_static",
+           load().env_rollout_static(ctypes.byref(cfg), ctypes.byref(state), 1 if reset else 0,
+                                     ctypes.byref(first) if first is not None else None, n_steps,
+                                     actions_ptr, ctypes.byref(traj) if traj is not None else None, K,
+                                     _stream_ptr(stream)))
+    del keep
 
 
 def env_sizes(ctx: int) -> tuple[int, int]:
