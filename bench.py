@@ -57,6 +57,9 @@ WORKLOADS = {
              "S in {5,6,8,16}, 20% FourRooms 19x19), random policy on device, trajectory ring in HBM",
     "tworoom8": "65536 TwoRoom key/door 8x8, T=640, random policy on device, trajectory ring in HBM",
     "empty8": "4096 Empty 8x8, T=256, random policy on device, trajectory ring in HBM",
+    "empty24": "{n} Empty 24x24, T=2304, random policy on device, trajectory ring in HBM",
+    "empty32": "{n} Empty 32x32, T=4096, random policy on device, trajectory ring in HBM",
+    "tworoom32": "{n} TwoRoom key/door 32x32, T=10240, random policy on device, trajectory ring in HBM",
     "empty5": "16 Empty 5x5, T=100, random policy on device, trajectory ring in HBM",
     "lava": "lava tasks: {n} envs in equal shares of LavaGap S5/S6/S7, Crossings S9N1/S9N2/S9N3/"
             "S11N5, DistShift1 (6x6), DistShift2 (8x8), random policy on device, trajectory ring in HBM",
@@ -100,12 +103,12 @@ def chunks(steps: int, K: int) -> list:
     return [K] * (steps // K) + ([steps % K] if steps % K else [])
 
 
-def profile_traffic(workload: str, k: int, n_envs: int):
-    """Calibrated HBM bytes of one k-step launch from the committed
-    rocprofv3 summaries of this workload, or None."""
+def profile_traffic(workload: str, k: int, n_envs: int, kernel: str = "k_fused"):
+    """Calibrated HBM bytes of one k-step launch of a kernel from the
+    committed rocprofv3 summaries of this workload, or None."""
     from paper_2407_19396_amd import profiling
-    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"k_fused_{workload}{n_envs}_*.txt"))):
-        t = profiling.traffic_bytes(path, k, n_envs)
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"{kernel}_{workload}{n_envs}_*.txt"))):
+        t = profiling.traffic_bytes(path, k, n_envs, kernel)
         if t is not None:
             return t
     return None
@@ -333,8 +336,12 @@ def main():
     ap.add_argument("--K", type=int, default=0, help="steps fused per launch (0: autotune)")
     ap.add_argument("--blocks", type=int, default=0, help="persistent workgroups (0: autotune or default)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner, use library defaults")
+    ap.add_argument("--tile-envs", type=int, default=0, help="envs per fused tile (0: autotune or 64)")
     ap.add_argument("--ring", type=int, default=0, help="trajectory ring rows (0: K)")
     ap.add_argument("--plain-steps", type=int, default=512)
+    ap.add_argument("--latency-launches", type=int, default=-1,
+                    help="launches of K steps timed one by one for the per-launch latency and the "
+                         "steady-state roofline (-1: 8 to 64; 0: skip)")
     ap.add_argument("--obs", default="symbolic_first_person", choices=list(OBS_MODES),
                     help="observation function (the paper's names): symbolic_first_person (147 B) or "
                          "categorical_first_person (49 B), the whole grid: symbolic (3 S^2 B) or "
@@ -384,6 +391,9 @@ def main():
             "tworoom8": lambda: wl.workload_tworoom8(seed=0),
             "empty8": lambda: wl.workload_empty8(seed=0),
             "empty5": lambda: wl.workload_empty5(seed=0),
+            "empty24": lambda: wl.uniform_table(args.envs or 65536, wl.FAMILY_EMPTY, 24, seed=0),
+            "empty32": lambda: wl.uniform_table(args.envs or 65536, wl.FAMILY_EMPTY, 32, seed=0),
+            "tworoom32": lambda: wl.uniform_table(args.envs or 65536, wl.FAMILY_TWOROOM, 32, seed=0),
             "lava": lambda: wl.workload_lava(seed=0, n=args.envs or 262144),
             "dynobs": lambda: wl.workload_dynobs(seed=0, n=args.envs or 262144),
             "gotodoor": lambda: wl.workload_gotodoor(seed=0, n=args.envs or 262144),
@@ -393,7 +403,8 @@ def main():
     if rgb and not args.envs:
         args.envs = 16384          # a step writes 2.5 GB of first-person images at this size
     table = make()
-    if args.envs and args.workload not in ("mixed", "lava", "dynobs", "gotodoor", "keycorridor"):
+    if args.envs and args.workload not in ("mixed", "lava", "dynobs", "gotodoor", "keycorridor", "empty24",
+                                           "empty32", "tworoom32"):
         table = table.subset(np.arange(args.envs) % table.n)
     sprites = None
     if rgb:
@@ -408,7 +419,9 @@ def main():
     if rgb:
         # launches of K steps, each drawn by the renderer right after
         env.set_launch(args.K or 16, args.blocks)
-    elif args.K or args.blocks or args.no_tune:
+    elif args.K or args.blocks or args.no_tune or args.tile_envs:
+        if args.tile_envs:
+            env.set_tiling(args.tile_envs)
         env.set_launch(args.K or env.info()["k_default"], args.blocks)
     else:
         from paper_2407_19396_amd import autotune
@@ -417,15 +430,17 @@ def main():
         Ks = [k for k in (128, 256, 512, 1024) if k * row_bytes <= RING_BUDGET] or [128]
         probe = env.traj(max(Ks))
         env.reset(first)
-        tuned = autotune.tune(env, probe, Ks=tuple(Ks), log=log)
+        tuned = autotune.tune(env, probe, Ks=tuple(Ks), steps=args.steps, log=log)
         del probe
-        log(f"[bench] autotuned K={tuned['K']} blocks={tuned['blocks']}")
+        log(f"[bench] autotuned tile_envs={tuned['tile_envs']} K={tuned['K']} blocks={tuned['blocks']}")
     info = env.info()
     K = info["k_default"]
     ring = args.ring or K
     log(f"[bench] {table.name}: grid {info['grid_bytes'] / 1e6:.1f} MB, tiles {info['n_tiles']}, "
         f"LDS/WG {info['lds_bytes']} B, blocks {info['blocks']}, K {K}, ring {ring}")
     traj = env.traj(ring)
+    if not np.any(table.family == 7):
+        traj.mission = None       # the mission output only carries GoToDoor's target
     env.reset(first)
     # warmup (also advances episodes away from the synchronous start)
     env.rollout(args.warmup, traj, K=K)
@@ -474,7 +489,8 @@ def main():
         reps.append(env_steps / (a.elapsed_time(b) / 1e3))
     # per-launch latency of the fused kernel at K steps per launch
     lat = []
-    for _ in range(min(64, max(8, len(timed_chunks)))):
+    n_lat = args.latency_launches if args.latency_launches >= 0 else min(64, max(8, len(timed_chunks)))
+    for _ in range(n_lat):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
         env.rollout(K, traj, K=K)
@@ -516,8 +532,9 @@ def main():
             # algorithmic bytes of a plain step: state, view cells (at most 49 in the grid), record
             cells = float(np.mean(np.minimum(49, table.side.astype(np.int64) ** 2)))
             per_step = table.n * (PLAIN_READ + 3 * cells + PLAIN_WRITE + RECORD_BYTES)
-            plain["roofline"] = roofline_entry(per_step, pms / args.plain_steps, None, kernel="k_plain",
-                                               bytes_per_env_step=per_step / table.n)
+            plain["roofline"] = roofline_entry(per_step, pms / args.plain_steps,
+                                               profile_traffic(args.workload, 1, table.n, "k_plain"),
+                                               kernel="k_plain", bytes_per_env_step=per_step / table.n)
         log(f"[bench] plain: {plain_rate / 1e9:.2f} G env-steps/s, launch p50 "
             f"{plain['launch_ms']['p50'] * 1e3:.1f} us")
 
@@ -539,9 +556,10 @@ def main():
                           ms / len(timed_chunks), traffic_of(timed_chunks), kernel=kernel,
                           launches=len(timed_chunks), steps_per_launch=sorted(set(timed_chunks)),
                           timing="HIP events around the timed rollout")
-    roof["steady_state"] = roofline_entry(launch_bytes(K), float(np.mean(lat)), traffic_of([K]),
-                                          steps_per_launch=K, launches=len(lat),
-                                          timing="HIP events around each launch of K steps, mean")
+    if len(lat):
+        roof["steady_state"] = roofline_entry(launch_bytes(K), float(np.mean(lat)), traffic_of([K]),
+                                              steps_per_launch=K, launches=len(lat),
+                                              timing="HIP events around each launch of K steps, mean")
 
     del traj, env, first
     torch.cuda.empty_cache()
@@ -578,10 +596,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload].replace("{n}", str(table.n)),
                    "n_envs": table.n, "K": K, "ring_rows": ring, "blocks": info["blocks"],
+                   "tile_envs": info["tile_envs"],
                    "lds_bytes_per_wg": info["lds_bytes"], "max_tile_cells": info["max_tile_cells"],
                    "global_batch": table.n, "autotuned": tuned is not None,
                    "hip_graph": graph is not None, "observation": args.obs},
-        "fused_launch_ms": {"K": K, "p50": pct(lat, 50), "p99": pct(lat, 99)},
+        "fused_launch_ms": {"K": K, "p50": pct(lat, 50), "p99": pct(lat, 99)} if len(lat) else None,
         "repeats": None if not reps else {"n": len(reps), "median": float(np.median(reps)),
                                           "min": float(np.min(reps)), "max": float(np.max(reps))},
         "plain": plain,

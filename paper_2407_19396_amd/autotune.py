@@ -1,13 +1,17 @@
 """Launch-shape autotuner for the fused rollout kernel.
 
-The fused kernel's speed depends on two choices the library cannot know in
-advance: K, the steps fused per launch (longer chunks amortise loading and
+The fused kernel's speed depends on three choices the library cannot know
+in advance: the envs per tile (one env per lane; fewer than a wave's 64
+lanes need less LDS per workgroup, so more workgroups fit a compute unit,
+which pays for large grids), K, the steps fused per launch (longer chunks amortise loading and
 storing each tile's grids, shorter ones bound the latency of a chunk), and
 the number of persistent workgroups (more hide latency better, but tiles
 are handed out in whole rounds, so a count that does not divide the tile
-count leaves the last round partly idle).  ``tune`` times short rollouts
-of the actual batch for each candidate and keeps the fastest, caching the
-choice on disk per device and batch composition.
+count leaves the last round partly idle, which matters most for short
+rollouts, where the grids' staging is a large share of a launch).
+``tune`` times rollouts of the actual batch and length for each candidate
+and keeps the fastest, caching the choice on disk per device, batch
+composition and rollout length.
 
 Tuning steps the envs: call it before the real run and reset afterwards.
 """
@@ -51,50 +55,92 @@ def block_candidates(n_tiles: int, lds_bytes: int, cus: int, lds_per_cu: int = 1
     return sorted(out)
 
 
-def tune(env, traj, Ks=(128, 256, 512), steps: int = 1024, use_cache: bool = True, log=None) -> dict:
+def _time_rollout(env, traj, steps: int, K: int, stream, budget_ms: float = 30.0) -> float:
+    """Mean milliseconds of a `steps`-step rollout at K steps per launch:
+    one untimed run, then enough timed runs to fill about budget_ms."""
     import torch
-    from . import gridenv as ge
+    env.rollout(steps, traj, K=K)
+    a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    env.rollout(steps, traj, K=K)
+    z.record(stream)
+    z.synchronize()
+    one = max(a.elapsed_time(z), 1e-3)
+    reps = int(min(50, max(1, budget_ms // one)))
+    if reps == 1:
+        return one
+    a.record(stream)
+    for _ in range(reps):
+        env.rollout(steps, traj, K=K)
+    z.record(stream)
+    z.synchronize()
+    return a.elapsed_time(z) / reps
+
+
+def tune(env, traj, Ks=(128, 256, 512), steps: int = 0, tile_envs=(64, 32, 16), use_cache: bool = True,
+         log=None) -> dict:
+    """Pick the envs per tile, K and the workgroup count for rollouts of
+    `steps` steps (0: one launch of each candidate K, the steady state).
+
+    First the envs per tile (each tiling at the workgroup count that fills
+    the compute units' LDS, K the largest candidate), then K x workgroups
+    for the best tiling.  When `steps` is shorter than every candidate K,
+    all of them run the same single launch, so only the workgroup count is
+    searched (at the largest K, which later full launches then use)."""
+    import torch
 
     dev = torch.cuda.current_device()
     props = torch.cuda.get_device_properties(dev)
     Ks = [k for k in Ks if k <= traj.rows]
-    key = batch_key(env.table, props.name, env.obs_mode, env.reward_mode, Ks)
+    Es = [e for e in tile_envs if 1 <= e <= 64]
+    key = (batch_key(env.table, props.name, env.obs_mode, env.reward_mode, Ks) +
+           f"|steps{steps}|E{','.join(str(e) for e in Es)}")
     cache = {}
     if use_cache and os.path.exists(CACHE):
         try:
             cache = json.load(open(CACHE))
         except (OSError, ValueError):
             cache = {}
-    if use_cache and key in cache and cache[key].get("K") in Ks:
+    if use_cache and key in cache and cache[key].get("K") in Ks and cache[key].get("tile_envs") in Es:
         best = cache[key]
+        env.set_tiling(best["tile_envs"])
         env.set_launch(best["K"], best["blocks"])
         return best | {"cached": True}
 
-    info = env.info()
-    blocks = block_candidates(info["n_tiles"], info["lds_bytes"], props.multi_processor_count)
-    results = []
+    search = [max(Ks)] if 0 < steps <= min(Ks) else Ks
     stream = torch.cuda.current_stream()
-    for K in Ks:
-        for b in blocks:
-            env.set_launch(K, b)
-            env.rollout(K, traj, K=K)          # warm this shape
-            a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            n = max(K, (steps // K) * K)
-            a.record(stream)
-            env.rollout(n, traj, K=K)
-            z.record(stream)
-            z.synchronize()
-            rate = env.n * n / (a.elapsed_time(z) / 1e3)
-            results.append({"K": K, "blocks": b, "rate": rate})
-            if log:
-                log(f"[autotune] K={K} blocks={b}: {rate / 1e9:.2f} G env-steps/s")
-    best = max(results, key=lambda r: r["rate"])
+    results = []
+
+    def trial(E, K, b):
+        n = steps if steps > 0 else K
+        env.set_launch(K, b)
+        ms = _time_rollout(env, traj, n, K, stream)
+        r = {"tile_envs": E, "K": K, "blocks": b, "lds_bytes": env.info()["lds_bytes"],
+             "rate": env.n * n / (ms / 1e3)}
+        results.append(r)
+        if log:
+            log(f"[autotune] E={E} K={K} blocks={b} ({n}-step rollouts): {r['rate'] / 1e9:.2f} G env-steps/s")
+        return r
+
+    # stage 1: envs per tile
+    firsts = []
+    for E in Es:
+        env.set_tiling(E)
+        firsts.append(trial(E, max(search), env.info()["blocks"]))
+    E = max(firsts, key=lambda r: r["rate"])["tile_envs"]
+    # stage 2: K x workgroups at that tiling
+    env.set_tiling(E)
+    info = env.info()
+    for K in search:
+        for b in block_candidates(info["n_tiles"], info["lds_bytes"], props.multi_processor_count):
+            trial(E, K, b)
+    best = max((r for r in results if r["tile_envs"] == E), key=lambda r: r["rate"])
     env.set_launch(best["K"], best["blocks"])
     if use_cache:
         try:
             os.makedirs(os.path.dirname(CACHE), exist_ok=True)
-            cache[key] = {"K": best["K"], "blocks": best["blocks"], "rate": best["rate"]}
+            cache[key] = {k: best[k] for k in ("tile_envs", "K", "blocks", "lds_bytes", "rate")} | {"steps": steps}
             json.dump(cache, open(CACHE, "w"), indent=1)
         except OSError:
             pass
-    return best | {"cached": False, "trials": results}
+    return best | {"cached": False, "trials": results, "steps": steps}

@@ -1679,7 +1679,8 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
     const bool fresh = kServe && (entry >> 31) != 0;
     // where this tile's envs live and where their records go: record of
     // step s, lane l is at index rec_base + s * rec_step (+ l) of the outputs
-    const int e0 = tile * kWave;
+    const int tile_envs = kServe ? kWave : a.tiles.tile_envs;
+    const int e0 = tile * tile_envs;
     int n_here, steps;
     uint64_t g0 = 0;
     uint8_t *o_obs, *o_flags, *o_action, *o_mission = nullptr;
@@ -1704,7 +1705,7 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
       o_flags += d.local0;
       o_action += d.local0;
     } else {
-      n_here = min(kWave, N - e0);
+      n_here = min(tile_envs, N - e0);
       steps = a.k_steps;
       o_obs = a.out.obs ? a.out.obs + (size_t)e0 * (kObs == 1 ? kCatBytes : kObsBytes) : nullptr;
       o_reward = a.out.reward + e0;

@@ -40,12 +40,13 @@ struct TrajBufs {
   uint8_t* mission = nullptr;  // [rows][N] the episode's mission (GoToDoor colour, else 0xFF), or nullptr
 };
 
-// Fused rollout tiling: tile i covers envs [i*64, i*64+64) (the last is
-// ragged); tile_cells[i] = sum of S^2 over its envs.
+// Fused rollout tiling: tile i covers envs [i*E, i*E+E) (the last is
+// ragged), E = tile_envs envs on the first E lanes of a wave (serving: 64).
 struct TileTables {
   int32_t n_tiles;
-  int32_t max_tile_cells;     // LDS bytes of the largest tile's code grids
+  int32_t max_tile_cells;     // LDS bytes of the largest tile's code grids (sum of S^2)
   const uint32_t* list;       // tile ids to run, n_tiles of them (serving), or nullptr: 0..n_tiles-1
+  int32_t tile_envs = 64;     // E, 1..64
 };
 
 // A tile of 64 slots serving one request (device memory, 64 bytes).  The

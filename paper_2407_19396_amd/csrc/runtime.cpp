@@ -28,10 +28,14 @@ struct gx_ctx {
   uint32_t* d_rng_id = nullptr;
   uint64_t* d_grid_off = nullptr;
   // fused tiling and launch shape
+  int32_t tile_envs = 64;
   int32_t n_tiles = 0;
   int32_t max_tile_cells = 0;
   int32_t blocks = 0;
   int32_t k_default = 64;
+  std::vector<int32_t> cells;          // S^2 per env, for re-tiling
+  int cus = 256;                       // the device's compute units and LDS per unit
+  size_t lds_per_cu = 160 * 1024;
   // rgb modes: the sprite atlas, and the staging ring of symbolic records
   // (obs [stage_rows][sym_row], then reward, flags, action, mission
   // [stage_rows][n]) that the step kernels fill and the renderer expands
@@ -77,6 +81,23 @@ void free_tables(gx_ctx* c) {
   c->d_seed = nullptr;
   c->d_rng_id = nullptr;
   c->d_grid_off = nullptr;
+}
+
+// Tiles of E consecutive envs; as many persistent single-wave workgroups
+// as the LDS of every compute unit holds for the largest tile, no more than
+// there are tiles.
+void set_tiling(gx_ctx* c, int32_t E) {
+  c->tile_envs = E;
+  c->n_tiles = (c->n + E - 1) / E;
+  c->max_tile_cells = 0;
+  for (int32_t t = 0; t < c->n_tiles; ++t) {
+    int32_t cells = 0;
+    for (int32_t i = t * E; i < std::min(c->n, (t + 1) * E); ++i) cells += c->cells[i];
+    c->max_tile_cells = std::max(c->max_tile_cells, cells);
+  }
+  const size_t lds = gx::fused_lds_bytes(c->max_tile_cells);
+  const int per_cu = std::max<int>(1, std::min<int>(16, (int)(c->lds_per_cu / lds)));
+  c->blocks = std::min<int32_t>(c->n_tiles, c->cus * per_cu);
 }
 
 bool state_ok(const gx_state* st) {
@@ -238,14 +259,14 @@ int env_create(const gx_config* cfg, gx_ctx** out) {
   c->reward_mode = cfg->reward_mode;
   c->obs_mode = cfg->obs_mode;
   c->grid_bytes = off;
-  c->n_tiles = (n + kTileEnvs - 1) / kTileEnvs;
-  for (int32_t t = 0; t < c->n_tiles; ++t) {
-    int32_t cells = 0;
-    for (int32_t i = t * kTileEnvs; i < std::min(n, (t + 1) * kTileEnvs); ++i)
-      cells += (int32_t)cfg->side[i] * (int32_t)cfg->side[i];
-    c->max_tile_cells = std::max(c->max_tile_cells, cells);
+  int rc = GX_OK;
+  try {
+    c->cells.resize(n);
+  } catch (const std::bad_alloc&) {
+    rc = GX_ENOMEM;
   }
-  int rc = upload(&c->d_meta, meta);
+  for (int32_t i = 0; rc == GX_OK && i < n; ++i) c->cells[i] = (int32_t)cfg->side[i] * (int32_t)cfg->side[i];
+  if (rc == GX_OK) rc = upload(&c->d_meta, meta);
   if (rc == GX_OK) rc = upload(&c->d_max_steps, max_steps);
   if (rc == GX_OK) rc = upload(&c->d_seed, seed);
   if (rc == GX_OK) rc = upload(&c->d_rng_id, rng_id);
@@ -273,18 +294,12 @@ int env_create(const gx_config* cfg, gx_ctx** out) {
     delete c;
     return rc;
   }
-  // persistent grid: as many single-wave workgroups as the LDS of every
-  // compute unit holds, but no more than there are tiles
   hipDeviceProp_t prop;
-  int cus = 256;
-  size_t lds_per_cu = 160 * 1024;
   if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
-    cus = prop.multiProcessorCount;
-    if (prop.maxSharedMemoryPerMultiProcessor > 0) lds_per_cu = prop.maxSharedMemoryPerMultiProcessor;
+    c->cus = prop.multiProcessorCount;
+    if (prop.maxSharedMemoryPerMultiProcessor > 0) c->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor;
   }
-  const size_t lds = gx::fused_lds_bytes(c->max_tile_cells);
-  const int per_cu = std::max<int>(1, std::min<int>(16, (int)(lds_per_cu / lds)));
-  c->blocks = std::min<int32_t>(c->n_tiles, cus * per_cu);
+  set_tiling(c, kTileEnvs);
   *out = c;
   return GX_OK;
 }
@@ -300,6 +315,7 @@ int env_info(const gx_ctx* c, gx_info* info) {
   if (!c || !info) return GX_EINVAL;
   info->n_envs = c->n;
   info->n_tiles = c->n_tiles;
+  info->tile_envs = c->tile_envs;
   info->max_tile_cells = c->max_tile_cells;
   info->lds_bytes = (int32_t)gx::fused_lds_bytes(c->max_tile_cells);
   info->blocks = c->blocks;
@@ -353,7 +369,7 @@ int env_rollout(gx_ctx* c, const gx_state* st, int32_t n_steps, const uint8_t* a
   // rgb: each fused launch fills the staging ring from row 0, then the
   // renderer draws those rows into the caller's ring
   const int32_t k = std::min(K > 0 ? K : c->k_default, stg ? c->stage_rows : INT32_MAX);
-  const gx::TileTables tiles{c->n_tiles, c->max_tile_cells, nullptr};   // every tile, in order
+  const gx::TileTables tiles{c->n_tiles, c->max_tile_cells, nullptr, c->tile_envs};   // every tile, in order
   for (int32_t s0 = 0; s0 < n_steps; s0 += k) {
     const int32_t ks = std::min(k, n_steps - s0);
     const uint8_t* act = actions ? actions + (size_t)s0 * (size_t)c->n : nullptr;
@@ -369,6 +385,12 @@ int env_set_launch(gx_ctx* c, int32_t K, int32_t blocks) {
   if (!c || K < 1 || blocks < 0) return GX_EINVAL;
   c->k_default = K;
   if (blocks > 0) c->blocks = blocks;
+  return GX_OK;
+}
+
+int env_set_tiling(gx_ctx* c, int32_t tile_envs) {
+  if (!c || tile_envs < 1 || tile_envs > kTileEnvs) return GX_EINVAL;
+  set_tiling(c, tile_envs);
   return GX_OK;
 }
 

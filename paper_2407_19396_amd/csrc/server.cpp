@@ -463,13 +463,16 @@ int env_serve_run(gx_server* s, const gx_serve_item* items, int32_t n_items, con
     }
     return issue_copies();
   };
+  // host side of finished launches, then of finished copies (polled on
+  // every call, so a delivery is stamped when the host can first see it,
+  // not only once the launch pipeline drains)
   auto retire = [&](bool wait) -> int {
     while (!inflight.empty()) {
       hipEvent_t ev = events[inflight.front().first];
       const double w0 = wait ? now_s() : 0.0;
       hipError_t q = wait ? hipEventSynchronize(ev) : hipEventQuery(ev);
       if (wait) t_wait += now_s() - w0;
-      if (q == hipErrorNotReady) return GX_OK;
+      if (q == hipErrorNotReady) break;
       if (q != hipSuccess) return GX_EDEVICE;
       const double t = now_s();
       std::vector<Live> fin_reqs;

@@ -23,7 +23,7 @@ GX_STATIC_MAX_ENVS = 262144
 OBS_BYTES = 147
 RGB_FIRST_PERSON = (224, 224, 3)
 EXPORTS = ("env_create", "env_sizes", "env_info", "env_reset", "env_step", "env_rollout",
-           "env_set_launch", "env_destroy", "env_strerror",
+           "env_set_launch", "env_set_tiling", "env_destroy", "env_strerror",
            "env_server_create", "env_server_admit", "env_server_step", "env_server_release",
            "env_server_info", "env_server_destroy", "env_serve_run", "env_rollout_static")
 
@@ -53,7 +53,8 @@ class GxInfo(ctypes.Structure):
     _fields_ = [("n_envs", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
                 ("max_tile_cells", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
                 ("blocks", ctypes.c_int32), ("k_default", ctypes.c_int32),
-                ("grid_bytes", ctypes.c_uint64), ("obs_row_bytes", ctypes.c_uint64)]
+                ("grid_bytes", ctypes.c_uint64), ("obs_row_bytes", ctypes.c_uint64),
+                ("tile_envs", ctypes.c_int32)]
 
 
 class GxRequest(ctypes.Structure):
@@ -114,6 +115,7 @@ def load(path: str = LIB_PATH):
     L.env_step.argtypes = [P, ctypes.POINTER(GxState), P, ctypes.POINTER(GxTraj), P]
     L.env_rollout.argtypes = [P, ctypes.POINTER(GxState), I32, P, ctypes.POINTER(GxTraj), I32, P]
     L.env_set_launch.argtypes = [P, I32, I32]
+    L.env_set_tiling.argtypes = [P, I32]
     L.env_destroy.argtypes = [P]
     L.env_server_create.argtypes = [I32, I32, I32, ctypes.POINTER(P)]
     L.env_server_admit.argtypes = [P, ctypes.POINTER(GxRequest), ctypes.POINTER(I32)]
@@ -226,6 +228,10 @@ def env_set_launch(ctx: int, K: int, blocks: int = 0):
     _check("env_set_launch", load().env_set_launch(ctx, K, blocks))
 
 
+def env_set_tiling(ctx: int, tile_envs: int):
+    _check("env_set_tiling", load().env_set_tiling(ctx, tile_envs))
+
+
 def env_destroy(ctx: int):
     _check("env_destroy", load().env_destroy(ctx))
 
@@ -323,6 +329,9 @@ class GridEnv:
 
     def set_launch(self, K: int, blocks: int = 0):
         env_set_launch(self.ctx, K, blocks)
+
+    def set_tiling(self, tile_envs: int):
+        env_set_tiling(self.ctx, tile_envs)
 
     def info(self) -> dict:
         return env_info(self.ctx)

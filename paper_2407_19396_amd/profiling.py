@@ -1,4 +1,4 @@
-"""rocprofv3 summaries for the fused rollout kernel.
+"""rocprofv3 summaries for the step kernels.
 
 ``summarize`` turns the CSV output of a kernel-trace run and of FETCH_SIZE /
 WRITE_SIZE (and optional SQ) counter runs into a short text summary for
@@ -10,7 +10,7 @@ it is ignored once the kernel's code has changed (comments and layout
 aside).
 
     python -m paper_2407_19396_amd.profiling --trace DIR --fetch DIR --write DIR
-        [--sq DIR] --copy-bytes N --K K --envs N --command "..." -o profiles/x.txt
+        [--sq DIR] --copy-bytes N --K K --envs N [--kernel k_plain] --command "..." -o profiles/x.txt
 
 ``render_summary`` covers the rgb path: the renderer's launches of K rows
 (the one-row launch after a reset left out) against their algorithmic bytes,
@@ -64,7 +64,10 @@ def kernel_source_hash(paths=KERNEL_SOURCES) -> str:
 
 
 def _one(pattern: str) -> str:
-    hits = sorted(glob.glob(pattern))
+    """The first file matching dir/pattern, in dir or below it (rocprofv3
+    may add host and process subdirectories)."""
+    d, base = os.path.split(pattern)
+    hits = sorted(glob.glob(pattern)) or sorted(glob.glob(os.path.join(d, "**", base), recursive=True))
     if not hits:
         raise FileNotFoundError(pattern)
     return hits[0]
@@ -98,20 +101,34 @@ def _mean(xs):
     return sum(xs) / len(xs)
 
 
+def _median(xs):
+    xs = sorted(xs)
+    n = len(xs)
+    return xs[n // 2] if n % 2 else 0.5 * (xs[n // 2 - 1] + xs[n // 2])
+
+
 def summarize(trace: str, fetch: str, write: str, sq, copy_bytes: int, K: int,
-              envs: int, command: str, source: str = KERNEL_SOURCE) -> str:
-    """sq: a directory or a list of directories of SQ counter runs; source:
-    the kernel source the profiled library was built from."""
+              envs: int, command: str, source=KERNEL_SOURCES, kernel_name: str = FUSED,
+              workload: str = "mixed") -> str:
+    """Summary of one kernel's launches (kernel_name: k_fused, launches of K
+    steps; or k_plain, one step per launch).  sq: a directory or a list of
+    directories of SQ counter runs; source: the sources the profiled library
+    was built from.  Counters are the median over the kernel's dispatches
+    (a k_plain run also holds a few reset launches, which the median leaves
+    out)."""
     kernel = kernel_source_hash(source)
     st = _stats(trace)
     fc, wc = _counters(fetch), _counters(write)
     copy_fetch = _mean(fc[(COPY_KERNEL, "FETCH_SIZE")]) * 1024
     copy_write = _mean(wc[(COPY_KERNEL, "WRITE_SIZE")]) * 1024
     f_scale, w_scale = copy_bytes / copy_fetch, copy_bytes / copy_write
-    fused_fetch = _mean(fc[(FUSED, "FETCH_SIZE")]) * 1024 * f_scale
-    fused_write = _mean(wc[(FUSED, "WRITE_SIZE")]) * 1024 * w_scale
+    k_fetch = _median(fc[(kernel_name, "FETCH_SIZE")]) * 1024 * f_scale
+    k_write = _median(wc[(kernel_name, "WRITE_SIZE")]) * 1024 * w_scale
+    durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+            for r in _dispatches(trace, "*kernel_trace.csv", kernel_name, None)]
+    shape = f"launches of K = {K} steps" if kernel_name == FUSED else "one step per launch"
     lines = [
-        "# k_fused on the mixed 262144-env workload (rocprofv3)",
+        f"# {kernel_name} on the {workload} {envs}-env workload, {shape} (rocprofv3)",
         "",
         f"command: {command}",
         f"kernel code sha256[:16] (kernels.hip + launch.h, comments aside): {kernel}",
@@ -121,38 +138,45 @@ def summarize(trace: str, fetch: str, write: str, sq, copy_bytes: int, K: int,
     ]
     for k in (FUSED, PLAIN):
         if k in st:
-            s = st[k]
-            lines.append(f"{k}: calls {s['calls']}, average {s['avg_ns'] / 1e3:.1f} us, "
-                         f"min {s['min_ns'] / 1e3:.1f} us, max {s['max_ns'] / 1e3:.1f} us")
+            s_ = st[k]
+            lines.append(f"{k}: calls {s_['calls']}, average {s_['avg_ns'] / 1e3:.1f} us, "
+                         f"min {s_['min_ns'] / 1e3:.1f} us, max {s_['max_ns'] / 1e3:.1f} us")
+    if durs:
+        lines.append(f"{kernel_name} median dispatch (kernel trace): {_median(durs) / 1e3:.1f} us "
+                     f"over {len(durs)} dispatches")
     lines += [
         "",
         "## HBM traffic (--pmc FETCH_SIZE, then --pmc WRITE_SIZE; KiB per dispatch)",
         f"copy probe of {copy_bytes} bytes: FETCH_SIZE {copy_fetch / 1024:.0f} KiB, "
         f"WRITE_SIZE {copy_write / 1024:.0f} KiB -> scale fetch x{f_scale:.3f}, write x{w_scale:.3f}",
-        f"k_fused per launch: fetch {fused_fetch / 1e6:.1f} MB, write {fused_write / 1e6:.1f} MB (scaled)",
+        f"{kernel_name} per launch (median): fetch {k_fetch / 1e6:.2f} MB, write {k_write / 1e6:.2f} MB (scaled)",
     ]
     if sq:
         wave_steps = envs / 64 * K
-        lines += ["", "## SQ counters per launch (and per wave-step of 64 env-steps)"]
+        lines += ["", "## SQ counters per launch, median (and per wave-step of 64 env-steps)"]
         for d in ([sq] if isinstance(sq, str) else sq):
             qc = _counters(d)
             for (k, c), v in sorted(qc.items()):
-                if k == FUSED:
-                    lines.append(f"{c}: {_mean(v):.4g} ({_mean(v) / wave_steps:.1f} per wave-step)")
-    lines += ["", f"machine: traffic_bytes_per_launch={fused_fetch + fused_write:.0f} K={K} envs={envs} "
-                  f"kernel={kernel} avg_ns={st.get(FUSED, {}).get('avg_ns', 0):.0f}"]
+                if k == kernel_name:
+                    m = _median(v)
+                    lines.append(f"{c}: {m:.4g} ({m / wave_steps:.1f} per wave-step)")
+    avg = st.get(kernel_name, {}).get("avg_ns", 0)
+    lines += ["", f"machine: name={kernel_name} traffic_bytes_per_launch={k_fetch + k_write:.0f} K={K} "
+                  f"envs={envs} kernel={kernel} avg_ns={avg:.0f} median_ns={_median(durs) if durs else 0:.0f}"]
     return "\n".join(lines) + "\n"
 
 
-def traffic_bytes(profile_path: str, K: int, envs: int) -> float | None:
-    """Calibrated HBM bytes per fused launch from a committed summary, or
-    None if it is missing or was taken for another kernel source, K or size."""
+def traffic_bytes(profile_path: str, K: int, envs: int, kernel_name: str = FUSED) -> float | None:
+    """Calibrated HBM bytes per launch of a kernel from a committed summary,
+    or None if it is missing or was taken for another kernel source, K or
+    size."""
     if not os.path.exists(profile_path):
         return None
     for line in open(profile_path):
         if line.startswith("machine:"):
             kv = dict(tok.split("=", 1) for tok in line.split()[1:])
-            if kv.get("kernel") == kernel_source_hash() and int(kv["K"]) == K and int(kv["envs"]) == envs:
+            if (kv.get("name", FUSED) == kernel_name and kv.get("kernel") == kernel_source_hash()
+                    and int(kv["K"]) == K and int(kv["envs"]) == envs):
                 return float(kv["traffic_bytes_per_launch"])
     return None
 
@@ -262,6 +286,8 @@ def main():
     ap.add_argument("--copy-bytes", type=int)
     ap.add_argument("--K", type=int)
     ap.add_argument("--envs", type=int)
+    ap.add_argument("--kernel", default=FUSED, choices=(FUSED, PLAIN), help="kernel to summarise")
+    ap.add_argument("--workload", default="mixed", help="workload name for the title")
     ap.add_argument("--command", required=True)
     ap.add_argument("-o", "--out", required=True)
     a = ap.parse_args()
@@ -274,7 +300,8 @@ def main():
     else:
         if not (a.trace and a.fetch and a.write and a.copy_bytes and a.K and a.envs):
             ap.error("--trace, --fetch, --write, --copy-bytes, --K and --envs are needed")
-        text = summarize(a.trace, a.fetch, a.write, a.sq, a.copy_bytes, a.K, a.envs, a.command, a.source)
+        text = summarize(a.trace, a.fetch, a.write, a.sq, a.copy_bytes, a.K, a.envs, a.command, a.source,
+                         a.kernel, a.workload)
     with open(a.out, "w") as f:
         f.write(text)
     print(text)

@@ -419,3 +419,30 @@ def test_gotodoor_done_and_out_of_range_actions(ge, kernel):
     torch.cuda.synchronize()
     P.assert_rows_equal(traj, ref, what=f"gotodoor {kernel}")
     P.assert_state_equal(env, s, f"gotodoor {kernel}")
+
+
+@pytest.mark.parametrize("tile_envs", [1, 13, 16, 32, 48])
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_tiling_parity(ge, tile_envs, mode):
+    """Tiles of fewer envs than a wave's lanes (env_set_tiling) change only
+    how envs map onto waves: every output and the state still equal the
+    oracle's, for each record kind, with ragged last tiles and tile sizes
+    whose records are not 16-byte aligned."""
+    import torch
+    table = wl.families_table(1000, seed=91, mix_seed=92)
+    env = ge.GridEnv(table, obs_mode=mode)
+    env.set_tiling(tile_envs)
+    info = env.info()
+    assert info["tile_envs"] == tile_envs and info["n_tiles"] == -(-table.n // tile_envs)
+    first = env.traj(1)
+    env.reset(first)
+    b, s, ref0 = P.oracle_reset(table, obs_mode=mode)
+    steps = 30
+    traj = env.traj(steps)
+    env.rollout(steps, traj, K=7)
+    ref = ox.rollout(b, s, steps, None, nthreads=8)
+    torch.cuda.synchronize()
+    P.assert_rows_equal(first, ref0, what=f"reset, tiles of {tile_envs}")
+    P.assert_rows_equal(traj, ref, what=f"rollout, tiles of {tile_envs}, mode {mode}")
+    P.assert_state_equal(env, s, f"tiles of {tile_envs}")
+    env.close()
