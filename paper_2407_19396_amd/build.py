@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgridenv.so")
 SOURCES = [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "render.hip"),
            os.path.join(CSRC, "runtime.cpp"), os.path.join(CSRC, "server.cpp"),
-           os.path.join(CSRC, "static_rollout.cpp")]
+           os.path.join(CSRC, "static_rollout.cpp"), os.path.join(CSRC, "probe.hip")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -24,6 +24,11 @@ busy the device was between the first and the last serving launch, and the
 launches' durations and gaps.
 
     python -m paper_2407_19396_amd.profiling --serving-trace DIR --command "..." -o profiles/y.txt
+
+``store_ceilings`` measures, without a profiler, what plain fills and copies
+and the fused kernel's own record store pattern reach on the GPU.
+
+    python -m paper_2407_19396_amd.profiling --ceilings -o profiles/hbm_store_ceilings.txt
 """
 from __future__ import annotations
 
@@ -241,40 +246,115 @@ def _is_serving_launch(name: str) -> bool:
     return FUSED in name and ("<false, true" in name or "ILb0ELb1E" in name)
 
 
-def serving_summary(trace: str, command: str) -> str:
-    """Device occupancy of a serving run from its --kernel-trace CSV."""
+def serving_summary(trace: str, command: str, split_ms: float = 20.0) -> str:
+    """Device occupancy of serving runs from their --kernel-trace CSV: the
+    serving launches, split into runs wherever the device sat idle for more
+    than split_ms (a bench invocation serves several runs in a row)."""
     rows = list(csv.DictReader(open(_one(os.path.join(trace, "*kernel_trace.csv")))))
     spans = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]) for r in rows)
     serve = [(a, b) for a, b, n in spans if _is_serving_launch(n)]
     if not serve:
         raise ValueError("no serving launches in the trace")
-    t0, t1 = serve[0][0], max(b for _, b in serve)
-    dur = sorted((b - a) / 1e6 for a, b in serve)
-    gaps = sorted((serve[i + 1][0] - serve[i][1]) / 1e3 for i in range(len(serve) - 1)) or [0.0]
-    others = collections.defaultdict(float)
-    for a, b, n in spans:
-        if a >= t0 and b <= t1 and not _is_serving_launch(n):
-            others[n.split("(")[0][:60]] += (b - a) / 1e6
-    busy = sum(dur)
+    runs, cur = [], [serve[0]]
+    for a, b in serve[1:]:
+        if (a - cur[-1][1]) / 1e6 > split_ms:
+            runs.append(cur)
+            cur = []
+        cur.append((a, b))
+    runs.append(cur)
     pct = lambda xs, q: xs[min(len(xs) - 1, int(q * (len(xs) - 1) + 0.5))]  # noqa: E731
     lines = [
         "# serving launches of k_fused (rocprofv3 --kernel-trace)",
         "",
         f"command: {command}",
         f"kernel code sha256[:16] (kernels.hip + launch.h, comments aside): {kernel_source_hash()}",
-        "",
-        f"serving launches: {len(serve)}; span {(t1 - t0) / 1e6:.1f} ms; busy {busy:.1f} ms "
-        f"({100.0 * busy / ((t1 - t0) / 1e6):.1f} % of the span)",
-        f"launch duration ms: p50 {pct(dur, 0.5):.3f}, p99 {pct(dur, 0.99):.3f}, max {dur[-1]:.3f}",
-        f"gap between launches us: p50 {pct(gaps, 0.5):.1f}, max {gaps[-1]:.1f}",
-        "other kernels inside the span (ms): " +
-        (", ".join(f"{k} {v:.2f}" for k, v in sorted(others.items(), key=lambda kv: -kv[1])) or "none"),
+        f"runs: the serving launches split wherever the device was idle for more than {split_ms:g} ms",
     ]
+    for k, run in enumerate(runs):
+        t0, t1 = run[0][0], max(b for _, b in run)
+        dur = sorted((b - a) / 1e6 for a, b in run)
+        gaps = sorted((run[i + 1][0] - run[i][1]) / 1e3 for i in range(len(run) - 1)) or [0.0]
+        others = collections.defaultdict(float)
+        for a, b, n in spans:
+            if a >= t0 and b <= t1 and not _is_serving_launch(n):
+                others[n.split("(")[0][:60]] += (b - a) / 1e6
+        busy = sum(dur)
+        lines += [
+            "",
+            f"## run {k + 1}",
+            f"serving launches: {len(run)}; span {(t1 - t0) / 1e6:.1f} ms; busy {busy:.1f} ms "
+            f"({100.0 * busy / max((t1 - t0) / 1e6, 1e-9):.1f} % of the span)",
+            f"launch duration ms: p50 {pct(dur, 0.5):.3f}, p99 {pct(dur, 0.99):.3f}, max {dur[-1]:.3f}",
+            f"gap between launches us: p50 {pct(gaps, 0.5):.1f}, max {gaps[-1]:.1f}",
+            "other kernels inside the span (ms): " +
+            (", ".join(f"{kk} {v:.2f}" for kk, v in sorted(others.items(), key=lambda kv: -kv[1])) or "none"),
+        ]
+    return "\n".join(lines) + "\n"
+
+
+def store_ceilings(n_envs: int = 262144, K: int = 1024, blocks: int = 2048, reps: int = 5) -> str:
+    """Write bandwidths this GPU reaches with no environment work: torch's
+    fill_ (write only) and copy_ (read + write) of large buffers, and the
+    fused rollout's record store pattern (gx_probe_record_stores) with and
+    without non-temporal stores, each timed with HIP events (median of
+    `reps` runs after one warm run)."""
+    import ctypes
+    import statistics
+    import torch
+    from . import gridenv
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        out = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            out.append(a.elapsed_time(b))
+        return statistics.median(out)
+
+    lines = ["# HBM store ceilings on this GPU (HIP events, median of %d runs)" % reps, ""]
+    buf = torch.empty(4 << 30, dtype=torch.uint8, device="cuda")
+    ms = timed(lambda: buf.fill_(7))
+    lines.append(f"torch fill_ of {buf.numel()} bytes: {ms:.3f} ms, {buf.numel() / ms / 1e6:.1f} GB/s (written)")
+    half = buf.numel() // 2
+    src, dst = buf[:half], buf[half:]
+    ms = timed(lambda: dst.copy_(src))
+    lines.append(f"torch copy_ of {half} bytes: {ms:.3f} ms, {2 * half / ms / 1e6:.1f} GB/s (read + written)")
+    del buf, src, dst
+    torch.cuda.empty_cache()
+
+    L = gridenv.load()
+    fn = L.gx_probe_record_stores
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    fn.argtypes = [P, P, P, P, I64, I32, I32, I32, I32, P]
+    fn.restype = ctypes.c_int
+    obs = torch.empty(K * n_envs * 147, dtype=torch.uint8, device="cuda")
+    rew = torch.empty(K * n_envs, dtype=torch.float32, device="cuda")
+    flg = torch.empty(K * n_envs, dtype=torch.uint8, device="cuda")
+    act = torch.empty(K * n_envs, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    algo = K * n_envs * (147 + 4 + 1 + 1)
+    for nt in (1, 0):
+        def run(nt=nt):
+            rc = fn(obs.data_ptr(), rew.data_ptr(), flg.data_ptr(), act.data_ptr(), n_envs, K, K, blocks, nt,
+                    stream)
+            if rc != 0:
+                raise RuntimeError(f"gx_probe_record_stores failed: {rc}")
+        ms = timed(run)
+        lines.append(f"record store pattern of k_fused ({n_envs} envs, {K} steps, {blocks} workgroups, "
+                     f"{'non-temporal' if nt else 'ordinary'} stores): {ms:.3f} ms for {algo} bytes, "
+                     f"{algo / ms / 1e6:.1f} GB/s")
     return "\n".join(lines) + "\n"
 
 
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--ceilings", action="store_true",
+                    help="measure the HBM store ceilings on the current GPU (no profiler needed)")
     ap.add_argument("--serving-trace", help="kernel trace directory of a serving run")
     ap.add_argument("--render-trace", help="kernel trace directory of an rgb_first_person run")
     ap.add_argument("--trace")
@@ -288,10 +368,14 @@ def main():
     ap.add_argument("--envs", type=int)
     ap.add_argument("--kernel", default=FUSED, choices=(FUSED, PLAIN), help="kernel to summarise")
     ap.add_argument("--workload", default="mixed", help="workload name for the title")
-    ap.add_argument("--command", required=True)
+    ap.add_argument("--command", default="")
     ap.add_argument("-o", "--out", required=True)
     a = ap.parse_args()
-    if a.serving_trace:
+    if a.ceilings:
+        text = (store_ceilings() + "\ncommand: python3 -m paper_2407_19396_amd.profiling --ceilings -o <file>\n")
+    elif not a.command:
+        ap.error("--command is needed")
+    elif a.serving_trace:
         text = serving_summary(a.serving_trace, a.command)
     elif a.render_trace:
         if not (a.fetch and a.write and a.copy_bytes and a.K and a.envs):

@@ -103,3 +103,19 @@ def test_null_arguments_are_rejected():
     assert lib.env_rollout(None, ctypes.byref(st), 1, None, ctypes.byref(tr), 0, None) == ge.GX_EINVAL
     assert lib.env_set_launch(None, 4, 0) == ge.GX_EINVAL
     assert lib.env_destroy(None) == ge.GX_EINVAL
+
+
+def test_store_probe_is_exported_and_validates_before_any_launch():
+    """The measurement tool of include/gridenv_probe.h: exported, and bad
+    arguments are refused before anything is launched."""
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "gridenv_probe.h")).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(gx_[a-z_]+)\s*\(", text)))
+    assert names == ["gx_probe_record_stores"]
+    lib = ctypes.CDLL(ge.LIB_PATH)
+    fn = lib.gx_probe_record_stores
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    fn.argtypes = [P, P, P, P, I64, I32, I32, I32, I32, P]
+    fn.restype = ctypes.c_int
+    assert fn(16, 16, 16, 16, 100, 1, 1, 1, 1, None) == -1      # n_envs not a multiple of 64
+    assert fn(None, 16, 16, 16, 64, 1, 1, 1, 1, None) == -1     # missing buffer
+    assert fn(16, 16, 16, 16, 64, 0, 1, 1, 1, None) == -1       # no rows
