@@ -300,7 +300,8 @@ def graph_leg(ge, wl, table, n_steps: int, warmup: int) -> dict:
     env.close()
     del graph
     return {"value": table.n * n_steps / (ms / 1e3), "unit": "env-steps/s", "steps": n_steps, "K": K,
-            "blocks": info["blocks"], "autotuned": True, "cached_tuning": bool(tuned.get("cached")),
+            "blocks": info["blocks"], "tile_envs": info["tile_envs"], "autotuned": True,
+            "cached_tuning": bool(tuned.get("cached")),
             "hip_graph": True, "replay_ms": ms, "replay_ms_range": [min(reps), max(reps)],
             "chunk_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)}, "roofline": roof}
 

@@ -100,3 +100,53 @@ def test_render_summary_leaves_out_the_reset_launch(tmp_path):
     assert f"achieved: {algo / 2_000_000:.1f} GB/s" in text
     # fetch is scaled x2 by the copy probe (512 KiB for 1 MiB), write x1
     assert f"fetch {2 * 100.0 * 1024 / 1e6:.1f} MB" in text
+
+
+def test_traffic_lookup_is_per_kernel(tmp_path):
+    p = tmp_path / "k.txt"
+    h = profiling.kernel_source_hash()
+    p.write_text(f"machine: name=k_plain traffic_bytes_per_launch=77 K=1 envs=64 kernel={h} avg_ns=1 median_ns=1\n")
+    assert profiling.traffic_bytes(str(p), 1, 64, "k_plain") == 77.0
+    assert profiling.traffic_bytes(str(p), 1, 64, "k_fused") is None
+
+
+def _bench():
+    import importlib.util
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_bench_launch_accounting():
+    b = _bench()
+    assert b.chunks(20, 1024) == [20]
+    assert b.chunks(4096, 1024) == [1024] * 4
+    assert b.chunks(2500, 1024) == [1024, 1024, 452]
+    # a 20-step launch counts 20 steps of records and the state once
+    n, g = 262144, 116_778_432
+    per = b.fused_bytes(n, g, 20)
+    assert per == n * 20 * 153 + 2 * (g + b.STATE_BYTES_PER_ENV * n)
+    r = b.roofline_entry(per, 0.25)
+    assert 0 < r["frac"] <= 1 and abs(r["achieved"] - per / 0.25e-3 / 1e9) < 1e-6
+    with pytest.raises(SystemExit):
+        b.roofline_entry(b.fused_bytes(n, g, 1024), 0.25)     # 1024 steps of bytes in a 20-step time
+
+
+def test_serving_summary_splits_runs(tmp_path):
+    rows = ["Kernel_Name,Start_Timestamp,End_Timestamp"]
+    name = "void gx::k_fused<false, true, 0>(gx::FusedArgs)"
+    t = 0
+    for run in range(2):
+        for k in range(5):
+            rows.append(f'"{name}",{t},{t + 1_000_000}')
+            t += 1_010_000                       # 1 ms launches, 10 us apart
+        t += 500_000_000                         # half a second idle between runs
+    d = tmp_path / "trace"
+    d.mkdir()
+    (d / "run_kernel_trace.csv").write_text("\n".join(rows) + "\n")
+    text = profiling.serving_summary(str(d), "cmd")
+    assert text.count("## run") == 2
+    assert "serving launches: 5" in text and "(99.2 % of the span)" in text
