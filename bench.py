@@ -603,7 +603,8 @@ def main():
                    "hip_graph": graph is not None, "observation": args.obs},
         "fused_launch_ms": {"K": K, "p50": pct(lat, 50), "p99": pct(lat, 99)} if len(lat) else None,
         "repeats": None if not reps else {"n": len(reps), "median": float(np.median(reps)),
-                                          "min": float(np.min(reps)), "max": float(np.max(reps))},
+                                          "min": float(np.min(reps)), "max": float(np.max(reps)),
+                                          "values": [float(r) for r in reps]},
         "plain": plain,
         "roofline": roof,
         "configs": configs,

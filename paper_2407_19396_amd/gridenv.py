@@ -307,9 +307,14 @@ class GridEnv:
         self.done_prev = torch.zeros(n, dtype=torch.uint8, device=dev)
         self.calls = torch.zeros(n, dtype=torch.int32, device=dev)        # uint32 bits
         self.obst = torch.full((n * 16,), 0xFF, dtype=torch.uint8, device=dev)
+        self._cstate = None
 
     def state(self) -> GxState:
-        return GxState(*[getattr(self, f).data_ptr() for f in self.FIELDS])
+        """The C view of the state tensors (built once: the tensors are
+        allocated here and only ever written in place)."""
+        if self._cstate is None:
+            self._cstate = GxState(*[getattr(self, f).data_ptr() for f in self.FIELDS])
+        return self._cstate
 
     def traj(self, rows: int, with_obs: bool = True) -> Traj:
         """Output rows shaped for this context's observation mode."""
