@@ -24,8 +24,9 @@
  *   - the first-person symbolic observation (Table "observations",
  *     symbolic_first_person, R = 7) with MiniGrid's occlusion rule, since
  *     Sec. 3.2.1 states the environments match MiniGrid exactly, and the
- *     other observation functions of that table except the RGB ones:
- *     categorical_first_person, symbolic and categorical;
+ *     other observation functions of that table: categorical_first_person,
+ *     symbolic and categorical, and the images rgb_first_person and rgb,
+ *     drawn from a sprite atlas the caller passes in;
  *   - the Empty, DoorKey (two rooms) and FourRooms families (Table "envs"),
  *     and the lava families LavaGap, Crossings and DistShift with the
  *     goal-or-lava reward R2 of Table "envs" (lava: -1 and termination,

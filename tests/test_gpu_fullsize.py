@@ -58,24 +58,30 @@ def test_empty8_plain_whole():
     P.assert_state_equal(env, s)
 
 
-def sampled_run(table, n_steps, K, sample, blocks=0):
-    """Fused rollout of the whole table in chunks of K steps (the bench's
-    launch shape); returns sampled records and the final state."""
+def sampled_run(table, n_steps, K, sample, blocks=0, tile_envs=0, calls=None):
+    """Fused rollout of the whole table in calls of at most K steps (the
+    bench's launch shape), or in calls of the given step counts; returns
+    sampled records and the final state."""
     import torch
     ge = _ge()
     env = ge.GridEnv(table)
+    if tile_envs:
+        env.set_tiling(tile_envs)
     if blocks:
         env.set_launch(K, blocks)
     env.reset()
     traj = ge.Traj.alloc(K, table.n)
     idx = torch.from_numpy(sample).cuda()
     obs, rew, flg, act = [], [], [], []
-    for c in range(n_steps // K):
-        env.rollout(K, traj, K=K)
-        obs.append(traj.obs[:, idx].cpu())
-        rew.append(traj.reward[:, idx].cpu())
-        flg.append(traj.flags[:, idx].cpu())
-        act.append(traj.action[:, idx].cpu())
+    if calls is None:
+        calls = [min(K, n_steps - c) for c in range(0, n_steps, K)]
+    assert sum(calls) == n_steps and max(calls) <= K
+    for k in calls:
+        env.rollout(k, traj, K=K)
+        obs.append(traj.obs[:k, idx].cpu())
+        rew.append(traj.reward[:k, idx].cpu())
+        flg.append(traj.flags[:k, idx].cpu())
+        act.append(traj.action[:k, idx].cpu())
     torch.cuda.synchronize()
     cat = lambda xs: torch.cat(xs).numpy()  # noqa: E731
     st = env.state_numpy()
@@ -83,9 +89,9 @@ def sampled_run(table, n_steps, K, sample, blocks=0):
     return cat(obs), cat(rew), cat(flg), cat(act), st
 
 
-def check_sample(table, n_steps, K, stride, blocks=0):
+def check_sample(table, n_steps, K, stride, blocks=0, tile_envs=0, calls=None):
     sample = np.arange(0, table.n, stride)
-    obs, rew, flg, act, st = sampled_run(table, n_steps, K, sample, blocks)
+    obs, rew, flg, act, st = sampled_run(table, n_steps, K, sample, blocks, tile_envs, calls)
     sub = table.subset(sample)
     b, s, _ = P.oracle_reset(sub)
     ref = ox.rollout(b, s, n_steps, None, nthreads=16)
@@ -122,3 +128,17 @@ def test_mixed_fused_sampled(K, blocks):
     benchmark's shape (K = 1024, 2048 workgroups: two tiles each) and in
     short launches."""
     check_sample(wl.workload_mixed(0), 4096, K, stride=683, blocks=blocks)
+
+
+def test_mixed_driver_shape_sampled():
+    """The driver's run: 5 warm-up steps, then 20 steps, each one fused
+    launch of the 262144-env mix in the tuner's shape (K = 1024, 2048
+    workgroups), split as the benchmark splits them."""
+    check_sample(wl.workload_mixed(0), 25, 1024, stride=683, blocks=2048, calls=[5, 20])
+
+
+@pytest.mark.parametrize("family,side", [(wl.FAMILY_EMPTY, 32), (wl.FAMILY_TWOROOM, 32), (wl.FAMILY_EMPTY, 24)])
+def test_large_grids_in_tiles_of_32(family, side):
+    """65536 envs of side 24 or 32 in the tiling the tuner picks for them
+    (32 envs per tile, four workgroups per compute unit), 1024 steps."""
+    check_sample(wl.uniform_table(65536, family, side, seed=3), 1024, 1024, stride=257, blocks=1024, tile_envs=32)
