@@ -89,7 +89,7 @@ def sampled_run(table, n_steps, K, sample, blocks=0, tile_envs=0, calls=None):
     return cat(obs), cat(rew), cat(flg), cat(act), st
 
 
-def check_sample(table, n_steps, K, stride, blocks=0, tile_envs=0, calls=None):
+def check_sample(table, n_steps, K, stride, blocks=0, tile_envs=0, calls=None, expect_resets=True):
     sample = np.arange(0, table.n, stride)
     obs, rew, flg, act, st = sampled_run(table, n_steps, K, sample, blocks, tile_envs, calls)
     sub = table.subset(sample)
@@ -111,7 +111,8 @@ def check_sample(table, n_steps, K, stride, blocks=0, tile_envs=0, calls=None):
     assert ((st["t"] >= 0) & (st["t"] <= table.max_steps)).all()
     assert ((st["x"] >= 1) & (st["x"] <= table.side.astype(np.int32) - 2)).all()
     assert ((st["y"] >= 1) & (st["y"] <= table.side.astype(np.int32) - 2)).all()
-    assert (st["episode"] > 0).any()
+    if expect_resets:
+        assert (st["episode"] > 0).any()
 
 
 @pytest.mark.parametrize("K,blocks", [(1024, 1024), (64, 0)])
@@ -140,5 +141,8 @@ def test_mixed_driver_shape_sampled():
 @pytest.mark.parametrize("family,side", [(wl.FAMILY_EMPTY, 32), (wl.FAMILY_TWOROOM, 32), (wl.FAMILY_EMPTY, 24)])
 def test_large_grids_in_tiles_of_32(family, side):
     """65536 envs of side 24 or 32 in the tiling the tuner picks for them
-    (32 envs per tile, four workgroups per compute unit), 1024 steps."""
-    check_sample(wl.uniform_table(65536, family, side, seed=3), 1024, 1024, stride=257, blocks=1024, tile_envs=32)
+    (32 envs per tile, four workgroups per compute unit), 1024 steps (far
+    fewer than T = 4S^2 or 10S^2, so episodes end only at a goal, which the
+    random policy may never reach)."""
+    check_sample(wl.uniform_table(65536, family, side, seed=3), 1024, 1024, stride=257, blocks=1024, tile_envs=32,
+                 expect_resets=False)
