@@ -422,7 +422,7 @@ def test_gotodoor_done_and_out_of_range_actions(ge, kernel):
 
 
 @pytest.mark.parametrize("tile_envs", [1, 13, 16, 32, 48])
-@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
 def test_tiling_parity(ge, tile_envs, mode):
     """Tiles of fewer envs than a wave's lanes (env_set_tiling) change only
     how envs map onto waves: every output and the state still equal the

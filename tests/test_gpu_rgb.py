@@ -179,3 +179,25 @@ def test_rgb_whole_grid_full_size_sample(ge):
         S = int(table.side[e])
         want = ref.obs[:, 1024 * int(sub_off[k]):1024 * int(sub_off[k]) + 3072 * S * S]
         assert np.array_equal(got[k], want), f"env {e} (side {S})"
+
+
+@pytest.mark.parametrize("mode", [4, 5])
+def test_rgb_with_tiles_of_32(ge, mode):
+    """The rgb path with 32 envs per tile (the tiling the tuner picks for
+    large grids): the step kernels' staged records and the images drawn
+    from them still equal the oracle's."""
+    import torch
+    table = wl.families_table(100, seed=17, mix_seed=18)
+    sprites = atlas(10 + mode)
+    env = ge.GridEnv(table, obs_mode=mode, sprites=sprites)
+    env.set_tiling(32)
+    env.reset()
+    b, s, _ = oracle_reset(table, mode, sprites)
+    steps = 12
+    ref = ox.rollout(b, s, steps, None, nthreads=8)
+    traj = env.traj(steps)
+    env.rollout(steps, traj, K=5)
+    torch.cuda.synchronize()
+    P.assert_rows_equal(traj, ref, what=f"rgb mode {mode}, tiles of 32")
+    P.assert_state_equal(env, s, f"rgb mode {mode}, tiles of 32")
+    env.close()
