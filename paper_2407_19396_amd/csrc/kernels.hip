@@ -34,6 +34,9 @@ constexpr int kView = 7;
 constexpr int kObsBytes = kView * kView * 3;        // 147
 constexpr int kStageBytes = kWave * kObsBytes;      // 9408, a multiple of 16
 constexpr int kHalfStageBytes = kStageBytes / 2;    // 4704, a multiple of 16
+// the fused kernel's record stage: 32 records behind up to 48 bytes carried
+// over from the previous piece (see k_fused)
+constexpr int kRecStageBytes = kHalfStageBytes + 48;
 constexpr int kObsWords = 37;                       // ceil(147 / 4)
 constexpr int kCatBytes = kView * kView;            // categorical record: 49
 constexpr int kCatWords = 13;                       // ceil(49 / 4)
@@ -888,14 +891,13 @@ __device__ __forceinline__ void wave_sync() {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-// Copies n_envs staged records of kBytes bytes (1 <= n_envs <= kMaxEnvs) to
-// dst.  The aligned path issues all of a lane's 16-byte LDS reads before
-// its stores, so the reads are in flight together.
-template <int kMaxEnvs, int kBytes>
-__device__ __forceinline__ void copy_out(const uint8_t* stage, uint8_t* dst, int n_envs, int lane) {
-  constexpr int kMaxChunks = (kMaxEnvs * kBytes + 15) / 16;
+// Copies the first `bytes` (1 <= bytes <= kMaxBytes) staged bytes to dst.
+// The aligned path issues all of a lane's 16-byte LDS reads before its
+// stores, so the reads are in flight together.
+template <int kMaxBytes>
+__device__ __forceinline__ void copy_piece(const uint8_t* stage, uint8_t* dst, int bytes, int lane) {
+  constexpr int kMaxChunks = (kMaxBytes + 15) / 16;
   constexpr int kPerLane = (kMaxChunks + kWave - 1) / kWave;
-  const int bytes = n_envs * kBytes;
   if (((reinterpret_cast<uintptr_t>(dst) & 15) == 0) && (bytes & 15) == 0) {
     const u32x4* src = reinterpret_cast<const u32x4*>(stage);
     u32x4* out = reinterpret_cast<u32x4*>(dst);
@@ -912,6 +914,12 @@ __device__ __forceinline__ void copy_out(const uint8_t* stage, uint8_t* dst, int
   } else {
     for (int b = lane; b < bytes; b += kWave) dst[b] = stage[b];
   }
+}
+
+// Copies n_envs staged records of kBytes bytes (1 <= n_envs <= kMaxEnvs) to dst.
+template <int kMaxEnvs, int kBytes>
+__device__ __forceinline__ void copy_out(const uint8_t* stage, uint8_t* dst, int n_envs, int lane) {
+  copy_piece<kMaxEnvs * kBytes>(stage, dst, n_envs * kBytes, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -1074,6 +1082,121 @@ struct HbmWindow {
   }
 };
 
+// The plain kernel's view, read before the action is applied.  The step can
+// only end in one of two 7x7 squares: a turn ends in the new heading's
+// square; forward ends in the current square or in the one a cell ahead;
+// every other action (and a reset) keeps the current square.  Their union is
+// the final heading's square extended by one cell along that heading, at
+// most 8 grid rows of 8 cells, and it holds the cell ahead as well.  Reading
+// it as soon as the action is known puts the cell ahead and the view in one
+// round trip to HBM instead of two dependent ones.
+//
+// Region cell (k, r) is world cell (X0 + k, Y0 + r).  Heading east the region
+// starts at the agent's column, west 7 cells behind it; south at the agent's
+// row, north 7 rows above it; across the heading it spans the square's 7
+// cells.  The final square starts at offset m along the heading: east and
+// south m = 1 when the agent moved, west and north m = 0 when it moved.
+struct HbmSpan {
+  uint32_t w[8][7];   // row r: the 28 bytes from the dword-aligned start of cell (X0, Y0 + r)
+  uintptr_t gb;
+  int S, X0, Y0, dir;
+
+  // dir: the heading the step ends with; rows outside the grid and the
+  // eighth row of a horizontal heading are not read
+  __device__ __forceinline__ void load(const uint8_t* g, int S_, int ax, int ay, int dir_) {
+    gb = reinterpret_cast<uintptr_t>(g);
+    S = S_;
+    dir = dir_;
+    X0 = dir == 0 ? ax : (dir == 2 ? ax - 7 : ax - 3);
+    Y0 = dir == 1 ? ay : (dir == 3 ? ay - 7 : ay - 3);
+    const bool vert = (dir & 1) != 0;
+    const uintptr_t lo = gb & ~(uintptr_t)3, hi = (gb + 3 * (uintptr_t)(S * S) + 3) & ~(uintptr_t)3;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int yy = Y0 + r;
+#pragma unroll
+      for (int d = 0; d < 7; ++d) w[r][d] = 0u;
+      if ((unsigned)yy < (unsigned)S && (r < 7 || vert)) {
+        const uintptr_t a = (uintptr_t)((intptr_t)gb + 3 * (intptr_t)(yy * S + X0)) & ~(uintptr_t)3;
+        if (a >= lo && a + 28 <= hi) {
+          const u32x4 v4 = *reinterpret_cast<const u32x4*>(a);
+          const uint32_t* q = reinterpret_cast<const uint32_t*>(a + 16);
+          w[r][0] = v4.x; w[r][1] = v4.y; w[r][2] = v4.z; w[r][3] = v4.w;
+          w[r][4] = q[0]; w[r][5] = q[1]; w[r][6] = q[2];
+        } else {
+#pragma unroll
+          for (int d = 0; d < 7; ++d)
+            if (a + 4 * d >= lo && a + 4 * d < hi) w[r][d] = reinterpret_cast<const uint32_t*>(a)[d];
+        }
+      }
+    }
+  }
+
+  // region cell (k, r), its see-through flag at bit 31; outside the grid a wall
+  __device__ __forceinline__ uint32_t cell(int k, int r) const {
+    const int yy = Y0 + r, xx = X0 + k;
+    const uint32_t rb = (uint32_t)((uintptr_t)((intptr_t)gb + 3 * (intptr_t)(yy * S + X0)) & 3);
+    const int o = 3 * k, d = o >> 2, off = o & 3;
+    const uint32_t b0 = __builtin_amdgcn_alignbyte(w[r][d + 1], w[r][d], rb);
+    const uint32_t b1 = d + 2 < 7 ? __builtin_amdgcn_alignbyte(w[r][d + 2], w[r][d + 1], rb) : w[r][d + 1] >> (8 * rb);
+    const uint32_t tri = __builtin_amdgcn_alignbyte(b1, b0, (uint32_t)off) & 0xFFFFFFu;
+    const bool in = (unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S;
+    return in ? tri | see_through(tri) : kCellWall;
+  }
+
+  // the cell ahead of the agent before it moves (heading dir, no turn)
+  __device__ __forceinline__ uint32_t front() const {
+    return dir == 0 ? cell(1, 3) : (dir == 1 ? cell(3, 1) : (dir == 2 ? cell(6, 3) : cell(3, 6)));
+  }
+
+  // c[j][i] as for observe_words, for the square at offset m along the
+  // heading; `patch` replaces the cell ahead of the unmoved agent (a
+  // pickup, drop or toggle, which neither move nor turn it)
+  __device__ __forceinline__ void view(bool moved, bool patch, uint32_t new_front,
+                                       uint32_t (&c)[kView][kView]) const {
+    const bool vert = (dir & 1) != 0;
+    const bool m = moved != (dir >= 2);
+    const uint32_t nf = new_front | see_through(new_front);
+    uint32_t R[8][8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) R[r][k] = (r == 7 && k == 7) ? 0u : cell(k, r);
+    R[3][1] = patch && dir == 0 ? nf : R[3][1];
+    R[1][3] = patch && dir == 1 ? nf : R[1][3];
+    R[3][6] = patch && dir == 2 ? nf : R[3][6];
+    R[6][3] = patch && dir == 3 ? nf : R[6][3];
+    // world cell (X0 + k, Y0 + r) of the final square, offset applied
+    uint32_t W[kView][kView];
+#pragma unroll
+    for (int r = 0; r < kView; ++r)
+#pragma unroll
+      for (int k = 0; k < kView; ++k) W[r][k] = m ? (vert ? R[r + 1][k] : R[r][k + 1]) : R[r][k];
+    // view cell (i, j) = world a + (i - 3) right + (6 - j) ahead
+#pragma unroll
+    for (int j = 0; j < kView; ++j)
+#pragma unroll
+      for (int i = 0; i < kView; ++i) {
+        uint32_t v = W[j][i];                              // north
+        v = dir == 0 ? W[i][6 - j] : v;                    // east
+        v = dir == 1 ? W[6 - j][6 - i] : v;                // south
+        v = dir == 2 ? W[6 - i][j] : v;                    // west
+        c[j][i] = (v & ~kSeeBit) | ((v & kSeeBit) >> i);
+      }
+  }
+};
+
+// A view computed beforehand, handed to observe_words.
+struct ViewCells {
+  const uint32_t (&c)[kView][kView];
+  __device__ __forceinline__ void load_all(uint32_t (&o)[kView][kView]) const {
+#pragma unroll
+    for (int j = 0; j < kView; ++j)
+#pragma unroll
+      for (int i = 0; i < kView; ++i) o[j][i] = c[j][i];
+  }
+};
+
 // View rows straight from the HBM grid, cells outside it read as walls.
 struct HbmRows {
   HbmCells cells;
@@ -1192,18 +1315,37 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
   __threadfence_block();
   __syncthreads();
 
-  float reward = 0.0f;
-  uint32_t flags = 0, act_rec = kActionNone;
+  uint32_t act = 0;
   if (active && !do_reset) {
-    uint32_t act;
     if (a.actions) {
       act = a.actions[e];
     } else {
       act = bounded(pick4(policy_block(seed, rid, calls), calls & 3u), 7u);
     }
+  }
+  // The first-person modes read the view as soon as the action is known
+  // (HbmSpan), the cell ahead included.  Dynamic-Obstacles envs, whose
+  // balls move before the action applies, read the cell ahead and the view
+  // from HBM afterwards instead, and so does every env when the records are
+  // whole grids (copied from the grids) or not written at all.
+  const bool span_view = a.out.obs != nullptr && a.env.obs_mode < 2;
+  HbmSpan span;
+  if (span_view) {
+    const int dir_f = do_reset ? dir : (dir + (act == kLeft ? 3 : (act == kRight ? 1 : 0))) & 3;
+    span.load(g, active && fam != kFamDynObs ? S : 0, x, y, dir_f);
+  }
+
+  float reward = 0.0f;
+  uint32_t flags = 0, act_rec = kActionNone;
+  bool moved = false, patch = false;
+  uint32_t new_front = 0;
+  if (active && !do_reset) {
     const int fx = x + dir_dx(dir), fy = y + dir_dy(dir);
     const HbmCells cells{g, S};
-    uint32_t front = cells(fx, fy, 0);
+    const bool ahead_in_span = span_view && fam != kFamDynObs;
+    uint32_t front;
+    if (ahead_in_span) front = span.front();
+    else front = cells(fx, fy, 0);
     bool blocked = false;
     if (fam == kFamDynObs) {
       // three actions; the cell ahead is judged before the balls move
@@ -1212,11 +1354,15 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
       move_obstacles(HbmGrid{g, S}, (int)((meta >> 16) & 0xFF), x, y, ob, seed, rid, calls);
       front = cells(fx, fy, 0);
     }
+    const int x_was = x, y_was = y;
     ActResult r = intervene(act, x, y, dir, carry, front, fx, fy);
+    moved = x != x_was || y != y_was;
     r.penalty = r.penalty || (blocked && act == kForward);
     r.terminated = r.terminated || r.penalty;
     if (fam == kFamGoToDoor) gotodoor_rules(r, act, front, ob[0] & 0xFFu);
     if (r.front_changed) store_triple(g + 3 * (fy * S + fx), r.new_front);
+    patch = r.front_changed;
+    new_front = r.new_front;
     t += 1;
     const bool trunc = t >= T;
     reward = step_reward(r, t, T, a.env.reward_mode);
@@ -1247,9 +1393,12 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
       emit_grids<kStageBytes>(dst + G0, n, stage, lane, active, 3 * cell, kAgent | ((uint32_t)dir << 16), 3,
                               FillHbmSymbolic{src, n});
   } else if (a.out.obs) {
-    // inactive lanes get an empty grid: every read is out of bounds (a wall)
+    // inactive lanes read no cell (S = 0 above): every cell is a wall
     uint32_t u[kObsWords + 1];
-    const HbmWindow rows{g, active ? S : 0, x, y, dir};
+    uint32_t view[kView][kView];
+    span.view(moved, patch, new_front, view);
+    if (active && fam == kFamDynObs) HbmWindow{g, S, x, y, dir}.load_all(view);
+    const ViewCells rows{view};
     if (a.env.obs_mode == 1) {
       observe_words<true>(rows, carry, active, lane, u);
       store_words<true>(stage, lane, u);
@@ -1647,7 +1796,7 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
   // static LDS (table and record stage) sits at fixed addresses, so table
   // reads take their base as an immediate; the tile grids are dynamic
   __shared__ __align__(16) uint32_t table[kKinds * kView];
-  __shared__ __align__(16) uint8_t stage[kHalfStageBytes];
+  __shared__ __align__(16) uint8_t stage[kRecStageBytes];
   extern __shared__ __align__(16) uint8_t grids[];
   uint8_t* codes = grids + kMargin;
   const int lane = threadIdx.x;
@@ -1878,17 +2027,33 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
         if (__ballot(edge_view))
           observe_words<false>(LdsCheckedRows{table, my_codes, S, x, y, dir}, carry, active, lane & 31, u);
         // the stage holds 32 records: lanes 0-31, then lanes 32-63 (each half
-        // starts and ends on a word boundary, so the halves are independent)
+        // starts and ends on a word boundary, so the halves are independent).
+        // HBM writes whole 64-byte units: a store that covers only part of
+        // one costs a read-modify-write, and so does a unit that two pieces
+        // of the block share, since they leave at different times.  So the
+        // first piece ends on a 64-byte boundary of the output and its last
+        // `keep` bytes (< 64) are moved to the front of the stage, with the
+        // second half staged right behind them.
         uint8_t* dst = o_obs + rec * kObsBytes;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int n_half = min(32, n_here - 32 * h);
-          if (n_half <= 0) break;
-          if ((lane >> 5) == h) store_words<false>(stage, lane & 31, u);
+        const int n_first = min(32, n_here);
+        const int bytes0 = n_first * kObsBytes;
+        const uintptr_t d = reinterpret_cast<uintptr_t>(dst);
+        const int keep = (n_here > 32 && (d & 15) == 0) ? (int)((d + (uintptr_t)bytes0) & 63) : 0;
+        if (lane < 32) store_words<false>(stage, lane, u);
+        wave_sync();
+        copy_piece<kHalfStageBytes>(stage, dst, bytes0 - keep, lane);
+        if (n_here > 32) {
+          // source [bytes0 - keep, bytes0) and destination [0, keep) are disjoint
+          if (lane < (keep >> 4)) {
+            const u32x4 v = *reinterpret_cast<const u32x4*>(stage + bytes0 - keep + 16 * lane);
+            *reinterpret_cast<u32x4*>(stage + 16 * lane) = v;
+          }
           wave_sync();
-          copy_out<kWave / 2, kObsBytes>(stage, dst + h * kHalfStageBytes, n_half, lane);
+          if (lane >= 32) store_words<false>(stage + keep, lane & 31, u);
           wave_sync();
+          copy_piece<kRecStageBytes>(stage, dst + bytes0 - keep, keep + (n_here - 32) * kObsBytes, lane);
         }
+        wave_sync();
       }
       if (active) {
         o_reward[rec + lane] = reward;
@@ -1924,7 +2089,7 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
 size_t fused_dynamic_lds_bytes(int32_t max_tile_cells) { return tile_lds_bytes(max_tile_cells); }
 
 size_t fused_lds_bytes(int32_t max_tile_cells) {
-  return kKinds * kView * 4 + kHalfStageBytes + fused_dynamic_lds_bytes(max_tile_cells);
+  return kKinds * kView * 4 + kRecStageBytes + fused_dynamic_lds_bytes(max_tile_cells);
 }
 
 hipError_t launch_plain(const EnvTables& env, const StateBufs& st, const uint8_t* actions,
