@@ -295,8 +295,10 @@ def serving_summary(trace: str, command: str, split_ms: float = 20.0) -> str:
 def store_ceilings(n_envs: int = 262144, K: int = 1024, blocks: int = 2048, reps: int = 5) -> str:
     """Write bandwidths this GPU reaches with no environment work: torch's
     fill_ (write only) and copy_ (read + write) of large buffers, and the
-    fused rollout's record store pattern (gx_probe_record_stores) with and
-    without non-temporal stores, each timed with HIP events (median of
+    fused rollout's record store pattern (gx_probe_record_stores): its
+    pieces as the fused kernel writes them (ending on 64-byte boundaries of
+    the output), with non-temporal and with ordinary stores, and as two
+    halves of each tile's block; each timed with HIP events (median of
     `reps` runs after one warm run)."""
     import ctypes
     import statistics
@@ -330,7 +332,7 @@ def store_ceilings(n_envs: int = 262144, K: int = 1024, blocks: int = 2048, reps
     L = gridenv.load()
     fn = L.gx_probe_record_stores
     P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
-    fn.argtypes = [P, P, P, P, I64, I32, I32, I32, I32, P]
+    fn.argtypes = [P, P, P, P, I64, I32, I32, I32, I32, I32, P]
     fn.restype = ctypes.c_int
     obs = torch.empty(K * n_envs * 147, dtype=torch.uint8, device="cuda")
     rew = torch.empty(K * n_envs, dtype=torch.float32, device="cuda")
@@ -338,14 +340,15 @@ def store_ceilings(n_envs: int = 262144, K: int = 1024, blocks: int = 2048, reps
     act = torch.empty(K * n_envs, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream().cuda_stream
     algo = K * n_envs * (147 + 4 + 1 + 1)
-    for nt in (1, 0):
-        def run(nt=nt):
+    for nt, aligned in ((1, 1), (0, 1), (1, 0)):
+        def run(nt=nt, aligned=aligned):
             rc = fn(obs.data_ptr(), rew.data_ptr(), flg.data_ptr(), act.data_ptr(), n_envs, K, K, blocks, nt,
-                    stream)
+                    aligned, stream)
             if rc != 0:
                 raise RuntimeError(f"gx_probe_record_stores failed: {rc}")
         ms = timed(run)
-        lines.append(f"record store pattern of k_fused ({n_envs} envs, {K} steps, {blocks} workgroups, "
+        pieces = "pieces ending on 64-byte boundaries" if aligned else "two 4704-byte halves per tile"
+        lines.append(f"record store pattern of k_fused ({n_envs} envs, {K} steps, {blocks} workgroups, {pieces}, "
                      f"{'non-temporal' if nt else 'ordinary'} stores): {ms:.3f} ms for {algo} bytes, "
                      f"{algo / ms / 1e6:.1f} GB/s")
     return "\n".join(lines) + "\n"

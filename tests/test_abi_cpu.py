@@ -114,8 +114,9 @@ def test_store_probe_is_exported_and_validates_before_any_launch():
     lib = ctypes.CDLL(ge.LIB_PATH)
     fn = lib.gx_probe_record_stores
     P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
-    fn.argtypes = [P, P, P, P, I64, I32, I32, I32, I32, P]
+    fn.argtypes = [P, P, P, P, I64, I32, I32, I32, I32, I32, P]
     fn.restype = ctypes.c_int
-    assert fn(16, 16, 16, 16, 100, 1, 1, 1, 1, None) == -1      # n_envs not a multiple of 64
-    assert fn(None, 16, 16, 16, 64, 1, 1, 1, 1, None) == -1     # missing buffer
-    assert fn(16, 16, 16, 16, 64, 0, 1, 1, 1, None) == -1       # no rows
+    assert fn(16, 16, 16, 16, 100, 1, 1, 1, 1, 1, None) == -1      # n_envs not a multiple of 64
+    assert fn(None, 16, 16, 16, 64, 1, 1, 1, 1, 1, None) == -1     # missing buffer
+    assert fn(16, 16, 16, 16, 64, 0, 1, 1, 1, 1, None) == -1       # no rows
+    assert fn(24, 16, 16, 16, 64, 1, 1, 1, 1, 1, None) == -1       # observations not 16-byte aligned
