@@ -1666,68 +1666,107 @@ __device__ __forceinline__ void emit_tile_grids(uint8_t* dst, int n_cells, const
   }
 }
 
+// Kind codes of triples by table: entry type << 5 | colour << 2 | state
+// (types 0-15, colours 0-7, states 0-3) holds code_of of that triple.  A
+// valid grid holds only types 0-9, colours 0-5 and states 0-2, so its every
+// cell gets code_of's code for five instructions and one LDS read instead
+// of code_of's fifteen; bits of a triple beyond those fields are ignored.
+// The table lives in the record stage while a tile is staged in.
+constexpr int kCodeLutBytes = 512;
+
+__device__ __forceinline__ void build_code_lut(uint8_t* lut, int lane) {
+#pragma unroll
+  for (int k = 0; k < kCodeLutBytes / kWave; ++k) {
+    const uint32_t i = (uint32_t)(lane + k * kWave);
+    lut[i] = (uint8_t)code_of((i >> 5) | (((i >> 2) & 7u) << 8) | ((i & 3u) << 16));
+  }
+}
+
+__device__ __forceinline__ uint32_t lut_code(const uint8_t* lut, uint32_t tri) {
+  const uint32_t i = ((tri & 15u) << 5) | (((tri >> 8) & 7u) << 2) | ((tri >> 16) & 3u);
+  return lut[i];
+}
+
 // Stages a tile's grids, the 3 * n_cells bytes at src (any alignment), into
 // LDS as codes.  Lane u converts cells [16u, 16u + 16), i.e. the 48 bytes
 // at src + 48u; 48 being a multiple of 16, every such run starts at the
 // same offset r = src mod 16 in its first aligned 16-byte chunk, so a run is
-// at most four aligned chunk loads and one wave-uniform realignment.  A
-// chunk is loaded only if it holds a byte of the block (so it lies in the
-// block's own memory pages); the codes of the at most 15 cells past n_cells
-// (decoded from bytes after the block, or zeros) land in the trailing LDS
-// margin, which needs nothing but valid codes.  Two runs per lane are in
-// flight together.
+// four aligned chunk loads and one realignment by the wave-uniform r (the
+// conversion is instantiated per r / 4, so the realignment needs no
+// selects).  A chunk past the block's last one is read as that last chunk
+// (so every load lies in the block's own memory pages); the codes of the at
+// most 15 cells past n_cells land in the trailing LDS margin, which needs
+// nothing but valid codes, and every table entry is one.  The lane's next
+// run is loaded before its current run is converted, so the wave's reads
+// stay in flight while it converts.
 struct GridRun {
   u32x4 q[4];
 };
 
-__device__ __forceinline__ GridRun load_run(uintptr_t a, uintptr_t end, uint32_t r) {
+__device__ __forceinline__ GridRun load_run(uintptr_t a, uintptr_t last) {
   GridRun g;
-  g.q[0] = *reinterpret_cast<const u32x4*>(a);
-  g.q[1] = g.q[2] = g.q[3] = u32x4{0u, 0u, 0u, 0u};
-  if (a + 16 < end) g.q[1] = *reinterpret_cast<const u32x4*>(a + 16);
-  if (a + 32 < end) g.q[2] = *reinterpret_cast<const u32x4*>(a + 32);
-  if (r != 0 && a + 48 < end) g.q[3] = *reinterpret_cast<const u32x4*>(a + 48);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uintptr_t c = a + 16 * (uintptr_t)k;
+    g.q[k] = *reinterpret_cast<const u32x4*>(c < last ? c : last);
+  }
   return g;
 }
 
-__device__ __forceinline__ void store_run_codes(const GridRun& g, uint32_t r, uint8_t* dst) {
+template <int kRW>
+__device__ __forceinline__ void convert_run(const GridRun& g, uint32_t rb, const uint8_t* lut, uint8_t* dst) {
   uint32_t w[16];
 #pragma unroll
   for (int k = 0; k < 4; ++k)
 #pragma unroll
     for (int c = 0; c < 4; ++c) w[4 * k + c] = g.q[k][c];
-  // bytes r .. r + 47 of the chunks as 12 words
-  const uint32_t rw = r >> 2, rb = r & 3u;
-  uint32_t v[13];
-#pragma unroll
-  for (int i = 0; i < 13; ++i) v[i] = rw == 0 ? w[i] : rw == 1 ? w[i + 1] : rw == 2 ? w[i + 2] : w[i + 3];
+  // bytes r .. r + 47 of the chunks as 12 words (r = 4 kRW + rb)
   uint32_t b[12];
 #pragma unroll
-  for (int i = 0; i < 12; ++i) b[i] = __builtin_amdgcn_alignbyte(v[i + 1], v[i], rb);
+  for (int i = 0; i < 12; ++i)
+    b[i] = i + kRW + 1 < 16 ? __builtin_amdgcn_alignbyte(w[i + kRW + 1], w[i + kRW], rb) : w[i + kRW] >> (8 * rb);
   uint32_t out[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     const int d = (3 * k) >> 2, off = (3 * k) & 3;
-    const uint32_t tri = (d + 1 < 12 ? __builtin_amdgcn_alignbyte(b[d + 1], b[d], (uint32_t)off)
-                                     : b[d] >> (8 * off)) & 0xFFFFFFu;
-    out[k >> 2] |= code_of(tri) << (8 * (k & 3));
+    const uint32_t tri = d + 1 < 12 ? __builtin_amdgcn_alignbyte(b[d + 1], b[d], (uint32_t)off)
+                                    : b[d] >> (8 * off);
+    out[k >> 2] |= lut_code(lut, tri) << (8 * (k & 3));
   }
   *reinterpret_cast<u32x4*>(dst) = u32x4{out[0], out[1], out[2], out[3]};
 }
 
-__device__ __forceinline__ void stage_in_codes(const uint8_t* src, int n_cells, uint8_t* codes, int lane) {
+template <int kRW>
+__device__ __forceinline__ void stage_in_runs(uintptr_t a0, uintptr_t last, uint32_t rb, int units,
+                                              const uint8_t* lut, uint8_t* codes, int lane) {
+  int u = lane;
+  if (u >= units) return;
+  GridRun cur = load_run(a0 + 48 * (uintptr_t)u, last);
+  while (true) {
+    const int nu = u + kWave;
+    const bool more = nu < units;
+    GridRun nxt;
+    if (more) nxt = load_run(a0 + 48 * (uintptr_t)nu, last);
+    convert_run<kRW>(cur, rb, lut, codes + 16 * u);
+    if (!more) break;
+    cur = nxt;
+    u = nu;
+  }
+}
+
+// lut: the code table (build_code_lut), visible to every lane
+__device__ __forceinline__ void stage_in_codes(const uint8_t* src, int n_cells, uint8_t* codes,
+                                               const uint8_t* lut, int lane) {
   const uintptr_t s0 = reinterpret_cast<uintptr_t>(src);
   const uint32_t r = (uint32_t)__builtin_amdgcn_readfirstlane((int)(s0 & 15u));
   const uintptr_t end = s0 + 3 * (uintptr_t)(uint32_t)n_cells;
-  const uintptr_t a0 = s0 - r;
+  const uintptr_t a0 = s0 - r, last = (end - 1) & ~(uintptr_t)15;
   const int units = (n_cells + 15) >> 4;
-  for (int u = lane; u < units; u += 2 * kWave) {
-    const bool two = u + kWave < units;
-    const GridRun g0 = load_run(a0 + 48 * (uintptr_t)u, end, r);
-    GridRun g1;
-    if (two) g1 = load_run(a0 + 48 * (uintptr_t)(u + kWave), end, r);
-    store_run_codes(g0, r, codes + 16 * u);
-    if (two) store_run_codes(g1, r, codes + 16 * (u + kWave));
+  switch (r >> 2) {
+    case 0: stage_in_runs<0>(a0, last, r & 3u, units, lut, codes, lane); break;
+    case 1: stage_in_runs<1>(a0, last, r & 3u, units, lut, codes, lane); break;
+    case 2: stage_in_runs<2>(a0, last, r & 3u, units, lut, codes, lane); break;
+    default: stage_in_runs<3>(a0, last, r & 3u, units, lut, codes, lane); break;
   }
 }
 
@@ -1921,7 +1960,10 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
     if (fresh) {
       fill_layouts(__ballot(active), L0, codes, my_off, lane);
     } else {
-      stage_in_codes(a.st.grid + g0, tile_cells, codes, lane);
+      // the record stage is idle until the first step: it holds the code table
+      build_code_lut(stage, lane);
+      wave_sync();
+      stage_in_codes(a.st.grid + g0, tile_cells, codes, stage, lane);
     }
     wave_sync();
 
