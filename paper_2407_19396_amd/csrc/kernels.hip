@@ -1132,16 +1132,16 @@ struct HbmSpan {
     }
   }
 
-  // region cell (k, r), its see-through flag at bit 31; outside the grid a wall
+  // the triple of region cell (k, r); a cell outside the grid reads as
+  // whatever the loaded bytes hold there (bytes of the grid's other rows, or
+  // zeros)
   __device__ __forceinline__ uint32_t cell(int k, int r) const {
-    const int yy = Y0 + r, xx = X0 + k;
+    const int yy = Y0 + r;
     const uint32_t rb = (uint32_t)((uintptr_t)((intptr_t)gb + 3 * (intptr_t)(yy * S + X0)) & 3);
     const int o = 3 * k, d = o >> 2, off = o & 3;
     const uint32_t b0 = __builtin_amdgcn_alignbyte(w[r][d + 1], w[r][d], rb);
     const uint32_t b1 = d + 2 < 7 ? __builtin_amdgcn_alignbyte(w[r][d + 2], w[r][d + 1], rb) : w[r][d + 1] >> (8 * rb);
-    const uint32_t tri = __builtin_amdgcn_alignbyte(b1, b0, (uint32_t)off) & 0xFFFFFFu;
-    const bool in = (unsigned)yy < (unsigned)S && (unsigned)xx < (unsigned)S;
-    return in ? tri | see_through(tri) : kCellWall;
+    return __builtin_amdgcn_alignbyte(b1, b0, (uint32_t)off) & 0xFFFFFFu;
   }
 
   // the cell ahead of the agent before it moves (heading dir, no turn)
@@ -1151,17 +1151,21 @@ struct HbmSpan {
 
   // c[j][i] as for observe_words, for the square at offset m along the
   // heading; `patch` replaces the cell ahead of the unmoved agent (a
-  // pickup, drop or toggle, which neither move nor turn it)
+  // pickup, drop or toggle, which neither move nor turn it).  Cells outside
+  // the grid are not masked: whenever the grid's outer ring is opaque (walls
+  // and closed or locked doors) sight never crosses it, so none of them is
+  // ever visible.  Only a door on the ring toggled open breaks that, and
+  // such a step reads its view bounds-checked instead.
   __device__ __forceinline__ void view(bool moved, bool patch, uint32_t new_front,
                                        uint32_t (&c)[kView][kView]) const {
     const bool vert = (dir & 1) != 0;
     const bool m = moved != (dir >= 2);
-    const uint32_t nf = new_front | see_through(new_front);
     uint32_t R[8][8];
 #pragma unroll
     for (int r = 0; r < 8; ++r)
 #pragma unroll
       for (int k = 0; k < 8; ++k) R[r][k] = (r == 7 && k == 7) ? 0u : cell(k, r);
+    const uint32_t nf = new_front;
     R[3][1] = patch && dir == 0 ? nf : R[3][1];
     R[1][3] = patch && dir == 1 ? nf : R[1][3];
     R[3][6] = patch && dir == 2 ? nf : R[3][6];
@@ -1181,7 +1185,7 @@ struct HbmSpan {
         v = dir == 0 ? W[i][6 - j] : v;                    // east
         v = dir == 1 ? W[6 - j][6 - i] : v;                // south
         v = dir == 2 ? W[6 - i][j] : v;                    // west
-        c[j][i] = (v & ~kSeeBit) | ((v & kSeeBit) >> i);
+        c[j][i] = v | (see_through(v) >> i);
       }
   }
 };
@@ -1337,7 +1341,7 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
 
   float reward = 0.0f;
   uint32_t flags = 0, act_rec = kActionNone;
-  bool moved = false, patch = false;
+  bool moved = false, patch = false, edge_view = false;
   uint32_t new_front = 0;
   if (active && !do_reset) {
     const int fx = x + dir_dx(dir), fy = y + dir_dy(dir);
@@ -1363,6 +1367,7 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
     if (r.front_changed) store_triple(g + 3 * (fy * S + fx), r.new_front);
     patch = r.front_changed;
     new_front = r.new_front;
+    edge_view = fam == kFamGoToDoor && r.front_changed;   // a door toggled, possibly on the outer ring
     t += 1;
     const bool trunc = t >= T;
     reward = step_reward(r, t, T, a.env.reward_mode);
@@ -1397,7 +1402,9 @@ __global__ __launch_bounds__(kWave) void k_plain(PlainArgs a) {
     uint32_t u[kObsWords + 1];
     uint32_t view[kView][kView];
     span.view(moved, patch, new_front, view);
-    if (active && fam == kFamDynObs) HbmWindow{g, S, x, y, dir}.load_all(view);
+    // balls that moved, or a door on the ring toggled open: read the view
+    // again, bounds-checked, from the grid as the step left it
+    if (fam == kFamDynObs || edge_view) HbmWindow{g, S, x, y, dir}.load_all(view);
     const ViewCells rows{view};
     if (a.env.obs_mode == 1) {
       observe_words<true>(rows, carry, active, lane, u);
