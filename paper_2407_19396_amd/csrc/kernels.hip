@@ -943,9 +943,12 @@ __device__ __forceinline__ void emit_grids(uint8_t* dst, int64_t n, uint8_t* sta
   static_assert(kWin % 16 == 0, "stage windows are whole 16-byte chunks");
   const uintptr_t d0 = reinterpret_cast<uintptr_t>(dst), d1 = d0 + (uintptr_t)n;
   uint32_t* words = reinterpret_cast<uint32_t*>(stage);
-  for (uintptr_t A = d0 & ~(uintptr_t)15; A < d1; A += kWin) {
+  // windows start on 64-byte boundaries of the output (kWin is a multiple
+  // of 64), so every store instruction covers whole 64-byte units of HBM
+  static_assert(kWin % 64 == 0, "windows keep the 64-byte alignment");
+  for (uintptr_t A = d0 & ~(uintptr_t)63; A < d1; A += kWin) {
     const int win = (int)min((uintptr_t)kWin, (d1 - A + 15) & ~(uintptr_t)15);
-    const int64_t rel = (int64_t)A - (int64_t)d0;   // output byte of stage byte 0, >= -15
+    const int64_t rel = (int64_t)A - (int64_t)d0;   // output byte of stage byte 0, >= -63
     for (int q = lane; q < (win >> 2); q += kWave) words[q] = fill(rel + 4 * q);
     wave_sync();
     if (has_agent) {
@@ -1610,10 +1613,13 @@ struct LdsGrid {
 // block [0, n) in aligned units held in registers and store each once.
 // Symbolic: 16-byte units, at most 6 cells each (18 triple bytes, taken
 // from offset r < 3); categorical: 4-byte units of 4 cells, so that
-// neighbouring lanes read neighbouring code words.  Units at the block's
-// two ends store only their bytes inside [0, n) (the rest belong to the
-// neighbouring tiles' records); their reads reach at most 15 cells before
-// or after the tile, inside the cleared margins.
+// neighbouring lanes read neighbouring code words.  The units start on the
+// 64-byte boundary at or below the block, so that every store instruction
+// covers whole 64-byte units of HBM (which writes a partial one as a
+// read-modify-write).  Units at the block's two ends store only their bytes
+// inside [0, n) (the rest belong to the neighbouring tiles' records); their
+// reads reach at most 21 cells before or 15 after the tile, inside the
+// cleared margins.
 // kNT: non-temporal stores (trajectory records); the state write-back uses
 // ordinary ones, since the next launch reads it again.
 template <bool kCat, bool kNT = true>
@@ -1622,8 +1628,8 @@ __device__ __forceinline__ void emit_tile_grids(uint8_t* dst, int n_cells, const
   constexpr int kUnit = kCat ? 4 : 16;
   const int64_t n = kCat ? n_cells : 3 * (int64_t)n_cells;
   const uintptr_t d0 = reinterpret_cast<uintptr_t>(dst), d1 = d0 + (uintptr_t)n;
-  const uintptr_t A = d0 & ~(uintptr_t)(kUnit - 1);
-  const int rel = (int)((int64_t)A - (int64_t)d0);   // in [1 - kUnit, 0]
+  const uintptr_t A = d0 & ~(uintptr_t)63;
+  const int rel = (int)((int64_t)A - (int64_t)d0);   // in [-63, 0]
   const int units = (int)((d1 - A + kUnit - 1) / kUnit);
   for (int q = lane; q < units; q += kWave) {
     const int o = rel + kUnit * q;   // output byte of the unit's first byte
@@ -1648,7 +1654,7 @@ __device__ __forceinline__ void emit_tile_grids(uint8_t* dst, int n_cells, const
           if (a + b >= d0 && a + b < d1) reinterpret_cast<uint8_t*>(a)[b] = (uint8_t)(w >> (8 * b));
       }
     } else {
-      const int c = (o + 48) / 3 - 16;   // floor(o / 3) for o >= -48
+      const int c = (o + 66) / 3 - 22;   // floor(o / 3) for o >= -66
       const uint32_t r = (uint32_t)(o - 3 * c);
       uint32_t t[6];
 #pragma unroll
