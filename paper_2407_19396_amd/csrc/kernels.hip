@@ -892,25 +892,30 @@ __device__ __forceinline__ void wave_sync() {
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // Copies the first `bytes` (1 <= bytes <= kMaxBytes) staged bytes to dst.
-// The aligned path issues all of a lane's 16-byte LDS reads before its
-// stores, so the reads are in flight together.
+// To a 16-byte aligned dst the whole 16-byte chunks go as vector stores
+// (all of a lane's LDS reads issued before its stores, so the reads are in
+// flight together) and the last bytes % 16 bytes one by one; otherwise
+// every byte goes alone.
 template <int kMaxBytes>
 __device__ __forceinline__ void copy_piece(const uint8_t* stage, uint8_t* dst, int bytes, int lane) {
   constexpr int kMaxChunks = (kMaxBytes + 15) / 16;
   constexpr int kPerLane = (kMaxChunks + kWave - 1) / kWave;
-  if (((reinterpret_cast<uintptr_t>(dst) & 15) == 0) && (bytes & 15) == 0) {
+  if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
     const u32x4* src = reinterpret_cast<const u32x4*>(stage);
     u32x4* out = reinterpret_cast<u32x4*>(dst);
     const int n = bytes >> 4;
-    // Reads clamp to the last chunk (n >= 1) so they need no branch.
-    u32x4 v[kPerLane];
+    if (n > 0) {
+      // Reads clamp to the last chunk so they need no branch.
+      u32x4 v[kPerLane];
 #pragma unroll
-    for (int i = 0; i < kPerLane; ++i) v[i] = src[min(lane + i * kWave, n - 1)];
+      for (int i = 0; i < kPerLane; ++i) v[i] = src[min(lane + i * kWave, n - 1)];
 #pragma unroll
-    for (int i = 0; i < kPerLane; ++i) {
-      const int c = lane + i * kWave;
-      if (c < n) __builtin_nontemporal_store(v[i], out + c);
+      for (int i = 0; i < kPerLane; ++i) {
+        const int c = lane + i * kWave;
+        if (c < n) __builtin_nontemporal_store(v[i], out + c);
+      }
     }
+    if (lane < (bytes & 15)) dst[16 * n + lane] = stage[16 * n + lane];
   } else {
     for (int b = lane; b < bytes; b += kWave) dst[b] = stage[b];
   }
