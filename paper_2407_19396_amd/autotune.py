@@ -42,10 +42,13 @@ def batch_key(table, device_name: str, obs_mode: int = 0, reward_mode: int = 0, 
 
 def block_candidates(n_tiles: int, lds_bytes: int, cus: int, lds_per_cu: int = 160 * 1024) -> list[int]:
     """Workgroup counts worth trying: the largest that fits the LDS of every
-    CU, smaller ones, and those that make every workgroup take the same
-    number of tiles."""
+    CU, smaller ones, those that make every workgroup take the same number
+    of tiles, and one workgroup per tile.  With more tiles than fit at once
+    the last gives up persistence: a later workgroup starts wherever an
+    earlier one has finished, instead of each workgroup taking its next tile
+    in turn, which balances short rollouts of tiles with uneven work."""
     fit = max(1, min(16, lds_per_cu // max(1, lds_bytes)))
-    out = set()
+    out = {n_tiles}
     for p in range(max(1, fit - 2), fit + 1):
         out.add(min(n_tiles, p * cus))
     for rounds in range(1, 9):

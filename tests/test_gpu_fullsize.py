@@ -131,11 +131,13 @@ def test_mixed_fused_sampled(K, blocks):
     check_sample(wl.workload_mixed(0), 4096, K, stride=683, blocks=blocks)
 
 
-def test_mixed_driver_shape_sampled():
+@pytest.mark.parametrize("blocks", [2048, 4096])
+def test_mixed_driver_shape_sampled(blocks):
     """The driver's run: 5 warm-up steps, then 20 steps, each one fused
-    launch of the 262144-env mix in the tuner's shape (K = 1024, 2048
-    workgroups), split as the benchmark splits them."""
-    check_sample(wl.workload_mixed(0), 25, 1024, stride=683, blocks=2048, calls=[5, 20])
+    launch of the 262144-env mix in the shapes the tuner picks from (K =
+    1024; 2048 persistent workgroups of two tiles each, or one workgroup per
+    tile), split as the benchmark splits them."""
+    check_sample(wl.workload_mixed(0), 25, 1024, stride=683, blocks=blocks, calls=[5, 20])
 
 
 @pytest.mark.parametrize("family,side", [(wl.FAMILY_EMPTY, 32), (wl.FAMILY_TWOROOM, 32), (wl.FAMILY_EMPTY, 24)])
