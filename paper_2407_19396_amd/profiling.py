@@ -339,18 +339,21 @@ def store_ceilings(n_envs: int = 262144, K: int = 1024, blocks: int = 2048, reps
     flg = torch.empty(K * n_envs, dtype=torch.uint8, device="cuda")
     act = torch.empty(K * n_envs, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream().cuda_stream
-    algo = K * n_envs * (147 + 4 + 1 + 1)
-    for nt, aligned in ((1, 1), (0, 1), (1, 0)):
-        def run(nt=nt, aligned=aligned):
-            rc = fn(obs.data_ptr(), rew.data_ptr(), flg.data_ptr(), act.data_ptr(), n_envs, K, K, blocks, nt,
+    # launches of K steps over a ring of K rows, and of 256 steps over a ring
+    # of 256 rows, where the two piece patterns differ most
+    for k, nt, aligned in ((K, 1, 1), (K, 0, 1), (K, 1, 0), (256, 1, 1), (256, 1, 0)):
+        algo = k * n_envs * (147 + 4 + 1 + 1)
+
+        def run(k=k, nt=nt, aligned=aligned):
+            rc = fn(obs.data_ptr(), rew.data_ptr(), flg.data_ptr(), act.data_ptr(), n_envs, k, k, blocks, nt,
                     aligned, stream)
             if rc != 0:
                 raise RuntimeError(f"gx_probe_record_stores failed: {rc}")
         ms = timed(run)
         pieces = "pieces ending on 64-byte boundaries" if aligned else "two 4704-byte halves per tile"
-        lines.append(f"record store pattern of k_fused ({n_envs} envs, {K} steps, {blocks} workgroups, {pieces}, "
-                     f"{'non-temporal' if nt else 'ordinary'} stores): {ms:.3f} ms for {algo} bytes, "
-                     f"{algo / ms / 1e6:.1f} GB/s")
+        lines.append(f"record store pattern of k_fused ({n_envs} envs, {k} steps over {k} rows, {blocks} "
+                     f"workgroups, {pieces}, {'non-temporal' if nt else 'ordinary'} stores): {ms:.3f} ms for "
+                     f"{algo} bytes, {algo / ms / 1e6:.1f} GB/s")
     return "\n".join(lines) + "\n"
 
 
