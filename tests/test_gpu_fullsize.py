@@ -132,11 +132,12 @@ def test_mixed_fused_sampled(K, blocks):
 
 
 @pytest.mark.parametrize("blocks", [2048, 4096])
-def test_mixed_driver_shape_sampled(blocks):
-    """The driver's run: 5 warm-up steps, then 20 steps, each one fused
-    launch of the 262144-env mix in the shapes the tuner picks from (K =
-    1024; 2048 persistent workgroups of two tiles each, or one workgroup per
-    tile), split as the benchmark splits them."""
+def test_mixed_short_run_shape_sampled(blocks):
+    """The benchmark's short run (`--steps 20 --warmup 5`): 5 warm-up
+    steps, then 20 steps, each one fused launch of the 262144-env mix in the
+    shapes the tuner picks from (K = 1024; 2048 persistent workgroups of two
+    tiles each, or one workgroup per tile), split as the benchmark splits
+    them."""
     check_sample(wl.workload_mixed(0), 25, 1024, stride=683, blocks=blocks, calls=[5, 20])
 
 
