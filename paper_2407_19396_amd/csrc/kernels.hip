@@ -1627,59 +1627,81 @@ struct LdsGrid {
 // cleared margins.
 // kNT: non-temporal stores (trajectory records); the state write-back uses
 // ordinary ones, since the next launch reads it again.
+// The output bytes of a categorical unit q (4 cells) or a symbolic one (16
+// bytes of at most 6 cells), from the LDS codes.
+__device__ __forceinline__ uint32_t cat_unit(int o, const uint32_t* table, const uint8_t* codes) {
+  // the unit's 4 codes: one aligned word, or two and a byte shift
+  const int lo = o & ~3, sh = o & 3;
+  const uint32_t* cw = reinterpret_cast<const uint32_t*>(codes + lo);
+  const uint32_t c4 = __builtin_amdgcn_alignbyte(cw[1], cw[0], (uint32_t)sh);
+  uint32_t ty[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) ty[k] = table_at(table, (c4 >> (8 * k)) & 0xFFu);
+  // bytes 0 of the four entries
+  return __builtin_amdgcn_perm(__builtin_amdgcn_perm(ty[3], ty[2], 0x0c0c0400u),
+                               __builtin_amdgcn_perm(ty[1], ty[0], 0x0c0c0400u), 0x05040100u);
+}
+
+__device__ __forceinline__ u32x4 sym_unit(int o, const uint32_t* table, const uint8_t* codes) {
+  const int c = (o + 66) / 3 - 22;   // floor(o / 3) for o >= -66
+  const uint32_t r = (uint32_t)(o - 3 * c);
+  uint32_t t[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) t[k] = table_at(table, codes[c + k]) & 0xFFFFFFu;
+  // the 18 bytes t0..t5 as words, then bytes r..r+15 of them
+  const uint32_t s0 = t[0] | (t[1] << 24), s1 = (t[1] >> 8) | (t[2] << 16),
+                 s2 = (t[2] >> 16) | (t[3] << 8), s3 = t[4] | (t[5] << 24), s4 = t[5] >> 8;
+  u32x4 w;
+  w.x = __builtin_amdgcn_alignbyte(s1, s0, r);
+  w.y = __builtin_amdgcn_alignbyte(s2, s1, r);
+  w.z = __builtin_amdgcn_alignbyte(s3, s2, r);
+  w.w = __builtin_amdgcn_alignbyte(s4, s3, r);
+  return w;
+}
+
+template <bool kCat, bool kNT>
+__device__ __forceinline__ void store_unit(uintptr_t a, uintptr_t d0, uintptr_t d1, u32x4 w) {
+  constexpr int kUnit = kCat ? 4 : 16;
+  if (a >= d0 && a + kUnit <= d1) {
+    if (kCat) {
+      if (kNT) __builtin_nontemporal_store(w.x, reinterpret_cast<uint32_t*>(a));
+      else *reinterpret_cast<uint32_t*>(a) = w.x;
+    } else {
+      if (kNT) __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(a));
+      else *reinterpret_cast<u32x4*>(a) = w;
+    }
+  } else {
+#pragma unroll
+    for (int b = 0; b < kUnit; ++b)
+      if (a + b >= d0 && a + b < d1) reinterpret_cast<uint8_t*>(a)[b] = (uint8_t)(w[b >> 2] >> (8 * (b & 3)));
+  }
+}
+
 template <bool kCat, bool kNT = true>
 __device__ __forceinline__ void emit_tile_grids(uint8_t* dst, int n_cells, const uint32_t* table,
                                                 const uint8_t* codes, int lane) {
   constexpr int kUnit = kCat ? 4 : 16;
+  // units per lane in flight: all their LDS reads are issued before the
+  // first of their stores, so the reads' latency overlaps
+  constexpr int kDepth = 4;
   const int64_t n = kCat ? n_cells : 3 * (int64_t)n_cells;
   const uintptr_t d0 = reinterpret_cast<uintptr_t>(dst), d1 = d0 + (uintptr_t)n;
   const uintptr_t A = d0 & ~(uintptr_t)63;
   const int rel = (int)((int64_t)A - (int64_t)d0);   // in [-63, 0]
   const int units = (int)((d1 - A + kUnit - 1) / kUnit);
-  for (int q = lane; q < units; q += kWave) {
-    const int o = rel + kUnit * q;   // output byte of the unit's first byte
-    const uintptr_t a = A + (uintptr_t)(kUnit * q);
-    if (kCat) {
-      // the unit's 4 codes: one aligned word, or two and a byte shift
-      const int lo = o & ~3, sh = o & 3;
-      const uint32_t* cw = reinterpret_cast<const uint32_t*>(codes + lo);
-      const uint32_t c4 = __builtin_amdgcn_alignbyte(cw[1], cw[0], (uint32_t)sh);
-      uint32_t ty[4];
+  for (int q0 = lane; q0 < units; q0 += kDepth * kWave) {
+    // a unit past the block's last one reads that last unit's cells again
+    u32x4 w[kDepth];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) ty[k] = table_at(table, (c4 >> (8 * k)) & 0xFFu);
-      // bytes 0 of the four entries
-      const uint32_t w = __builtin_amdgcn_perm(__builtin_amdgcn_perm(ty[3], ty[2], 0x0c0c0400u),
-                                               __builtin_amdgcn_perm(ty[1], ty[0], 0x0c0c0400u), 0x05040100u);
-      if (a >= d0 && a + 4 <= d1) {
-        if (kNT) __builtin_nontemporal_store(w, reinterpret_cast<uint32_t*>(a));
-        else *reinterpret_cast<uint32_t*>(a) = w;
-      } else {
+    for (int u = 0; u < kDepth; ++u) {
+      const int o = rel + kUnit * min(q0 + u * kWave, units - 1);   // output byte of the unit's first byte
+      if (kCat) w[u] = u32x4{cat_unit(o, table, codes), 0u, 0u, 0u};
+      else w[u] = sym_unit(o, table, codes);
+    }
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
-          if (a + b >= d0 && a + b < d1) reinterpret_cast<uint8_t*>(a)[b] = (uint8_t)(w >> (8 * b));
-      }
-    } else {
-      const int c = (o + 66) / 3 - 22;   // floor(o / 3) for o >= -66
-      const uint32_t r = (uint32_t)(o - 3 * c);
-      uint32_t t[6];
-#pragma unroll
-      for (int k = 0; k < 6; ++k) t[k] = table_at(table, codes[c + k]) & 0xFFFFFFu;
-      // the 18 bytes t0..t5 as words, then bytes r..r+15 of them
-      const uint32_t s0 = t[0] | (t[1] << 24), s1 = (t[1] >> 8) | (t[2] << 16),
-                     s2 = (t[2] >> 16) | (t[3] << 8), s3 = t[4] | (t[5] << 24), s4 = t[5] >> 8;
-      u32x4 w;
-      w.x = __builtin_amdgcn_alignbyte(s1, s0, r);
-      w.y = __builtin_amdgcn_alignbyte(s2, s1, r);
-      w.z = __builtin_amdgcn_alignbyte(s3, s2, r);
-      w.w = __builtin_amdgcn_alignbyte(s4, s3, r);
-      if (a >= d0 && a + 16 <= d1) {
-        if (kNT) __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(a));
-        else *reinterpret_cast<u32x4*>(a) = w;
-      } else {
-#pragma unroll
-        for (int b = 0; b < 16; ++b)
-          if (a + b >= d0 && a + b < d1) reinterpret_cast<uint8_t*>(a)[b] = (uint8_t)(w[b >> 2] >> (8 * (b & 3)));
-      }
+    for (int u = 0; u < kDepth; ++u) {
+      const int q = q0 + u * kWave;
+      if (q < units) store_unit<kCat, kNT>(A + (uintptr_t)(kUnit * q), d0, d1, w[u]);
     }
   }
 }
