@@ -8,7 +8,7 @@ writing its record (147-byte symbolic first-person observation, fp32
 reward, flags, action) to an HBM trajectory ring.  One benchmark "step" is
 one environment step of the whole batch; the fused persistent kernel runs
 K of them per launch.  Before the timed region: the autotuner (or its cached
-choice), about 0.3 s of untimed rollouts in the chosen shape, a reset, and
+choice), about 0.3 s of untimed rollouts of the timed length, a reset, and
 the --warmup steps.
 
 Reported beside it:
@@ -444,14 +444,15 @@ def main():
     traj = env.traj(ring)
     if not np.any(table.family == 7):
         traj.mission = None       # the mission output only carries GoToDoor's target
-    # about 0.3 s of untimed rollouts in the chosen shape first, so that the
+    # about 0.3 s of untimed rollouts of the timed length first, so that the
     # GPU runs at its working clocks whether or not the tuner has just run
-    # (a cached tuning leaves it idle until here); the reset below starts
-    # the measured sequence afresh
+    # (a cached tuning leaves it idle until here); they launch exactly what
+    # the timed region launches, so a kernel trace of the run holds launches
+    # of that one shape; the reset below starts the measured sequence afresh
     env.reset(first)
     t_warm = time.perf_counter()
     while time.perf_counter() - t_warm < 0.3:
-        env.rollout(K, traj, K=K)
+        env.rollout(args.steps, traj, K=K)
         torch.cuda.synchronize()
     env.reset(first)
     # warmup (also advances episodes away from the synchronous start)
