@@ -373,7 +373,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the environment "
-              "batch would shard by env id with no exchange, see the design notes.", file=sys.stderr)
+              "batch would shard by env id (each GPU steps its own envs; nothing is exchanged "
+              "between them), so one GPU's share is what is measured.", file=sys.stderr)
         sys.exit(2)
 
     import torch
