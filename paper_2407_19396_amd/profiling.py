@@ -114,13 +114,15 @@ def _median(xs):
 
 def summarize(trace: str, fetch: str, write: str, sq, copy_bytes: int, K: int,
               envs: int, command: str, source=KERNEL_SOURCES, kernel_name: str = FUSED,
-              workload: str = "mixed") -> str:
+              workload: str = "mixed", valu: str | None = None) -> str:
     """Summary of one kernel's launches (kernel_name: k_fused, launches of K
     steps; or k_plain, one step per launch).  sq: a directory or a list of
-    directories of SQ counter runs; source: the sources the profiled library
-    was built from.  Counters are the median over the kernel's dispatches
-    (a k_plain run also holds a few reset launches, which the median leaves
-    out)."""
+    directories of SQ counter runs; valu: a run of rocprofv3's derived
+    VALUBusy and VALUUtilization (percentages: the share of the time the
+    SIMDs' vector ALUs are busy, and the share of lanes active when they
+    are); source: the sources the profiled library was built from.  Counters
+    are the median over the kernel's dispatches (a k_plain run also holds a
+    few reset launches, which the median leaves out)."""
     kernel = kernel_source_hash(source)
     st = _stats(trace)
     fc, wc = _counters(fetch), _counters(write)
@@ -165,6 +167,11 @@ def summarize(trace: str, fetch: str, write: str, sq, copy_bytes: int, K: int,
                 if k == kernel_name:
                     m = _median(v)
                     lines.append(f"{c}: {m:.4g} ({m / wave_steps:.1f} per wave-step)")
+    if valu:
+        lines += ["", "## vector ALU (--pmc VALUBusy VALUUtilization), median over dispatches"]
+        for (k, c), v in sorted(_counters(valu).items()):
+            if k == kernel_name:
+                lines.append(f"{c}: {_median(v):.1f} %")
     avg = st.get(kernel_name, {}).get("avg_ns", 0)
     lines += ["", f"machine: name={kernel_name} traffic_bytes_per_launch={k_fetch + k_write:.0f} K={K} "
                   f"envs={envs} kernel={kernel} avg_ns={avg:.0f} median_ns={_median(durs) if durs else 0:.0f}"]
@@ -367,6 +374,7 @@ def main():
     ap.add_argument("--fetch")
     ap.add_argument("--write")
     ap.add_argument("--sq", action="append", help="SQ counter run directory (repeatable)")
+    ap.add_argument("--valu", help="run directory of --pmc VALUBusy VALUUtilization")
     ap.add_argument("--source", nargs="+", default=list(KERNEL_SOURCES),
                     help="kernel source and launch header the profiled build used")
     ap.add_argument("--copy-bytes", type=int)
@@ -391,7 +399,7 @@ def main():
         if not (a.trace and a.fetch and a.write and a.copy_bytes and a.K and a.envs):
             ap.error("--trace, --fetch, --write, --copy-bytes, --K and --envs are needed")
         text = summarize(a.trace, a.fetch, a.write, a.sq, a.copy_bytes, a.K, a.envs, a.command, a.source,
-                         a.kernel, a.workload)
+                         a.kernel, a.workload, a.valu)
     with open(a.out, "w") as f:
         f.write(text)
     print(text)
