@@ -268,9 +268,9 @@ int env_server_step(gx_server* s, int32_t K, void* stream, int32_t* finished, in
         s->fresh[t] = 0;
         max_cells = std::max(max_cells, s->tile_cells[t]);
       }
-    const size_t lds = gx::fused_lds_bytes(max_cells);
-    const int per_cu = std::max<int>(1, std::min<int>(16, (int)(s->lds_per_cu / lds)));
-    const int32_t blocks = std::min<int32_t>(n, s->cus * per_cu);
+    // one workgroup per tile: a later tile starts on whichever workgroup
+    // slot frees first, so the list (longest first) is scheduled greedily
+    const int32_t blocks = n;
     const gx::TileTables tiles{n, max_cells, list};
     const gx::TrajBufs none{nullptr, nullptr, nullptr, nullptr, 1};
     if (gx::launch_fused(tables_of(s), tiles, state_of(s), nullptr, K, none, 0, blocks, st,
