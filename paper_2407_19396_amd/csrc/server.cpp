@@ -42,8 +42,6 @@ struct gx_server {
   int device = 0;
   int32_t max_tiles = 0, max_side = 0, reward_mode = 0;
   uint64_t tile_grid_bytes = 0, device_bytes = 0;
-  int cus = 256;
-  size_t lds_per_cu = 160 * 1024;
   // device pool
   uint32_t* d_meta = nullptr;
   int32_t* d_max_steps = nullptr;
@@ -154,11 +152,6 @@ int env_server_create(int32_t max_tiles, int32_t max_side, int32_t reward_mode, 
     free_all(s);
     delete s;
     return GX_ENOMEM;
-  }
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, s->device) == hipSuccess) {
-    s->cus = prop.multiProcessorCount;
-    if (prop.maxSharedMemoryPerMultiProcessor > 0) s->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor;
   }
   for (int32_t t = 0; t < max_tiles; ++t) s->free_tiles.insert(t);
   s->tile_cells.assign(max_tiles, 0);
