@@ -213,7 +213,7 @@ typedef struct {
   int32_t n_tiles;            /* workgroup tiles of tile_envs envs (fused rollout) */
   int32_t max_tile_cells;     /* largest tile's cells, one LDS byte each */
   int32_t lds_bytes;          /* LDS per workgroup of the fused kernel */
-  int32_t blocks;             /* persistent workgroups of the fused kernel */
+  int32_t blocks;             /* workgroups of the fused kernel (each takes tiles blocks apart) */
   int32_t k_default;          /* steps fused per launch when K = 0 */
   uint64_t grid_bytes;
   uint64_t obs_row_bytes;     /* bytes of one row of observation outputs */
@@ -264,7 +264,9 @@ int env_rollout(gx_ctx* ctx, const gx_state* st, int32_t n_steps, const uint8_t*
                 const gx_traj* traj, int32_t K, void* stream);
 
 /* Set the fused kernel's launch shape: steps per launch (K >= 1) and
- * persistent workgroups (blocks >= 1; 0 keeps the current value). */
+ * workgroups (blocks >= 1; 0 keeps the current value).  Fewer workgroups
+ * than tiles are persistent: workgroup b takes tiles b, b + blocks, ...
+ * The default is one workgroup per tile. */
 int env_set_launch(gx_ctx* ctx, int32_t K, int32_t blocks);
 
 /* Set the fused kernel's tiling: tiles of tile_envs (1..64, default 64)
@@ -272,10 +274,10 @@ int env_set_launch(gx_ctx* ctx, int32_t K, int32_t blocks);
  * tile's grids in the workgroup's LDS.  Fewer envs per tile leave lanes
  * idle but need less LDS per workgroup, so more workgroups fit a compute
  * unit: the trade for large grids (Sec. 4.2 scales the batch; this picks
- * how a batch maps onto waves).  Resets the workgroup count to as many as
- * the LDS of every compute unit holds.  Multiples of 16 keep the
- * observation records' stores 16-byte aligned; other values fall back to
- * byte stores.  Results do not depend on the tiling. */
+ * how a batch maps onto waves).  Resets the workgroup count to one per
+ * tile.  Multiples of 16 keep the observation records' stores 16-byte
+ * aligned; other values fall back to byte stores.  Results do not depend
+ * on the tiling. */
 int env_set_tiling(gx_ctx* ctx, int32_t tile_envs);
 
 /* Free the context and its device tables (after the stream is idle). */

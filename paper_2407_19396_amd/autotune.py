@@ -5,10 +5,11 @@ in advance: the envs per tile (one env per lane; fewer than a wave's 64
 lanes need less LDS per workgroup, so more workgroups fit a compute unit,
 which pays for large grids), K, the steps fused per launch (longer chunks amortise loading and
 storing each tile's grids, shorter ones bound the latency of a chunk), and
-the number of persistent workgroups (more hide latency better, but tiles
-are handed out in whole rounds, so a count that does not divide the tile
-count leaves the last round partly idle, which matters most for short
-rollouts, where the grids' staging is a large share of a launch).
+the number of workgroups (one per tile lets the hardware start each tile
+wherever a workgroup slot frees up; fewer are persistent and take their
+tiles in whole rounds, so a count that does not divide the tile count
+leaves the last round partly idle, which matters most for short rollouts,
+where the grids' staging is a large share of a launch).
 ``tune`` times rollouts of the actual batch and length for each candidate
 and keeps the fastest, caching the choice on disk per device, batch
 composition and rollout length.
@@ -85,9 +86,9 @@ def tune(env, traj, Ks=(128, 256, 512), steps: int = 0, tile_envs=(64, 32, 16), 
     """Pick the envs per tile, K and the workgroup count for rollouts of
     `steps` steps (0: one launch of each candidate K, the steady state).
 
-    First the envs per tile (each tiling at the workgroup count that fills
-    the compute units' LDS, K the largest candidate), then K x workgroups
-    for the best tiling.  When `steps` is shorter than every candidate K,
+    First the envs per tile (each tiling at its default workgroup count, one
+    per tile, K the largest candidate), then K x workgroups for the best
+    tiling.  When `steps` is shorter than every candidate K,
     all of them run the same single launch, so only the workgroup count is
     searched (at the largest K, which later full launches then use)."""
     import torch

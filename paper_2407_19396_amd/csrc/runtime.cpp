@@ -34,8 +34,6 @@ struct gx_ctx {
   int32_t blocks = 0;
   int32_t k_default = 64;
   std::vector<int32_t> cells;          // S^2 per env, for re-tiling
-  int cus = 256;                       // the device's compute units and LDS per unit
-  size_t lds_per_cu = 160 * 1024;
   // rgb modes: the sprite atlas, and the staging ring of symbolic records
   // (obs [stage_rows][sym_row], then reward, flags, action, mission
   // [stage_rows][n]) that the step kernels fill and the renderer expands
@@ -83,9 +81,10 @@ void free_tables(gx_ctx* c) {
   c->d_grid_off = nullptr;
 }
 
-// Tiles of E consecutive envs; as many persistent single-wave workgroups
-// as the LDS of every compute unit holds for the largest tile, no more than
-// there are tiles.
+// Tiles of E consecutive envs, one single-wave workgroup per tile: the
+// hardware starts a tile's workgroup wherever an earlier one has finished,
+// which balances tiles of uneven work better than persistent workgroups
+// that take their tiles in a fixed order (env_set_launch can ask for fewer).
 void set_tiling(gx_ctx* c, int32_t E) {
   c->tile_envs = E;
   c->n_tiles = (c->n + E - 1) / E;
@@ -95,9 +94,7 @@ void set_tiling(gx_ctx* c, int32_t E) {
     for (int32_t i = t * E; i < std::min(c->n, (t + 1) * E); ++i) cells += c->cells[i];
     c->max_tile_cells = std::max(c->max_tile_cells, cells);
   }
-  const size_t lds = gx::fused_lds_bytes(c->max_tile_cells);
-  const int per_cu = std::max<int>(1, std::min<int>(16, (int)(c->lds_per_cu / lds)));
-  c->blocks = std::min<int32_t>(c->n_tiles, c->cus * per_cu);
+  c->blocks = c->n_tiles;
 }
 
 bool state_ok(const gx_state* st) {
@@ -293,11 +290,6 @@ int env_create(const gx_config* cfg, gx_ctx** out) {
     free_tables(c);
     delete c;
     return rc;
-  }
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
-    c->cus = prop.multiProcessorCount;
-    if (prop.maxSharedMemoryPerMultiProcessor > 0) c->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor;
   }
   set_tiling(c, kTileEnvs);
   *out = c;

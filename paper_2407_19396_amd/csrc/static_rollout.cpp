@@ -39,8 +39,6 @@ alignas(256) uint8_t g_host_tables[kScratchBytes];
 // What a call needs of a device, found once per device (with it current).
 struct DeviceSlot {
   uint8_t* scratch = nullptr;   // device address of scratch on this device
-  int cus = 256;                // compute units
-  size_t lds_per_cu = 160 * 1024;
 };
 
 std::mutex g_mutex;                 // guards g_host_tables and g_devices
@@ -52,11 +50,6 @@ int device_slot(int device, const DeviceSlot** out) {
   if (!d.scratch) {
     void* p = nullptr;
     if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GX_EDEVICE;
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
-      d.cus = prop.multiProcessorCount;
-      if (prop.maxSharedMemoryPerMultiProcessor > 0) d.lds_per_cu = prop.maxSharedMemoryPerMultiProcessor;
-    }
     d.scratch = static_cast<uint8_t*>(p);
   }
   *out = &d;
@@ -150,12 +143,9 @@ extern "C" int env_rollout_static(const gx_config* cfg, const gx_state* st, int3
   }
   if (n_steps == 0) return GX_OK;
 
-  // the launch shape env_create picks: single-wave workgroups, as many as
-  // the LDS of every compute unit holds, no more than there are tiles
+  // the launch shape env_create picks: one single-wave workgroup per tile
   const int32_t n_tiles = (n + kTileEnvs - 1) / kTileEnvs;
-  const int per_cu =
-      std::max<int>(1, std::min<int>(16, (int)(dev->lds_per_cu / gx::fused_lds_bytes(max_tile_cells))));
-  const int32_t blocks = std::min<int32_t>(n_tiles, dev->cus * per_cu);
+  const int32_t blocks = n_tiles;
   const int32_t k = K > 0 ? K : 64;
   const gx::TileTables tiles{n_tiles, max_tile_cells, nullptr};
   const gx::TrajBufs tb{traj->obs, traj->reward, traj->flags, traj->action, traj->rows, obs_row, traj->mission};
