@@ -1141,8 +1141,9 @@ struct HbmSpan {
   }
 
   // the triple of region cell (k, r); a cell outside the grid reads as
-  // whatever the loaded bytes hold there (bytes of the grid's other rows, or
-  // zeros)
+  // whatever the loaded bytes hold there (bytes of the grid's other rows, up
+  // to 3 bytes of a neighbouring env's grid in the dwords at the grid's two
+  // ends, or zeros for rows that were not read)
   __device__ __forceinline__ uint32_t cell(int k, int r) const {
     const int yy = Y0 + r;
     const uint32_t rb = (uint32_t)((uintptr_t)((intptr_t)gb + 3 * (intptr_t)(yy * S + X0)) & 3);
@@ -1623,8 +1624,8 @@ struct LdsGrid {
 // covers whole 64-byte units of HBM (which writes a partial one as a
 // read-modify-write).  Units at the block's two ends store only their bytes
 // inside [0, n) (the rest belong to the neighbouring tiles' records); their
-// reads reach at most 21 cells before or 15 after the tile, inside the
-// cleared margins.
+// reads reach at most 64 cells before the tile (21 for symbolic units) and
+// 7 after it, inside the cleared margins.
 // kNT: non-temporal stores (trajectory records); the state write-back uses
 // ordinary ones, since the next launch reads it again.
 // The output bytes of a categorical unit q (4 cells) or a symbolic one (16
