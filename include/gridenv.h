@@ -320,7 +320,10 @@ typedef struct {
   uint64_t device_bytes;       /* device memory the server owns */
 } gx_server_info;
 
-/* Allocate a server for up to max_tiles * 64 envs of side <= max_side. */
+/* Allocate a server for up to max_tiles * 64 envs of side <= max_side
+ * (1 <= max_tiles <= 2^20, 4 <= max_side <= 32), with its device pool and
+ * the host bookkeeping of up to max_tiles live requests, so that admitting,
+ * stepping and releasing allocate nothing afterwards. */
 int env_server_create(int32_t max_tiles, int32_t max_side, int32_t reward_mode, gx_server** out);
 
 /* Queue a request (host work only; the next env_server_step's launch resets
@@ -338,8 +341,9 @@ int env_server_admit(gx_server* srv, const gx_request* req, int32_t* handle);
 int env_server_step(gx_server* srv, int32_t K, void* stream, int32_t* finished, int32_t cap,
                     int32_t* n_finished);
 
-/* Return a finished request's tiles to the pool.  Call only after the
- * stream has completed its last step. */
+/* Return a finished request's tiles to the pool and free its handle.  Call
+ * only after env_server_step has returned the handle (GX_ESTATE before) and
+ * the stream has completed that request's last step. */
 int env_server_release(gx_server* srv, int32_t handle);
 
 int env_server_info(const gx_server* srv, gx_server_info* info);

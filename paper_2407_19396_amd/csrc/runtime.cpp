@@ -229,11 +229,20 @@ int env_create(const gx_config* cfg, gx_ctx** out) {
   const int32_t n = cfg->n_envs;
   // the grid of a tile must fit the LDS of one workgroup; side <= 32 and
   // 64 envs per tile bound it at 64 KiB of cells
-  std::vector<uint32_t> meta(n);
-  std::vector<int32_t> max_steps(n);
-  std::vector<uint2> seed(n);
-  std::vector<uint32_t> rng_id(n);
-  std::vector<uint64_t> grid_off(n);
+  std::vector<uint32_t> meta;
+  std::vector<int32_t> max_steps;
+  std::vector<uint2> seed;
+  std::vector<uint32_t> rng_id;
+  std::vector<uint64_t> grid_off;
+  try {
+    meta.resize(n);
+    max_steps.resize(n);
+    seed.resize(n);
+    rng_id.resize(n);
+    grid_off.resize(n);
+  } catch (const std::bad_alloc&) {
+    return GX_ENOMEM;
+  }
   uint64_t off = 0;
   for (int32_t i = 0; i < n; ++i) {
     const int fam = cfg->family[i], S = cfg->side[i], P = cfg->param ? cfg->param[i] : 0;
@@ -272,15 +281,19 @@ int env_create(const gx_config* cfg, gx_ctx** out) {
     // the atlas, and a staging ring of up to 64 rows within 256 MiB
     const uint64_t per_row = stage_bytes(c, 1);
     c->stage_rows = (int32_t)std::max<uint64_t>(1, std::min<uint64_t>(64, (256ull << 20) / per_row));
-    std::vector<uint8_t> atlas(cfg->sprites, cfg->sprites + (size_t)gx::kSprites * gx::kSpriteBytes);
-    rc = upload(&c->d_sprites, atlas);
-    if (rc == GX_OK && c->obs_mode == 5) {
-      std::vector<uint2> cell_rows;
-      for (int32_t i = 0; i < n; ++i)
-        for (uint32_t y = 0; y < cfg->side[i]; ++y)
-          cell_rows.push_back(make_uint2((uint32_t)(grid_off[i] / 3 + (uint64_t)y * cfg->side[i]), cfg->side[i]));
-      c->n_cell_rows = (uint32_t)cell_rows.size();
-      rc = upload(&c->d_cell_rows, cell_rows);
+    try {
+      const std::vector<uint8_t> atlas(cfg->sprites, cfg->sprites + (size_t)gx::kSprites * gx::kSpriteBytes);
+      rc = upload(&c->d_sprites, atlas);
+      if (rc == GX_OK && c->obs_mode == 5) {
+        std::vector<uint2> cell_rows;
+        for (int32_t i = 0; i < n; ++i)
+          for (uint32_t y = 0; y < cfg->side[i]; ++y)
+            cell_rows.push_back(make_uint2((uint32_t)(grid_off[i] / 3 + (uint64_t)y * cfg->side[i]), cfg->side[i]));
+        c->n_cell_rows = (uint32_t)cell_rows.size();
+        rc = upload(&c->d_cell_rows, cell_rows);
+      }
+    } catch (const std::bad_alloc&) {
+      rc = GX_ENOMEM;
     }
     if (rc == GX_OK && hipMalloc(reinterpret_cast<void**>(&c->d_stage), stage_bytes(c, c->stage_rows)) !=
                            hipSuccess)

@@ -15,9 +15,7 @@
 #include <chrono>
 #include <cstdint>
 #include <deque>
-#include <map>
 #include <new>
-#include <set>
 #include <thread>
 #include <vector>
 
@@ -32,8 +30,9 @@ constexpr int kLists = 8;   // tile lists kept for launches still in flight
 
 struct Request {
   bool live = false;
+  bool reported = false;     // its handle has been returned by env_server_step
   int32_t n_envs = 0, n_steps = 0, done = 0;
-  std::vector<int32_t> tiles;
+  int32_t first_tile = -1;   // its tiles, chained through gx_server::tile_next
 };
 
 }  // namespace
@@ -64,13 +63,17 @@ struct gx_server {
   uint32_t* h_lists = nullptr;
   hipEvent_t list_done[kLists] = {};
   int64_t launches = 0;
-  // bookkeeping
-  std::set<int32_t> free_tiles;
+  // bookkeeping, sized in env_server_create so that admitting, stepping and
+  // releasing allocate nothing: every live request holds at least one tile,
+  // so at most max_tiles requests are live (and have handles) at once
+  std::vector<int32_t> free_tiles;   // stack of free tile ids
+  std::vector<int32_t> tile_next;    // the next tile of the same request, -1 after its last
   std::vector<int32_t> tile_cells;   // cells of a live tile, 0 when free
-  std::vector<Request> reqs;
+  std::vector<Request> reqs;         // by handle
   std::vector<int32_t> free_handles;
   std::vector<uint8_t> fresh;        // 1: admitted, not yet in a launch
-  std::deque<int32_t> finished;      // requests whose last step has been launched
+  std::vector<int32_t> finished;     // ring of max_tiles: last step launched, handle not yet returned
+  int32_t fin_head = 0, fin_count = 0;
   std::vector<int32_t> running;      // requests with steps left to launch
   int32_t live = 0;
 };
@@ -148,14 +151,27 @@ int env_server_create(int32_t max_tiles, int32_t max_side, int32_t reward_mode, 
     ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
   // every descriptor starts inactive
   ok = ok && hipMemset(s->d_tiles, 0, sizeof(gx::ServeTile) * max_tiles) == hipSuccess;
+  if (ok) {
+    try {
+      // tile 0 on top of the stack: the first request takes the lowest tiles
+      s->free_tiles.resize(max_tiles);
+      for (int32_t t = 0; t < max_tiles; ++t) s->free_tiles[t] = max_tiles - 1 - t;
+      s->tile_next.assign(max_tiles, -1);
+      s->tile_cells.assign(max_tiles, 0);
+      s->fresh.assign(max_tiles, 0);
+      s->finished.assign(max_tiles, -1);
+      s->reqs.reserve(max_tiles);
+      s->free_handles.reserve(max_tiles);
+      s->running.reserve(max_tiles);
+    } catch (const std::bad_alloc&) {
+      ok = false;
+    }
+  }
   if (!ok) {
     free_all(s);
     delete s;
     return GX_ENOMEM;
   }
-  for (int32_t t = 0; t < max_tiles; ++t) s->free_tiles.insert(t);
-  s->tile_cells.assign(max_tiles, 0);
-  s->fresh.assign(max_tiles, 0);
   *out = s;
   return GX_OK;
 }
@@ -171,6 +187,8 @@ int env_server_admit(gx_server* s, const gx_request* r, int32_t* handle) {
       return GX_EINVAL;
   const int32_t need = (r->n_envs + kTileEnvs - 1) / kTileEnvs;
   if ((int32_t)s->free_tiles.size() < need) return GX_EBUSY;
+  // a free tile means fewer than max_tiles live requests, so a new handle
+  // stays within the capacity reserved at creation
   int32_t h;
   if (!s->free_handles.empty()) {
     h = s->free_handles.back();
@@ -181,15 +199,20 @@ int env_server_admit(gx_server* s, const gx_request* r, int32_t* handle) {
   }
   Request& q = s->reqs[h];
   q.live = true;
+  q.reported = false;
   q.n_envs = r->n_envs;
   q.n_steps = r->n_steps;
   q.done = 0;
-  q.tiles.clear();
+  q.first_tile = -1;
   const uint2 seed = make_uint2((uint32_t)r->seed, (uint32_t)(r->seed >> 32));
+  int32_t prev = -1;
   for (int32_t i = 0; i < need; ++i) {
-    const int32_t t = *s->free_tiles.begin();
-    s->free_tiles.erase(s->free_tiles.begin());
-    q.tiles.push_back(t);
+    const int32_t t = s->free_tiles.back();
+    s->free_tiles.pop_back();
+    s->tile_next[t] = -1;
+    if (prev < 0) q.first_tile = t;
+    else s->tile_next[prev] = t;
+    prev = t;
     const int32_t l0 = i * kTileEnvs, n = std::min(kTileEnvs, r->n_envs - l0);
     const uint64_t base = (uint64_t)t * s->tile_grid_bytes;
     uint64_t off = base;
@@ -256,7 +279,7 @@ int env_server_step(gx_server* s, int32_t K, void* stream, int32_t* finished, in
     // a tile admitted since the last launch carries the top bit: that launch
     // takes its descriptor and slots from host staging and resets its envs
     for (int32_t h : s->running)
-      for (int32_t t : s->reqs[h].tiles) {
+      for (int32_t t = s->reqs[h].first_tile; t >= 0; t = s->tile_next[t]) {
         list[n++] = (uint32_t)t | (s->fresh[t] ? 0x80000000u : 0u);
         s->fresh[t] = 0;
         max_cells = std::max(max_cells, s->tile_cells[t]);
@@ -276,15 +299,23 @@ int env_server_step(gx_server* s, int32_t K, void* stream, int32_t* finished, in
       const int32_t h = s->running[i];
       Request& q = s->reqs[h];
       q.done += std::min(K, q.n_steps - q.done);
-      if (q.done == q.n_steps) s->finished.push_back(h);
-      else s->running[keep++] = h;
+      if (q.done == q.n_steps) {
+        // at most max_tiles handles wait here: each is live until returned
+        s->finished[(s->fin_head + s->fin_count) % s->max_tiles] = h;
+        ++s->fin_count;
+      } else {
+        s->running[keep++] = h;
+      }
     }
     s->running.resize(keep);
   }
   int32_t n = 0;
-  while (n < cap && !s->finished.empty()) {
-    finished[n++] = s->finished.front();
-    s->finished.pop_front();
+  while (n < cap && s->fin_count > 0) {
+    const int32_t h = s->finished[s->fin_head];
+    s->reqs[h].reported = true;
+    finished[n++] = h;
+    s->fin_head = (s->fin_head + 1) % s->max_tiles;
+    --s->fin_count;
   }
   *n_finished = n;
   return GX_OK;
@@ -293,12 +324,15 @@ int env_server_step(gx_server* s, int32_t K, void* stream, int32_t* finished, in
 int env_server_release(gx_server* s, int32_t handle) {
   if (!s || handle < 0 || handle >= (int32_t)s->reqs.size() || !s->reqs[handle].live) return GX_EINVAL;
   Request& q = s->reqs[handle];
-  if (q.done < q.n_steps) return GX_ESTATE;
-  for (int32_t t : q.tiles) {
-    s->free_tiles.insert(t);
+  if (q.done < q.n_steps || !q.reported) return GX_ESTATE;
+  for (int32_t t = q.first_tile; t >= 0;) {
+    const int32_t next = s->tile_next[t];
+    s->free_tiles.push_back(t);
     s->tile_cells[t] = 0;
+    s->tile_next[t] = -1;
+    t = next;
   }
-  q.tiles.clear();
+  q.first_tile = -1;
   q.live = false;
   s->free_handles.push_back(handle);
   s->live -= 1;
@@ -338,14 +372,10 @@ Layout output_layout(int32_t stride, int32_t n_steps, bool keep_obs) {
   return l;
 }
 
-}  // namespace
-
-extern "C" {
-
-int env_serve_run(gx_server* s, const gx_serve_item* items, int32_t n_items, const uint8_t* family,
-                  const uint8_t* side, const uint8_t* param, const int32_t* max_steps,
-                  const gx_serve_opts* o, void* stream, double* admit_s, double* done_s,
-                  gx_serve_stats* stats) {
+// The loop of env_serve_run; its host containers may throw std::bad_alloc.
+int serve_run(gx_server* s, const gx_serve_item* items, int32_t n_items, const uint8_t* family,
+              const uint8_t* side, const uint8_t* param, const int32_t* max_steps, const gx_serve_opts* o,
+              void* stream, double* admit_s, double* done_s, gx_serve_stats* stats) {
   if (!s || !items || n_items < 0 || !family || !side || !max_steps || !o || !admit_s || !done_s ||
       !stats || o->K < 1 || o->max_inflight < 1 || !o->arena)
     return GX_EINVAL;
@@ -394,7 +424,8 @@ int env_serve_run(gx_server* s, const gx_serve_item* items, int32_t n_items, con
   std::deque<int32_t> queue;
   int32_t next = 0, completed = 0, delivered = 0, launches = 0;
   uint64_t env_steps = 0;
-  std::vector<int32_t> fin(4096);
+  // every finished handle comes back from the step call that finished it
+  std::vector<int32_t> fin(s->max_tiles);
   int rc = GX_OK;
   double t_admit = 0, t_step = 0, t_wait = 0;
   const auto t0 = clock::now();
@@ -587,6 +618,25 @@ out:
   stats->step_s = t_step;
   stats->wait_s = t_wait;
   return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int env_serve_run(gx_server* s, const gx_serve_item* items, int32_t n_items, const uint8_t* family,
+                  const uint8_t* side, const uint8_t* param, const int32_t* max_steps,
+                  const gx_serve_opts* o, void* stream, double* admit_s, double* done_s,
+                  gx_serve_stats* stats) {
+  try {
+    return serve_run(s, items, n_items, family, side, param, max_steps, o, stream, admit_s, done_s, stats);
+  } catch (const std::bad_alloc&) {
+    // launches and output copies of admitted requests may still be running
+    // (on the caller's stream and the loop's copy stream): let them end
+    // before the caller reuses the arenas
+    (void)hipDeviceSynchronize();
+    return GX_ENOMEM;
+  }
 }
 
 int env_server_destroy(gx_server* s) {

@@ -388,7 +388,9 @@ class Server:
         self.ptr = ctypes.c_void_p()
         _check("env_server_create", load().env_server_create(max_tiles, max_side, reward_mode,
                                                               ctypes.byref(self.ptr)))
-        self._fin = (ctypes.c_int32 * 4096)()
+        # at most max_tiles requests are live, so one step call returns every
+        # finished handle
+        self._fin = (ctypes.c_int32 * max_tiles)()
 
     def admit(self, table: workloads.EnvTable, n_steps: int, out: Traj, stride: int) -> int | None:
         """Queue a request for the envs of `table` (its first seed keys them

@@ -126,6 +126,56 @@ def test_busy_and_release():
     srv.close()
 
 
+def test_release_needs_the_returned_handle():
+    """A request whose last step is launched but whose handle no step call
+    has returned yet cannot be released; the next step call returns it
+    (without a launch, nothing else being live) and then it can."""
+    import ctypes
+    import torch
+    from paper_2407_19396_amd import gridenv as ge
+    srv = ge.Server(max_tiles=2)
+    t = wl.mixed_table(20, seed=21, mix_seed=22)
+    out = ge.Traj.alloc(8, 32)
+    h = srv.admit(t, 8, out, 32)
+    assert h is not None
+    n = ctypes.c_int32(-1)
+    fin = (ctypes.c_int32 * 1)()
+    rc = ge.load().env_server_step(srv.ptr, 64, ge._stream_ptr(None), fin, 0, ctypes.byref(n))
+    assert rc == ge.GX_OK and n.value == 0
+    torch.cuda.synchronize()
+    with pytest.raises(ge.GridEnvError) as ei:
+        srv.release(h)
+    assert ei.value.status == ge.GX_ESTATE
+    assert srv.step(64) == [h]
+    torch.cuda.synchronize()
+    srv.release(h)
+    assert srv.info()["free_tiles"] == 2
+    P.assert_rows_equal(crop(out, 20), oracle_of(wl.Request(0, 0.0, 20, 8, int(t.seed[0]), t)),
+                        what="released request")
+    srv.close()
+
+
+def test_native_loop_with_more_finishing_requests_than_4096():
+    """4500 one-env requests arriving together all finish in the same
+    launch; the loop collects every handle and completes."""
+    import torch
+    from paper_2407_19396_amd import gridenv as ge
+    reqs = []
+    for i in range(4500):
+        t = wl.mixed_table(1, seed=1000 + i, mix_seed=i)
+        reqs.append(wl.Request(i, 0.0, 1, 4, int(t.seed[0]), t))
+    srv = ge.Server(max_tiles=4608)
+    budget = srv.info()["device_bytes"] + (256 << 20)
+    arena = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    res = ge.serve_run(srv, reqs, 16, budget, arena, keep_obs=False)
+    assert res["completed"] == len(reqs)
+    assert res["launches"] == 1
+    assert res["env_steps"] == 4 * len(reqs)
+    info = srv.info()
+    assert info["live_requests"] == 0 and info["free_tiles"] == 4608
+    srv.close()
+
+
 def test_native_serving_loop_completes_everything():
     import torch
     from paper_2407_19396_amd import gridenv as ge
