@@ -226,17 +226,18 @@ def plain_leg(ge, wl, table, n_steps: int, seed: int) -> dict:
     import torch
     env = ge.GridEnv(table)
     traj = env.traj(n_steps)
+    rows = [traj.row(k) for k in range(n_steps)]
     acts = torch.from_numpy(wl.random_actions(n_steps, table.n, seed=seed)).to("cuda")
     stream = torch.cuda.current_stream()
     env.reset()
     for k in range(min(8, n_steps)):
-        env.step(traj.row(k), acts[k])
+        env.step(rows[k], acts[k])
     env.reset()
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record(stream)
     for k in range(n_steps):
-        env.step(traj.row(k), acts[k])
+        env.step(rows[k], acts[k])
     b.record(stream)
     torch.cuda.synchronize()
     ms = a.elapsed_time(b)
@@ -245,7 +246,7 @@ def plain_leg(ge, wl, table, n_steps: int, seed: int) -> dict:
     for k in range(n_steps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        env.step(traj.row(k), acts[k])
+        env.step(rows[k], acts[k])
         e1.record(stream)
         e1.synchronize()
         lat.append(e0.elapsed_time(e1))

@@ -237,6 +237,34 @@ def env_destroy(ctx: int):
 
 
 # --------------------------------------------------------------- tensors
+def check_buffer(t, what: str, dtype, numel: int, device) -> None:
+    """A tensor whose pointer a kernel is given: contiguous, of `dtype`, on
+    `device` and at least `numel` elements long (the kernels index it by the
+    batch size and the step count alone, so a shorter one would be read or
+    written past its end)."""
+    on_device = t.is_cuda if device.type == "cuda" else t.device.type == device.type
+    if (t.dtype is not dtype or t.numel() < numel or not t.is_contiguous() or not on_device
+            or (device.index is not None and t.device.index != device.index)):
+        raise ValueError(f"{what}: need a contiguous {dtype} tensor on {device} with at least {numel} "
+                         f"elements, got {t.dtype} {tuple(t.shape)} on {t.device}"
+                         f"{'' if t.is_contiguous() else ' (not contiguous)'}")
+
+
+def check_traj(tr: "Traj", n: int, obs_row_bytes: int, device, stride: int | None = None) -> None:
+    """Output rows for a batch of n envs: reward, flags, action (and mission,
+    if given) of rows x stride records (stride = n unless given), obs (if
+    given) of rows x obs_row_bytes bytes."""
+    import torch
+    recs = tr.rows * (n if stride is None else stride)
+    check_buffer(tr.reward, "reward", torch.float32, recs, device)
+    check_buffer(tr.flags, "flags", torch.uint8, recs, device)
+    check_buffer(tr.action, "action", torch.uint8, recs, device)
+    if tr.mission is not None:
+        check_buffer(tr.mission, "mission", torch.uint8, recs, device)
+    if tr.obs is not None:
+        check_buffer(tr.obs, "obs", torch.uint8, tr.rows * obs_row_bytes, device)
+
+
 @dataclass
 class Traj:
     """Device output rows: obs u8 [rows][N][7][7][3] (mode 0), [rows][N][7][7]
@@ -248,6 +276,28 @@ class Traj:
     flags: object
     action: object
     mission: object = None   # u8 [rows][N]: the episode's mission (GoToDoor colour, else 0xFF)
+
+    # A check (check_traj) holds for the buffers it saw: the record of the
+    # last one keeps those tensors and their C view, and a buffer replaced
+    # since is checked again.
+    def _buffers(self) -> tuple:
+        return (self.obs, self.reward, self.flags, self.action, self.mission)
+
+    def checked_view(self, key) -> GxTraj | None:
+        """The C view, if these buffers were checked for `key`."""
+        ck = self.__dict__.get("_ck")
+        if ck is None or ck[0] != key:
+            return None
+        b = ck[1]
+        if (b[0] is self.obs and b[1] is self.reward and b[2] is self.flags and b[3] is self.action
+                and b[4] is self.mission):
+            return ck[2]
+        return None
+
+    def mark_checked(self, key) -> GxTraj:
+        g = self.c()
+        self.__dict__["_ck"] = (key, self._buffers(), g)
+        return g
 
     @staticmethod
     def alloc(rows: int, n: int, device="cuda", with_obs: bool = True, obs_mode: int = 0,
@@ -268,7 +318,12 @@ class Traj:
     def row(self, k: int) -> "Traj":
         """Row k alone, as a one-row Traj (e.g. the output of one env_step)."""
         sl = lambda t: None if t is None else t[k:k + 1]   # noqa: E731
-        return Traj(sl(self.obs), sl(self.reward), sl(self.flags), sl(self.action), sl(self.mission))
+        r = Traj(sl(self.obs), sl(self.reward), sl(self.flags), sl(self.action), sl(self.mission))
+        # one row of checked rows holds the same records per row
+        ck = self.__dict__.get("_ck")
+        if ck is not None and self.checked_view(ck[0]) is not None:
+            r.mark_checked(ck[0])
+        return r
 
     def c(self) -> GxTraj:
         return GxTraj(self.obs.data_ptr() if self.obs is not None else None, self.reward.data_ptr(),
@@ -308,6 +363,9 @@ class GridEnv:
         self.calls = torch.zeros(n, dtype=torch.int32, device=dev)        # uint32 bits
         self.obst = torch.full((n * 16,), 0xFF, dtype=torch.uint8, device=dev)
         self._cstate = None
+        self._row_bytes = int(self.info()["obs_row_bytes"])
+        self._key = (self.n, self._row_bytes, self.device)
+        self._u8 = torch.uint8
 
     def state(self) -> GxState:
         """The C view of the state tensors (built once: the tensors are
@@ -317,20 +375,39 @@ class GridEnv:
         return self._cstate
 
     def traj(self, rows: int, with_obs: bool = True) -> Traj:
-        """Output rows shaped for this context's observation mode."""
-        return Traj.alloc(rows, self.n, self.device, with_obs, self.obs_mode,
-                          int(self.info()["obs_row_bytes"]))
+        """Output rows shaped for this context's observation mode (checked
+        for it from the start, and so are their rows)."""
+        tr = Traj.alloc(rows, self.n, self.device, with_obs, self.obs_mode, self._row_bytes)
+        check_traj(tr, self.n, self._row_bytes, self.device)
+        tr.mark_checked(self._key)
+        return tr
+
+    def _out(self, tr: Traj) -> GxTraj:
+        """The C view of output rows, their sizes checked against this batch
+        (once per set of buffers and batch shape)."""
+        g = tr.checked_view(self._key)
+        if g is None:
+            check_traj(tr, self.n, self._row_bytes, self.device)
+            g = tr.mark_checked(self._key)
+        return g
+
+    def _actions(self, actions, n_steps: int) -> int | None:
+        """Pointer of external actions u8 [n_steps][N], or None (the on-device
+        random policy)."""
+        if actions is None:
+            return None
+        check_buffer(actions, "actions", self._u8, n_steps * self.n, self.device)
+        return actions.data_ptr()
 
     def reset(self, first: Traj | None = None, stream=None):
-        env_reset(self.ctx, self.state(), first.c() if first is not None else None, stream)
+        env_reset(self.ctx, self.state(), self._out(first) if first is not None else None, stream)
 
     def step(self, out: Traj, actions=None, stream=None):
-        env_step(self.ctx, self.state(), actions.data_ptr() if actions is not None else None,
-                 out.c(), stream)
+        env_step(self.ctx, self.state(), self._actions(actions, 1), self._out(out), stream)
 
     def rollout(self, n_steps: int, traj: Traj, actions=None, K: int = 0, stream=None):
-        env_rollout(self.ctx, self.state(), n_steps,
-                    actions.data_ptr() if actions is not None else None, traj.c(), K, stream)
+        env_rollout(self.ctx, self.state(), n_steps, self._actions(actions, n_steps), self._out(traj), K,
+                    stream)
 
     def set_launch(self, K: int, blocks: int = 0):
         env_set_launch(self.ctx, K, blocks)
@@ -394,7 +471,13 @@ class Server:
 
     def admit(self, table: workloads.EnvTable, n_steps: int, out: Traj, stride: int) -> int | None:
         """Queue a request for the envs of `table` (its first seed keys them
-        all); returns its handle, or None when no tiles are free now."""
+        all); returns its handle, or None when no tiles are free now.
+        `out` holds at least n_steps rows of `stride` records."""
+        import torch
+        if out.rows < n_steps or stride < table.n:
+            raise ValueError(f"request outputs: need {n_steps} rows of stride >= {table.n}, "
+                             f"got {out.rows} rows of stride {stride}")
+        check_traj(out, table.n, stride * OBS_BYTES, torch.device("cuda"), stride=stride)
         fam = np.ascontiguousarray(table.family, np.uint8)
         side = np.ascontiguousarray(table.side, np.uint8)
         ms = np.ascontiguousarray(table.max_steps, np.int32)

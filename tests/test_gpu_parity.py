@@ -266,6 +266,33 @@ def test_step_before_reset_is_an_error(ge):
         env.rollout(3, traj)
 
 
+def test_buffers_too_small_or_mistyped_are_refused(ge):
+    """Actions and outputs are checked against the batch before a launch:
+    a refused call enqueues nothing, and the state carries on as if it had
+    not been made."""
+    import torch
+    table = wl.uniform_table(70, wl.FAMILY_TWOROOM, 6, seed=4)
+    env, _ = make(ge, table)
+    b, s, _ = P.oracle_reset(table)
+    acts = wl.random_actions(6, table.n, seed=9)
+    d = torch.from_numpy(acts).cuda()
+    traj = ge.Traj.alloc(6, table.n)
+    with pytest.raises(ValueError):
+        env.rollout(6, traj, d.long(), K=4)                   # int64 actions
+    with pytest.raises(ValueError):
+        env.rollout(7, traj, d, K=4)                          # 6 rows of actions for 7 steps
+    with pytest.raises(ValueError):
+        env.step(traj.row(0), d[0, :69])                      # one env short
+    with pytest.raises(ValueError):
+        env.rollout(6, ge.Traj.alloc(6, table.n - 1), d, K=4)   # outputs for a smaller batch
+    with pytest.raises(ValueError):
+        env.rollout(6, ge.Traj.alloc(6, table.n, device="cpu"), d, K=4)   # host outputs
+    env.rollout(6, traj, d, K=4)
+    torch.cuda.synchronize()
+    P.assert_rows_equal(traj, ox.rollout(b, s, 6, acts, nthreads=8), what="after refused calls")
+    P.assert_state_equal(env, s, "after refused calls")
+
+
 def test_rollouts_are_deterministic(ge):
     import torch
     table = wl.mixed_table(4096, seed=1, mix_seed=2)

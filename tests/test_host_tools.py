@@ -151,3 +151,46 @@ def test_serving_summary_splits_runs(tmp_path):
     text = profiling.serving_summary(str(d), "cmd")
     assert text.count("## run") == 2
     assert "serving launches: 5" in text and "(99.2 % of the span)" in text
+
+
+def test_buffer_checks_of_the_binding():
+    """The binding refuses, before any kernel sees it, a buffer of the wrong
+    type, too short for the batch, not contiguous or on another device."""
+    import torch
+    from paper_2407_19396_amd import gridenv as ge
+    cpu = torch.device("cpu")
+    ge.check_buffer(torch.zeros(4, 10, dtype=torch.uint8), "a", torch.uint8, 40, cpu)
+    ge.check_buffer(torch.zeros(4, 10, dtype=torch.uint8)[1], "a", torch.uint8, 10, cpu)   # a row
+    bad = [(torch.zeros(40, dtype=torch.int64), torch.uint8, 40, cpu),          # type
+           (torch.zeros(39, dtype=torch.uint8), torch.uint8, 40, cpu),          # length
+           (torch.zeros(10, 4, dtype=torch.uint8).t(), torch.uint8, 40, cpu),   # layout
+           (torch.zeros(40, dtype=torch.uint8), torch.uint8, 40, torch.device("cuda"))]   # device
+    for t, dt, n, dev in bad:
+        with pytest.raises(ValueError):
+            ge.check_buffer(t, "a", dt, n, dev)
+    rows, n = 3, 5
+    tr = ge.Traj.alloc(rows, n, device="cpu")
+    ge.check_traj(tr, n, n * ge.OBS_BYTES, cpu)
+    with pytest.raises(ValueError):
+        ge.check_traj(tr, n + 1, (n + 1) * ge.OBS_BYTES, cpu)                  # a bigger batch
+    with pytest.raises(ValueError):
+        ge.check_traj(tr, n, n * ge.OBS_BYTES, cpu, stride=8)                  # a wider request row
+    tr2 = ge.Traj(tr.obs, tr.reward.double(), tr.flags, tr.action)
+    with pytest.raises(ValueError):
+        ge.check_traj(tr2, n, n * ge.OBS_BYTES, cpu)                           # reward not f32
+    # a check holds for the buffers it saw, in the rows too, until a buffer
+    # is replaced
+    key = (n, n * ge.OBS_BYTES, cpu)
+    assert tr.checked_view(key) is None
+    g = tr.mark_checked(key)
+    assert tr.checked_view(key) is g and tr.checked_view((n + 1,) + key[1:]) is None
+    r1 = tr.row(1)
+    assert r1.checked_view(key) is not None
+    assert r1.reward.data_ptr() == tr.reward[1].data_ptr() and r1.rows == 1
+    r1.flags = torch.zeros(1, n, dtype=torch.uint8)
+    assert r1.checked_view(key) is None
+    tr.flags = torch.zeros(rows, n, dtype=torch.uint8)
+    assert tr.checked_view(key) is None
+    r1b = tr.row(1)
+    assert r1b.checked_view(key) is None
+    assert r1b.flags.data_ptr() == tr.flags[1].data_ptr()
