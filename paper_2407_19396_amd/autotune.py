@@ -97,12 +97,16 @@ def tune(env, traj, Ks=(128, 256, 512), steps: int = 0, tile_envs=(64, 32, 16), 
     props = torch.cuda.get_device_properties(dev)
     Ks = [k for k in Ks if k <= traj.rows]
     Es = [e for e in tile_envs if 1 <= e <= 64]
+    if not Ks or not Es:
+        raise ValueError(f"nothing to tune: no K candidate fits a ring of {traj.rows} rows "
+                         f"or no envs per tile in 1..64 (Ks {Ks}, tile_envs {tuple(tile_envs)})")
     key = (batch_key(env.table, props.name, env.obs_mode, env.reward_mode, Ks) +
            f"|steps{steps}|E{','.join(str(e) for e in Es)}")
     cache = {}
     if use_cache and os.path.exists(CACHE):
         try:
-            cache = json.load(open(CACHE))
+            with open(CACHE) as f:
+                cache = json.load(f)
         except (OSError, ValueError):
             cache = {}
     if use_cache and key in cache and cache[key].get("K") in Ks and cache[key].get("tile_envs") in Es:
@@ -144,7 +148,12 @@ def tune(env, traj, Ks=(128, 256, 512), steps: int = 0, tile_envs=(64, 32, 16), 
         try:
             os.makedirs(os.path.dirname(CACHE), exist_ok=True)
             cache[key] = {k: best[k] for k in ("tile_envs", "K", "blocks", "lds_bytes", "rate")} | {"steps": steps}
-            json.dump(cache, open(CACHE, "w"), indent=1)
+            # written whole and then renamed, so a concurrent reader sees the
+            # old file or the new one
+            tmp = f"{CACHE}.{os.getpid()}.tmp"
+            with open(tmp, "w") as f:
+                json.dump(cache, f, indent=1)
+            os.replace(tmp, CACHE)
         except OSError:
             pass
     return best | {"cached": False, "trials": results, "steps": steps}
