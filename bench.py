@@ -27,7 +27,11 @@ Reported beside it:
     latency) and with each request's scalar outputs delivered to pinned host
     memory (host-ready latency, anchored on the delivering loop's own
     saturated capacity);
-  * cpu_baseline: the oracle on the host's cores on a bounded sample.
+  * cpu_baseline: the oracle on the host's cores on a bounded sample, and
+    under parity the timed run itself checked against the oracle: the state
+    and the last output row of every env (or of an even sample when that is
+    too much CPU work), bit for bit; a mismatch ends the run with an error
+    after the line is printed.
 --workload and --obs select the other task mixes and observation functions.
 """
 from __future__ import annotations
@@ -160,6 +164,58 @@ def cpu_baseline(table, n_envs: int, n_steps: int, obs_mode: int = 0, sprites=No
                       f"observations on, {dt:.1f} s",
             "single_thread": {"value": n1 * n_steps / dt1, "cores": 1,
                               "sample": f"first {n1} envs, {n_steps} steps, {dt1:.1f} s"}}
+
+
+def snapshot(env, traj, row: int, with_obs: bool) -> dict:
+    """Host copy of the state and of output row `row` (the timed rollout's
+    last step; its observations only if with_obs), taken before later runs
+    move them on."""
+    last = {f: (None if getattr(traj, f) is None else getattr(traj, f)[row].cpu().numpy())
+            for f in ("reward", "flags", "action", "mission")}
+    last["obs"] = traj.obs[row].cpu().numpy() if with_obs and traj.obs is not None else None
+    return {"state": env.state_numpy(), "last": last}
+
+
+def oracle_parity(table, snap: dict, n_steps: int, obs_mode: int, max_env_steps: float = 2e8) -> dict:
+    """The timed run against the oracle: every env (or an even sample of
+    them when that is more than max_env_steps of CPU work) reset and stepped
+    n_steps times by the random policy, as the GPU did since the rollout's
+    reset; its state and last output row compared bit for bit (first-person
+    observations included)."""
+    import oracle as ox
+    n = table.n
+    n_check = int(min(n, max(64, max_env_steps // max(1, n_steps))))
+    idx = np.unique(np.linspace(0, n - 1, n_check).round().astype(np.int64))
+    sub = table.subset(idx)
+    check_obs = obs_mode in (0, 1)
+    b = ox.Batch(sub.family, sub.side, sub.max_steps, sub.seed, sub.rng_id, 0, sub.param,
+                 obs_mode if check_obs else 0)
+    s = ox.State.empty(b)
+    threads = host_threads()
+    t0 = time.perf_counter()
+    ox.reset(b, s, nthreads=threads)
+    ref = ox.rollout(b, s, n_steps, None, rows=1, with_obs=check_obs, nthreads=threads)
+    dt = time.perf_counter() - t0
+    g = snap["state"]
+    sides = table.side.astype(np.int64)
+    off = np.concatenate([[0], np.cumsum(3 * sides * sides)])
+    gpu = {"grid": np.concatenate([g["grid"][off[i]:off[i + 1]] for i in idx]),
+           "obst": g["obst"].reshape(n, -1)[idx].reshape(-1)}
+    for f in ("x", "y", "dir", "t", "carry", "episode", "done_prev", "calls"):
+        gpu[f] = g[f][idx]
+    bad = [f for f in gpu if not np.array_equal(gpu[f].view(getattr(s, f).dtype), getattr(s, f))]
+    last = snap["last"]
+    for f in ("reward", "flags", "action", "mission"):
+        r = getattr(ref, f)
+        if last[f] is not None and r is not None:
+            a = last[f][idx]
+            if not np.array_equal(a.view(np.uint8), r[0].view(np.uint8)):
+                bad.append(f"last row {f}")
+    if check_obs and last["obs"] is not None and not np.array_equal(last["obs"][idx], ref.obs[0]):
+        bad.append("last row obs")
+    return {"envs": int(len(idx)), "of": n, "steps_since_reset": n_steps,
+            "compared": "state and the last output row" + (" with observations" if check_obs else ""),
+            "bit_exact": not bad, "mismatch": bad, "oracle_s": round(dt, 2)}
 
 
 def pct(xs, q):
@@ -377,6 +433,8 @@ def main():
               "batch would shard by env id (each GPU steps its own envs; nothing is exchanged "
               "between them), so one GPU's share is what is measured.", file=sys.stderr)
         sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        ap.error("--steps must be at least 1 and --warmup at least 0")
 
     import torch
     from paper_2407_19396_amd import gridenv as ge
@@ -484,6 +542,10 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = start.elapsed_time(stop)
+    # every step since the reset before the warmup (the graph's untimed
+    # replay included), for the oracle's check of the timed run
+    since_reset = args.warmup + args.steps * (2 if graph is not None else 1)
+    snap = None if args.no_cpu else snapshot(env, traj, (args.steps - 1) % ring, obs_mode in (0, 1))
     timed_chunks = chunks(args.steps, K)
     env_steps = table.n * args.steps
     value = env_steps / (ms / 1e3)
@@ -595,6 +657,11 @@ def main():
         else:
             cpu = cpu_baseline(table, min(args.cpu_envs or table.n, table.n), args.cpu_steps, obs_mode)
         log(f"[bench] cpu oracle: {cpu['value'] / 1e6:.2f} M env-steps/s on {cpu['cores']} threads")
+        cpu["parity"] = oracle_parity(table, snap, since_reset, obs_mode)
+        snap = None
+        par = cpu["parity"]
+        log(f"[bench] timed run vs oracle ({par['envs']} of {par['of']} envs, {since_reset} steps): "
+            + ("bit-exact" if par["bit_exact"] else f"MISMATCH in {', '.join(par['mismatch'])}"))
 
     out = {
         "metric": "env-steps/sec on 1 MI355X, fused multi-size vs plain step; p50/p99 latency",
@@ -626,6 +693,8 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    if cpu is not None and not cpu["parity"]["bit_exact"]:
+        sys.exit("bench: the timed run does not match the oracle")
 
 
 if __name__ == "__main__":

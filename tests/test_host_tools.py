@@ -194,3 +194,37 @@ def test_buffer_checks_of_the_binding():
     r1b = tr.row(1)
     assert r1b.checked_view(key) is None
     assert r1b.flags.data_ptr() == tr.flags[1].data_ptr()
+
+
+def _oracle_snapshot(table, steps):
+    """What bench.snapshot would hold after a reset and `steps` steps, made
+    by the oracle itself in the GPU's layout."""
+    import oracle as ox
+    b = ox.Batch(table.family, table.side, table.max_steps, table.seed, table.rng_id, 0, table.param)
+    s = ox.State.empty(b)
+    ox.reset(b, s, nthreads=4)
+    out = ox.rollout(b, s, steps, None, rows=1, nthreads=4)
+    state = {f: getattr(s, f).copy() for f in ("grid", "x", "y", "dir", "t", "carry", "episode",
+                                               "done_prev", "calls", "obst")}
+    last = {f: getattr(out, f)[0].copy() for f in ("obs", "reward", "flags", "action")}
+    last["mission"] = out.mission[0].copy() if out.mission is not None else None
+    return {"state": state, "last": last}
+
+
+def test_bench_oracle_check_of_the_timed_run():
+    """The bench's check passes a run that is the oracle's, over every env
+    and over an even sample, and names what differs in one that is not."""
+    b = _bench()
+    table = wl.mixed_table(300, seed=5, mix_seed=6)
+    snap = _oracle_snapshot(table, 13)
+    whole = b.oracle_parity(table, snap, 13, 0)
+    assert whole["bit_exact"] and whole["envs"] == 300 and whole["mismatch"] == []
+    part = b.oracle_parity(table, snap, 13, 0, max_env_steps=13 * 100)
+    assert part["bit_exact"] and part["envs"] == 100
+    # one grid byte of the last env and one observation byte of env 0
+    snap["state"]["grid"][-1] ^= 1
+    snap["last"]["obs"][0, 3, 3, 0] ^= 1
+    bad = b.oracle_parity(table, snap, 13, 0)
+    assert not bad["bit_exact"] and bad["mismatch"] == ["grid", "last row obs"]
+    # a different step count is a different run
+    assert not b.oracle_parity(table, _oracle_snapshot(table, 12), 13, 0)["bit_exact"]
