@@ -365,17 +365,17 @@ def graph_leg(ge, wl, table, n_steps: int, warmup: int) -> dict:
             "chunk_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)}, "roofline": roof}
 
 
-def run_configs(steps_c3: int) -> dict:
+def run_configs(steps_c3: int, seed: int = 0) -> dict:
     from paper_2407_19396_amd import gridenv as ge
     from paper_2407_19396_amd import workloads as wl
     out = {}
-    t = wl.workload_empty5(seed=0)
+    t = wl.workload_empty5(seed=seed)
     out["empty5_plain"] = {"workload": "16 Empty 5x5, T=100, 100 steps of external uniform actions, "
                                        "plain kernel (one launch per step)", **plain_leg(ge, wl, t, 100, 1)}
-    t = wl.workload_empty8(seed=0)
+    t = wl.workload_empty8(seed=seed)
     out["empty8_plain"] = {"workload": "4096 Empty 8x8, T=256, 1000 steps of external uniform actions, "
                                        "plain kernel (one launch per step)", **plain_leg(ge, wl, t, 1000, 2)}
-    t = wl.workload_tworoom8(seed=0)
+    t = wl.workload_tworoom8(seed=seed)
     out["tworoom8_graph"] = {"workload": f"65536 TwoRoom key/door 8x8, T=640, {steps_c3} steps, random "
                                          "policy on device, fused kernel, rollout captured in a HIP graph",
                              **graph_leg(ge, wl, t, steps_c3, 256)}
@@ -392,6 +392,9 @@ def main():
     ap.add_argument("--repeats", type=int, default=5,
                     help="further timed runs of the same rollout, reported as median / min / max")
     ap.add_argument("--workload", default="mixed", choices=sorted(WORKLOADS))
+    ap.add_argument("--seed", type=int, default=0,
+                    help="master seed of the workloads: keys every env's layouts and random policy "
+                         "(the mix of families and sizes stays the same)")
     ap.add_argument("--envs", type=int, default=0, help="override the workload's env count")
     ap.add_argument("--K", type=int, default=0, help="steps fused per launch (0: autotune)")
     ap.add_argument("--blocks", type=int, default=0, help="persistent workgroups (0: autotune or default)")
@@ -450,17 +453,17 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copy probe: {n} bytes read and {n} bytes written by one copy kernel")
         del src, dst
-    make = {"mixed": lambda: wl.workload_mixed(seed=0, n=args.envs or 262144),
-            "tworoom8": lambda: wl.workload_tworoom8(seed=0),
-            "empty8": lambda: wl.workload_empty8(seed=0),
-            "empty5": lambda: wl.workload_empty5(seed=0),
-            "empty24": lambda: wl.uniform_table(args.envs or 65536, wl.FAMILY_EMPTY, 24, seed=0),
-            "empty32": lambda: wl.uniform_table(args.envs or 65536, wl.FAMILY_EMPTY, 32, seed=0),
-            "tworoom32": lambda: wl.uniform_table(args.envs or 65536, wl.FAMILY_TWOROOM, 32, seed=0),
-            "lava": lambda: wl.workload_lava(seed=0, n=args.envs or 262144),
-            "dynobs": lambda: wl.workload_dynobs(seed=0, n=args.envs or 262144),
-            "gotodoor": lambda: wl.workload_gotodoor(seed=0, n=args.envs or 262144),
-            "keycorridor": lambda: wl.workload_keycorridor(seed=0, n=args.envs or 262144)}[args.workload]
+    make = {"mixed": lambda: wl.workload_mixed(seed=args.seed, n=args.envs or 262144),
+            "tworoom8": lambda: wl.workload_tworoom8(seed=args.seed),
+            "empty8": lambda: wl.workload_empty8(seed=args.seed),
+            "empty5": lambda: wl.workload_empty5(seed=args.seed),
+            "empty24": lambda: wl.uniform_table(args.envs or 65536, wl.FAMILY_EMPTY, 24, seed=args.seed),
+            "empty32": lambda: wl.uniform_table(args.envs or 65536, wl.FAMILY_EMPTY, 32, seed=args.seed),
+            "tworoom32": lambda: wl.uniform_table(args.envs or 65536, wl.FAMILY_TWOROOM, 32, seed=args.seed),
+            "lava": lambda: wl.workload_lava(seed=args.seed, n=args.envs or 262144),
+            "dynobs": lambda: wl.workload_dynobs(seed=args.seed, n=args.envs or 262144),
+            "gotodoor": lambda: wl.workload_gotodoor(seed=args.seed, n=args.envs or 262144),
+            "keycorridor": lambda: wl.workload_keycorridor(seed=args.seed, n=args.envs or 262144)}[args.workload]
     obs_mode = OBS_MODES[args.obs]
     rgb = obs_mode >= 4
     if rgb and not args.envs:
@@ -642,7 +645,7 @@ def main():
     torch.cuda.empty_cache()
     configs = None
     if not args.no_configs and args.workload == "mixed" and obs_mode == 0:
-        configs = run_configs(args.c3_steps)
+        configs = run_configs(args.c3_steps, args.seed)
     serving = None
     if args.serve_requests > 0 and args.workload == "mixed" and obs_mode == 0:
         loads = tuple(float(x) for x in args.serve_loads.split(","))
@@ -681,7 +684,7 @@ def main():
                    "tile_envs": info["tile_envs"],
                    "lds_bytes_per_wg": info["lds_bytes"], "max_tile_cells": info["max_tile_cells"],
                    "global_batch": table.n, "autotuned": tuned is not None,
-                   "hip_graph": graph is not None, "observation": args.obs},
+                   "hip_graph": graph is not None, "observation": args.obs, "seed": args.seed},
         "fused_launch_ms": {"K": K, "p50": pct(lat, 50), "p99": pct(lat, 99)} if len(lat) else None,
         "repeats": None if not reps else {"n": len(reps), "median": float(np.median(reps)),
                                           "min": float(np.min(reps)), "max": float(np.max(reps)),
