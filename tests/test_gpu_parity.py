@@ -448,6 +448,54 @@ def test_gotodoor_done_and_out_of_range_actions(ge, kernel):
     P.assert_state_equal(env, s, f"gotodoor {kernel}")
 
 
+def largest_tiles_table():
+    """Three tiles: 64 envs of side 32 (the largest LDS a tile can take,
+    64 KiB of codes), 64 of side 31 (the families that need an odd side),
+    and a ragged tile of 5 more of side 32; every family and parameter
+    range that those sides allow."""
+    big = ([(wl.FAMILY_EMPTY, 32, 0), (wl.FAMILY_TWOROOM, 32, 0), (wl.FAMILY_LAVAGAP, 32, 0),
+            (wl.FAMILY_DISTSHIFT, 32, 1), (wl.FAMILY_DISTSHIFT, 32, 2), (wl.FAMILY_GOTODOOR, 32, 0)] +
+           [(wl.FAMILY_DYNOBS, 32, k) for k in range(1, 9)])
+    odd = ([(wl.FAMILY_FOURROOMS, 31, 0)] + [(wl.FAMILY_CROSSINGS, 31, k) for k in range(1, 9)] +
+           [(wl.FAMILY_KEYCORRIDOR, 31, r) for r in (1, 2, 3)])
+    tasks = [big[i % len(big)] for i in range(64)] + [odd[i % len(odd)] for i in range(64)] + big[:5]
+    fam, side, par = (np.array(c, np.uint8) for c in zip(*tasks))
+    n = len(tasks)
+    ms = np.array([wl.default_max_steps(int(f), int(s)) for f, s in zip(fam, side)], np.int32)
+    return wl.EnvTable(fam, side, ms, np.full(n, 61, np.uint64), np.arange(n, dtype=np.uint32),
+                       "largest tiles", par)
+
+
+@pytest.mark.parametrize("kernel", ["fused", "plain"])
+@pytest.mark.parametrize("mode", [0, 2])
+def test_largest_tiles(ge, kernel, mode):
+    """Tiles at the LDS limit (the fused kernel stages 64 grids of side 32)
+    and side-31 grids of every odd-side family, first-person and whole-grid
+    records, through both kernels: every record and the state equal the
+    oracle's."""
+    import torch
+    table = largest_tiles_table()
+    env = ge.GridEnv(table, obs_mode=mode)
+    info = env.info()
+    assert info["n_tiles"] == 3 and info["max_tile_cells"] == 64 * 32 * 32
+    first = env.traj(1)
+    env.reset(first)
+    b, s, ref0 = P.oracle_reset(table, obs_mode=mode)
+    steps = 60
+    traj = env.traj(steps)
+    if kernel == "fused":
+        env.rollout(steps, traj, K=16)
+    else:
+        for k in range(steps):
+            env.step(traj.row(k))
+    ref = ox.rollout(b, s, steps, None, nthreads=8)
+    torch.cuda.synchronize()
+    P.assert_rows_equal(first, ref0, what=f"reset, largest tiles, mode {mode}")
+    P.assert_rows_equal(traj, ref, what=f"{kernel}, largest tiles, mode {mode}")
+    P.assert_state_equal(env, s, f"{kernel}, largest tiles")
+    env.close()
+
+
 @pytest.mark.parametrize("tile_envs", [1, 13, 16, 32, 48])
 @pytest.mark.parametrize("mode", [0, 1, 2, 3])
 def test_tiling_parity(ge, tile_envs, mode):
