@@ -1626,8 +1626,8 @@ struct LdsGrid {
 // inside [0, n) (the rest belong to the neighbouring tiles' records); their
 // reads reach at most 64 cells before the tile (21 for symbolic units) and
 // 7 after it, inside the cleared margins.
-// kNT: non-temporal stores (trajectory records); the state write-back uses
-// ordinary ones, since the next launch reads it again.
+// kNT: non-temporal stores (trajectory records); the state write-back
+// (emit_dirty_grids) uses ordinary ones, since the next launch reads it again.
 // The output bytes of a categorical unit q (4 cells) or a symbolic one (16
 // bytes of at most 6 cells), from the LDS codes.
 __device__ __forceinline__ uint32_t cat_unit(int o, const uint32_t* table, const uint8_t* codes) {
@@ -1703,6 +1703,45 @@ __device__ __forceinline__ void emit_tile_grids(uint8_t* dst, int n_cells, const
     for (int u = 0; u < kDepth; ++u) {
       const int q = q0 + u * kWave;
       if (q < units) store_unit<kCat, kNT>(A + (uintptr_t)(kUnit * q), d0, d1, w[u]);
+    }
+  }
+}
+
+// Write-back of the grids that changed in a launch (the lanes in `dirty`;
+// every other env's grid in HBM still holds the bytes staged in, so writing
+// it again would change nothing).  Each run of consecutive dirty lanes is
+// one range of the tile's block, written as the symbolic units of
+// emit_tile_grids that make up the 64-byte lines holding it: the lines'
+// other bytes are neighbouring envs' current cells, equal to what HBM holds,
+// and the units at the block's two ends store only their bytes inside it.
+__device__ __forceinline__ void emit_dirty_grids(uint8_t* dst, int n_cells, uint64_t dirty, int my_off,
+                                                 int my_cells, const uint32_t* table, const uint8_t* codes,
+                                                 int lane) {
+  const uintptr_t d0 = reinterpret_cast<uintptr_t>(dst), d1 = d0 + 3 * (uintptr_t)(uint32_t)n_cells;
+  const uintptr_t A = d0 & ~(uintptr_t)63;
+  const int rel = (int)((int64_t)A - (int64_t)d0);   // in [-63, 0]
+  const int units = (int)((d1 - A + 15) / 16);
+  while (dirty) {
+    const int r = __ffsll((unsigned long long)dirty) - 1;
+    const uint64_t from = dirty >> r;   // bit 0 set: the run's length is its trailing ones
+    const int len = ~from == 0 ? kWave - r : __ffsll((unsigned long long)~from) - 1;
+    const int r2 = r + len - 1;
+    dirty = r2 == kWave - 1 ? 0 : dirty & ~(((1ull << len) - 1) << r);
+    // the run's cells [c0, c1), as bytes from A, widened to whole lines
+    const int c0 = bcast(my_off, r), c1 = bcast(my_off, r2) + bcast(my_cells, r2);
+    const int q0 = ((3 * c0 - rel) & ~63) >> 4;
+    const int q1 = min(units, ((3 * c1 - rel + 63) & ~63) >> 4);
+    // as in emit_tile_grids: a lane's units read before any is stored
+    constexpr int kDepth = 4;
+    for (int qb = q0 + lane; qb < q1; qb += kDepth * kWave) {
+      u32x4 w[kDepth];
+#pragma unroll
+      for (int u = 0; u < kDepth; ++u) w[u] = sym_unit(rel + 16 * min(qb + u * kWave, q1 - 1), table, codes);
+#pragma unroll
+      for (int u = 0; u < kDepth; ++u) {
+        const int q = qb + u * kWave;
+        if (q < q1) store_unit<false, false>(A + (uintptr_t)(16 * q), d0, d1, w[u]);
+      }
     }
   }
 }
@@ -1877,6 +1916,8 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
   // reads take their base as an immediate; the tile grids are dynamic
   __shared__ __align__(16) uint32_t table[kKinds * kView];
   __shared__ __align__(16) uint8_t stage[kRecStageBytes];
+  // per lane: whether a pickup, drop or toggle changed a cell of its grid
+  __shared__ uint8_t cell_changed[kWave];
   extern __shared__ __align__(16) uint8_t grids[];
   uint8_t* codes = grids + kMargin;
   const int lane = threadIdx.x;
@@ -1994,6 +2035,7 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
     }
     int tile_cells;
     const int my_off = wave_excl_scan(S * S, lane, tile_cells);
+    cell_changed[lane] = 0;
     uint8_t* my_codes = codes + my_off;
     // the tile's grids are contiguous in HBM: stage them as codes (a fresh
     // tile's are laid out here instead)
@@ -2064,7 +2106,10 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
           gotodoor_rules(r, act, front, ob[0] & 0xFFu);
           edge_view = r.front_changed;   // a door toggled, possibly on the outer ring
         }
-        if (r.front_changed) my_codes[fy * S + fx] = (uint8_t)code_of(r.new_front);
+        if (r.front_changed) {
+          my_codes[fy * S + fx] = (uint8_t)code_of(r.new_front);
+          cell_changed[lane] = 1;
+        }
         t += 1;
         const bool trunc = t >= T;
         reward = step_reward(r, t, T, a.env.reward_mode);
@@ -2147,10 +2192,13 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
       wave_sync();
     }
 
-    // write the chunk's final state back: the grids as aligned 16-byte
-    // units (the two at the block's ends byte by byte, since neighbouring
-    // tiles own the rest of those units)
-    emit_tile_grids<false, false>(a.st.grid + g0, tile_cells, table, codes, lane);
+    // write the chunk's final state back: the grids that changed (laid out
+    // afresh, by a reset (the episode counter moved on from the one still
+    // in HBM) or at admission, written by a pickup, drop or toggle, or
+    // holding balls, which move every step)
+    const bool dirty = active && (fresh || fam == kFamDynObs || cell_changed[lane] != 0 ||
+                                  episode != a.st.episode[e]);
+    emit_dirty_grids(a.st.grid + g0, tile_cells, __ballot(dirty), my_off, S * S, table, codes, lane);
     if (active) {
       a.st.x[e] = x;
       a.st.y[e] = y;
@@ -2172,7 +2220,7 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
 size_t fused_dynamic_lds_bytes(int32_t max_tile_cells) { return tile_lds_bytes(max_tile_cells); }
 
 size_t fused_lds_bytes(int32_t max_tile_cells) {
-  return kKinds * kView * 4 + kRecStageBytes + fused_dynamic_lds_bytes(max_tile_cells);
+  return kKinds * kView * 4 + kRecStageBytes + kWave + fused_dynamic_lds_bytes(max_tile_cells);
 }
 
 hipError_t launch_plain(const EnvTables& env, const StateBufs& st, const uint8_t* actions,
