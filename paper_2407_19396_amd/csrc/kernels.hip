@@ -1707,42 +1707,47 @@ __device__ __forceinline__ void emit_tile_grids(uint8_t* dst, int n_cells, const
   }
 }
 
-// Write-back of the grids that changed in a launch (the lanes in `dirty`;
-// every other env's grid in HBM still holds the bytes staged in, so writing
-// it again would change nothing).  Each run of consecutive dirty lanes is
-// one range of the tile's block, written as the symbolic units of
-// emit_tile_grids that make up the 64-byte lines holding it: the lines'
-// other bytes are neighbouring envs' current cells, equal to what HBM holds,
-// and the units at the block's two ends store only their bytes inside it.
-__device__ __forceinline__ void emit_dirty_grids(uint8_t* dst, int n_cells, uint64_t dirty, int my_off,
-                                                 int my_cells, const uint32_t* table, const uint8_t* codes,
+// Write-back of the grids that changed in a launch (the lanes with `dirty`
+// set; every other env's grid in HBM still holds the bytes staged in, so
+// writing it again would change nothing).  The dirty lanes mark the 64-byte
+// lines of the tile's block that their grids touch, in a bitmap in `lines`
+// (LDS, one bit per line), and the symbolic units of emit_tile_grids are
+// then stored for the marked lines only: a line's other bytes belong to
+// neighbouring envs and are rewritten with their current cells, which equal
+// what HBM holds, and the units at the block's two ends store only their
+// bytes inside it.
+__device__ __forceinline__ void emit_dirty_grids(uint8_t* dst, int n_cells, bool dirty, int my_off, int my_cells,
+                                                 const uint32_t* table, const uint8_t* codes, uint32_t* lines,
                                                  int lane) {
   const uintptr_t d0 = reinterpret_cast<uintptr_t>(dst), d1 = d0 + 3 * (uintptr_t)(uint32_t)n_cells;
   const uintptr_t A = d0 & ~(uintptr_t)63;
   const int rel = (int)((int64_t)A - (int64_t)d0);   // in [-63, 0]
   const int units = (int)((d1 - A + 15) / 16);
-  while (dirty) {
-    const int r = __ffsll((unsigned long long)dirty) - 1;
-    const uint64_t from = dirty >> r;   // bit 0 set: the run's length is its trailing ones
-    const int len = ~from == 0 ? kWave - r : __ffsll((unsigned long long)~from) - 1;
-    const int r2 = r + len - 1;
-    dirty = r2 == kWave - 1 ? 0 : dirty & ~(((1ull << len) - 1) << r);
-    // the run's cells [c0, c1), as bytes from A, widened to whole lines
-    const int c0 = bcast(my_off, r), c1 = bcast(my_off, r2) + bcast(my_cells, r2);
-    const int q0 = ((3 * c0 - rel) & ~63) >> 4;
-    const int q1 = min(units, ((3 * c1 - rel + 63) & ~63) >> 4);
-    // as in emit_tile_grids: a lane's units read before any is stored
-    constexpr int kDepth = 4;
-    for (int qb = q0 + lane; qb < q1; qb += kDepth * kWave) {
-      u32x4 w[kDepth];
-#pragma unroll
-      for (int u = 0; u < kDepth; ++u) w[u] = sym_unit(rel + 16 * min(qb + u * kWave, q1 - 1), table, codes);
-#pragma unroll
-      for (int u = 0; u < kDepth; ++u) {
-        const int q = qb + u * kWave;
-        if (q < q1) store_unit<false, false>(A + (uintptr_t)(16 * q), d0, d1, w[u]);
-      }
+  const int n_words = (((units + 3) >> 2) + 31) >> 5;
+  for (int w = lane; w < n_words; w += kWave) lines[w] = 0u;
+  wave_sync();
+  if (dirty && my_cells > 0) {
+    // lines [l0, l1) hold this grid's bytes; at most 49 lines, so 3 words
+    const int l0 = (3 * my_off - rel) >> 6, l1 = (3 * (my_off + my_cells) - rel + 63) >> 6;
+    for (int w = l0 >> 5; w <= (l1 - 1) >> 5; ++w) {
+      const int lo = max(l0 - 32 * w, 0), hi = min(l1 - 32 * w, 32);
+      atomicOr(&lines[w], (hi - lo == 32 ? ~0u : ((1u << (hi - lo)) - 1u)) << lo);
     }
+  }
+  wave_sync();
+  constexpr int kDepth = 4;
+  for (int qb = lane; qb < units; qb += kDepth * kWave) {
+    u32x4 w[kDepth];
+    bool keep[kDepth];
+#pragma unroll
+    for (int u = 0; u < kDepth; ++u) {
+      const int q = qb + u * kWave;
+      keep[u] = q < units && ((lines[q >> 7] >> ((q >> 2) & 31)) & 1u) != 0;
+      w[u] = keep[u] ? sym_unit(rel + 16 * q, table, codes) : u32x4{0u, 0u, 0u, 0u};
+    }
+#pragma unroll
+    for (int u = 0; u < kDepth; ++u)
+      if (keep[u]) store_unit<false, false>(A + (uintptr_t)(16 * (qb + u * kWave)), d0, d1, w[u]);
   }
 }
 
@@ -2198,7 +2203,12 @@ __global__ __launch_bounds__(kWave) void k_fused(FusedArgs a) {
     // holding balls, which move every step)
     const bool dirty = active && (fresh || fam == kFamDynObs || cell_changed[lane] != 0 ||
                                   episode != a.st.episode[e]);
-    emit_dirty_grids(a.st.grid + g0, tile_cells, __ballot(dirty), my_off, S * S, table, codes, lane);
+    // the record stage is idle after the last step: it holds the line bitmap
+    // (a tile of 64 grids of side 32 spans at most 3074 lines)
+    static_assert(((3 * kWave * 32 * 32 + 63 + 15) / 16 / 4 + 1 + 31) / 32 * 4 <= kRecStageBytes,
+                  "the line bitmap fits the record stage");
+    emit_dirty_grids(a.st.grid + g0, tile_cells, dirty, my_off, S * S, table, codes,
+                     reinterpret_cast<uint32_t*>(stage), lane);
     if (active) {
       a.st.x[e] = x;
       a.st.y[e] = y;
