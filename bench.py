@@ -126,8 +126,12 @@ def roofline_entry(bytes_per_launch: float, launch_ms: float, traffic=None, **ex
     if not frac <= 1.0:
         raise SystemExit(f"bench.py: roofline fraction {frac:.3f} > 1 ({bytes_per_launch:.4g} B in "
                          f"{launch_ms:.4g} ms): the byte or time accounting is wrong")
-    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": frac,
-            "traffic": traffic, "bytes_per_launch": bytes_per_launch, "launch_ms": launch_ms, **extra}
+    out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": frac,
+           "traffic": traffic, "bytes_per_launch": bytes_per_launch, "launch_ms": launch_ms, **extra}
+    if traffic is not None and traffic < bytes_per_launch and extra.get("kernel") == "k_fused":
+        out["traffic_note"] = ("below the algorithmic bytes: the state term counts every grid written "
+                               "back, the kernel writes back only the grids that changed")
+    return out
 
 
 def host_threads() -> int:

@@ -134,6 +134,9 @@ def test_bench_launch_accounting():
     assert 0 < r["frac"] <= 1 and abs(r["achieved"] - per / 0.25e-3 / 1e9) < 1e-6
     with pytest.raises(SystemExit):
         b.roofline_entry(b.fused_bytes(n, g, 1024), 0.25)     # 1024 steps of bytes in a 20-step time
+    # counter traffic below the algorithmic bytes is explained on the line
+    assert "traffic_note" in b.roofline_entry(per, 0.25, 0.9 * per, kernel="k_fused")
+    assert "traffic_note" not in b.roofline_entry(per, 0.25, 1.01 * per, kernel="k_fused")
 
 
 def test_serving_summary_splits_runs(tmp_path):
