@@ -496,6 +496,34 @@ def test_largest_tiles(ge, kernel, mode):
     env.close()
 
 
+@pytest.mark.parametrize("blocks", [1, 3])
+@pytest.mark.parametrize("tile_envs,mode", [(64, 0), (16, 0), (64, 2)])
+def test_persistent_workgroups_many_tiles_each(ge, blocks, tile_envs, mode):
+    """Far fewer workgroups than tiles: each workgroup runs many tiles in
+    turn, so whatever one tile leaves in LDS (codes, the record stage, the
+    write-back's line bitmap, the per-lane cell-written flags) must not leak
+    into the next; every family, resets, pickups, toggles and moving balls,
+    launches of a few steps and a partial last one."""
+    import torch
+    table = wl.families_table(700, seed=95, mix_seed=96)
+    env = ge.GridEnv(table, obs_mode=mode)
+    env.set_tiling(tile_envs)
+    env.set_launch(6, blocks)
+    assert env.info()["blocks"] == blocks and env.info()["n_tiles"] >= 3 * blocks
+    first = env.traj(1)
+    env.reset(first)
+    b, s, ref0 = P.oracle_reset(table, obs_mode=mode)
+    steps = 40
+    traj = env.traj(steps)
+    env.rollout(steps, traj)
+    ref = ox.rollout(b, s, steps, None, nthreads=8)
+    torch.cuda.synchronize()
+    assert (ref.flags & 4).sum() > 100      # resets happen inside the launches
+    P.assert_rows_equal(traj, ref, what=f"{blocks} workgroups, tiles of {tile_envs}, mode {mode}")
+    P.assert_state_equal(env, s, f"{blocks} workgroups, tiles of {tile_envs}")
+    env.close()
+
+
 @pytest.mark.parametrize("tile_envs", [1, 13, 16, 32, 48])
 @pytest.mark.parametrize("mode", [0, 1, 2, 3])
 def test_tiling_parity(ge, tile_envs, mode):
