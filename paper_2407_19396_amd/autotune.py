@@ -41,6 +41,13 @@ def batch_key(table, device_name: str, obs_mode: int = 0, reward_mode: int = 0, 
             f"code{kernel_source_hash()}")
 
 
+def resident_blocks(n_tiles: int, lds_bytes: int, cus: int, lds_per_cu: int = 160 * 1024) -> int:
+    """The most workgroups that are resident at once by LDS (at most 16 per
+    compute unit), or the tile count if that is smaller."""
+    fit = max(1, min(16, lds_per_cu // max(1, lds_bytes)))
+    return min(n_tiles, fit * cus)
+
+
 def block_candidates(n_tiles: int, lds_bytes: int, cus: int, lds_per_cu: int = 160 * 1024) -> list[int]:
     """Workgroup counts worth trying: the largest that fits the LDS of every
     CU, smaller ones, those that make every workgroup take the same number
@@ -86,9 +93,10 @@ def tune(env, traj, Ks=(128, 256, 512), steps: int = 0, tile_envs=(64, 32, 16), 
     """Pick the envs per tile, K and the workgroup count for rollouts of
     `steps` steps (0: one launch of each candidate K, the steady state).
 
-    First the envs per tile (each tiling at its default workgroup count, one
-    per tile, K the largest candidate), then K x workgroups for the best
-    tiling.  When `steps` is shorter than every candidate K,
+    First the envs per tile (each tiling at one workgroup per tile and at
+    the count resident at once by LDS, K the largest candidate: large grids
+    can run a tiling faster in persistent workgroups), then K x workgroups
+    for the best tiling.  When `steps` is shorter than every candidate K,
     all of them run the same single launch, so only the workgroup count is
     searched (at the largest K, which later full launches then use)."""
     import torch
@@ -134,7 +142,10 @@ def tune(env, traj, Ks=(128, 256, 512), steps: int = 0, tile_envs=(64, 32, 16), 
     firsts = []
     for E in Es:
         env.set_tiling(E)
-        firsts.append(trial(E, max(search), env.info()["blocks"]))
+        info = env.info()
+        counts = sorted({info["blocks"], resident_blocks(info["n_tiles"], info["lds_bytes"],
+                                                         props.multi_processor_count)})
+        firsts.append(max((trial(E, max(search), b) for b in counts), key=lambda r: r["rate"]))
     E = max(firsts, key=lambda r: r["rate"])["tile_envs"]
     # stage 2: K x workgroups at that tiling
     env.set_tiling(E)

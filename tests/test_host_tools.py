@@ -17,6 +17,14 @@ def test_block_candidates_include_full_occupancy_and_whole_rounds():
     assert max(c) == 10                   # never more workgroups than tiles
 
 
+def test_resident_blocks_by_lds():
+    # side-32 grids in tiles of 32 envs: 39 760 B a workgroup, four per CU
+    assert autotune.resident_blocks(n_tiles=2048, lds_bytes=39760, cus=256) == 1024
+    assert autotune.resident_blocks(n_tiles=700, lds_bytes=39760, cus=256) == 700
+    assert autotune.resident_blocks(n_tiles=10**6, lds_bytes=100, cus=256) == 16 * 256   # wave cap
+    assert autotune.resident_blocks(n_tiles=10**6, lds_bytes=200_000, cus=256) == 256    # at least one
+
+
 def test_traffic_is_read_only_for_the_same_kernel(tmp_path):
     p = tmp_path / "k.txt"
     h = profiling.kernel_source_hash()
